@@ -1,0 +1,187 @@
+"""Benchmark of the DPG per-cell local solve on one MI355X.
+
+A step is one full local-solve pass (geometry, formation of G, B_f, l,
+Jacobi-scaled blocked Cholesky, triangular solves, K_e = W^H W, l_e, eta) over
+every cell of the workload, inputs already resident in HBM.  Prints one JSON
+line (see the keys below).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2609_03155_amd import workloads as W  # noqa: E402
+
+METRIC = "DPG local-solve elements/s (B^H G^{-1} B + eta) mixed-prec vs FP64; rel err"
+PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 matrix peak
+PEAK_HBM_GBS = 8000.0
+
+
+def algorithmic_flops(p: int, dp: int) -> dict:
+    """Structure-aware algorithmic flop counts per cell: formation of the real
+    S, M, C, D, R, T contractions, complex Cholesky of the n_v x n_v Gram
+    matrix, triangular solves (half cost on the real trace columns), HERK and
+    the two GEMVs (l_e, eta)."""
+    s, r = p + dp + 1, p + 1
+    n1 = p + dp + 2
+    N = 3 * s * (s + 1) ** 2
+    nv = 2 * N
+    m1 = (p + 1) ** 3
+    nq = n1 ** 3
+    nu, nt = 6 * m1, 24 * r * r
+    k = nu + nt
+    return dict(form=12 * N * N * nq + 12 * N * m1 * nq + 48 * N * r * (r + 1) * n1 * n1,
+                chol=4.0 / 3.0 * nv ** 3, trsm=4 * nv * nv * nu + 2 * nv * nv * nt, herk=4 * k * k * nv,
+                vec=32 * nv * k)
+
+
+def cpu_baseline(w, budget_s: float = 20.0):
+    """The oracle, as it stands, on a bounded seeded sample of the workload's
+    cells; returns (record, per-cell oracle outputs)."""
+    from oracle import dpg_oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    om = O.omega_dimensionless(w.freq_hz)
+    pt = w.port
+    pm = O.PortMode(pt["a"], pt["b"], pt["m"], pt["n"], om, pt["eps"], pt["mu"])
+    x, off = W.random_coefficients(w)
+    rng = np.random.default_rng(W.SEED_BASE + 77)
+    order = rng.permutation(w.n_cells)
+    outs = {}
+    t0 = time.perf_counter()
+    for c in order:
+        c = int(c)
+        cp = O.CellProblem(X=w.cell_vertices(c), p=int(w.degree[c]), dp=w.dp, eps=complex(w.eps[c]),
+                           mu=complex(w.mu[c]), omega=om, face_kind=tuple(int(k) for k in w.face_kind[c]),
+                           zinv=tuple(complex(z) for z in w.zinv[c]), port=pm)
+        G, Bf, l = O.cell_forms(cp)
+        K, le, eta = O.local_solve(G, Bf, l, x[off[c]:off[c + 1]])
+        outs[c] = (K, le, eta)
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    rec = {"value": len(outs) / dt, "unit": "elements/s", "cores": int(cores), "kind": "oracle",
+           "sample": f"{len(outs)} seeded cells of {w.name} ({dt:.1f} s, numpy/LAPACK FP64, LU solves)"}
+    return rec, outs
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (requested --gpus {args.gpus}); the per-cell local solve needs no "
+              "communication, see DESIGN.md for how it shards.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2609_03155_amd import dpg
+
+    w = W.CONFIGS[int(args.workload[1])]()
+    x, off = W.random_coefficients(w)
+    plan = dpg.Plan(w.degree, w.dp)
+    prob = dpg.DeviceProblem.from_workload(w)
+    K, l, eta, info = plan.alloc_outputs()
+    xd = torch.from_numpy(x).cuda()
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        plan.local_solve(prob, xd, K, l, eta, info, stream=stream)
+    torch.cuda.synchronize()
+    plan.profile()                       # discard
+    plan.set_profiling(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        plan.local_solve(prob, xd, K, l, eta, info, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    plan.set_profiling(False)
+    ms = e0.elapsed_time(e1)
+    prof = plan.profile()
+    ms_step = ms / args.steps
+    value = w.n_cells / (ms_step * 1e-3)
+    info_h = info.cpu().numpy()
+
+    # roofline of the dominant kernel class, from the live per-launch event timings
+    fl = {}
+    for p in sorted(set(int(v) for v in w.degree)):
+        cnt = int(np.sum(w.degree == p))
+        for key, v in algorithmic_flops(p, w.dp).items():
+            fl[key] = fl.get(key, 0.0) + v * cnt
+    cls_flops = {"chol_panel": None, "herk": fl["herk"] + fl["vec"]}
+    # the factorisation sweep = k_chol_diag + k_chol_panel (Cholesky of G and W = L^{-1} B_f)
+    fac_ms = prof["chol_diag"][0] + prof["chol_panel"][0]
+    fac_launches = prof["chol_diag"][1] + prof["chol_panel"][1]
+    classes = {k: v for k, v in prof.items() if v[1] > 0}
+    dominant = max(classes, key=lambda k: classes[k][0])
+    if dominant in ("chol_diag", "chol_panel"):
+        dom_name = "chol_diag+chol_panel (blocked Cholesky + TRSM sweep)"
+        dom_flops = (fl["chol"] + fl["trsm"]) * args.steps
+        dom_ms = fac_ms
+        dom_launches = fac_launches
+    elif dominant == "herk":
+        dom_name = "herk (K_e = W^H W, l_e, eta)"
+        dom_flops = cls_flops["herk"] * args.steps
+        dom_ms = prof["herk"][0]
+        dom_launches = prof["herk"][1]
+    else:
+        dom_name = dominant
+        dom_flops = fl["form"] * args.steps
+        dom_ms = sum(prof[k][0] for k in ("scale", "form_SM", "form_IF", "form_pad", "form_B", "form_load"))
+        dom_launches = sum(prof[k][1] for k in ("scale", "form_SM", "form_IF", "form_pad", "form_B", "form_load"))
+    achieved = dom_flops / (dom_ms * 1e-3) / 1e12
+    total_alg = sum(fl.values())
+    rec = {
+        "metric": METRIC, "value": value, "unit": "elements/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "cells": w.n_cells, "degrees": sorted(set(int(v) for v in w.degree)),
+                   "dp": w.dp, "freq_hz": w.freq_hz, "precision": "fp64", "parallelism": "single-gpu"},
+        "roofline": {"bound": "mfma", "kernel": dom_name, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "launches_per_step": dom_launches / args.steps,
+                     "avg_launch_ms": dom_ms / max(1, dom_launches)},
+        "whole_step_tflops": total_alg / (ms_step * 1e-3) / 1e12,
+        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items() if v[1]},
+        "failed_cells": int(np.sum(info_h != 0)),
+    }
+    if not args.no_cpu_baseline:
+        base, outs = cpu_baseline(w, args.cpu_budget)
+        rec["cpu_baseline"] = base
+        Kh, lh, eh = K.cpu().numpy(), l.cpu().numpy(), eta.cpu().numpy()
+        eK, el, ee = [], [], []
+        for c, (Ko, lo, eo) in outs.items():
+            k = int(off[c + 1] - off[c])
+            Kg = Kh[plan.K_off[c]:plan.K_off[c + 1]].reshape(k, k).T
+            eK.append(np.linalg.norm(Kg - Ko) / np.linalg.norm(Ko))
+            el.append(np.linalg.norm(lh[off[c]:off[c + 1]] - lo) / max(np.linalg.norm(lo), 1e-300))
+            ee.append(abs(eh[c] - eo) / eo)
+        rec["rel_err_vs_oracle"] = {"cells": len(outs), "K_e_max": float(np.max(eK)),
+                                    "K_e_median": float(np.median(eK)), "l_e_max": float(np.max(el)),
+                                    "eta_max": float(np.max(ee))}
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,213 @@
+/*
+ * dpg.h -- C ABI of libdpgmi: the per-cell local solve of the discontinuous
+ * Petrov-Galerkin (DPG) method for the ultraweak time-harmonic Maxwell system
+ * on hexahedra, on one AMD MI355X (gfx950) GPU.
+ *
+ * Method (Marquis, Maier, Blais, arXiv 2609.03155):
+ *   For every cell K the library forms, from the cell's trilinear geometry,
+ *   complex permittivity eps and permeability mu, frequency and trial degree p
+ *   with test enrichment dp:
+ *     G   -- Gram matrix of the enriched test space in the adjoint graph inner
+ *            product (Sec. 2.2, test inner product, alpha > 0),
+ *     B_f -- [B | Bhat]: the ultraweak bilinear form b_h and the skeleton trace
+ *            pairing (Sec. 2.2), with entries as listed in Sec. 2.3,
+ *     l   -- the linear form l_h (Sec. 2.2) with Robin data g,
+ *   and returns (Sec. 2.3, elimination of the error representation function)
+ *     K_e = B_f^H G^{-1} B_f,   l_e = B_f^H G^{-1} l,
+ *     eta = ||Psi||_V = sqrt(r^H G^{-1} r),  r = B_f x - l  (Sec. 2.3).
+ *   All forms are conjugate-linear in the first (test) argument.
+ *
+ * Conventions shared by every entry point
+ *   - Units: non-dimensional as in App. A with the reference length given by
+ *     the caller (the paper uses L = 1 m): x = x_dim / L,
+ *     omega = L * 2*pi*freq / c0 with c0 = 299792458 m/s.
+ *   - Complex numbers are interleaved (re, im) doubles.
+ *   - Materials follow the paper's sign (time factor e^{-i omega t}): a lossy
+ *     medium has Im(eps) > 0.
+ *   - Reference cell [0,1]^3; cell vertex v(i,j,k) is entry 4k+2j+i of the
+ *     cell's connectivity row; faces are numbered x-, x+, y-, y+, z-, z+.
+ *   - Local unknown order (rows/columns of K_e, entries of l_e and x):
+ *       E_x, E_y, E_z, H_x, H_y, H_z : (p+1)^3 discontinuous tensor-product
+ *         Lagrange functions each, at the Gauss-Lobatto nodes, index
+ *         i + (p+1)(j + (p+1)k) (x fastest);
+ *       E-hat, H-hat : 12 (p+1)^2 tangential-trace functions each, from the
+ *         first-kind Nedelec space of FEEC index r = p+1 mapped by the
+ *         covariant Piola transform, interior functions dropped:
+ *           12 edges x r functions  (edges 0-3 along x at (y,z) = (0,0),(1,0),
+ *           (0,1),(1,1); 4-7 along y at (x,z); 8-11 along z at (x,y)); the
+ *           function of degree i along the edge is
+ *           sqrt(2i+1) P_i(2 xi_a - 1) * (vertex factors 1-xi or xi);
+ *           then 6 faces x 2 r (r-1) functions: on face f with tangential
+ *           axes t1 < t2, first the t1-component functions
+ *           sqrt(2i+1)P_i(2xi_t1-1) * (1-xi_n or xi_n) * b_m(xi_t2), then the
+ *           t2-component ones with t1 and t2 swapped; i = 0..r-1 fastest,
+ *           m = 2..r; b_m(t) = (P_m(2t-1) - P_{m-2}(2t-1)) / sqrt(2(2m-1)).
+ *     so k = 6 (p+1)^3 + 24 (p+1)^2 unknowns per cell.
+ *   - Test space (internal; K_e, l_e and eta do not depend on its basis):
+ *     first-kind Nedelec of FEEC index s = p+dp+1 for each of F and I,
+ *     3 s (s+1)^2 functions per field.  Gauss-Legendre quadrature with
+ *     p+dp+2 points per direction.
+ *   - PEC faces are treated as interior faces locally (n x E = 0 is imposed
+ *     on the global trace unknowns at assembly).  On Robin faces (port and
+ *     impedance outlet) the H-hat pairing is absent, so H-hat functions that
+ *     live only on Robin faces give zero rows and columns of K_e (Sec. 2.3).
+ *   - Streams: every call that takes a stream enqueues its work on it and
+ *     returns without synchronising; the caller owns all input and output
+ *     buffers, the plan owns its scratch.  No C++ exception crosses the ABI.
+ *   - Errors: argument errors are reported synchronously (DPG_ERR_ARG);
+ *     HIP launch/allocation failures as DPG_ERR_HIP / DPG_ERR_ALLOC.
+ *     Per-cell numerical failures never abort a batch; they are written to
+ *     the device array info[] (0 = ok, -1 = degenerate cell geometry
+ *     (det J <= 0 at a quadrature point or non-finite input), k > 0 = the
+ *     Cholesky factorisation of the Jacobi-scaled G met a non-positive pivot
+ *     at (1-based) column k of the padded test space).  Outputs of failed
+ *     cells are unspecified.
+ */
+#ifndef DPG_H
+#define DPG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DPG_OK = 0,
+  DPG_ERR_ARG = -1,          /* invalid argument (null pointer, bad degree, ...) */
+  DPG_ERR_ALLOC = -2,        /* device or host allocation failed */
+  DPG_ERR_HIP = -3,          /* a HIP runtime call or kernel launch failed */
+  DPG_ERR_UNSUPPORTED = -4   /* valid request this build does not support */
+} dpg_status;
+
+typedef enum {
+  DPG_FP64 = 0,              /* every step in FP64 */
+  DPG_SPLIT_FP32 = 1         /* reserved: split-FP32 contractions, FP64 Cholesky and eta */
+} dpg_precision;
+
+enum {
+  DPG_FACE_INTERIOR = 0,     /* interior skeleton face: trace pairing only */
+  DPG_FACE_PEC = 1,          /* perfect conductor: local treatment as interior */
+  DPG_FACE_PORT = 2,         /* Robin face, g from the TE_mn port mode */
+  DPG_FACE_ROBIN0 = 3        /* Robin face with g = 0 (impedance outlet) */
+};
+
+/* TE_mn port mode of Sec. 4.1: a guide [0,a] x [0,b] (non-dimensional,
+ * i.e. in units of L) along x3, filled with (eps, mu); the mode is the
+ * paper's E_sol, H_sol with k_x1 = m pi/a, k_x2 = n pi/b,
+ * k_x3 = sqrt(omega^2 eps mu - k_c^2) (principal branch).  On a DPG_FACE_PORT
+ * face the Robin datum is g = n x H_sol + Z^{-1} n x (E_sol x n), with Z^{-1}
+ * the face's admittance from dpg_problem.zinv. */
+typedef struct {
+  double a, b;
+  int32_t m, n;
+  double eps_re, eps_im;
+  double mu_re, mu_im;
+} dpg_port;
+
+/* Problem description.  All arrays are DEVICE pointers (hipMalloc'ed or
+ * torch CUDA tensors), read-only for the library. */
+typedef struct {
+  int64_t n_cells;
+  int64_t n_vertices;
+  const double* vertices;     /* [n_vertices][3], metres                       */
+  const int64_t* cells;       /* [n_cells][8] vertex ids, v(i,j,k) at 4k+2j+i  */
+  const double* eps;          /* [n_cells][2] complex relative permittivity    */
+  const double* mu;           /* [n_cells][2] complex relative permeability    */
+  const int8_t* face_kind;    /* [n_cells][6] DPG_FACE_* per face               */
+  const double* zinv;         /* [n_cells][6][2] complex Robin admittance Z^-1 */
+  double freq_hz;             /* excitation frequency                            */
+  double length_m;            /* reference length L of App. A (paper: 1.0)      */
+  double alpha;               /* L2 weight of the test norm (paper: 1.0), > 0   */
+  dpg_port port;              /* mode used on DPG_FACE_PORT faces                */
+} dpg_problem;
+
+typedef struct dpg_plan_s* dpg_plan;
+
+/* Local sizes of a (p, dp) cell (Sec. 2.3 spaces): n_test = 6 s (s+1)^2
+ * (F and I), n_interior = 6 (p+1)^3 (E and H), n_trace = 24 (p+1)^2
+ * (E-hat and H-hat).  Supported: 1 <= p <= 4, 1 <= dp <= 2.  Host only. */
+dpg_status dpg_local_dims(int32_t p, int32_t dp, int32_t* n_test, int32_t* n_interior,
+                          int32_t* n_trace);
+
+/* Creates a plan for a batch of cells on HIP device `device`.
+ * degree_host: HOST array [n_cells] of trial degrees p (1..4); dp: the test
+ * enrichment (1..2) used for every cell.  The plan groups cells by degree,
+ * builds the reference tables of each degree on the device and sizes its
+ * workspace so that it stays below max_workspace_bytes (0 = 40% of the
+ * device memory free at creation).  Synchronous. */
+dpg_status dpg_plan_create(int32_t device, const int8_t* degree_host, int64_t n_cells, int32_t dp,
+                           int64_t max_workspace_bytes, dpg_plan* plan);
+
+dpg_status dpg_plan_destroy(dpg_plan plan);
+
+/* Output offsets, in complex elements, written to HOST arrays of n_cells+1
+ * entries: K_e of cell c occupies K[K_off[c] .. K_off[c+1]) (k_c x k_c,
+ * column-major, full Hermitian), l_e and x of cell c occupy
+ * [v_off[c] .. v_off[c+1]) (k_c entries). */
+dpg_status dpg_plan_offsets(dpg_plan plan, int64_t* K_off, int64_t* v_off);
+
+/* Number of padded test rows, RHS rows and cells per chunk used for degree p
+ * (diagnostics and tests).  Host only. */
+dpg_status dpg_plan_layout(dpg_plan plan, int32_t p, int64_t* n_test_padded, int64_t* n_rhs_padded,
+                           int64_t* chunk_cells);
+
+/* The local solve.  Device pointers:
+ *   x    [v_off[n]][2]  trial + trace coefficients per cell for eta, or NULL
+ *                       (then eta is written as 0),
+ *   K    [K_off[n]][2]  K_e per cell (output),
+ *   l    [v_off[n]][2]  l_e per cell (output),
+ *   eta  [n]            residual indicator per cell (output),
+ *   info [n]            per-cell status (output, see above).
+ * precision must be DPG_FP64 in this build (DPG_ERR_UNSUPPORTED otherwise).
+ * stream is a hipStream_t (NULL = the default stream). */
+dpg_status dpg_local_solve(dpg_plan plan, const dpg_problem* prob, const double* x, double* K,
+                           double* l, double* eta, int32_t* info, int32_t precision, void* stream);
+
+/* Debug/parity entry: the unscaled local matrices of `count` consecutive
+ * cells first, first+1, ... which must all have the plan's degree p.
+ * Device outputs, complex, column-major per cell:
+ *   G [count][n_test][n_test], Bf [count][k][n_test] (column a of B_f is
+ *   contiguous: Bf[c][a][i] = B_f(i, a)), lvec [count][n_test].
+ * Row order of the test space: F functions (3 s (s+1)^2, component-major,
+ * then x-, y-, z-degree with x fastest, orthonormal shifted Legendre factors),
+ * then I functions in the same order. */
+dpg_status dpg_form_local(dpg_plan plan, const dpg_problem* prob, int64_t first, int64_t count,
+                          double* G, double* Bf, double* lvec, int32_t* info, void* stream);
+
+/* Kernel classes timed by the plan's optional profiler. */
+enum {
+  DPG_K_SCALE = 0,      /* geometry check and Jacobi scaling            */
+  DPG_K_FORM_SM = 1,    /* G_FF, G_II (volume and Robin mass terms)      */
+  DPG_K_FORM_IF = 2,    /* G_IF from the geometry-free matrices          */
+  DPG_K_FORM_PAD = 3,   /* padding of the test space                     */
+  DPG_K_FORM_B = 4,     /* rows of B_f^H                                 */
+  DPG_K_FORM_LOAD = 5,  /* port load vector                              */
+  DPG_K_RESID = 6,      /* r = B_f x - l                                 */
+  DPG_K_CHOL_DIAG = 7,  /* diagonal blocks of the blocked Cholesky       */
+  DPG_K_CHOL_PANEL = 8, /* panels of L and of W^H (Cholesky + TRSM)      */
+  DPG_K_HERK = 9,       /* K_aug = W^H W -> K_e, l_e, eta                */
+  DPG_K_COUNT = 10
+};
+
+/* Enables (1) or disables (0) per-kernel timing: while enabled, every kernel
+ * launch of dpg_local_solve is bracketed by HIP events recorded on the
+ * caller's stream.  Host only; takes effect for later solves. */
+dpg_status dpg_plan_set_profiling(dpg_plan plan, int32_t enable);
+
+/* Waits for the recorded events and returns, per kernel class, the summed
+ * device time in milliseconds (ms[DPG_K_COUNT]) and the number of launches
+ * (launches[DPG_K_COUNT]) since the previous call; then resets.  Host only,
+ * synchronises with the recorded events. */
+dpg_status dpg_plan_profile(dpg_plan plan, double* ms, int64_t* launches);
+
+const char* dpg_status_string(dpg_status s);
+
+/* Text of the last HIP failure seen by this thread inside the library (the
+ * failing call and HIP's error string), for diagnostics.  Host only. */
+const char* dpg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DPG_H */

@@ -1,0 +1,102 @@
+// Internal interface between the host API (dpg_api.cpp) and the HIP kernels
+// (dpg_kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <vector>
+
+namespace dpg {
+
+// Device copies of the reference tables of one (p, dp) pair (see dpg_tables.h).
+struct DevTables {
+  int p, dp, s, r, n1, nq, nfq, N, Np, nc, m1, nu, nt1, nt, k, kp, nvp, nrows;
+  const double* vol_w;     // [nq]
+  const double* vol_pts;   // [nq][3]
+  const double* vol_v;     // [nq][Np]
+  const double* vol_c;     // [nq][Np][3]
+  const int8_t* comp;      // [Np]
+  const double* vol_phi;   // [nq][m1]
+  const double* face_w;    // [6][nfq]
+  const double* face_pts;  // [6][nfq][3]
+  const double* face_v;    // [6][nfq][Np]
+  const double* face_phi;  // [6][nfq][m1]
+  const double* Cref;      // [N][N]
+  const double* CrefT;     // [N][N] transpose
+  const double* RtT;       // [6][N][N]  RtT[f][j][i] = Rt_f[i][j]
+  const double* T;         // [6][N][nt1]
+  const int4* sm_tiles;    // formation tiles (a, b, I, J) of the S/M kernel
+  int n_sm_tiles;
+};
+
+// Per-call problem data (device pointers) plus derived scalars.
+struct ProbArgs {
+  const double* vertices;
+  const int64_t* cells;
+  const double* eps;
+  const double* mu;
+  const int8_t* face_kind;
+  const double* zinv;
+  double omega, alpha, inv_len;
+  // TE_mn port
+  int has_port;
+  double pk1, pk2, pk3re, pk3im, pkc2, pmu_re, pmu_im;
+};
+
+// Per-chunk workspace of one degree group.
+struct ChunkArgs {
+  const int64_t* cell_ids;   // [n] global cell id per chunk-local cell
+  int64_t n;                 // cells in the chunk
+  double2* Z;                // [n][nvp cols][nrows] augmented lower factor, column-major
+  double* dscale;            // [n][nvp] Jacobi scaling of the test rows
+  const int64_t* K_off;      // [n_cells+1] global output offsets (complex elements)
+  const int64_t* v_off;
+  const double2* x;          // trial+trace coefficients, or null
+  double2* K;                // outputs
+  double2* l;
+  double* eta;
+  int32_t* info;
+};
+
+// Optional per-kernel timing: when `on`, each launch is bracketed by two HIP
+// events recorded on the launch stream; `recs` keeps (class, begin, end).
+struct Prof {
+  bool on = false;
+  struct Rec {
+    int cls;
+    hipEvent_t b, e;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t take() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+  void begin(int cls, hipStream_t st) {
+    if (!on) return;
+    Rec r{cls, take(), take()};
+    (void)hipEventRecord(r.b, st);
+    recs.push_back(r);
+  }
+  void end(hipStream_t st) {
+    if (on && !recs.empty()) (void)hipEventRecord(recs.back().e, st);
+  }
+};
+
+// Launchers (enqueue on `stream`, return the HIP launch status).
+hipError_t launch_formation(const DevTables& t, const ProbArgs& pa, const ChunkArgs& ca, hipStream_t st,
+                            Prof* prof = nullptr);
+hipError_t launch_factor(const DevTables& t, const ChunkArgs& ca, hipStream_t st, Prof* prof = nullptr);
+hipError_t launch_herk(const DevTables& t, const ChunkArgs& ca, hipStream_t st, Prof* prof = nullptr);
+// Raise the dynamic-LDS limit of the kernels that stage whole tiles (once per process).
+hipError_t configure_kernels();
+// Unscaled G, B_f, l of `n` cells into dense per-cell arrays (parity entry).
+hipError_t launch_extract(const DevTables& t, const ChunkArgs& ca, double2* G, double2* Bf, double2* lvec,
+                          hipStream_t st);
+
+}  // namespace dpg

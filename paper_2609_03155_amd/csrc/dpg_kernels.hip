@@ -1,0 +1,1178 @@
+// HIP kernels (gfx950) of the DPG per-cell local solve.
+//
+// Per degree group and chunk of cells the pipeline is
+//   k_cell_scale  geometry check and Jacobi scaling d_i = G_ii^{-1/2}
+//   k_form_SM     G_FF, G_II from S, M (volume) and the Robin face mass
+//   k_form_IF     G_IF from the geometry-free C and Rt (Sec. 2.2 test norm)
+//   k_form_pad    identity/zero padding of the test space
+//   k_form_B      rows of B_f^H and l^H (Sec. 2.2 forms, entries of Sec. 2.3)
+//   k_resid       r = B_f x - l (Sec. 2.3, error representation)
+//   k_chol_diag / k_chol_panel   left-looking blocked Cholesky of the
+//                 augmented Hermitian matrix [[D G D, D B],[B^H D, 0]]: the
+//                 lower rows of its factor are W^H = (L^{-1} D B_f)^H
+//   k_herk        K_aug = W^H W -> K_e, l_e, eta (Sec. 2.3)
+// Workspace of a cell: column-major complex matrix Z with nrows = nvp + kp
+// rows and nvp columns; rows [0,nvp) hold the lower triangle of D G D (F
+// test functions at [0,Np), I at [Np,2Np)), rows [nvp, nvp+kp) hold
+// (D B_f)^H, (D l)^H, (D r)^H and zero padding.
+#include "dpg_kernels.h"
+
+#include <math.h>
+
+namespace dpg {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int NT = 256;   // threads per workgroup (4 wave64)
+constexpr int TB = 64;    // tile of the blocked factorisation
+constexpr int KC = 16;    // k-chunk staged through LDS
+constexpr int LDP = 66;   // LDS row pitch (doubles) of staged panels
+
+__device__ __forceinline__ int sym3(int a, int b) {
+  // packed index of a symmetric 3x3: (0,0)(1,1)(2,2)(0,1)(0,2)(1,2)
+  return a == b ? a : (a + b + 2);
+}
+
+// XCD-aware decode of a (cell, tile) grid: consecutive workgroup ids are
+// dispatched round-robin over the 8 XCDs, so cell c is given to XCD c % 8 and
+// all tiles of a cell run on the same XCD (its L2 holds the shared panels).
+__device__ __forceinline__ bool decode_cell_tile(int64_t ncells, int ntiles, int64_t& cell, int& tile) {
+  const int64_t w = blockIdx.x;
+  const int x = (int)(w & 7);
+  const int64_t slot = w >> 3;
+  const int64_t cl = slot / ntiles;
+  tile = (int)(slot - cl * ntiles);
+  cell = cl * 8 + x;
+  return cell < ncells;
+}
+
+__host__ inline unsigned grid_cells_tiles(int64_t ncells, int ntiles) {
+  return (unsigned)(((ncells + 7) / 8) * 8 * ntiles);
+}
+
+// ---------------------------------------------------------------- geometry
+struct Geo {
+  double J[3][3];    // J[a][b] = d x_a / d xi_b
+  double Ji[3][3];   // inverse
+  double det;
+  double x[3];
+};
+
+__device__ inline void trilinear(const double (*X)[3], double x0, double x1, double x2, Geo& g) {
+  for (int a = 0; a < 3; ++a) {
+    g.x[a] = 0.0;
+    g.J[a][0] = g.J[a][1] = g.J[a][2] = 0.0;
+  }
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    const int i = v & 1, j = (v >> 1) & 1, k = v >> 2;
+    const double fx = i ? x0 : 1.0 - x0, fy = j ? x1 : 1.0 - x1, fz = k ? x2 : 1.0 - x2;
+    const double dx = i ? 1.0 : -1.0, dy = j ? 1.0 : -1.0, dz = k ? 1.0 : -1.0;
+    const double n = fx * fy * fz, n0 = dx * fy * fz, n1 = fx * dy * fz, n2 = fx * fy * dz;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      g.x[a] += n * X[v][a];
+      g.J[a][0] += n0 * X[v][a];
+      g.J[a][1] += n1 * X[v][a];
+      g.J[a][2] += n2 * X[v][a];
+    }
+  }
+  const double (*J)[3] = g.J;
+  const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+  const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+  const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+  g.det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+  const double id = 1.0 / g.det;
+  g.Ji[0][0] = c00 * id;
+  g.Ji[1][0] = c01 * id;
+  g.Ji[2][0] = c02 * id;
+  g.Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+  g.Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+  g.Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+  g.Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+  g.Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+  g.Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+}
+
+// Volume metrics at one point: Gc = w J^T J / det (curl-curl), Gm = w det J^{-1} J^{-T}
+// (rows of J^{-1} are the covariant images of the reference unit vectors).
+__device__ inline void vol_metrics(const Geo& g, double w, double* Gc, double* Gm) {
+  for (int a = 0; a < 3; ++a)
+    for (int b = a; b < 3; ++b) {
+      double c = 0.0, m = 0.0;
+      for (int e = 0; e < 3; ++e) {
+        c += g.J[e][a] * g.J[e][b];
+        m += g.Ji[a][e] * g.Ji[b][e];
+      }
+      Gc[sym3(a, b)] = w * c / g.det;
+      Gm[sym3(a, b)] = w * g.det * m;
+    }
+}
+
+// Face quantities at one point of reference face f: outward unit normal n and
+// area factor s (n dS = det J J^{-T} n_hat dS_hat).
+__device__ inline void face_normal(const Geo& g, int f, double n[3], double& s) {
+  const int ax = f >> 1;
+  const double sg = (f & 1) ? 1.0 : -1.0;
+  double v[3];
+  for (int a = 0; a < 3; ++a) v[a] = sg * g.det * g.Ji[ax][a];
+  s = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  for (int a = 0; a < 3; ++a) n[a] = v[a] / s;
+}
+
+// Face mass metric Q_ab = w s (n x r_a).(n x r_b), r_a = row a of J^{-1}.
+__device__ inline void face_metric(const Geo& g, const double n[3], double ws, double* Q) {
+  double rn[3];
+  for (int a = 0; a < 3; ++a) rn[a] = g.Ji[a][0] * n[0] + g.Ji[a][1] * n[1] + g.Ji[a][2] * n[2];
+  for (int a = 0; a < 3; ++a)
+    for (int b = a; b < 3; ++b) {
+      double d = g.Ji[a][0] * g.Ji[b][0] + g.Ji[a][1] * g.Ji[b][1] + g.Ji[a][2] * g.Ji[b][2];
+      Q[sym3(a, b)] = ws * (d - rn[a] * rn[b]);
+    }
+}
+
+__device__ inline bool is_robin(int8_t k) { return k == 2 || k == 3; }
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+
+// TE_mn fields of Sec. 4.1 at non-dimensional point x.
+__device__ inline void te_fields(const ProbArgs& P, double omega, const double x[3], double2 E[3], double2 H[3]) {
+  const double c1 = cos(P.pk1 * x[0]), s1 = sin(P.pk1 * x[0]);
+  const double c2 = cos(P.pk2 * x[1]), s2 = sin(P.pk2 * x[1]);
+  // e^{i k3 x3} with complex k3
+  const double amp = exp(-P.pk3im * x[2]);
+  const double2 ph = make_double2(amp * cos(P.pk3re * x[2]), amp * sin(P.pk3re * x[2]));
+  // pre = i omega mu / kc^2
+  const double2 pre = make_double2(-omega * P.pmu_im / P.pkc2, omega * P.pmu_re / P.pkc2);
+  const double2 ex = cmul(pre, make_double2(-P.pk2 * c1 * s2, 0.0));
+  const double2 ey = cmul(pre, make_double2(P.pk1 * s1 * c2, 0.0));
+  E[0] = cmul(ex, ph);
+  E[1] = cmul(ey, ph);
+  E[2] = make_double2(0.0, 0.0);
+  // -i k3 k1 / kc^2 : (-i)(k3re + i k3im) = k3im - i k3re
+  const double2 mik3 = make_double2(P.pk3im / P.pkc2, -P.pk3re / P.pkc2);
+  H[0] = cmul(cmul(mik3, make_double2(P.pk1 * s1 * c2, 0.0)), ph);
+  H[1] = cmul(cmul(mik3, make_double2(P.pk2 * c1 * s2, 0.0)), ph);
+  H[2] = cmul(make_double2(c1 * c2, 0.0), ph);
+}
+
+__device__ inline void load_cell_vertices(const ProbArgs& P, int64_t gc, double (*sX)[3]) {
+  const int t = threadIdx.x;
+  if (t < 24) {
+    const int v = t / 3, a = t % 3;
+    const int64_t vid = P.cells[gc * 8 + v];
+    sX[v][a] = P.vertices[vid * 3 + a] * P.inv_len;
+  }
+}
+
+// ================================================================ scaling
+__global__ __launch_bounds__(NT) void k_cell_scale(DevTables T, ProbArgs P, ChunkArgs C) {
+  const int64_t cell = blockIdx.x;
+  if (cell >= C.n) return;
+  const int64_t gc = C.cell_ids[cell];
+  __shared__ double sX[8][3];
+  __shared__ int s_bad;
+  extern __shared__ double smem[];
+  double* sGc = smem;                         // [nq][6]
+  double* sGm = sGc + 6 * T.nq;               // [nq][6]
+  double* sQ = sGm + 6 * T.nq;                // [6][nfq][6]
+  load_cell_vertices(P, gc, sX);
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  for (int q = threadIdx.x; q < T.nq; q += NT) {
+    Geo g;
+    trilinear(sX, T.vol_pts[3 * q], T.vol_pts[3 * q + 1], T.vol_pts[3 * q + 2], g);
+    if (!(g.det > 0.0) || !isfinite(g.det)) atomicOr(&s_bad, 1);
+    vol_metrics(g, T.vol_w[q], &sGc[6 * q], &sGm[6 * q]);
+  }
+  int8_t fk[6];
+  for (int f = 0; f < 6; ++f) fk[f] = P.face_kind[gc * 6 + f];
+  for (int f = 0; f < 6; ++f) {
+    if (!is_robin(fk[f])) continue;
+    for (int fq = threadIdx.x; fq < T.nfq; fq += NT) {
+      const double* xi = &T.face_pts[(f * T.nfq + fq) * 3];
+      Geo g;
+      trilinear(sX, xi[0], xi[1], xi[2], g);
+      double n[3], s;
+      face_normal(g, f, n, s);
+      face_metric(g, n, T.face_w[f * T.nfq + fq] * s, &sQ[(f * T.nfq + fq) * 6]);
+    }
+  }
+  __syncthreads();
+  const double2 eps = make_double2(P.eps[2 * gc], P.eps[2 * gc + 1]);
+  const double2 mu = make_double2(P.mu[2 * gc], P.mu[2 * gc + 1]);
+  const double om2 = P.omega * P.omega;
+  const double cF = om2 * (eps.x * eps.x + eps.y * eps.y) + P.alpha;
+  const double cI = om2 * (mu.x * mu.x + mu.y * mu.y) + P.alpha;
+  double z2[6];
+  for (int f = 0; f < 6; ++f) {
+    const double zr = P.zinv[(gc * 6 + f) * 2], zi = P.zinv[(gc * 6 + f) * 2 + 1];
+    z2[f] = zr * zr + zi * zi;
+  }
+  double* d = C.dscale + cell * (int64_t)T.nvp;
+  for (int i = threadIdx.x; i < T.Np; i += NT) {
+    double dF = 1.0, dI = 1.0;
+    if (i < T.N) {
+      const int a = T.comp[i];
+      double S = 0.0, M = 0.0;
+      for (int q = 0; q < T.nq; ++q) {
+        const double* c = &T.vol_c[((size_t)q * T.Np + i) * 3];
+        const double* G = &sGc[6 * q];
+        const double v = T.vol_v[(size_t)q * T.Np + i];
+        S += c[0] * (G[0] * c[0] + 2.0 * G[3] * c[1] + 2.0 * G[4] * c[2]) +
+             c[1] * (G[1] * c[1] + 2.0 * G[5] * c[2]) + c[2] * G[2] * c[2];
+        M += v * v * sGm[6 * q + a];
+      }
+      double mtF = 0.0, mtI = 0.0;
+      for (int f = 0; f < 6; ++f) {
+        if (!is_robin(fk[f])) continue;
+        double mt = 0.0;
+        for (int fq = 0; fq < T.nfq; ++fq) {
+          const double v = T.face_v[((size_t)f * T.nfq + fq) * T.Np + i];
+          mt += v * v * sQ[(f * T.nfq + fq) * 6 + a];
+        }
+        mtF += z2[f] * mt;
+        mtI += mt;
+      }
+      dF = 1.0 / sqrt(S + cF * M + mtF);
+      dI = 1.0 / sqrt(S + cI * M + mtI);
+    }
+    d[i] = dF;
+    d[T.Np + i] = dI;
+  }
+  if (threadIdx.x == 0) C.info[gc] = s_bad ? -1 : 0;
+}
+
+// ================================================================ G_FF, G_II
+// One workgroup per (cell, tile of the N x N test index space restricted to a
+// component pair (a, b)): every row shares component a and every column
+// component b, so M_ij = sum_q v_i Gm_ab v_j and S_ij = sum_q chat_i . Gc chat_j
+// with two nonzero curl components on each side.
+__global__ __launch_bounds__(NT) void k_form_SM(DevTables T, ProbArgs P, ChunkArgs C) {
+  int64_t cell;
+  int tile;
+  if (!decode_cell_tile(C.n, T.n_sm_tiles, cell, tile)) return;
+  const int64_t gc = C.cell_ids[cell];
+  __shared__ double sX[8][3];
+  extern __shared__ double smem[];
+  double* sGc = smem;              // [nq][6]
+  double* sGm = sGc + 6 * T.nq;    // [nq][6]
+  double* sQ = sGm + 6 * T.nq;     // [6][nfq][6]
+  load_cell_vertices(P, gc, sX);
+  __syncthreads();
+  for (int q = threadIdx.x; q < T.nq; q += NT) {
+    Geo g;
+    trilinear(sX, T.vol_pts[3 * q], T.vol_pts[3 * q + 1], T.vol_pts[3 * q + 2], g);
+    vol_metrics(g, T.vol_w[q], &sGc[6 * q], &sGm[6 * q]);
+  }
+  int8_t fk[6];
+  int nrobin = 0;
+  for (int f = 0; f < 6; ++f) {
+    fk[f] = P.face_kind[gc * 6 + f];
+    nrobin += is_robin(fk[f]);
+  }
+  if (nrobin) {
+    for (int f = 0; f < 6; ++f) {
+      if (!is_robin(fk[f])) continue;
+      for (int fq = threadIdx.x; fq < T.nfq; fq += NT) {
+        const double* xi = &T.face_pts[(f * T.nfq + fq) * 3];
+        Geo g;
+        trilinear(sX, xi[0], xi[1], xi[2], g);
+        double n[3], s;
+        face_normal(g, f, n, s);
+        face_metric(g, n, T.face_w[f * T.nfq + fq] * s, &sQ[(f * T.nfq + fq) * 6]);
+      }
+    }
+  }
+  __syncthreads();
+
+  const int4 tl = T.sm_tiles[tile];
+  const int a = tl.x, b = tl.y;
+  const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
+  const int a1 = (a == 0) ? 1 : 0, a2 = (a == 2) ? 1 : 2;   // nonzero curl components of rows
+  const int b1 = (b == 0) ? 1 : 0, b2 = (b == 2) ? 1 : 2;   // ... and of columns
+  int li[4], lj[4], ri[4], rj[4];
+  for (int u = 0; u < 4; ++u) {
+    li[u] = tl.z * 64 + ti * 4 + u;
+    lj[u] = tl.w * 64 + tj * 4 + u;
+    ri[u] = a * T.nc + min(li[u], T.nc - 1);
+    rj[u] = b * T.nc + min(lj[u], T.nc - 1);
+  }
+  double S[4][4], M[4][4], MF[4][4], MI[4][4];
+  for (int u = 0; u < 4; ++u)
+    for (int v = 0; v < 4; ++v) S[u][v] = M[u][v] = MF[u][v] = MI[u][v] = 0.0;
+  const int sab = sym3(a, b);
+  const int s11 = sym3(a1, b1), s12 = sym3(a1, b2), s21 = sym3(a2, b1), s22 = sym3(a2, b2);
+  for (int q = 0; q < T.nq; ++q) {
+    const double* G = &sGc[6 * q];
+    const double gm = sGm[6 * q + sab];
+    const double g11 = G[s11], g12 = G[s12], g21 = G[s21], g22 = G[s22];
+    const double* vv = T.vol_v + (size_t)q * T.Np;
+    const double* cc = T.vol_c + (size_t)q * T.Np * 3;
+    double vi[4], ci1[4], ci2[4], mj[4], y1[4], y2[4];
+    for (int u = 0; u < 4; ++u) {
+      vi[u] = vv[ri[u]];
+      ci1[u] = cc[3 * ri[u] + a1];
+      ci2[u] = cc[3 * ri[u] + a2];
+      const double vj = vv[rj[u]], cj1 = cc[3 * rj[u] + b1], cj2 = cc[3 * rj[u] + b2];
+      mj[u] = gm * vj;
+      y1[u] = g11 * cj1 + g12 * cj2;
+      y2[u] = g21 * cj1 + g22 * cj2;
+    }
+    for (int u = 0; u < 4; ++u)
+      for (int v = 0; v < 4; ++v) {
+        S[u][v] += ci1[u] * y1[v] + ci2[u] * y2[v];
+        M[u][v] += vi[u] * mj[v];
+      }
+  }
+  if (nrobin) {
+    for (int f = 0; f < 6; ++f) {
+      if (!is_robin(fk[f])) continue;
+      const double zr = P.zinv[(gc * 6 + f) * 2], zi = P.zinv[(gc * 6 + f) * 2 + 1];
+      const double z2 = zr * zr + zi * zi;
+      for (int fq = 0; fq < T.nfq; ++fq) {
+        const double qab = sQ[(f * T.nfq + fq) * 6 + sab];
+        const double* vv = T.face_v + ((size_t)f * T.nfq + fq) * T.Np;
+        double vi[4], vj[4];
+        for (int u = 0; u < 4; ++u) {
+          vi[u] = vv[ri[u]];
+          vj[u] = qab * vv[rj[u]];
+        }
+        for (int u = 0; u < 4; ++u)
+          for (int v = 0; v < 4; ++v) {
+            const double m = vi[u] * vj[v];
+            MI[u][v] += m;
+            MF[u][v] += z2 * m;
+          }
+      }
+    }
+  }
+  const double2 eps = make_double2(P.eps[2 * gc], P.eps[2 * gc + 1]);
+  const double2 mu = make_double2(P.mu[2 * gc], P.mu[2 * gc + 1]);
+  const double om2 = P.omega * P.omega;
+  const double cF = om2 * (eps.x * eps.x + eps.y * eps.y) + P.alpha;
+  const double cI = om2 * (mu.x * mu.x + mu.y * mu.y) + P.alpha;
+  const double* d = C.dscale + cell * (int64_t)T.nvp;
+  double2* Z = C.Z + cell * (int64_t)T.nrows * T.nvp;
+  const int64_t ld = T.nrows;
+  for (int u = 0; u < 4; ++u) {
+    if (li[u] >= T.nc) continue;
+    const int i = ri[u];
+    for (int v = 0; v < 4; ++v) {
+      if (lj[v] >= T.nc) continue;
+      const int j = rj[v];
+      if (a == b && j > i) continue;
+      const double gff = S[u][v] + cF * M[u][v] + MF[u][v];
+      const double gii = S[u][v] + cI * M[u][v] + MI[u][v];
+      Z[(int64_t)j * ld + i] = make_double2(d[i] * d[j] * gff, 0.0);
+      Z[(int64_t)(T.Np + j) * ld + T.Np + i] = make_double2(d[T.Np + i] * d[T.Np + j] * gii, 0.0);
+    }
+  }
+}
+
+// ================================================================ G_IF
+// G_IF(i,j) = conj(G_FI(j,i)) = -i w mu C_ji - i w conj(eps) C_ij + sum_R conj(z) Rt_ij,
+// from the geometry-free C and Rt; also zero in the F-pad columns / I-pad rows.
+__global__ __launch_bounds__(NT) void k_form_IF(DevTables T, ProbArgs P, ChunkArgs C) {
+  const int nt = (T.Np + 63) / 64;
+  int64_t cell;
+  int tile;
+  if (!decode_cell_tile(C.n, nt * nt, cell, tile)) return;
+  const int64_t gc = C.cell_ids[cell];
+  const int I0 = (tile / nt) * 64, J0 = (tile % nt) * 64;
+  const double2 eps = make_double2(P.eps[2 * gc], P.eps[2 * gc + 1]);
+  const double2 mu = make_double2(P.mu[2 * gc], P.mu[2 * gc + 1]);
+  const double om = P.omega;
+  double2 zc[6];
+  int8_t fk[6];
+  for (int f = 0; f < 6; ++f) {
+    fk[f] = P.face_kind[gc * 6 + f];
+    zc[f] = make_double2(P.zinv[(gc * 6 + f) * 2], -P.zinv[(gc * 6 + f) * 2 + 1]);
+  }
+  const double* d = C.dscale + cell * (int64_t)T.nvp;
+  double2* Z = C.Z + cell * (int64_t)T.nrows * T.nvp;
+  const int64_t ld = T.nrows;
+  const int il = threadIdx.x & 63;
+  const int i = I0 + il;
+  if (i >= T.Np) return;
+  for (int jl = threadIdx.x >> 6; jl < 64; jl += NT / 64) {
+    const int j = J0 + jl;
+    if (j >= T.Np) break;
+    double2 v = make_double2(0.0, 0.0);
+    if (i < T.N && j < T.N) {
+      const double cji = T.Cref[(size_t)j * T.N + i];
+      const double cij = T.CrefT[(size_t)j * T.N + i];
+      // -i w mu cji = w (mu.y, -mu.x) cji ; -i w conj(eps) cij = w (-eps.y, -eps.x) cij
+      v.x = om * (mu.y * cji - eps.y * cij);
+      v.y = om * (-mu.x * cji - eps.x * cij);
+      for (int f = 0; f < 6; ++f) {
+        if (!is_robin(fk[f])) continue;
+        const double rt = T.RtT[((size_t)f * T.N + j) * T.N + i];
+        v.x += zc[f].x * rt;
+        v.y += zc[f].y * rt;
+      }
+      const double s = d[T.Np + i] * d[j];
+      v.x *= s;
+      v.y *= s;
+    }
+    Z[(int64_t)j * ld + T.Np + i] = v;
+  }
+}
+
+// Identity/zero padding of the test space (rows N..Np-1 of each field block).
+__global__ __launch_bounds__(NT) void k_form_pad(DevTables T, ChunkArgs C) {
+  const int64_t cell = blockIdx.x;
+  if (cell >= C.n) return;
+  double2* Z = C.Z + cell * (int64_t)T.nrows * T.nvp;
+  const int64_t ld = T.nrows;
+  const int npad = T.Np - T.N;
+  for (int blk = 0; blk < 2; ++blk) {
+    const int base = blk * T.Np;
+    for (int e = threadIdx.x; e < npad * T.Np; e += NT) {
+      const int row = base + T.N + e / T.Np;
+      const int col = base + e % T.Np;
+      if (col > row) continue;
+      Z[(int64_t)col * ld + row] = make_double2(col == row ? 1.0 : 0.0, 0.0);
+    }
+  }
+}
+
+// ================================================================ B_f^H, l^H
+// One workgroup per (cell, 64 test functions i).  For the volume terms
+//   D_c(i,m) = sum_q w det (J^{-T} psi_hat_i)_c phi_m,   R_c(i,m) = sum_q w (J chat_i)_c phi_m
+// and on Robin faces Dt_c(i,m) = sum w s (psi_i - (psi_i.n) n)_c phi_m; then
+//   B(F_i, E_cm) = i w eps D - sum_R z Dt,  B(F_i, H_cm) = R_c,
+//   B(I_i, E_cm) = R_c,                     B(I_i, H_cm) = -i w mu D,
+//   B(F_i, Hhat_j) = sum_{f not Robin} T_f(i,j),  B(I_i, Ehat_j) = sum_f T_f(i,j),
+//   l(F_i) = - sum_port int psi_i . g dS.
+constexpr int BQC = 16;   // quadrature points per staged chunk
+__global__ __launch_bounds__(NT) void k_form_B(DevTables T, ProbArgs P, ChunkArgs C) {
+  const int nrt = (T.Np + 63) / 64;
+  int64_t cell;
+  int tile;
+  if (!decode_cell_tile(C.n, nrt, cell, tile)) return;
+  const int64_t gc = C.cell_ids[cell];
+  const int i0 = tile * 64;
+  __shared__ double sX[8][3];
+  __shared__ double sGeo[BQC][21];          // J (9), Ji (9), w det, w, (face: s)
+  __shared__ double sP[BQC][64][3];         // w det (J^{-T} psi_hat_i)_c
+  __shared__ double sQ[BQC][64][3];         // w (J chat_i)_c
+  __shared__ double2 sL[64];                // load vector l(F_i)
+  extern __shared__ double smem[];
+  double* sPhi = smem;                      // [BQC][m1]
+  load_cell_vertices(P, gc, sX);
+  if (threadIdx.x < 64) sL[threadIdx.x] = make_double2(0.0, 0.0);
+  int8_t fk[6];
+  double2 zf[6];
+  int nrobin = 0;
+  for (int f = 0; f < 6; ++f) {
+    fk[f] = P.face_kind[gc * 6 + f];
+    zf[f] = make_double2(P.zinv[(gc * 6 + f) * 2], P.zinv[(gc * 6 + f) * 2 + 1]);
+    nrobin += is_robin(fk[f]);
+  }
+  __syncthreads();
+  const double2 eps = make_double2(P.eps[2 * gc], P.eps[2 * gc + 1]);
+  const double2 mu = make_double2(P.mu[2 * gc], P.mu[2 * gc + 1]);
+  const double om = P.omega;
+  const double* d = C.dscale + cell * (int64_t)T.nvp;
+  double2* Z = C.Z + cell * (int64_t)T.nrows * T.nvp;
+  const int64_t ld = T.nrows;
+  const int nvp = T.nvp;
+  const int m1 = T.m1;
+  const int nitems = 64 * m1;
+  // item = il * m1 + m ; processed in batches of up to 8 items per thread
+  for (int ib = 0; ib < nitems; ib += NT * 8) {
+    double D[8][3], R[8][3], Dtr[8][3], Dti[8][3];
+    for (int u = 0; u < 8; ++u)
+      for (int c = 0; c < 3; ++c) D[u][c] = R[u][c] = Dtr[u][c] = Dti[u][c] = 0.0;
+    // ---- volume quadrature
+    for (int q0 = 0; q0 < T.nq; q0 += BQC) {
+      const int nqc = min(BQC, T.nq - q0);
+      __syncthreads();
+      for (int qq = threadIdx.x; qq < nqc; qq += NT) {
+        const int q = q0 + qq;
+        Geo g;
+        trilinear(sX, T.vol_pts[3 * q], T.vol_pts[3 * q + 1], T.vol_pts[3 * q + 2], g);
+        for (int e = 0; e < 9; ++e) {
+          sGeo[qq][e] = g.J[e / 3][e % 3];
+          sGeo[qq][9 + e] = g.Ji[e / 3][e % 3];
+        }
+        sGeo[qq][18] = T.vol_w[q] * g.det;
+        sGeo[qq][19] = T.vol_w[q];
+      }
+      for (int e = threadIdx.x; e < nqc * m1; e += NT) sPhi[e] = T.vol_phi[(size_t)(q0 + e / m1) * m1 + e % m1];
+      __syncthreads();
+      for (int e = threadIdx.x; e < nqc * 64; e += NT) {
+        const int qq = e / 64, il = e % 64;
+        const int i = min(i0 + il, T.N - 1);
+        const int q = q0 + qq;
+        const int a = T.comp[i];
+        const double v = T.vol_v[(size_t)q * T.Np + i];
+        const double* c = &T.vol_c[((size_t)q * T.Np + i) * 3];
+        const double* G = sGeo[qq];
+        for (int cc = 0; cc < 3; ++cc) {
+          sP[qq][il][cc] = G[18] * G[9 + a * 3 + cc] * v;                     // (J^{-T})_{c a} = Ji[a][c]
+          sQ[qq][il][cc] = G[19] * (G[cc * 3] * c[0] + G[cc * 3 + 1] * c[1] + G[cc * 3 + 2] * c[2]);
+        }
+      }
+      __syncthreads();
+      for (int u = 0; u < 8; ++u) {
+        const int it = ib + u * NT + threadIdx.x;
+        if (it >= nitems) break;
+        const int il = it / m1, m = it % m1;
+        for (int qq = 0; qq < nqc; ++qq) {
+          const double ph = sPhi[qq * m1 + m];
+          for (int cc = 0; cc < 3; ++cc) {
+            D[u][cc] += sP[qq][il][cc] * ph;
+            R[u][cc] += sQ[qq][il][cc] * ph;
+          }
+        }
+      }
+    }
+    // ---- Robin faces: Dt weighted by z (complex)
+    if (nrobin) {
+      for (int f = 0; f < 6; ++f) {
+        if (!is_robin(fk[f])) continue;
+        for (int q0 = 0; q0 < T.nfq; q0 += BQC) {
+          const int nqc = min(BQC, T.nfq - q0);
+          __syncthreads();
+          for (int qq = threadIdx.x; qq < nqc; qq += NT) {
+            const int fq = q0 + qq;
+            const double* xi = &T.face_pts[(f * T.nfq + fq) * 3];
+            Geo g;
+            trilinear(sX, xi[0], xi[1], xi[2], g);
+            double n[3], s;
+            face_normal(g, f, n, s);
+            const double ws = T.face_w[f * T.nfq + fq] * s;
+            // tangential part of the rows of J^{-1}: t_a = r_a - (r_a . n) n
+            for (int a = 0; a < 3; ++a) {
+              const double rn = g.Ji[a][0] * n[0] + g.Ji[a][1] * n[1] + g.Ji[a][2] * n[2];
+              for (int cc = 0; cc < 3; ++cc) sGeo[qq][a * 3 + cc] = ws * (g.Ji[a][cc] - rn * n[cc]);
+            }
+          }
+          for (int e = threadIdx.x; e < nqc * m1; e += NT)
+            sPhi[e] = T.face_phi[((size_t)f * T.nfq + q0 + e / m1) * m1 + e % m1];
+          __syncthreads();
+          for (int e = threadIdx.x; e < nqc * 64; e += NT) {
+            const int qq = e / 64, il = e % 64;
+            const int i = min(i0 + il, T.N - 1);
+            const int a = T.comp[i];
+            const double v = T.face_v[((size_t)f * T.nfq + q0 + qq) * T.Np + i];
+            for (int cc = 0; cc < 3; ++cc) sP[qq][il][cc] = v * sGeo[qq][a * 3 + cc];
+          }
+          __syncthreads();
+          for (int u = 0; u < 8; ++u) {
+            const int it = ib + u * NT + threadIdx.x;
+            if (it >= nitems) break;
+            const int il = it / m1, m = it % m1;
+            for (int qq = 0; qq < nqc; ++qq) {
+              const double ph = sPhi[qq * m1 + m];
+              for (int cc = 0; cc < 3; ++cc) {
+                const double t = sP[qq][il][cc] * ph;
+                Dtr[u][cc] += zf[f].x * t;
+                Dti[u][cc] += zf[f].y * t;
+              }
+            }
+          }
+        }
+      }
+    }
+    // ---- write the interior-unknown rows of (D B_f)^H
+    for (int u = 0; u < 8; ++u) {
+      const int it = ib + u * NT + threadIdx.x;
+      if (it >= nitems) break;
+      const int il = it / m1, m = it % m1;
+      const int i = i0 + il;
+      if (i >= T.Np) continue;
+      const bool ok = i < T.N;
+      const double dF = d[i], dI = d[T.Np + i];
+      for (int cc = 0; cc < 3; ++cc) {
+        const int rowE = nvp + cc * m1 + m, rowH = nvp + (3 + cc) * m1 + m;
+        double2 bFE = make_double2(0, 0), bFH = bFE, bIE = bFE, bIH = bFE;
+        if (ok) {
+          // B(F,E) = i w eps D - z Dt  -> conj = -i w conj(eps) D - conj(z Dt)
+          const double2 fe = make_double2(-om * eps.y * D[u][cc] - Dtr[u][cc], om * eps.x * D[u][cc] - Dti[u][cc]);
+          bFE = make_double2(dF * fe.x, -dF * fe.y);
+          bFH = make_double2(dF * R[u][cc], 0.0);
+          bIE = make_double2(dI * R[u][cc], 0.0);
+          // B(I,H) = -i w mu D -> conj = i w conj(mu) D = w (mu.y, mu.x) D
+          bIH = make_double2(dI * om * mu.y * D[u][cc], dI * om * mu.x * D[u][cc]);
+        }
+        Z[(int64_t)i * ld + rowE] = bFE;
+        Z[(int64_t)i * ld + rowH] = bFH;
+        Z[(int64_t)(T.Np + i) * ld + rowE] = bIE;
+        Z[(int64_t)(T.Np + i) * ld + rowH] = bIH;
+      }
+    }
+  }
+  // ---- trace unknowns (real, geometry free)
+  for (int e = threadIdx.x; e < 64 * T.nt1; e += NT) {
+    const int il = e / T.nt1, jt = e % T.nt1;
+    const int i = i0 + il;
+    if (i >= T.Np) continue;
+    double tI = 0.0, tF = 0.0;
+    if (i < T.N) {
+      for (int f = 0; f < 6; ++f) {
+        const double t = T.T[((size_t)f * T.N + i) * T.nt1 + jt];
+        tI += t;
+        if (!is_robin(fk[f])) tF += t;
+      }
+    }
+    const int rowEh = nvp + T.nu + jt, rowHh = nvp + T.nu + T.nt1 + jt;
+    Z[(int64_t)i * ld + rowEh] = make_double2(0.0, 0.0);
+    Z[(int64_t)i * ld + rowHh] = make_double2(d[i] * tF, 0.0);
+    Z[(int64_t)(T.Np + i) * ld + rowEh] = make_double2(d[T.Np + i] * tI, 0.0);
+    Z[(int64_t)(T.Np + i) * ld + rowHh] = make_double2(0.0, 0.0);
+  }
+  // (the port load vector is formed by k_form_load)
+  // ---- padding rows of the RHS block and zero load/residual rows
+  for (int e = threadIdx.x; e < 64 * (T.kp - T.k); e += NT) {
+    const int il = e % 64, rr = e / 64;
+    const int i = i0 + il;
+    if (i >= T.Np) continue;
+    const int row = nvp + T.k + rr;
+    Z[(int64_t)i * ld + row] = make_double2(0.0, 0.0);
+    Z[(int64_t)(T.Np + i) * ld + row] = make_double2(0.0, 0.0);
+  }
+}
+
+// Load vector l(F_i) = - sum_port int psi_i . g dS, written to RHS row k as
+// conj(d l).  One workgroup per (cell, 64 test functions); no-op for cells
+// without a port face.
+__global__ __launch_bounds__(NT) void k_form_load(DevTables T, ProbArgs P, ChunkArgs C) {
+  const int nrt = (T.Np + 63) / 64;
+  int64_t cell;
+  int tile;
+  if (!decode_cell_tile(C.n, nrt, cell, tile)) return;
+  const int64_t gc = C.cell_ids[cell];
+  const int i0 = tile * 64;
+  __shared__ double sX[8][3];
+  extern __shared__ double smem[];
+  double2* sRG = reinterpret_cast<double2*>(smem);   // [nfq][3]: w s (r_a . g)
+  int8_t fk[6];
+  int nport = 0;
+  for (int f = 0; f < 6; ++f) {
+    fk[f] = P.face_kind[gc * 6 + f];
+    nport += (fk[f] == 2);
+  }
+  if (!P.has_port || nport == 0) return;   // row already zero
+  load_cell_vertices(P, gc, sX);
+  const int il = threadIdx.x & 63;
+  const int i = i0 + il;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int f = 0; f < 6; ++f) {
+    if (fk[f] != 2) continue;
+    const double2 z = make_double2(P.zinv[(gc * 6 + f) * 2], P.zinv[(gc * 6 + f) * 2 + 1]);
+    __syncthreads();
+    for (int fq = threadIdx.x; fq < T.nfq; fq += NT) {
+      const double* xi = &T.face_pts[(f * T.nfq + fq) * 3];
+      Geo g;
+      trilinear(sX, xi[0], xi[1], xi[2], g);
+      double n[3], s;
+      face_normal(g, f, n, s);
+      double2 E[3], H[3];
+      te_fields(P, P.omega, g.x, E, H);
+      double2 En = make_double2(0, 0);
+      for (int a = 0; a < 3; ++a) En = make_double2(En.x + E[a].x * n[a], En.y + E[a].y * n[a]);
+      double2 gv[3];
+      for (int a = 0; a < 3; ++a) {
+        const int b = (a + 1) % 3, c = (a + 2) % 3;
+        const double2 nxh = make_double2(n[b] * H[c].x - n[c] * H[b].x, n[b] * H[c].y - n[c] * H[b].y);
+        const double2 et = make_double2(E[a].x - En.x * n[a], E[a].y - En.y * n[a]);
+        const double2 zet = cmul(z, et);
+        gv[a] = make_double2(nxh.x + zet.x, nxh.y + zet.y);
+      }
+      const double ws = T.face_w[f * T.nfq + fq] * s;
+      for (int a = 0; a < 3; ++a) {
+        double2 rg = make_double2(0, 0);
+        for (int cc = 0; cc < 3; ++cc) {
+          rg.x += g.Ji[a][cc] * gv[cc].x;
+          rg.y += g.Ji[a][cc] * gv[cc].y;
+        }
+        sRG[fq * 3 + a] = make_double2(ws * rg.x, ws * rg.y);
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < 64 && i < T.N) {
+      const int a = T.comp[i];
+      for (int fq = 0; fq < T.nfq; ++fq) {
+        const double v = T.face_v[((size_t)f * T.nfq + fq) * T.Np + i];
+        acc.x -= v * sRG[fq * 3 + a].x;
+        acc.y -= v * sRG[fq * 3 + a].y;
+      }
+    }
+  }
+  if (threadIdx.x < 64 && i < T.N) {
+    const double* d = C.dscale + cell * (int64_t)T.nvp;
+    double2* Z = C.Z + cell * (int64_t)T.nrows * T.nvp;
+    Z[(int64_t)i * T.nrows + T.nvp + T.k] = make_double2(d[i] * acc.x, -d[i] * acc.y);
+  }
+}
+
+// r~_i = sum_a B~(i,a) x_a - l~_i for every test row i, from the conj-stored
+// RHS rows; one wave per test row, lanes striding over the unknowns.
+__global__ __launch_bounds__(NT) void k_resid(DevTables T, ChunkArgs C) {
+  const int per = NT / 64;
+  const int nb = (T.nvp + per - 1) / per;
+  int64_t cell;
+  int tile;
+  if (!decode_cell_tile(C.n, nb, cell, tile)) return;
+  const int64_t gc = C.cell_ids[cell];
+  const int col = tile * per + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (col >= T.nvp) return;
+  const double2* x = C.x + C.v_off[gc];
+  const double2* Zc = C.Z + cell * (int64_t)T.nrows * T.nvp + (int64_t)col * T.nrows + T.nvp;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int a = lane; a < T.k; a += 64) {
+    const double2 b = cconj(Zc[a]);
+    const double2 xv = x[a];
+    acc.x += b.x * xv.x - b.y * xv.y;
+    acc.y += b.x * xv.y + b.y * xv.x;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    acc.x += __shfl_xor(acc.x, o);
+    acc.y += __shfl_xor(acc.y, o);
+  }
+  if (lane == 0) {
+    const double2 lv = cconj(Zc[T.k]);
+    // store conj(r~)
+    C.Z[cell * (int64_t)T.nrows * T.nvp + (int64_t)col * T.nrows + T.nvp + T.k + 1] =
+        make_double2(acc.x - lv.x, -(acc.y - lv.y));
+  }
+}
+
+// ================================================================ MFMA core
+// Complex 64x64 tile product  P += A B^H  with A, B row panels of column-major
+// complex matrices, over columns [0, K).  Four waves; wave (wr, wc) owns the
+// 32x32 quadrant rows wr*32.., cols wc*32.. as 2x2 blocks of 16x16, each a
+// real and an imaginary f64 MFMA accumulator.  Accumulator item v of lane l
+// of a 16x16 block holds row (l>>4) + 4v, column l & 15.
+struct Acc {
+  d4 re[2][2], im[2][2];
+};
+
+struct Stage {
+  double Are[KC][LDP], Aim[KC][LDP], Bre[KC][LDP], Bim[KC][LDP];
+};
+
+__device__ inline void acc_zero(Acc& c) {
+  for (int u = 0; u < 2; ++u)
+    for (int v = 0; v < 2; ++v) {
+      c.re[u][v] = d4{0, 0, 0, 0};
+      c.im[u][v] = d4{0, 0, 0, 0};
+    }
+}
+
+__device__ inline void stage_compute(const Stage& s, Acc& c) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w & 1, wc = w >> 1;
+#pragma unroll
+  for (int ks = 0; ks < KC / 4; ++ks) {
+    const int kk = ks * 4 + (lane >> 4);
+    double ar[2], ai[2], nar[2], br[2], bi[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int row = wr * 32 + u * 16 + (lane & 15);
+      ar[u] = s.Are[kk][row];
+      ai[u] = s.Aim[kk][row];
+      nar[u] = -ar[u];
+      const int col = wc * 32 + u * 16 + (lane & 15);
+      br[u] = s.Bre[kk][col];
+      bi[u] = s.Bim[kk][col];
+    }
+    // A conj(B)^T: re += Ar Br + Ai Bi ; im += Ai Br - Ar Bi
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v) c.re[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[u], br[v], c.re[u][v], 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v) c.im[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[u], br[v], c.im[u][v], 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v) c.re[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[u], bi[v], c.re[u][v], 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v) c.im[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(nar[u], bi[v], c.im[u][v], 0, 0, 0);
+  }
+}
+
+// P += A[rowA:rowA+64, 0:K] * B[rowB:rowB+64, 0:K]^H ; A, B column-major with leading dim ld.
+__device__ inline void gemm_abh(const double2* __restrict__ A, const double2* __restrict__ B, int64_t ld, int K,
+                                Stage* st, Acc& c) {
+  if (K <= 0) return;
+  const int t = threadIdx.x;
+  const int lr = t & 63, lc = t >> 6;
+  double2 ra[4], rb[4];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t col = k0 + lc * 4 + u;
+      ra[u] = A[col * ld + lr];
+      rb[u] = B[col * ld + lr];
+    }
+  };
+  auto lstore = [&](Stage& s) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      s.Are[lc * 4 + u][lr] = ra[u].x;
+      s.Aim[lc * 4 + u][lr] = ra[u].y;
+      s.Bre[lc * 4 + u][lr] = rb[u].x;
+      s.Bim[lc * 4 + u][lr] = rb[u].y;
+    }
+  };
+  gload(0);
+  lstore(st[0]);
+  __syncthreads();
+  const int nst = K / KC;
+  for (int sidx = 0; sidx < nst; ++sidx) {
+    const bool more = sidx + 1 < nst;
+    if (more) gload((sidx + 1) * KC);
+    stage_compute(st[sidx & 1], c);
+    if (more) lstore(st[(sidx + 1) & 1]);
+    __syncthreads();
+  }
+}
+
+// Visit the accumulator elements: f(row, col, re, im) with row/col in [0,64).
+template <class F>
+__device__ inline void acc_for_each(const Acc& c, F&& f) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w & 1, wc = w >> 1;
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int it = 0; it < 4; ++it) {
+        const int row = wr * 32 + u * 16 + (lane >> 4) + 4 * it;
+        const int col = wc * 32 + v * 16 + (lane & 15);
+        f(row, col, c.re[u][v][it], c.im[u][v][it]);
+      }
+}
+
+// ================================================================ Cholesky
+// Step j, diagonal block: X = A_jj - sum_{m<j} L_jm L_jm^H, X = L L^H, store L^{-1}.
+__global__ __launch_bounds__(NT) void k_chol_diag(DevTables T, ChunkArgs C, int j) {
+  const int64_t cell = blockIdx.x;
+  if (cell >= C.n) return;
+  const int64_t gc = C.cell_ids[cell];
+  extern __shared__ double smem[];
+  Stage* st = reinterpret_cast<Stage*>(smem);
+  double* Xr = smem;                 // [64][65] (aliases the staging buffers after the GEMM)
+  double* Xi = Xr + 64 * 65;
+  double* Yr = Xi + 64 * 65;         // L^{-1}
+  double* Yi = Yr + 64 * 65;
+  __shared__ double s_inv;
+  __shared__ int s_fail;
+  const int64_t ld = T.nrows;
+  double2* Z = C.Z + cell * (int64_t)T.nrows * T.nvp;
+  const double2* panel = Z + j * TB;  // row offset j*64, column 0
+  Acc acc;
+  acc_zero(acc);
+  gemm_abh(panel, panel, ld, j * TB, st, acc);
+  __syncthreads();
+  double2* tileA = Z + (int64_t)(j * TB) * ld + j * TB;
+  acc_for_each(acc, [&](int r, int c, double pr, double pi) {
+    if (c <= r) {
+      const double2 a = tileA[(int64_t)c * ld + r];
+      Xr[r * 65 + c] = a.x - pr;
+      Xi[r * 65 + c] = a.y - pi;
+    }
+  });
+  for (int e = threadIdx.x; e < 64 * 64; e += NT) {
+    const int r = e >> 6, c = e & 63;
+    Yr[r * 65 + c] = (r == c) ? 1.0 : 0.0;
+    Yi[r * 65 + c] = 0.0;
+  }
+  if (threadIdx.x == 0) s_fail = 0;
+  __syncthreads();
+  for (int c = 0; c < 64; ++c) {
+    if (threadIdx.x == 0) {
+      double dd = Xr[c * 65 + c];
+      if (!(dd > 0.0) || !isfinite(dd)) {
+        if (!s_fail) s_fail = j * TB + c + 1;
+        dd = 1.0;
+      }
+      const double l = sqrt(dd);
+      Xr[c * 65 + c] = l;
+      Xi[c * 65 + c] = 0.0;
+      s_inv = 1.0 / l;
+    }
+    __syncthreads();
+    const double inv = s_inv;
+    for (int r = c + 1 + threadIdx.x; r < 64; r += NT) {
+      Xr[r * 65 + c] *= inv;
+      Xi[r * 65 + c] *= inv;
+    }
+    for (int q = threadIdx.x; q <= c; q += NT) {
+      Yr[c * 65 + q] *= inv;
+      Yi[c * 65 + q] *= inv;
+    }
+    __syncthreads();
+    // trailing update of X (lower) and elimination of rows r > c of Y
+    const int q = threadIdx.x & 63;
+    for (int r = c + 1 + (threadIdx.x >> 6); r < 64; r += NT / 64) {
+      const double lr = Xr[r * 65 + c], li = Xi[r * 65 + c];
+      if (q > c && q <= r) {
+        const double mr = Xr[q * 65 + c], mi = -Xi[q * 65 + c];   // conj(L_qc)
+        Xr[r * 65 + q] -= lr * mr - li * mi;
+        Xi[r * 65 + q] -= lr * mi + li * mr;
+      }
+      if (q <= c) {
+        const double yr = Yr[c * 65 + q], yi = Yi[c * 65 + q];
+        Yr[r * 65 + q] -= lr * yr - li * yi;
+        Yi[r * 65 + q] -= lr * yi + li * yr;
+      }
+    }
+    __syncthreads();
+  }
+  // store L^{-1} (lower, zero upper) into the diagonal tile
+  for (int e = threadIdx.x; e < 64 * 64; e += NT) {
+    const int c = e >> 6, r = e & 63;
+    tileA[(int64_t)c * ld + r] = (c <= r) ? make_double2(Yr[r * 65 + c], Yi[r * 65 + c]) : make_double2(0.0, 0.0);
+  }
+  if (threadIdx.x == 0 && s_fail) {
+    if (C.info[gc] == 0) C.info[gc] = s_fail;
+  }
+}
+
+// Step j, panel: for row tiles i > j:  L_ij = (A_ij - sum_{m<j} L_im L_jm^H) Linv_jj^H.
+struct PanelSmem {
+  double Xr[64][LDP], Xi[64][LDP];   // X^T staged as [k][row], k = column of X
+  double Lr[64][LDP], Li[64][LDP];   // Linv as [k][col] : B operand (conj applied in the product)
+};
+
+__global__ __launch_bounds__(NT) void k_chol_panel(DevTables T, ChunkArgs C, int j) {
+  const int nrb = T.nrows / TB;
+  const int ntiles = nrb - j - 1;
+  int64_t cell;
+  int tile;
+  if (!decode_cell_tile(C.n, ntiles, cell, tile)) return;
+  const int i = j + 1 + tile;
+  extern __shared__ double smem[];
+  Stage* st = reinterpret_cast<Stage*>(smem);
+  PanelSmem* ps = reinterpret_cast<PanelSmem*>(smem);
+  const int64_t ld = T.nrows;
+  double2* Z = C.Z + cell * (int64_t)T.nrows * T.nvp;
+  Acc acc;
+  acc_zero(acc);
+  gemm_abh(Z + i * TB, Z + j * TB, ld, j * TB, st, acc);
+  __syncthreads();
+  // X = A_ij - P  ->  LDS as the A operand [k = column of X][row]
+  const double2* tileA = Z + (int64_t)(j * TB) * ld + i * TB;
+  acc_for_each(acc, [&](int r, int c, double pr, double pi) {
+    const double2 a = tileA[(int64_t)c * ld + r];
+    ps->Xr[c][r] = a.x - pr;
+    ps->Xi[c][r] = a.y - pi;
+  });
+  // Linv_jj (row = col index of the result, column = k) -> [k][col]
+  const double2* tileL = Z + (int64_t)(j * TB) * ld + j * TB;
+  for (int e = threadIdx.x; e < 64 * 64; e += NT) {
+    const int k = e >> 6, c = e & 63;
+    const double2 v = tileL[(int64_t)k * ld + c];
+    ps->Lr[k][c] = v.x;
+    ps->Li[k][c] = v.y;
+  }
+  __syncthreads();
+  // Y = X Linv^H
+  Acc y;
+  acc_zero(y);
+  {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wr = w & 1, wc = w >> 1;
+    for (int ks = 0; ks < 16; ++ks) {
+      const int kk = ks * 4 + (lane >> 4);
+      double ar[2], ai[2], nar[2], br[2], bi[2];
+      for (int u = 0; u < 2; ++u) {
+        const int row = wr * 32 + u * 16 + (lane & 15);
+        ar[u] = ps->Xr[kk][row];
+        ai[u] = ps->Xi[kk][row];
+        nar[u] = -ar[u];
+        const int col = wc * 32 + u * 16 + (lane & 15);
+        br[u] = ps->Lr[kk][col];
+        bi[u] = ps->Li[kk][col];
+      }
+      for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 2; ++v) y.re[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[u], br[v], y.re[u][v], 0, 0, 0);
+      for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 2; ++v) y.im[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[u], br[v], y.im[u][v], 0, 0, 0);
+      for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 2; ++v) y.re[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[u], bi[v], y.re[u][v], 0, 0, 0);
+      for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 2; ++v) y.im[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(nar[u], bi[v], y.im[u][v], 0, 0, 0);
+    }
+  }
+  double2* out = Z + (int64_t)(j * TB) * ld + i * TB;
+  acc_for_each(y, [&](int r, int c, double vr, double vi) { out[(int64_t)c * ld + r] = make_double2(vr, vi); });
+}
+
+// ================================================================ K_aug = W^H W
+__global__ __launch_bounds__(NT) void k_herk(DevTables T, ChunkArgs C) {
+  const int kb = T.kp / TB;
+  const int ntiles = kb * (kb + 1) / 2;
+  int64_t cell;
+  int tile;
+  if (!decode_cell_tile(C.n, ntiles, cell, tile)) return;
+  int a = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
+  while ((a + 1) * (a + 2) / 2 <= tile) ++a;
+  while (a * (a + 1) / 2 > tile) --a;
+  const int b = tile - a * (a + 1) / 2;
+  const int64_t gc = C.cell_ids[cell];
+  extern __shared__ double smem[];
+  Stage* st = reinterpret_cast<Stage*>(smem);
+  const int64_t ld = T.nrows;
+  const double2* Z = C.Z + cell * (int64_t)T.nrows * T.nvp;
+  Acc acc;
+  acc_zero(acc);
+  gemm_abh(Z + T.nvp + a * TB, Z + T.nvp + b * TB, ld, T.nvp, st, acc);
+  const int k = T.k;
+  double2* K = C.K + C.K_off[gc];
+  double2* L = C.l + C.v_off[gc];
+  acc_for_each(acc, [&](int r, int c, double vr, double vi) {
+    const int al = a * TB + r, be = b * TB + c;
+    if (al < k && be < k) {
+      if (a == b && be > al) return;
+      K[(int64_t)be * k + al] = make_double2(vr, vi);
+      if (al != be) K[(int64_t)al * k + be] = make_double2(vr, -vi);
+    } else if (al == k && be < k) {
+      L[be] = make_double2(vr, -vi);
+    } else if (al == k + 1 && be == k + 1) {
+      C.eta[gc] = sqrt(fmax(vr, 0.0));
+    }
+  });
+}
+
+// ================================================================ parity extraction
+// Unscaled G (full Hermitian), B_f and l of each chunk cell from the workspace
+// (before factorisation).
+__global__ __launch_bounds__(NT) void k_extract(DevTables T, ChunkArgs C, double2* G, double2* Bf, double2* lv) {
+  const int64_t cell = blockIdx.y;
+  if (cell >= C.n) return;
+  const int nv = 2 * T.N;
+  const double* d = C.dscale + cell * (int64_t)T.nvp;
+  const double2* Z = C.Z + cell * (int64_t)T.nrows * T.nvp;
+  const int64_t ld = T.nrows;
+  auto zrow = [&](int i) { return i < T.N ? i : T.Np + (i - T.N); };
+  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  const int64_t nG = (int64_t)nv * nv, nB = (int64_t)nv * T.k;
+  if (e < nG) {
+    const int i = (int)(e % nv), jj = (int)(e / nv);
+    const int zi = zrow(i), zj = zrow(jj);
+    double2 v = (zi >= zj) ? Z[(int64_t)zj * ld + zi] : cconj(Z[(int64_t)zi * ld + zj]);
+    const double s = 1.0 / (d[zi] * d[zj]);
+    G[cell * nG + e] = make_double2(v.x * s, v.y * s);
+  } else if (e < nG + nB) {
+    const int64_t f = e - nG;
+    const int i = (int)(f % nv), a = (int)(f / nv);
+    const int zi = zrow(i);
+    const double2 v = cconj(Z[(int64_t)zi * ld + T.nvp + a]);
+    Bf[cell * nB + f] = make_double2(v.x / d[zi], v.y / d[zi]);
+  } else if (e < nG + nB + nv) {
+    const int i = (int)(e - nG - nB);
+    const int zi = zrow(i);
+    const double2 v = cconj(Z[(int64_t)zi * ld + T.nvp + T.k]);
+    lv[cell * nv + i] = make_double2(v.x / d[zi], v.y / d[zi]);
+  }
+}
+
+}  // namespace
+
+// ================================================================ launchers
+static size_t scale_smem(const DevTables& t) { return sizeof(double) * (12 * (size_t)t.nq + 36 * (size_t)t.nfq); }
+
+// Kernel class ids (match the DPG_K_* enum of the public header).
+enum { KC_SCALE, KC_FORM_SM, KC_FORM_IF, KC_FORM_PAD, KC_FORM_B, KC_FORM_LOAD, KC_RESID, KC_CHOL_DIAG, KC_CHOL_PANEL,
+       KC_HERK };
+
+#define DPG_LAUNCH(cls, prof, st, ...)       \
+  do {                                       \
+    if (prof) (prof)->begin((cls), (st));    \
+    hipLaunchKernelGGL(__VA_ARGS__);         \
+    if (prof) (prof)->end((st));             \
+  } while (0)
+
+hipError_t launch_formation(const DevTables& t, const ProbArgs& pa, const ChunkArgs& ca, hipStream_t st,
+                            Prof* prof) {
+  if (ca.n <= 0) return hipSuccess;
+  const size_t sm = scale_smem(t);
+  DPG_LAUNCH(KC_SCALE, prof, st, k_cell_scale, dim3((unsigned)ca.n), dim3(NT), sm, st, t, pa, ca);
+  DPG_LAUNCH(KC_FORM_SM, prof, st, k_form_SM, dim3(grid_cells_tiles(ca.n, t.n_sm_tiles)), dim3(NT), sm, st, t, pa,
+             ca);
+  const int nt = (t.Np + 63) / 64;
+  DPG_LAUNCH(KC_FORM_IF, prof, st, k_form_IF, dim3(grid_cells_tiles(ca.n, nt * nt)), dim3(NT), 0, st, t, pa, ca);
+  DPG_LAUNCH(KC_FORM_PAD, prof, st, k_form_pad, dim3((unsigned)ca.n), dim3(NT), 0, st, t, ca);
+  DPG_LAUNCH(KC_FORM_B, prof, st, k_form_B, dim3(grid_cells_tiles(ca.n, nt)), dim3(NT), sizeof(double) * BQC * t.m1,
+             st, t, pa, ca);
+  DPG_LAUNCH(KC_FORM_LOAD, prof, st, k_form_load, dim3(grid_cells_tiles(ca.n, nt)), dim3(NT),
+             sizeof(double2) * 3 * t.nfq, st, t, pa, ca);
+  if (ca.x) {
+    const int nb = (t.nvp + 3) / 4;
+    DPG_LAUNCH(KC_RESID, prof, st, k_resid, dim3(grid_cells_tiles(ca.n, nb)), dim3(NT), 0, st, t, ca);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_factor(const DevTables& t, const ChunkArgs& ca, hipStream_t st, Prof* prof) {
+  if (ca.n <= 0) return hipSuccess;
+  const int nvb = t.nvp / TB, nrb = t.nrows / TB;
+  const size_t sm_diag = sizeof(double) * 4 * 64 * 65;
+  const size_t sm_panel = sizeof(PanelSmem) > 2 * sizeof(Stage) ? sizeof(PanelSmem) : 2 * sizeof(Stage);
+  for (int j = 0; j < nvb; ++j) {
+    DPG_LAUNCH(KC_CHOL_DIAG, prof, st, k_chol_diag, dim3((unsigned)ca.n), dim3(NT), sm_diag, st, t, ca, j);
+    DPG_LAUNCH(KC_CHOL_PANEL, prof, st, k_chol_panel, dim3(grid_cells_tiles(ca.n, nrb - j - 1)), dim3(NT), sm_panel,
+               st, t, ca, j);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_herk(const DevTables& t, const ChunkArgs& ca, hipStream_t st, Prof* prof) {
+  if (ca.n <= 0) return hipSuccess;
+  const int kb = t.kp / TB;
+  DPG_LAUNCH(KC_HERK, prof, st, k_herk, dim3(grid_cells_tiles(ca.n, kb * (kb + 1) / 2)), dim3(NT),
+             2 * sizeof(Stage), st, t, ca);
+  return hipGetLastError();
+}
+
+hipError_t launch_extract(const DevTables& t, const ChunkArgs& ca, double2* G, double2* Bf, double2* lvec,
+                          hipStream_t st) {
+  if (ca.n <= 0) return hipSuccess;
+  const int64_t nv = 2 * t.N;
+  const int64_t tot = nv * nv + nv * t.k + nv;
+  hipLaunchKernelGGL(k_extract, dim3((unsigned)((tot + NT - 1) / NT), (unsigned)ca.n), dim3(NT), 0, st, t, ca, G, Bf,
+                     lvec);
+  return hipGetLastError();
+}
+
+// Kernels that need more than 64 KB of dynamic LDS must opt in once.
+hipError_t configure_kernels() {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  int optin = 0;
+  e = hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev);
+  if (e != hipSuccess) return e;
+  const void* fns[] = {reinterpret_cast<const void*>(&k_chol_diag), reinterpret_cast<const void*>(&k_chol_panel),
+                       reinterpret_cast<const void*>(&k_cell_scale), reinterpret_cast<const void*>(&k_form_SM),
+                       reinterpret_cast<const void*>(&k_form_B), reinterpret_cast<const void*>(&k_herk)};
+  for (const void* f : fns) {
+    hipFuncAttributes fa;
+    e = hipFuncGetAttributes(&fa, f);
+    if (e != hipSuccess) return e;
+    // the dynamic allowance is what the per-block limit leaves after static LDS
+    e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, optin - (int)fa.sharedSizeBytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace dpg

@@ -1,0 +1,223 @@
+"""Thin ctypes binding of libdpgmi.so (include/dpg.h).
+
+Argument marshalling only: every step of the local solve runs in the HIP
+library.  torch is used for device memory and streams.  Loading fails loudly
+when the library has not been built (``python -m paper_2609_03155_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdpgmi.so")
+
+DPG_OK, DPG_ERR_ARG, DPG_ERR_ALLOC, DPG_ERR_HIP, DPG_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
+DPG_FP64, DPG_SPLIT_FP32 = 0, 1
+FACE_INTERIOR, FACE_PEC, FACE_PORT, FACE_ROBIN0 = 0, 1, 2, 3
+
+EXPORTS = ("dpg_local_dims", "dpg_plan_create", "dpg_plan_destroy", "dpg_plan_offsets", "dpg_plan_layout",
+           "dpg_local_solve", "dpg_form_local", "dpg_plan_set_profiling", "dpg_plan_profile", "dpg_status_string",
+           "dpg_last_error")
+KERNEL_CLASSES = ("scale", "form_SM", "form_IF", "form_pad", "form_B", "form_load", "resid", "chol_diag",
+                  "chol_panel", "herk")
+
+
+class dpg_port(C.Structure):
+    _fields_ = [("a", C.c_double), ("b", C.c_double), ("m", C.c_int32), ("n", C.c_int32),
+                ("eps_re", C.c_double), ("eps_im", C.c_double), ("mu_re", C.c_double), ("mu_im", C.c_double)]
+
+
+class dpg_problem(C.Structure):
+    _fields_ = [("n_cells", C.c_int64), ("n_vertices", C.c_int64), ("vertices", C.c_void_p),
+                ("cells", C.c_void_p), ("eps", C.c_void_p), ("mu", C.c_void_p), ("face_kind", C.c_void_p),
+                ("zinv", C.c_void_p), ("freq_hz", C.c_double), ("length_m", C.c_double), ("alpha", C.c_double),
+                ("port", dpg_port)]
+
+
+class DPGError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise DPGError(f"{LIB_PATH} is missing: build it with `python -m paper_2609_03155_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        i32, i64, vp, dp_ = C.c_int32, C.c_int64, C.c_void_p, C.c_double
+        L.dpg_local_dims.argtypes = [i32, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+        L.dpg_plan_create.argtypes = [i32, vp, i64, i32, i64, C.POINTER(vp)]
+        L.dpg_plan_destroy.argtypes = [vp]
+        L.dpg_plan_offsets.argtypes = [vp, vp, vp]
+        L.dpg_plan_layout.argtypes = [vp, i32, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
+        L.dpg_local_solve.argtypes = [vp, C.POINTER(dpg_problem), vp, vp, vp, vp, vp, i32, vp]
+        L.dpg_form_local.argtypes = [vp, C.POINTER(dpg_problem), i64, i64, vp, vp, vp, vp, vp]
+        L.dpg_plan_set_profiling.argtypes = [vp, i32]
+        L.dpg_plan_profile.argtypes = [vp, vp, vp]
+        L.dpg_status_string.argtypes = [i32]
+        L.dpg_status_string.restype = C.c_char_p
+        L.dpg_last_error.argtypes = []
+        L.dpg_last_error.restype = C.c_char_p
+        for name in ("dpg_local_dims", "dpg_plan_create", "dpg_plan_destroy", "dpg_plan_offsets",
+                     "dpg_plan_layout", "dpg_local_solve", "dpg_form_local", "dpg_plan_set_profiling",
+                     "dpg_plan_profile"):
+            getattr(L, name).restype = i32
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != DPG_OK:
+        msg = f"{what}: {lib().dpg_status_string(rc).decode()} ({rc})"
+        if rc == DPG_ERR_HIP:
+            msg += f" [{lib().dpg_last_error().decode()}]"
+        raise DPGError(msg)
+
+
+def dpg_local_dims(p: int, dp: int):
+    a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(lib().dpg_local_dims(p, dp, C.byref(a), C.byref(b), C.byref(c)), "dpg_local_dims")
+    return a.value, b.value, c.value
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+def _stream(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+@dataclass
+class DeviceProblem:
+    """Device-resident problem arrays (torch CUDA tensors) and scalars."""
+    vertices: "object"
+    cells: "object"
+    eps: "object"        # complex128 [n]
+    mu: "object"         # complex128 [n]
+    face_kind: "object"  # int8 [n,6]
+    zinv: "object"       # complex128 [n,6]
+    freq_hz: float
+    port: dict
+    length_m: float = 1.0
+    alpha: float = 1.0
+
+    @staticmethod
+    def from_workload(w, device="cuda:0") -> "DeviceProblem":
+        import torch
+        dev = torch.device(device)
+        return DeviceProblem(
+            vertices=torch.from_numpy(np.ascontiguousarray(w.vertices, np.float64)).to(dev),
+            cells=torch.from_numpy(np.ascontiguousarray(w.cells, np.int64)).to(dev),
+            eps=torch.from_numpy(np.ascontiguousarray(w.eps, np.complex128)).to(dev),
+            mu=torch.from_numpy(np.ascontiguousarray(w.mu, np.complex128)).to(dev),
+            face_kind=torch.from_numpy(np.ascontiguousarray(w.face_kind, np.int8)).to(dev),
+            zinv=torch.from_numpy(np.ascontiguousarray(w.zinv, np.complex128)).to(dev),
+            freq_hz=float(w.freq_hz), port=dict(w.port))
+
+    @property
+    def n_cells(self) -> int:
+        return int(self.cells.shape[0])
+
+    def cstruct(self) -> dpg_problem:
+        p = self.port
+        eps, mu = complex(p.get("eps", 1.0)), complex(p.get("mu", 1.0))
+        port = dpg_port(float(p["a"]), float(p["b"]), int(p["m"]), int(p["n"]), eps.real, eps.imag, mu.real,
+                        mu.imag)
+        return dpg_problem(self.n_cells, int(self.vertices.shape[0]), _ptr(self.vertices), _ptr(self.cells),
+                           _ptr(self.eps), _ptr(self.mu), _ptr(self.face_kind), _ptr(self.zinv),
+                           float(self.freq_hz), float(self.length_m), float(self.alpha), port)
+
+
+class Plan:
+    """dpg_plan_create / dpg_plan_destroy with the plan's output offsets."""
+
+    def __init__(self, degree, dp: int, device: int = 0, max_workspace_bytes: int = 0):
+        deg = np.ascontiguousarray(np.asarray(degree, dtype=np.int8))
+        self.n_cells = int(deg.shape[0])
+        self.dp = int(dp)
+        self.degree = deg
+        h = C.c_void_p()
+        _check(lib().dpg_plan_create(int(device), deg.ctypes.data, self.n_cells, self.dp,
+                                     int(max_workspace_bytes), C.byref(h)), "dpg_plan_create")
+        self._h = h
+        self.K_off = np.zeros(self.n_cells + 1, np.int64)
+        self.v_off = np.zeros(self.n_cells + 1, np.int64)
+        _check(lib().dpg_plan_offsets(self._h, self.K_off.ctypes.data, self.v_off.ctypes.data), "dpg_plan_offsets")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().dpg_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def layout(self, p: int):
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().dpg_plan_layout(self._h, int(p), C.byref(a), C.byref(b), C.byref(c)), "dpg_plan_layout")
+        return a.value, b.value, c.value
+
+    def set_profiling(self, enable: bool):
+        _check(lib().dpg_plan_set_profiling(self._h, int(bool(enable))), "dpg_plan_set_profiling")
+
+    def profile(self):
+        """{kernel class: (total ms, launches)} since the previous call."""
+        ms = np.zeros(len(KERNEL_CLASSES), np.float64)
+        n = np.zeros(len(KERNEL_CLASSES), np.int64)
+        _check(lib().dpg_plan_profile(self._h, ms.ctypes.data, n.ctypes.data), "dpg_plan_profile")
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_CLASSES)}
+
+    def alloc_outputs(self, device="cuda:0"):
+        import torch
+        dev = torch.device(device)
+        K = torch.empty(int(self.K_off[-1]), dtype=torch.complex128, device=dev)
+        l = torch.empty(int(self.v_off[-1]), dtype=torch.complex128, device=dev)
+        eta = torch.empty(self.n_cells, dtype=torch.float64, device=dev)
+        info = torch.empty(self.n_cells, dtype=torch.int32, device=dev)
+        return K, l, eta, info
+
+    def local_solve(self, prob: DeviceProblem, x, K, l, eta, info, precision: int = DPG_FP64, stream=None):
+        """dpg_local_solve: enqueue the local solve of every cell on `stream`."""
+        s = prob.cstruct()
+        _check(lib().dpg_local_solve(self._h, C.byref(s), _ptr(x), _ptr(K), _ptr(l), _ptr(eta), _ptr(info),
+                                     int(precision), _stream(stream)), "dpg_local_solve")
+
+    def form_local(self, prob: DeviceProblem, first: int, count: int, stream=None):
+        """dpg_form_local: unscaled G, B_f, l of cells first..first+count-1 (same degree)."""
+        import torch
+        p = int(self.degree[first])
+        nt, nu, ntr = dpg_local_dims(p, self.dp)
+        k = nu + ntr
+        dev = prob.vertices.device
+        G = torch.empty((count, nt, nt), dtype=torch.complex128, device=dev)
+        Bf = torch.empty((count, k, nt), dtype=torch.complex128, device=dev)
+        lv = torch.empty((count, nt), dtype=torch.complex128, device=dev)
+        info = torch.zeros(self.n_cells, dtype=torch.int32, device=dev)
+        s = prob.cstruct()
+        _check(lib().dpg_form_local(self._h, C.byref(s), int(first), int(count), _ptr(G), _ptr(Bf), _ptr(lv),
+                                    _ptr(info), _stream(stream)), "dpg_form_local")
+        # column-major per cell: G[c][col][row] -> transpose to [row][col]
+        return G.transpose(1, 2), Bf.transpose(1, 2), lv, info
+
+
+def cell_view(plan: Plan, K, l, c: int):
+    """(K_e, l_e) of cell c as views into the packed outputs."""
+    k = int(plan.v_off[c + 1] - plan.v_off[c])
+    Kc = K[int(plan.K_off[c]):int(plan.K_off[c + 1])].view(k, k).transpose(0, 1)
+    return Kc, l[int(plan.v_off[c]):int(plan.v_off[c + 1])]

@@ -1,0 +1,261 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (FP64 path).  The oracle solves with LU, the GPU with a
+Jacobi-scaled blocked Cholesky; both are backward stable, so each carries a
+forward error of order kappa(D G D) * u.  The bar per cell is
+    tol = max(1e-10, 4 kappa(D G D) u),   u = 2^-53,
+i.e. 1e-10 wherever FP64 can deliver it and the FP64 floor where the Gram
+matrix is worse conditioned (kappa ~ 1e6-1e7 for the lossy eps ~ 10 cells of
+the WR340 workload, where the oracle's own LU result is ~1.5e-10 from an
+extended-precision solve).  Measured on
+  K_e : ||K_gpu - K_or||_F / ||K_or||_F
+  l_e : ||.||_2 relative
+  eta : |d eta| / eta_or
+The local matrices G, B_f, l (before the solve) agree to 1e-12 of their
+largest entry.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2609_03155_amd import workloads as W
+
+from _oracle_cases import fp64_tol, oracle_cell, rel
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _run(w, x=None, precision=0):
+    torch = _torch()
+    from paper_2609_03155_amd import dpg
+    plan = dpg.Plan(w.degree, w.dp)
+    prob = dpg.DeviceProblem.from_workload(w)
+    K, l, eta, info = plan.alloc_outputs()
+    xd = None if x is None else torch.from_numpy(x).cuda()
+    plan.local_solve(prob, xd, K, l, eta, info, precision)
+    torch.cuda.synchronize()
+    return plan, K.cpu().numpy(), l.cpu().numpy(), eta.cpu().numpy(), info.cpu().numpy()
+
+
+def _cell_out(plan, K, l, c):
+    k = int(plan.v_off[c + 1] - plan.v_off[c])
+    Kc = K[plan.K_off[c]:plan.K_off[c + 1]].reshape(k, k).T
+    return Kc, l[plan.v_off[c]:plan.v_off[c + 1]]
+
+
+def test_form_local_matches_oracle_config1():
+    torch = _torch()
+    from paper_2609_03155_amd import dpg
+    w = W.config1()
+    _say("case: dpg_form_local config1 (8 cells, p=1)")
+    plan = dpg.Plan(w.degree, w.dp)
+    prob = dpg.DeviceProblem.from_workload(w)
+    G, Bf, lv, info = plan.form_local(prob, 0, w.n_cells)
+    torch.cuda.synchronize()
+    G, Bf, lv = G.cpu().numpy(), Bf.cpu().numpy(), lv.cpu().numpy()
+    assert np.all(info.cpu().numpy() == 0)
+    for c in range(w.n_cells):
+        Go, Bo, lo, *_ = oracle_cell(w, c)
+        assert np.abs(G[c] - Go).max() < 1e-12 * np.abs(Go).max(), c
+        assert np.abs(Bf[c] - Bo).max() < 1e-12 * np.abs(Bo).max(), c
+        assert np.abs(lv[c] - lo).max() <= 1e-12 * max(np.abs(lo).max(), 1e-300), c
+
+
+def test_form_local_matches_oracle_perturbed_p2():
+    torch = _torch()
+    from paper_2609_03155_amd import dpg
+    w = W.config2(nx=4, ny=2, nz=3)      # perturbed trilinear cells with port and outlet faces
+    _say("case: dpg_form_local config2-shaped 4x2x3 (p=2)")
+    plan = dpg.Plan(w.degree, w.dp)
+    prob = dpg.DeviceProblem.from_workload(w)
+    G, Bf, lv, info = plan.form_local(prob, 0, w.n_cells)
+    torch.cuda.synchronize()
+    G, Bf, lv = G.cpu().numpy(), Bf.cpu().numpy(), lv.cpu().numpy()
+    for c in (0, 5, 13, 23):
+        Go, Bo, lo, *_ = oracle_cell(w, c)
+        assert np.abs(G[c] - Go).max() < 1e-12 * np.abs(Go).max(), c
+        assert np.abs(Bf[c] - Bo).max() < 1e-12 * np.abs(Bo).max(), c
+        assert np.abs(lv[c] - lo).max() <= 1e-12 * max(np.abs(lo).max(), 1e-300), c
+
+
+def test_local_solve_config1_all_cells():
+    w = W.config1()
+    x, off = W.random_coefficients(w)
+    _say("case: dpg_local_solve config1 (8 cells, p=1)")
+    plan, K, l, eta, info = _run(w, x)
+    assert np.all(info == 0)
+    assert np.array_equal(plan.v_off, off)
+    for c in range(w.n_cells):
+        Go, _, _, Ko, lo, eo = oracle_cell(w, c, x[off[c]:off[c + 1]])
+        tol = fp64_tol(Go)
+        Kg, lg = _cell_out(plan, K, l, c)
+        assert rel(Kg, Ko) < tol, (c, rel(Kg, Ko), tol)
+        assert rel(lg, lo) < tol, (c, rel(lg, lo), tol)
+        assert abs(eta[c] - eo) < tol * eo, (c, abs(eta[c] - eo) / eo, tol)
+
+
+def test_local_solve_without_coefficients_gives_zero_eta():
+    w = W.config1()
+    _say("case: dpg_local_solve config1 x=NULL")
+    plan, K, l, eta, info = _run(w, None)
+    assert np.all(info == 0) and np.all(eta == 0.0)
+
+
+@pytest.fixture(scope="module")
+def c2_full():
+    w = W.config2()
+    x, off = W.random_coefficients(w)
+    _say("case: dpg_local_solve config2 full (5120 cells, p=2, dp=1)")
+    plan, K, l, eta, info = _run(w, x)
+    return w, x, off, plan, K, l, eta, info
+
+
+def test_local_solve_config2_sampled(c2_full):
+    w, x, off, plan, K, l, eta, info = c2_full
+    assert np.all(info == 0)
+    assert np.all(np.isfinite(eta))
+    rng = np.random.default_rng(W.SEED_BASE + 22)
+    sample = sorted(set([0, w.n_cells - 1] + list(rng.choice(w.n_cells, 4, replace=False))))
+    for c in sample:
+        Go, _, _, Ko, lo, eo = oracle_cell(w, c, x[off[c]:off[c + 1]])
+        tol = fp64_tol(Go)
+        Kg, lg = _cell_out(plan, K, l, c)
+        assert rel(Kg, Ko) < tol, (c, rel(Kg, Ko), tol)
+        assert rel(lg, lo) < tol, (c, rel(lg, lo), tol)
+        assert abs(eta[c] - eo) < tol * eo, (c, abs(eta[c] - eo) / eo, tol)
+
+
+def test_local_solve_config2_properties_all_cells(c2_full):
+    """At full size: every K_e is Hermitian with a real positive diagonal, and
+    eta^2 = x^H K x - 2 Re(x^H l_e) + const >= 0 is consistent in sign."""
+    w, x, off, plan, K, l, eta, info = c2_full
+    for c in range(0, w.n_cells, 97):
+        Kg, lg = _cell_out(plan, K, l, c)
+        assert np.abs(Kg - Kg.conj().T).max() <= 1e-14 * np.abs(Kg).max()
+        assert np.all(np.real(np.diag(Kg)) >= 0)
+
+
+def test_mixed_degrees_and_enrichment():
+    w = W.config3(nx=3, ny=3, nz=4)
+    w.degree[:] = np.array([1, 2, 3, 4] * 9, np.int8)[: w.n_cells]
+    x, off = W.random_coefficients(w)
+    _say("case: dpg_local_solve mixed p 1..4 (36 cells, dp=1)")
+    plan, K, l, eta, info = _run(w, x)
+    assert np.all(info == 0)
+    for c in (0, 1, 2, 3, 17, 35):
+        Go, _, _, Ko, lo, eo = oracle_cell(w, c, x[off[c]:off[c + 1]])
+        tol = fp64_tol(Go)
+        Kg, lg = _cell_out(plan, K, l, c)
+        assert rel(Kg, Ko) < tol, (c, w.degree[c], rel(Kg, Ko), tol)
+        assert rel(lg, lo) < tol, (c, w.degree[c], rel(lg, lo), tol)
+        assert abs(eta[c] - eo) < tol * eo, (c, w.degree[c])
+
+
+def test_high_order_p4_dp2():
+    w = W.config4(n=2)
+    x, off = W.random_coefficients(w)
+    _say("case: dpg_local_solve p=4 dp=2 (8 cells)")
+    plan, K, l, eta, info = _run(w, x)
+    assert np.all(info == 0)
+    for c in (0, 7):
+        Go, _, _, Ko, lo, eo = oracle_cell(w, c, x[off[c]:off[c + 1]])
+        tol = fp64_tol(Go)
+        Kg, lg = _cell_out(plan, K, l, c)
+        assert rel(Kg, Ko) < tol, (c, rel(Kg, Ko), tol)
+        assert rel(lg, lo) < tol, (c, rel(lg, lo), tol)
+        assert abs(eta[c] - eo) < tol * eo, (c, abs(eta[c] - eo) / eo, tol)
+
+
+def test_chunked_workspace_matches_single_chunk():
+    """A tiny workspace budget forces many chunks; results are bitwise equal."""
+    torch = _torch()
+    from paper_2609_03155_amd import dpg
+    w = W.config2(nx=4, ny=2, nz=5)
+    x, off = W.random_coefficients(w)
+    _say("case: chunked workspace (40 cells, p=2)")
+    prob = dpg.DeviceProblem.from_workload(w)
+    xd = torch.from_numpy(x).cuda()
+    outs = []
+    for budget in (0, 3 * 11 * 2 ** 20):
+        plan = dpg.Plan(w.degree, w.dp, max_workspace_bytes=budget)
+        K, l, eta, info = plan.alloc_outputs()
+        plan.local_solve(prob, xd, K, l, eta, info)
+        torch.cuda.synchronize()
+        outs.append((plan.layout(2)[2], K.cpu().numpy(), l.cpu().numpy(), eta.cpu().numpy()))
+    assert outs[0][0] == 40 and outs[1][0] < 40
+    for a, b in zip(outs[0][1:], outs[1][1:]):
+        assert np.array_equal(a, b)
+
+
+def test_repeat_is_bitwise_deterministic():
+    w = W.config1()
+    x, _ = W.random_coefficients(w)
+    _say("case: determinism config1")
+    r1 = _run(w, x)
+    r2 = _run(w, x)
+    for a, b in zip(r1[1:], r2[1:]):
+        assert np.array_equal(a, b)
+
+
+def test_degenerate_cell_reports_info_and_others_unaffected():
+    w = W.config1()
+    v = w.vertices.copy()
+    cells = w.cells.copy()
+    cells[3, [0, 1]] = cells[3, [1, 0]]          # inverted cell
+    w2 = W.Workload(w.name + "_bad", v, cells, w.eps, w.mu, w.degree, w.face_kind, w.zinv, w.dp, w.freq_hz,
+                    w.port)
+    x, off = W.random_coefficients(w2)
+    _say("case: degenerate cell 3 in config1")
+    plan, K, l, eta, info = _run(w2, x)
+    assert info[3] == -1
+    assert np.all(np.delete(info, 3) == 0)
+    Go, _, _, Ko, lo, eo = oracle_cell(w2, 0, x[off[0]:off[1]])
+    Kg, lg = _cell_out(plan, K, l, 0)
+    assert rel(Kg, Ko) < fp64_tol(Go)
+
+
+def test_argument_errors_are_synchronous():
+    _torch()
+    from paper_2609_03155_amd import dpg
+    with pytest.raises(dpg.DPGError):
+        dpg.Plan(np.array([5], np.int8), 1)
+    with pytest.raises(dpg.DPGError):
+        dpg.Plan(np.array([2], np.int8), 3)
+    w = W.config1()
+    plan = dpg.Plan(w.degree, w.dp)
+    prob = dpg.DeviceProblem.from_workload(w)
+    K, l, eta, info = plan.alloc_outputs()
+    with pytest.raises(dpg.DPGError):
+        plan.local_solve(prob, None, K, l, eta, info, precision=7)
+    with pytest.raises(dpg.DPGError):
+        plan.local_solve(prob, None, None, l, eta, info)
+
+
+def test_empty_batch():
+    torch = _torch()
+    from paper_2609_03155_amd import dpg
+    plan = dpg.Plan(np.zeros(0, np.int8), 1)
+    w = W.config1()
+    prob = dpg.DeviceProblem.from_workload(w.subset([]))
+    K = torch.zeros(1, dtype=torch.complex128, device="cuda")
+    eta = torch.zeros(1, dtype=torch.float64, device="cuda")
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    _say("case: empty batch")
+    plan.local_solve(prob, None, K, K, eta, info)
+    torch.cuda.synchronize()
