@@ -41,6 +41,7 @@ struct dpg_plan_s {
   std::vector<DegreeGroup> groups;
   double2* Z = nullptr;
   double* dscale = nullptr;
+  double* met = nullptr;
   std::vector<void*> misc;            // other device allocations
   dpg::Prof prof;
 };
@@ -153,6 +154,7 @@ void free_plan(dpg_plan_s* p) {
   for (auto e : p->prof.pool) (void)hipEventDestroy(e);
   if (p->Z) (void)hipFree(p->Z);
   if (p->dscale) (void)hipFree(p->dscale);
+  if (p->met) (void)hipFree(p->met);
   delete p;
 }
 
@@ -254,21 +256,24 @@ dpg_status dpg_plan_create(int32_t device, const int8_t* degree_host, int64_t n_
     size_t free_b = 0, total_b = 0;
     HIP_CHECK(hipMemGetInfo(&free_b, &total_b));
     int64_t budget = max_workspace_bytes > 0 ? max_workspace_bytes : (int64_t)(0.4 * (double)free_b);
-    size_t zmax = 0, dmax = 0;
+    size_t zmax = 0, dmax = 0, mmax = 0;
     for (auto& g : P->groups) {
-      const int64_t per = (int64_t)g.d.nrows * g.d.nvp * 16 + (int64_t)g.d.nvp * 8;
+      const int64_t mper = 12 * (int64_t)g.d.nq + 36 * (int64_t)g.d.nfq;
+      const int64_t per = (int64_t)g.d.nrows * g.d.nvp * 16 + (int64_t)g.d.nvp * 8 + mper * 8;
       int64_t ch = std::max<int64_t>(1, budget / per);
       ch = std::min<int64_t>(ch, (int64_t)g.cells.size());
       g.chunk = ch;
       zmax = std::max(zmax, (size_t)ch * g.d.nrows * g.d.nvp * 16);
       dmax = std::max(dmax, (size_t)ch * g.d.nvp * 8);
+      mmax = std::max(mmax, (size_t)(ch * mper * 8));
     }
     if (zmax) {
       if (hipMalloc(reinterpret_cast<void**>(&P->Z), zmax) != hipSuccess) {
         free_plan(P);
         return DPG_ERR_ALLOC;
       }
-      if (hipMalloc(reinterpret_cast<void**>(&P->dscale), dmax) != hipSuccess) {
+      if (hipMalloc(reinterpret_cast<void**>(&P->dscale), dmax) != hipSuccess ||
+          hipMalloc(reinterpret_cast<void**>(&P->met), mmax) != hipSuccess) {
         free_plan(P);
         return DPG_ERR_ALLOC;
       }
@@ -330,6 +335,7 @@ dpg_status dpg_local_solve(dpg_plan plan, const dpg_problem* prob, const double*
       ca.n = std::min<int64_t>(g.chunk, cnt - s0);
       ca.Z = plan->Z;
       ca.dscale = plan->dscale;
+      ca.met = plan->met;
       ca.K_off = plan->K_off_dev;
       ca.v_off = plan->v_off_dev;
       ca.x = reinterpret_cast<const double2*>(x);
@@ -413,6 +419,7 @@ dpg_status dpg_form_local(dpg_plan plan, const dpg_problem* prob, int64_t first,
     ca.n = std::min<int64_t>(grp->chunk, count - s0);
     ca.Z = plan->Z;
     ca.dscale = plan->dscale;
+    ca.met = plan->met;
     ca.K_off = plan->K_off_dev;
     ca.v_off = plan->v_off_dev;
     ca.x = nullptr;

@@ -48,6 +48,7 @@ struct ChunkArgs {
   int64_t n;                 // cells in the chunk
   double2* Z;                // [n][nvp cols][nrows] augmented lower factor, column-major
   double* dscale;            // [n][nvp] Jacobi scaling of the test rows
+  double* met;               // [n][12 nq + 36 nfq] point metrics: volume Gc|Gm, Robin-face Q
   const int64_t* K_off;      // [n_cells+1] global output offsets (complex elements)
   const int64_t* v_off;
   const double2* x;          // trial+trace coefficients, or null

@@ -245,134 +245,10 @@ __global__ __launch_bounds__(NT) void k_cell_scale(DevTables T, ProbArgs P, Chun
     d[i] = dF;
     d[T.Np + i] = dI;
   }
+  // keep the point metrics for the formation kernels
+  double* gm = C.met + cell * (int64_t)(12 * T.nq + 36 * T.nfq);
+  for (int e = threadIdx.x; e < 12 * T.nq + 36 * T.nfq; e += NT) gm[e] = smem[e];
   if (threadIdx.x == 0) C.info[gc] = s_bad ? -1 : 0;
-}
-
-// ================================================================ G_FF, G_II
-// One workgroup per (cell, tile of the N x N test index space restricted to a
-// component pair (a, b)): every row shares component a and every column
-// component b, so M_ij = sum_q v_i Gm_ab v_j and S_ij = sum_q chat_i . Gc chat_j
-// with two nonzero curl components on each side.
-__global__ __launch_bounds__(NT) void k_form_SM(DevTables T, ProbArgs P, ChunkArgs C) {
-  int64_t cell;
-  int tile;
-  if (!decode_cell_tile(C.n, T.n_sm_tiles, cell, tile)) return;
-  const int64_t gc = C.cell_ids[cell];
-  __shared__ double sX[8][3];
-  extern __shared__ double smem[];
-  double* sGc = smem;              // [nq][6]
-  double* sGm = sGc + 6 * T.nq;    // [nq][6]
-  double* sQ = sGm + 6 * T.nq;     // [6][nfq][6]
-  load_cell_vertices(P, gc, sX);
-  __syncthreads();
-  for (int q = threadIdx.x; q < T.nq; q += NT) {
-    Geo g;
-    trilinear(sX, T.vol_pts[3 * q], T.vol_pts[3 * q + 1], T.vol_pts[3 * q + 2], g);
-    vol_metrics(g, T.vol_w[q], &sGc[6 * q], &sGm[6 * q]);
-  }
-  int8_t fk[6];
-  int nrobin = 0;
-  for (int f = 0; f < 6; ++f) {
-    fk[f] = P.face_kind[gc * 6 + f];
-    nrobin += is_robin(fk[f]);
-  }
-  if (nrobin) {
-    for (int f = 0; f < 6; ++f) {
-      if (!is_robin(fk[f])) continue;
-      for (int fq = threadIdx.x; fq < T.nfq; fq += NT) {
-        const double* xi = &T.face_pts[(f * T.nfq + fq) * 3];
-        Geo g;
-        trilinear(sX, xi[0], xi[1], xi[2], g);
-        double n[3], s;
-        face_normal(g, f, n, s);
-        face_metric(g, n, T.face_w[f * T.nfq + fq] * s, &sQ[(f * T.nfq + fq) * 6]);
-      }
-    }
-  }
-  __syncthreads();
-
-  const int4 tl = T.sm_tiles[tile];
-  const int a = tl.x, b = tl.y;
-  const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
-  const int a1 = (a == 0) ? 1 : 0, a2 = (a == 2) ? 1 : 2;   // nonzero curl components of rows
-  const int b1 = (b == 0) ? 1 : 0, b2 = (b == 2) ? 1 : 2;   // ... and of columns
-  int li[4], lj[4], ri[4], rj[4];
-  for (int u = 0; u < 4; ++u) {
-    li[u] = tl.z * 64 + ti * 4 + u;
-    lj[u] = tl.w * 64 + tj * 4 + u;
-    ri[u] = a * T.nc + min(li[u], T.nc - 1);
-    rj[u] = b * T.nc + min(lj[u], T.nc - 1);
-  }
-  double S[4][4], M[4][4], MF[4][4], MI[4][4];
-  for (int u = 0; u < 4; ++u)
-    for (int v = 0; v < 4; ++v) S[u][v] = M[u][v] = MF[u][v] = MI[u][v] = 0.0;
-  const int sab = sym3(a, b);
-  const int s11 = sym3(a1, b1), s12 = sym3(a1, b2), s21 = sym3(a2, b1), s22 = sym3(a2, b2);
-  for (int q = 0; q < T.nq; ++q) {
-    const double* G = &sGc[6 * q];
-    const double gm = sGm[6 * q + sab];
-    const double g11 = G[s11], g12 = G[s12], g21 = G[s21], g22 = G[s22];
-    const double* vv = T.vol_v + (size_t)q * T.Np;
-    const double* cc = T.vol_c + (size_t)q * T.Np * 3;
-    double vi[4], ci1[4], ci2[4], mj[4], y1[4], y2[4];
-    for (int u = 0; u < 4; ++u) {
-      vi[u] = vv[ri[u]];
-      ci1[u] = cc[3 * ri[u] + a1];
-      ci2[u] = cc[3 * ri[u] + a2];
-      const double vj = vv[rj[u]], cj1 = cc[3 * rj[u] + b1], cj2 = cc[3 * rj[u] + b2];
-      mj[u] = gm * vj;
-      y1[u] = g11 * cj1 + g12 * cj2;
-      y2[u] = g21 * cj1 + g22 * cj2;
-    }
-    for (int u = 0; u < 4; ++u)
-      for (int v = 0; v < 4; ++v) {
-        S[u][v] += ci1[u] * y1[v] + ci2[u] * y2[v];
-        M[u][v] += vi[u] * mj[v];
-      }
-  }
-  if (nrobin) {
-    for (int f = 0; f < 6; ++f) {
-      if (!is_robin(fk[f])) continue;
-      const double zr = P.zinv[(gc * 6 + f) * 2], zi = P.zinv[(gc * 6 + f) * 2 + 1];
-      const double z2 = zr * zr + zi * zi;
-      for (int fq = 0; fq < T.nfq; ++fq) {
-        const double qab = sQ[(f * T.nfq + fq) * 6 + sab];
-        const double* vv = T.face_v + ((size_t)f * T.nfq + fq) * T.Np;
-        double vi[4], vj[4];
-        for (int u = 0; u < 4; ++u) {
-          vi[u] = vv[ri[u]];
-          vj[u] = qab * vv[rj[u]];
-        }
-        for (int u = 0; u < 4; ++u)
-          for (int v = 0; v < 4; ++v) {
-            const double m = vi[u] * vj[v];
-            MI[u][v] += m;
-            MF[u][v] += z2 * m;
-          }
-      }
-    }
-  }
-  const double2 eps = make_double2(P.eps[2 * gc], P.eps[2 * gc + 1]);
-  const double2 mu = make_double2(P.mu[2 * gc], P.mu[2 * gc + 1]);
-  const double om2 = P.omega * P.omega;
-  const double cF = om2 * (eps.x * eps.x + eps.y * eps.y) + P.alpha;
-  const double cI = om2 * (mu.x * mu.x + mu.y * mu.y) + P.alpha;
-  const double* d = C.dscale + cell * (int64_t)T.nvp;
-  double2* Z = C.Z + cell * (int64_t)T.nrows * T.nvp;
-  const int64_t ld = T.nrows;
-  for (int u = 0; u < 4; ++u) {
-    if (li[u] >= T.nc) continue;
-    const int i = ri[u];
-    for (int v = 0; v < 4; ++v) {
-      if (lj[v] >= T.nc) continue;
-      const int j = rj[v];
-      if (a == b && j > i) continue;
-      const double gff = S[u][v] + cF * M[u][v] + MF[u][v];
-      const double gii = S[u][v] + cI * M[u][v] + MI[u][v];
-      Z[(int64_t)j * ld + i] = make_double2(d[i] * d[j] * gff, 0.0);
-      Z[(int64_t)(T.Np + j) * ld + T.Np + i] = make_double2(d[T.Np + i] * d[T.Np + j] * gii, 0.0);
-    }
-  }
 }
 
 // ================================================================ G_IF
@@ -860,100 +736,325 @@ __device__ inline void acc_for_each(const Acc& c, F&& f) {
       }
 }
 
+// ================================================================ G_FF, G_II
+// One workgroup per (cell, 64x64 tile of the N x N test index space restricted
+// to a component pair (a, b)): rows share reference component a, columns b.
+// With v the nonzero component and chat the curl of the reference functions,
+//   M_ij = sum_q v_i(q) Gm_ab(q) v_j(q),
+//   S_ij = sum_q sum_{u != a} chat_iu(q) (sum_{w != b} Gc_uw(q) chat_jw(q)),
+// two real GEMMs over quadrature points on f64 MFMA (the metric is folded into
+// the column operand); Robin faces add Mt_ij = sum v_i Q_ab v_j.
+constexpr int SQC = 16;   // quadrature points per staged chunk
+
+struct RAcc {
+  d4 b[2][2];
+};
+
+__device__ inline void racc_zero(RAcc& c) {
+  for (int u = 0; u < 2; ++u)
+    for (int v = 0; v < 2; ++v) c.b[u][v] = d4{0, 0, 0, 0};
+}
+
+template <class F>
+__device__ inline void racc_for_each(const RAcc& c, F&& f) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w & 1, wc = w >> 1;
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int it = 0; it < 4; ++it)
+        f(wr * 32 + u * 16 + (lane >> 4) + 4 * it, wc * 32 + v * 16 + (lane & 15), c.b[u][v][it]);
+}
+
+// acc += A^T B over a staged chunk: A, B as [k][row] planes of pitch LDP.
+__device__ inline void lds_atb(const double* A, const double* B, int K, RAcc& c) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w & 1, wc = w >> 1;
+#pragma unroll
+  for (int ks = 0; ks < K / 4; ++ks) {
+    const int kk = ks * 4 + (lane >> 4);
+    double a[2], b[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      a[u] = A[kk * LDP + wr * 32 + u * 16 + (lane & 15)];
+      b[u] = B[kk * LDP + wc * 32 + u * 16 + (lane & 15)];
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v) c.b[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[v], c.b[u][v], 0, 0, 0);
+  }
+}
+
+__global__ __launch_bounds__(NT, 2) void k_form_SM(DevTables T, ProbArgs P, ChunkArgs C) {
+  int64_t cell;
+  int tile;
+  if (!decode_cell_tile(C.n, T.n_sm_tiles, cell, tile)) return;
+  const int64_t gc = C.cell_ids[cell];
+  __shared__ double sMet[SQC][12];          // Gc (6) | Gm (6) of the chunk's points
+  __shared__ double Av[SQC * LDP], Ac1[SQC * LDP], Ac2[SQC * LDP];
+  __shared__ double Bv[SQC * LDP], By1[SQC * LDP], By2[SQC * LDP];
+  int8_t fk[6];
+  for (int f = 0; f < 6; ++f) fk[f] = P.face_kind[gc * 6 + f];
+  const int4 tl = T.sm_tiles[tile];
+  const int a = tl.x, b = tl.y;
+  const int a1 = (a == 0) ? 1 : 0, a2 = (a == 2) ? 1 : 2;
+  const int b1 = (b == 0) ? 1 : 0, b2 = (b == 2) ? 1 : 2;
+  const int sab = sym3(a, b);
+  const int s11 = sym3(a1, b1), s12 = sym3(a1, b2), s21 = sym3(a2, b1), s22 = sym3(a2, b2);
+  RAcc S, M, MF, MI;
+  racc_zero(S);
+  racc_zero(M);
+  racc_zero(MF);
+  racc_zero(MI);
+  __syncthreads();
+  const double* gmet = C.met + cell * (int64_t)(12 * T.nq + 36 * T.nfq);
+  // ---- volume points
+  for (int q0 = 0; q0 < T.nq; q0 += SQC) {
+    if (threadIdx.x < SQC * 12) {
+      const int qq = threadIdx.x / 12, e = threadIdx.x % 12, q = q0 + qq;
+      // gmet layout: Gc[nq][6] then Gm[nq][6]
+      sMet[qq][e] = (q < T.nq) ? gmet[(e < 6 ? 0 : 6 * T.nq) + 6 * q + (e % 6)] : 0.0;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < SQC * 64; e += NT) {
+      const int qq = e >> 6, il = e & 63;
+      const int q = min(q0 + qq, T.nq - 1);
+      const int i = a * T.nc + min(tl.z * 64 + il, T.nc - 1);
+      const int jj = b * T.nc + min(tl.w * 64 + il, T.nc - 1);
+      const double* m = sMet[qq];
+      const double* ci = &T.vol_c[((size_t)q * T.Np + i) * 3];
+      const double* cj = &T.vol_c[((size_t)q * T.Np + jj) * 3];
+      Av[qq * LDP + il] = T.vol_v[(size_t)q * T.Np + i];
+      Ac1[qq * LDP + il] = ci[a1];
+      Ac2[qq * LDP + il] = ci[a2];
+      const double cj1 = cj[b1], cj2 = cj[b2];
+      Bv[qq * LDP + il] = m[6 + sab] * T.vol_v[(size_t)q * T.Np + jj];
+      By1[qq * LDP + il] = m[s11] * cj1 + m[s12] * cj2;
+      By2[qq * LDP + il] = m[s21] * cj1 + m[s22] * cj2;
+    }
+    __syncthreads();
+    lds_atb(Av, Bv, SQC, M);
+    lds_atb(Ac1, By1, SQC, S);
+    lds_atb(Ac2, By2, SQC, S);
+    __syncthreads();
+  }
+  // ---- Robin faces
+  for (int f = 0; f < 6; ++f) {
+    if (!is_robin(fk[f])) continue;
+    const double zr = P.zinv[(gc * 6 + f) * 2], zi = P.zinv[(gc * 6 + f) * 2 + 1];
+    const double z2 = zr * zr + zi * zi;
+    for (int q0 = 0; q0 < T.nfq; q0 += SQC) {
+      if (threadIdx.x < SQC) {
+        const int fq = q0 + threadIdx.x;
+        sMet[threadIdx.x][0] = (fq < T.nfq) ? gmet[12 * T.nq + (f * T.nfq + fq) * 6 + sab] : 0.0;
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < SQC * 64; e += NT) {
+        const int qq = e >> 6, il = e & 63;
+        const int fq = min(q0 + qq, T.nfq - 1);
+        const int i = a * T.nc + min(tl.z * 64 + il, T.nc - 1);
+        const int jj = b * T.nc + min(tl.w * 64 + il, T.nc - 1);
+        const double* vv = T.face_v + ((size_t)f * T.nfq + fq) * T.Np;
+        const double bq = sMet[qq][0] * vv[jj];
+        Av[qq * LDP + il] = vv[i];
+        Bv[qq * LDP + il] = bq;
+        By1[qq * LDP + il] = z2 * bq;
+      }
+      __syncthreads();
+      lds_atb(Av, Bv, SQC, MI);
+      lds_atb(Av, By1, SQC, MF);
+      __syncthreads();
+    }
+  }
+  const double2 eps = make_double2(P.eps[2 * gc], P.eps[2 * gc + 1]);
+  const double2 mu = make_double2(P.mu[2 * gc], P.mu[2 * gc + 1]);
+  const double om2 = P.omega * P.omega;
+  const double cF = om2 * (eps.x * eps.x + eps.y * eps.y) + P.alpha;
+  const double cI = om2 * (mu.x * mu.x + mu.y * mu.y) + P.alpha;
+  const double* d = C.dscale + cell * (int64_t)T.nvp;
+  double2* Z = C.Z + cell * (int64_t)T.nrows * T.nvp;
+  const int64_t ld = T.nrows;
+  // combine per item (same lane mapping for all four accumulators)
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w & 1, wc = w >> 1;
+  for (int u = 0; u < 2; ++u)
+    for (int v = 0; v < 2; ++v)
+      for (int it = 0; it < 4; ++it) {
+        const int li = tl.z * 64 + wr * 32 + u * 16 + (lane >> 4) + 4 * it;
+        const int lj = tl.w * 64 + wc * 32 + v * 16 + (lane & 15);
+        if (li >= T.nc || lj >= T.nc) continue;
+        const int i = a * T.nc + li, j = b * T.nc + lj;
+        if (a == b && j > i) continue;
+        const double sv = S.b[u][v][it], mv = M.b[u][v][it];
+        const double gff = sv + cF * mv + MF.b[u][v][it];
+        const double gii = sv + cI * mv + MI.b[u][v][it];
+        Z[(int64_t)j * ld + i] = make_double2(d[i] * d[j] * gff, 0.0);
+        Z[(int64_t)(T.Np + j) * ld + T.Np + i] = make_double2(d[T.Np + i] * d[T.Np + j] * gii, 0.0);
+      }
+}
+
 // ================================================================ Cholesky
-// Step j, diagonal block: X = A_jj - sum_{m<j} L_jm L_jm^H, X = L L^H, store L^{-1}.
-__global__ __launch_bounds__(NT) void k_chol_diag(DevTables T, ChunkArgs C, int j) {
+// Product of two LDS-resident operands, P += A B^H over K columns: A and B
+// are stored as [k][row] planes (row pitch LDP), the same convention as Stage.
+__device__ inline void lds_abh(const double* Ar, const double* Ai, const double* Br, const double* Bi, int K,
+                               Acc& c) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w & 1, wc = w >> 1;
+  for (int ks = 0; ks < K / 4; ++ks) {
+    const int kk = ks * 4 + (lane >> 4);
+    double ar[2], ai[2], nar[2], br[2], bi[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int row = wr * 32 + u * 16 + (lane & 15);
+      ar[u] = Ar[kk * LDP + row];
+      ai[u] = Ai[kk * LDP + row];
+      nar[u] = -ar[u];
+      const int col = wc * 32 + u * 16 + (lane & 15);
+      br[u] = Br[kk * LDP + col];
+      bi[u] = Bi[kk * LDP + col];
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v) c.re[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[u], br[v], c.re[u][v], 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v) c.im[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[u], br[v], c.im[u][v], 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v) c.re[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[u], bi[v], c.re[u][v], 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v) c.im[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(nar[u], bi[v], c.im[u][v], 0, 0, 0);
+  }
+}
+
+// LDS layout of the factorisation kernels (aliased phases, <= 68 KB so that
+// two workgroups fit one CU):
+//   GEMM staging            2 x Stage
+//   X Linv^H in k-halves    Xr, Xi [32][LDP] (k = column of X), Lr, Li [32][LDP]
+//   Y Y^H (lookahead)       Yr, Yi [64][LDP]
+//   Cholesky + inverse      Cr, Ci [64][65], Yd [64]
+constexpr size_t kFactorSmem = 2 * sizeof(Stage) > 4 * 32 * LDP * 8 ? 2 * sizeof(Stage) : 4 * 32 * LDP * 8;
+static_assert(2 * 64 * LDP * 8 <= kFactorSmem, "LDS plan");
+static_assert(2 * 64 * 65 * 8 + 64 * 8 <= kFactorSmem, "LDS plan");
+
+// In-place Cholesky and inverse of the 64x64 Hermitian tile held (lower part)
+// in Cr/Ci[r*65+q]: on exit the lower part holds L and the strict upper part
+// holds L^{-1} transposed (Linv[r][q] at [q*65+r]); the (real) diagonal of
+// L^{-1} is in Yd.  Returns the first failing column + 1 (0 if none) in s_fail.
+__device__ inline void tile_chol_inv(double* Cr, double* Ci, double* Yd, int* s_fail, double* s_inv) {
+  for (int e = threadIdx.x; e < 64 * 64; e += NT) {
+    const int r = e >> 6, q = e & 63;
+    if (q > r) {
+      Cr[r * 65 + q] = 0.0;
+      Ci[r * 65 + q] = 0.0;
+    }
+  }
+  if (threadIdx.x == 0) *s_fail = 0;
+  __syncthreads();
+  for (int c = 0; c < 64; ++c) {
+    if (threadIdx.x == 0) {
+      double dd = Cr[c * 65 + c];
+      if (!(dd > 0.0) || !isfinite(dd)) {
+        if (!*s_fail) *s_fail = c + 1;
+        dd = 1.0;
+      }
+      const double l = sqrt(dd);
+      Cr[c * 65 + c] = l;
+      Ci[c * 65 + c] = 0.0;
+      *s_inv = 1.0 / l;
+      Yd[c] = 1.0 / l;
+    }
+    __syncthreads();
+    const double inv = *s_inv;
+    // column c of L below the diagonal; row c of L^{-1} left of the diagonal (stored at [q][c])
+    for (int r = c + 1 + threadIdx.x; r < 64; r += NT) {
+      Cr[r * 65 + c] *= inv;
+      Ci[r * 65 + c] *= inv;
+    }
+    for (int q = threadIdx.x; q < c; q += NT) {
+      Cr[q * 65 + c] *= inv;
+      Ci[q * 65 + c] *= inv;
+    }
+    __syncthreads();
+    const int q = threadIdx.x & 63;
+    for (int r = c + 1 + (threadIdx.x >> 6); r < 64; r += NT / 64) {
+      const double lr = Cr[r * 65 + c], li = Ci[r * 65 + c];
+      if (q > c && q <= r) {
+        const double mr = Cr[q * 65 + c], mi = -Ci[q * 65 + c];   // conj(L_qc)
+        Cr[r * 65 + q] -= lr * mr - li * mi;
+        Ci[r * 65 + q] -= lr * mi + li * mr;
+      } else if (q <= c) {
+        // Linv[r][q] -= L[r][c] Linv[c][q]
+        double yr, yi;
+        if (q == c) {
+          yr = Yd[c];
+          yi = 0.0;
+        } else {
+          yr = Cr[q * 65 + c];
+          yi = Ci[q * 65 + c];
+        }
+        Cr[q * 65 + r] -= lr * yr - li * yi;
+        Ci[q * 65 + r] -= lr * yi + li * yr;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Writes L^{-1} (lower, zero upper) from the tile_chol_inv layout into a
+// column-major global tile.
+__device__ inline void store_linv(const double* Cr, const double* Ci, const double* Yd, double2* tile, int64_t ld) {
+  for (int e = threadIdx.x; e < 64 * 64; e += NT) {
+    const int q = e >> 6, r = e & 63;   // column q, row r
+    double2 v = make_double2(0.0, 0.0);
+    if (r == q) v = make_double2(Yd[r], 0.0);
+    else if (r > q) v = make_double2(Cr[q * 65 + r], Ci[q * 65 + r]);
+    tile[(int64_t)q * ld + r] = v;
+  }
+}
+
+// Step 0 diagonal block: A_00 = L L^H, store L^{-1}.
+__global__ __launch_bounds__(NT) void k_chol_diag0(DevTables T, ChunkArgs C) {
   const int64_t cell = blockIdx.x;
   if (cell >= C.n) return;
   const int64_t gc = C.cell_ids[cell];
   extern __shared__ double smem[];
-  Stage* st = reinterpret_cast<Stage*>(smem);
-  double* Xr = smem;                 // [64][65] (aliases the staging buffers after the GEMM)
-  double* Xi = Xr + 64 * 65;
-  double* Yr = Xi + 64 * 65;         // L^{-1}
-  double* Yi = Yr + 64 * 65;
+  double* Cr = smem;
+  double* Ci = Cr + 64 * 65;
+  double* Yd = Ci + 64 * 65;
   __shared__ double s_inv;
   __shared__ int s_fail;
   const int64_t ld = T.nrows;
-  double2* Z = C.Z + cell * (int64_t)T.nrows * T.nvp;
-  const double2* panel = Z + j * TB;  // row offset j*64, column 0
-  Acc acc;
-  acc_zero(acc);
-  gemm_abh(panel, panel, ld, j * TB, st, acc);
-  __syncthreads();
-  double2* tileA = Z + (int64_t)(j * TB) * ld + j * TB;
-  acc_for_each(acc, [&](int r, int c, double pr, double pi) {
-    if (c <= r) {
-      const double2 a = tileA[(int64_t)c * ld + r];
-      Xr[r * 65 + c] = a.x - pr;
-      Xi[r * 65 + c] = a.y - pi;
-    }
-  });
+  double2* tile = C.Z + cell * (int64_t)T.nrows * T.nvp;
   for (int e = threadIdx.x; e < 64 * 64; e += NT) {
-    const int r = e >> 6, c = e & 63;
-    Yr[r * 65 + c] = (r == c) ? 1.0 : 0.0;
-    Yi[r * 65 + c] = 0.0;
+    const int q = e >> 6, r = e & 63;
+    if (q <= r) {
+      const double2 a = tile[(int64_t)q * ld + r];
+      Cr[r * 65 + q] = a.x;
+      Ci[r * 65 + q] = a.y;
+    }
   }
-  if (threadIdx.x == 0) s_fail = 0;
   __syncthreads();
-  for (int c = 0; c < 64; ++c) {
-    if (threadIdx.x == 0) {
-      double dd = Xr[c * 65 + c];
-      if (!(dd > 0.0) || !isfinite(dd)) {
-        if (!s_fail) s_fail = j * TB + c + 1;
-        dd = 1.0;
-      }
-      const double l = sqrt(dd);
-      Xr[c * 65 + c] = l;
-      Xi[c * 65 + c] = 0.0;
-      s_inv = 1.0 / l;
-    }
-    __syncthreads();
-    const double inv = s_inv;
-    for (int r = c + 1 + threadIdx.x; r < 64; r += NT) {
-      Xr[r * 65 + c] *= inv;
-      Xi[r * 65 + c] *= inv;
-    }
-    for (int q = threadIdx.x; q <= c; q += NT) {
-      Yr[c * 65 + q] *= inv;
-      Yi[c * 65 + q] *= inv;
-    }
-    __syncthreads();
-    // trailing update of X (lower) and elimination of rows r > c of Y
-    const int q = threadIdx.x & 63;
-    for (int r = c + 1 + (threadIdx.x >> 6); r < 64; r += NT / 64) {
-      const double lr = Xr[r * 65 + c], li = Xi[r * 65 + c];
-      if (q > c && q <= r) {
-        const double mr = Xr[q * 65 + c], mi = -Xi[q * 65 + c];   // conj(L_qc)
-        Xr[r * 65 + q] -= lr * mr - li * mi;
-        Xi[r * 65 + q] -= lr * mi + li * mr;
-      }
-      if (q <= c) {
-        const double yr = Yr[c * 65 + q], yi = Yi[c * 65 + q];
-        Yr[r * 65 + q] -= lr * yr - li * yi;
-        Yi[r * 65 + q] -= lr * yi + li * yr;
-      }
-    }
-    __syncthreads();
-  }
-  // store L^{-1} (lower, zero upper) into the diagonal tile
-  for (int e = threadIdx.x; e < 64 * 64; e += NT) {
-    const int c = e >> 6, r = e & 63;
-    tileA[(int64_t)c * ld + r] = (c <= r) ? make_double2(Yr[r * 65 + c], Yi[r * 65 + c]) : make_double2(0.0, 0.0);
-  }
-  if (threadIdx.x == 0 && s_fail) {
-    if (C.info[gc] == 0) C.info[gc] = s_fail;
-  }
+  tile_chol_inv(Cr, Ci, Yd, &s_fail, &s_inv);
+  store_linv(Cr, Ci, Yd, tile, ld);
+  if (threadIdx.x == 0 && s_fail && C.info[gc] == 0) C.info[gc] = s_fail;
 }
 
-// Step j, panel: for row tiles i > j:  L_ij = (A_ij - sum_{m<j} L_im L_jm^H) Linv_jj^H.
-struct PanelSmem {
-  double Xr[64][LDP], Xi[64][LDP];   // X^T staged as [k][row], k = column of X
-  double Lr[64][LDP], Li[64][LDP];   // Linv as [k][col] : B operand (conj applied in the product)
-};
-
-__global__ __launch_bounds__(NT) void k_chol_panel(DevTables T, ChunkArgs C, int j) {
-  const int nrb = T.nrows / TB;
+// Step j of the left-looking factorisation, one workgroup per row tile i > j:
+//   L_ij = (A_ij - sum_{m<j} L_im L_jm^H) Linv_jj^H .
+// Lookahead: the workgroup of tile i = j+1 (< number of test tiles) then forms
+//   A_ii - sum_{m<=j} L_im L_im^H  and factorises it (Cholesky + inverse),
+// storing Linv_ii for step j+1, so no separate launch factors diagonal blocks.
+__global__ __launch_bounds__(NT, 2) void k_chol_step(DevTables T, ChunkArgs C, int j) {
+  const int nrb = T.nrows / TB, nvb = T.nvp / TB;
   const int ntiles = nrb - j - 1;
   int64_t cell;
   int tile;
@@ -961,63 +1062,82 @@ __global__ __launch_bounds__(NT) void k_chol_panel(DevTables T, ChunkArgs C, int
   const int i = j + 1 + tile;
   extern __shared__ double smem[];
   Stage* st = reinterpret_cast<Stage*>(smem);
-  PanelSmem* ps = reinterpret_cast<PanelSmem*>(smem);
   const int64_t ld = T.nrows;
   double2* Z = C.Z + cell * (int64_t)T.nrows * T.nvp;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wc = w >> 1;
+
   Acc acc;
   acc_zero(acc);
   gemm_abh(Z + i * TB, Z + j * TB, ld, j * TB, st, acc);
-  __syncthreads();
-  // X = A_ij - P  ->  LDS as the A operand [k = column of X][row]
+  // X = A_ij - P ; Y = X Linv_jj^H, in two k-halves through LDS
+  double* Xr = smem;
+  double* Xi = Xr + 32 * LDP;
+  double* Lr = Xi + 32 * LDP;
+  double* Li = Lr + 32 * LDP;
   const double2* tileA = Z + (int64_t)(j * TB) * ld + i * TB;
-  acc_for_each(acc, [&](int r, int c, double pr, double pi) {
-    const double2 a = tileA[(int64_t)c * ld + r];
-    ps->Xr[c][r] = a.x - pr;
-    ps->Xi[c][r] = a.y - pi;
-  });
-  // Linv_jj (row = col index of the result, column = k) -> [k][col]
   const double2* tileL = Z + (int64_t)(j * TB) * ld + j * TB;
-  for (int e = threadIdx.x; e < 64 * 64; e += NT) {
-    const int k = e >> 6, c = e & 63;
-    const double2 v = tileL[(int64_t)k * ld + c];
-    ps->Lr[k][c] = v.x;
-    ps->Li[k][c] = v.y;
-  }
-  __syncthreads();
-  // Y = X Linv^H
   Acc y;
   acc_zero(y);
-  {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int wr = w & 1, wc = w >> 1;
-    for (int ks = 0; ks < 16; ++ks) {
-      const int kk = ks * 4 + (lane >> 4);
-      double ar[2], ai[2], nar[2], br[2], bi[2];
-      for (int u = 0; u < 2; ++u) {
-        const int row = wr * 32 + u * 16 + (lane & 15);
-        ar[u] = ps->Xr[kk][row];
-        ai[u] = ps->Xi[kk][row];
-        nar[u] = -ar[u];
-        const int col = wc * 32 + u * 16 + (lane & 15);
-        br[u] = ps->Lr[kk][col];
-        bi[u] = ps->Li[kk][col];
-      }
-      for (int u = 0; u < 2; ++u)
-        for (int v = 0; v < 2; ++v) y.re[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[u], br[v], y.re[u][v], 0, 0, 0);
-      for (int u = 0; u < 2; ++u)
-        for (int v = 0; v < 2; ++v) y.im[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[u], br[v], y.im[u][v], 0, 0, 0);
-      for (int u = 0; u < 2; ++u)
-        for (int v = 0; v < 2; ++v) y.re[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[u], bi[v], y.re[u][v], 0, 0, 0);
-      for (int u = 0; u < 2; ++u)
-        for (int v = 0; v < 2; ++v) y.im[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(nar[u], bi[v], y.im[u][v], 0, 0, 0);
+  for (int h = 0; h < 2; ++h) {
+    __syncthreads();
+    if (wc == h) {
+      acc_for_each(acc, [&](int r, int c, double pr, double pi) {
+        const double2 a = tileA[(int64_t)c * ld + r];
+        Xr[(c - 32 * h) * LDP + r] = a.x - pr;
+        Xi[(c - 32 * h) * LDP + r] = a.y - pi;
+      });
     }
+    for (int e = threadIdx.x; e < 32 * 64; e += NT) {
+      const int kk = e >> 6, col = e & 63;
+      const double2 v = tileL[(int64_t)(32 * h + kk) * ld + col];
+      Lr[kk * LDP + col] = v.x;
+      Li[kk * LDP + col] = v.y;
+    }
+    __syncthreads();
+    lds_abh(Xr, Xi, Lr, Li, 32, y);
   }
   double2* out = Z + (int64_t)(j * TB) * ld + i * TB;
   acc_for_each(y, [&](int r, int c, double vr, double vi) { out[(int64_t)c * ld + r] = make_double2(vr, vi); });
+
+  if (tile != 0 || i >= nvb) return;   // uniform per workgroup
+  // ---- lookahead: diagonal block i
+  const int64_t gc = C.cell_ids[cell];
+  __syncthreads();
+  acc_zero(acc);
+  gemm_abh(Z + i * TB, Z + i * TB, ld, j * TB, st, acc);
+  __syncthreads();
+  double* Yr = smem;
+  double* Yi = Yr + 64 * LDP;
+  acc_for_each(y, [&](int r, int c, double vr, double vi) {
+    Yr[c * LDP + r] = vr;
+    Yi[c * LDP + r] = vi;
+  });
+  __syncthreads();
+  lds_abh(Yr, Yi, Yr, Yi, 64, acc);
+  __syncthreads();
+  double* Cr = smem;
+  double* Ci = Cr + 64 * 65;
+  double* Yd = Ci + 64 * 65;
+  __shared__ double s_inv;
+  __shared__ int s_fail;
+  double2* tileD = Z + (int64_t)(i * TB) * ld + i * TB;
+  acc_for_each(acc, [&](int r, int c, double pr, double pi) {
+    if (c <= r) {
+      const double2 a = tileD[(int64_t)c * ld + r];
+      Cr[r * 65 + c] = a.x - pr;
+      Ci[r * 65 + c] = a.y - pi;
+    }
+  });
+  __syncthreads();
+  tile_chol_inv(Cr, Ci, Yd, &s_fail, &s_inv);
+  store_linv(Cr, Ci, Yd, tileD, ld);
+  if (threadIdx.x == 0 && s_fail && C.info[gc] == 0) C.info[gc] = i * TB + s_fail;
+  (void)lane;
 }
 
 // ================================================================ K_aug = W^H W
-__global__ __launch_bounds__(NT) void k_herk(DevTables T, ChunkArgs C) {
+__global__ __launch_bounds__(NT, 2) void k_herk(DevTables T, ChunkArgs C) {
   const int kb = T.kp / TB;
   const int ntiles = kb * (kb + 1) / 2;
   int64_t cell;
@@ -1106,7 +1226,7 @@ hipError_t launch_formation(const DevTables& t, const ProbArgs& pa, const ChunkA
   if (ca.n <= 0) return hipSuccess;
   const size_t sm = scale_smem(t);
   DPG_LAUNCH(KC_SCALE, prof, st, k_cell_scale, dim3((unsigned)ca.n), dim3(NT), sm, st, t, pa, ca);
-  DPG_LAUNCH(KC_FORM_SM, prof, st, k_form_SM, dim3(grid_cells_tiles(ca.n, t.n_sm_tiles)), dim3(NT), sm, st, t, pa,
+  DPG_LAUNCH(KC_FORM_SM, prof, st, k_form_SM, dim3(grid_cells_tiles(ca.n, t.n_sm_tiles)), dim3(NT), 0, st, t, pa,
              ca);
   const int nt = (t.Np + 63) / 64;
   DPG_LAUNCH(KC_FORM_IF, prof, st, k_form_IF, dim3(grid_cells_tiles(ca.n, nt * nt)), dim3(NT), 0, st, t, pa, ca);
@@ -1125,13 +1245,10 @@ hipError_t launch_formation(const DevTables& t, const ProbArgs& pa, const ChunkA
 hipError_t launch_factor(const DevTables& t, const ChunkArgs& ca, hipStream_t st, Prof* prof) {
   if (ca.n <= 0) return hipSuccess;
   const int nvb = t.nvp / TB, nrb = t.nrows / TB;
-  const size_t sm_diag = sizeof(double) * 4 * 64 * 65;
-  const size_t sm_panel = sizeof(PanelSmem) > 2 * sizeof(Stage) ? sizeof(PanelSmem) : 2 * sizeof(Stage);
-  for (int j = 0; j < nvb; ++j) {
-    DPG_LAUNCH(KC_CHOL_DIAG, prof, st, k_chol_diag, dim3((unsigned)ca.n), dim3(NT), sm_diag, st, t, ca, j);
-    DPG_LAUNCH(KC_CHOL_PANEL, prof, st, k_chol_panel, dim3(grid_cells_tiles(ca.n, nrb - j - 1)), dim3(NT), sm_panel,
-               st, t, ca, j);
-  }
+  DPG_LAUNCH(KC_CHOL_DIAG, prof, st, k_chol_diag0, dim3((unsigned)ca.n), dim3(NT), kFactorSmem, st, t, ca);
+  for (int j = 0; j < nvb; ++j)
+    DPG_LAUNCH(KC_CHOL_PANEL, prof, st, k_chol_step, dim3(grid_cells_tiles(ca.n, nrb - j - 1)), dim3(NT),
+               kFactorSmem, st, t, ca, j);
   return hipGetLastError();
 }
 
@@ -1161,8 +1278,8 @@ hipError_t configure_kernels() {
   int optin = 0;
   e = hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev);
   if (e != hipSuccess) return e;
-  const void* fns[] = {reinterpret_cast<const void*>(&k_chol_diag), reinterpret_cast<const void*>(&k_chol_panel),
-                       reinterpret_cast<const void*>(&k_cell_scale), reinterpret_cast<const void*>(&k_form_SM),
+  const void* fns[] = {reinterpret_cast<const void*>(&k_chol_diag0), reinterpret_cast<const void*>(&k_chol_step),
+                       reinterpret_cast<const void*>(&k_cell_scale),
                        reinterpret_cast<const void*>(&k_form_B), reinterpret_cast<const void*>(&k_herk)};
   for (const void* f : fns) {
     hipFuncAttributes fa;
