@@ -122,6 +122,11 @@ void build_group(DegreeGroup& g, int dp) {
   t.kp = d.kp;
   t.nvp = d.nvp;
   t.nrows = d.nrows;
+  // Padded strides: columns and cells would otherwise sit at power-of-two
+  // distances (16 KiB, multiples of 2 MiB), which maps concurrent tiles onto
+  // the same HBM channels.
+  t.ldz = d.nrows + 4;
+  t.zstride = t.ldz * d.nvp + 36;
   t.vol_w = upload(g.bufs, rt.vol_w);
   t.vol_pts = upload(g.bufs, rt.vol_pts);
   t.vol_v = upload(g.bufs, rt.vol_v);
@@ -259,11 +264,11 @@ dpg_status dpg_plan_create(int32_t device, const int8_t* degree_host, int64_t n_
     size_t zmax = 0, dmax = 0, mmax = 0;
     for (auto& g : P->groups) {
       const int64_t mper = 12 * (int64_t)g.d.nq + 36 * (int64_t)g.d.nfq;
-      const int64_t per = (int64_t)g.d.nrows * g.d.nvp * 16 + (int64_t)g.d.nvp * 8 + mper * 8;
+      const int64_t per = g.dt.zstride * 16 + (int64_t)g.d.nvp * 8 + mper * 8;
       int64_t ch = std::max<int64_t>(1, budget / per);
       ch = std::min<int64_t>(ch, (int64_t)g.cells.size());
       g.chunk = ch;
-      zmax = std::max(zmax, (size_t)ch * g.d.nrows * g.d.nvp * 16);
+      zmax = std::max(zmax, (size_t)ch * g.dt.zstride * 16);
       dmax = std::max(dmax, (size_t)ch * g.d.nvp * 8);
       mmax = std::max(mmax, (size_t)(ch * mper * 8));
     }

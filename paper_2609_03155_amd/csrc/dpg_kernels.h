@@ -10,6 +10,8 @@ namespace dpg {
 // Device copies of the reference tables of one (p, dp) pair (see dpg_tables.h).
 struct DevTables {
   int p, dp, s, r, n1, nq, nfq, N, Np, nc, m1, nu, nt1, nt, k, kp, nvp, nrows;
+  int64_t ldz;             // leading dimension of a cell's workspace (nrows + 4: breaks power-of-two strides)
+  int64_t zstride;         // complex elements between consecutive cells' workspaces
   const double* vol_w;     // [nq]
   const double* vol_pts;   // [nq][3]
   const double* vol_v;     // [nq][Np]

@@ -5,8 +5,8 @@
 //   k_form_SM     G_FF, G_II from S, M (volume) and the Robin face mass
 //   k_form_IF     G_IF from the geometry-free C and Rt (Sec. 2.2 test norm)
 //   k_form_pad    identity/zero padding of the test space
-//   k_form_B      rows of B_f^H and l^H (Sec. 2.2 forms, entries of Sec. 2.3)
-//   k_resid       r = B_f x - l (Sec. 2.3, error representation)
+//   k_form_B      rows of B_f^H, l^H and r^H = (B_f x - l)^H (Sec. 2.2 forms,
+//                 entries of Sec. 2.3; r for the error representation)
 //   k_chol_diag / k_chol_panel   left-looking blocked Cholesky of the
 //                 augmented Hermitian matrix [[D G D, D B],[B^H D, 0]]: the
 //                 lower rows of its factor are W^H = (L^{-1} D B_f)^H
@@ -28,7 +28,8 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int NT = 256;   // threads per workgroup (4 wave64)
 constexpr int TB = 64;    // tile of the blocked factorisation
 constexpr int KC = 16;    // k-chunk staged through LDS
-constexpr int LDP = 66;   // LDS row pitch (doubles) of staged panels
+constexpr int LDP = 65;   // LDS row pitch (doubles) of staged panels: odd, so that
+                          // column-wise (transposed) writes hit distinct banks
 
 __device__ __forceinline__ int sym3(int a, int b) {
   // packed index of a symmetric 3x3: (0,0)(1,1)(2,2)(0,1)(0,2)(1,2)
@@ -271,8 +272,8 @@ __global__ __launch_bounds__(NT) void k_form_IF(DevTables T, ProbArgs P, ChunkAr
     zc[f] = make_double2(P.zinv[(gc * 6 + f) * 2], -P.zinv[(gc * 6 + f) * 2 + 1]);
   }
   const double* d = C.dscale + cell * (int64_t)T.nvp;
-  double2* Z = C.Z + cell * (int64_t)T.nrows * T.nvp;
-  const int64_t ld = T.nrows;
+  double2* Z = C.Z + cell * T.zstride;
+  const int64_t ld = T.ldz;
   const int il = threadIdx.x & 63;
   const int i = I0 + il;
   if (i >= T.Np) return;
@@ -304,8 +305,8 @@ __global__ __launch_bounds__(NT) void k_form_IF(DevTables T, ProbArgs P, ChunkAr
 __global__ __launch_bounds__(NT) void k_form_pad(DevTables T, ChunkArgs C) {
   const int64_t cell = blockIdx.x;
   if (cell >= C.n) return;
-  double2* Z = C.Z + cell * (int64_t)T.nrows * T.nvp;
-  const int64_t ld = T.nrows;
+  double2* Z = C.Z + cell * T.zstride;
+  const int64_t ld = T.ldz;
   const int npad = T.Np - T.N;
   for (int blk = 0; blk < 2; ++blk) {
     const int base = blk * T.Np;
@@ -327,7 +328,12 @@ __global__ __launch_bounds__(NT) void k_form_pad(DevTables T, ChunkArgs C) {
 //   B(F_i, Hhat_j) = sum_{f not Robin} T_f(i,j),  B(I_i, Ehat_j) = sum_f T_f(i,j),
 //   l(F_i) = - sum_port int psi_i . g dS.
 constexpr int BQC = 16;   // quadrature points per staged chunk
-__global__ __launch_bounds__(NT) void k_form_B(DevTables T, ProbArgs P, ChunkArgs C) {
+constexpr int BIT = 4;    // DG functions per thread and batch
+// Thread t owns test row il = t/4 of the tile and the DG functions / trace
+// functions m = t%4, t%4 + 4, ...; its share of (D B_f x) for its row is
+// accumulated in a fixed order and the four shares of a row are added in a
+// fixed order, so the residual row is bitwise reproducible.
+__global__ __launch_bounds__(NT, 2) void k_form_B(DevTables T, ProbArgs P, ChunkArgs C) {
   const int nrt = (T.Np + 63) / 64;
   int64_t cell;
   int tile;
@@ -335,14 +341,14 @@ __global__ __launch_bounds__(NT) void k_form_B(DevTables T, ProbArgs P, ChunkArg
   const int64_t gc = C.cell_ids[cell];
   const int i0 = tile * 64;
   __shared__ double sX[8][3];
-  __shared__ double sGeo[BQC][21];          // J (9), Ji (9), w det, w, (face: s)
+  __shared__ double sGeo[BQC][21];          // J (9), Ji (9), w det, w
   __shared__ double sP[BQC][64][3];         // w det (J^{-T} psi_hat_i)_c
   __shared__ double sQ[BQC][64][3];         // w (J chat_i)_c
-  __shared__ double2 sL[64];                // load vector l(F_i)
+  __shared__ double2 sRes[64][4][2];        // per-thread shares of (D B_f x): [row][share][F/I]
   extern __shared__ double smem[];
   double* sPhi = smem;                      // [BQC][m1]
   load_cell_vertices(P, gc, sX);
-  if (threadIdx.x < 64) sL[threadIdx.x] = make_double2(0.0, 0.0);
+  const double2* xc = C.x ? C.x + C.v_off[gc] : nullptr;
   int8_t fk[6];
   double2 zf[6];
   int nrobin = 0;
@@ -356,15 +362,18 @@ __global__ __launch_bounds__(NT) void k_form_B(DevTables T, ProbArgs P, ChunkArg
   const double2 mu = make_double2(P.mu[2 * gc], P.mu[2 * gc + 1]);
   const double om = P.omega;
   const double* d = C.dscale + cell * (int64_t)T.nvp;
-  double2* Z = C.Z + cell * (int64_t)T.nrows * T.nvp;
-  const int64_t ld = T.nrows;
+  double2* Z = C.Z + cell * T.zstride;
+  const int64_t ld = T.ldz;
   const int nvp = T.nvp;
   const int m1 = T.m1;
-  const int nitems = 64 * m1;
-  // item = il * m1 + m ; processed in batches of up to 8 items per thread
-  for (int ib = 0; ib < nitems; ib += NT * 8) {
-    double D[8][3], R[8][3], Dtr[8][3], Dti[8][3];
-    for (int u = 0; u < 8; ++u)
+  const int il = threadIdx.x >> 2, sub = threadIdx.x & 3;
+  const int i = i0 + il;
+  const bool inrange = i < T.Np, ok = i < T.N;
+  const double dF = inrange ? d[i] : 0.0, dI = inrange ? d[T.Np + i] : 0.0;
+  double2 rF = make_double2(0.0, 0.0), rI = rF;
+  for (int ib = 0; ib < m1; ib += 4 * BIT) {
+    double D[BIT][3], R[BIT][3], Dtr[BIT][3], Dti[BIT][3];
+    for (int u = 0; u < BIT; ++u)
       for (int c = 0; c < 3; ++c) D[u][c] = R[u][c] = Dtr[u][c] = Dti[u][c] = 0.0;
     // ---- volume quadrature
     for (int q0 = 0; q0 < T.nq; q0 += BQC) {
@@ -384,23 +393,22 @@ __global__ __launch_bounds__(NT) void k_form_B(DevTables T, ProbArgs P, ChunkArg
       for (int e = threadIdx.x; e < nqc * m1; e += NT) sPhi[e] = T.vol_phi[(size_t)(q0 + e / m1) * m1 + e % m1];
       __syncthreads();
       for (int e = threadIdx.x; e < nqc * 64; e += NT) {
-        const int qq = e / 64, il = e % 64;
-        const int i = min(i0 + il, T.N - 1);
+        const int qq = e / 64, jl = e % 64;
+        const int ii = min(i0 + jl, T.N - 1);
         const int q = q0 + qq;
-        const int a = T.comp[i];
-        const double v = T.vol_v[(size_t)q * T.Np + i];
-        const double* c = &T.vol_c[((size_t)q * T.Np + i) * 3];
+        const int a = T.comp[ii];
+        const double v = T.vol_v[(size_t)q * T.Np + ii];
+        const double* c = &T.vol_c[((size_t)q * T.Np + ii) * 3];
         const double* G = sGeo[qq];
         for (int cc = 0; cc < 3; ++cc) {
-          sP[qq][il][cc] = G[18] * G[9 + a * 3 + cc] * v;                     // (J^{-T})_{c a} = Ji[a][c]
-          sQ[qq][il][cc] = G[19] * (G[cc * 3] * c[0] + G[cc * 3 + 1] * c[1] + G[cc * 3 + 2] * c[2]);
+          sP[qq][jl][cc] = G[18] * G[9 + a * 3 + cc] * v;                     // (J^{-T})_{c a} = Ji[a][c]
+          sQ[qq][jl][cc] = G[19] * (G[cc * 3] * c[0] + G[cc * 3 + 1] * c[1] + G[cc * 3 + 2] * c[2]);
         }
       }
       __syncthreads();
-      for (int u = 0; u < 8; ++u) {
-        const int it = ib + u * NT + threadIdx.x;
-        if (it >= nitems) break;
-        const int il = it / m1, m = it % m1;
+      for (int u = 0; u < BIT; ++u) {
+        const int m = ib + sub + 4 * u;
+        if (m >= m1) break;
         for (int qq = 0; qq < nqc; ++qq) {
           const double ph = sPhi[qq * m1 + m];
           for (int cc = 0; cc < 3; ++cc) {
@@ -422,9 +430,9 @@ __global__ __launch_bounds__(NT) void k_form_B(DevTables T, ProbArgs P, ChunkArg
             const double* xi = &T.face_pts[(f * T.nfq + fq) * 3];
             Geo g;
             trilinear(sX, xi[0], xi[1], xi[2], g);
-            double n[3], s;
-            face_normal(g, f, n, s);
-            const double ws = T.face_w[f * T.nfq + fq] * s;
+            double n[3], sa;
+            face_normal(g, f, n, sa);
+            const double ws = T.face_w[f * T.nfq + fq] * sa;
             // tangential part of the rows of J^{-1}: t_a = r_a - (r_a . n) n
             for (int a = 0; a < 3; ++a) {
               const double rn = g.Ji[a][0] * n[0] + g.Ji[a][1] * n[1] + g.Ji[a][2] * n[2];
@@ -435,17 +443,16 @@ __global__ __launch_bounds__(NT) void k_form_B(DevTables T, ProbArgs P, ChunkArg
             sPhi[e] = T.face_phi[((size_t)f * T.nfq + q0 + e / m1) * m1 + e % m1];
           __syncthreads();
           for (int e = threadIdx.x; e < nqc * 64; e += NT) {
-            const int qq = e / 64, il = e % 64;
-            const int i = min(i0 + il, T.N - 1);
-            const int a = T.comp[i];
-            const double v = T.face_v[((size_t)f * T.nfq + q0 + qq) * T.Np + i];
-            for (int cc = 0; cc < 3; ++cc) sP[qq][il][cc] = v * sGeo[qq][a * 3 + cc];
+            const int qq = e / 64, jl = e % 64;
+            const int ii = min(i0 + jl, T.N - 1);
+            const int a = T.comp[ii];
+            const double v = T.face_v[((size_t)f * T.nfq + q0 + qq) * T.Np + ii];
+            for (int cc = 0; cc < 3; ++cc) sP[qq][jl][cc] = v * sGeo[qq][a * 3 + cc];
           }
           __syncthreads();
-          for (int u = 0; u < 8; ++u) {
-            const int it = ib + u * NT + threadIdx.x;
-            if (it >= nitems) break;
-            const int il = it / m1, m = it % m1;
+          for (int u = 0; u < BIT; ++u) {
+            const int m = ib + sub + 4 * u;
+            if (m >= m1) break;
             for (int qq = 0; qq < nqc; ++qq) {
               const double ph = sPhi[qq * m1 + m];
               for (int cc = 0; cc < 3; ++cc) {
@@ -458,62 +465,89 @@ __global__ __launch_bounds__(NT) void k_form_B(DevTables T, ProbArgs P, ChunkArg
         }
       }
     }
-    // ---- write the interior-unknown rows of (D B_f)^H
-    for (int u = 0; u < 8; ++u) {
-      const int it = ib + u * NT + threadIdx.x;
-      if (it >= nitems) break;
-      const int il = it / m1, m = it % m1;
-      const int i = i0 + il;
-      if (i >= T.Np) continue;
-      const bool ok = i < T.N;
-      const double dF = d[i], dI = d[T.Np + i];
-      for (int cc = 0; cc < 3; ++cc) {
-        const int rowE = nvp + cc * m1 + m, rowH = nvp + (3 + cc) * m1 + m;
-        double2 bFE = make_double2(0, 0), bFH = bFE, bIE = bFE, bIH = bFE;
-        if (ok) {
-          // B(F,E) = i w eps D - z Dt  -> conj = -i w conj(eps) D - conj(z Dt)
-          const double2 fe = make_double2(-om * eps.y * D[u][cc] - Dtr[u][cc], om * eps.x * D[u][cc] - Dti[u][cc]);
-          bFE = make_double2(dF * fe.x, -dF * fe.y);
-          bFH = make_double2(dF * R[u][cc], 0.0);
-          bIE = make_double2(dI * R[u][cc], 0.0);
-          // B(I,H) = -i w mu D -> conj = i w conj(mu) D = w (mu.y, mu.x) D
-          bIH = make_double2(dI * om * mu.y * D[u][cc], dI * om * mu.x * D[u][cc]);
+    // ---- write the interior-unknown rows of (D B_f)^H and accumulate D B_f x
+    if (inrange) {
+      for (int u = 0; u < BIT; ++u) {
+        const int m = ib + sub + 4 * u;
+        if (m >= m1) break;
+        for (int cc = 0; cc < 3; ++cc) {
+          const int rowE = nvp + cc * m1 + m, rowH = nvp + (3 + cc) * m1 + m;
+          double2 bFE = make_double2(0, 0), bFH = bFE, bIE = bFE, bIH = bFE;
+          if (ok) {
+            // B(F,E) = i w eps D - z Dt  -> stored conj(dF B)
+            const double2 fe =
+                make_double2(-om * eps.y * D[u][cc] - Dtr[u][cc], om * eps.x * D[u][cc] - Dti[u][cc]);
+            bFE = make_double2(dF * fe.x, -dF * fe.y);
+            bFH = make_double2(dF * R[u][cc], 0.0);
+            bIE = make_double2(dI * R[u][cc], 0.0);
+            // B(I,H) = -i w mu D -> conj = i w conj(mu) D = w (mu.y, mu.x) D
+            bIH = make_double2(dI * om * mu.y * D[u][cc], dI * om * mu.x * D[u][cc]);
+          }
+          Z[(int64_t)i * ld + rowE] = bFE;
+          Z[(int64_t)i * ld + rowH] = bFH;
+          Z[(int64_t)(T.Np + i) * ld + rowE] = bIE;
+          Z[(int64_t)(T.Np + i) * ld + rowH] = bIH;
+          if (xc && ok) {
+            // (d B x) += conj(stored) x
+            const double2 xe = xc[rowE - nvp], xh = xc[rowH - nvp];
+            rF.x += bFE.x * xe.x + bFE.y * xe.y + bFH.x * xh.x + bFH.y * xh.y;
+            rF.y += bFE.x * xe.y - bFE.y * xe.x + bFH.x * xh.y - bFH.y * xh.x;
+            rI.x += bIE.x * xe.x + bIE.y * xe.y + bIH.x * xh.x + bIH.y * xh.y;
+            rI.y += bIE.x * xe.y - bIE.y * xe.x + bIH.x * xh.y - bIH.y * xh.x;
+          }
         }
-        Z[(int64_t)i * ld + rowE] = bFE;
-        Z[(int64_t)i * ld + rowH] = bFH;
-        Z[(int64_t)(T.Np + i) * ld + rowE] = bIE;
-        Z[(int64_t)(T.Np + i) * ld + rowH] = bIH;
       }
     }
   }
   // ---- trace unknowns (real, geometry free)
-  for (int e = threadIdx.x; e < 64 * T.nt1; e += NT) {
-    const int il = e / T.nt1, jt = e % T.nt1;
-    const int i = i0 + il;
-    if (i >= T.Np) continue;
-    double tI = 0.0, tF = 0.0;
-    if (i < T.N) {
-      for (int f = 0; f < 6; ++f) {
-        const double t = T.T[((size_t)f * T.N + i) * T.nt1 + jt];
-        tI += t;
-        if (!is_robin(fk[f])) tF += t;
+  if (inrange) {
+    for (int jt = sub; jt < T.nt1; jt += 4) {
+      double tI = 0.0, tF = 0.0;
+      if (ok) {
+        for (int f = 0; f < 6; ++f) {
+          const double t = T.T[((size_t)f * T.N + i) * T.nt1 + jt];
+          tI += t;
+          if (!is_robin(fk[f])) tF += t;
+        }
+      }
+      const int rowEh = nvp + T.nu + jt, rowHh = nvp + T.nu + T.nt1 + jt;
+      const double tf = dF * tF, ti = dI * tI;
+      Z[(int64_t)i * ld + rowEh] = make_double2(0.0, 0.0);
+      Z[(int64_t)i * ld + rowHh] = make_double2(tf, 0.0);
+      Z[(int64_t)(T.Np + i) * ld + rowEh] = make_double2(ti, 0.0);
+      Z[(int64_t)(T.Np + i) * ld + rowHh] = make_double2(0.0, 0.0);
+      if (xc && ok) {
+        const double2 xe = xc[T.nu + jt], xh = xc[T.nu + T.nt1 + jt];
+        rF.x += tf * xh.x;
+        rF.y += tf * xh.y;
+        rI.x += ti * xe.x;
+        rI.y += ti * xe.y;
       }
     }
-    const int rowEh = nvp + T.nu + jt, rowHh = nvp + T.nu + T.nt1 + jt;
-    Z[(int64_t)i * ld + rowEh] = make_double2(0.0, 0.0);
-    Z[(int64_t)i * ld + rowHh] = make_double2(d[i] * tF, 0.0);
-    Z[(int64_t)(T.Np + i) * ld + rowEh] = make_double2(d[T.Np + i] * tI, 0.0);
-    Z[(int64_t)(T.Np + i) * ld + rowHh] = make_double2(0.0, 0.0);
   }
-  // (the port load vector is formed by k_form_load)
-  // ---- padding rows of the RHS block and zero load/residual rows
+  sRes[il][sub][0] = rF;
+  sRes[il][sub][1] = rI;
+  __syncthreads();
+  // ---- padding rows of the RHS block, zero load row, residual row conj(D B_f x)
+  // (k_form_load subtracts the load on port cells)
   for (int e = threadIdx.x; e < 64 * (T.kp - T.k); e += NT) {
-    const int il = e % 64, rr = e / 64;
-    const int i = i0 + il;
-    if (i >= T.Np) continue;
+    const int jl = e % 64, rr = e / 64;
+    const int ii = i0 + jl;
+    if (ii >= T.Np) continue;
     const int row = nvp + T.k + rr;
-    Z[(int64_t)i * ld + row] = make_double2(0.0, 0.0);
-    Z[(int64_t)(T.Np + i) * ld + row] = make_double2(0.0, 0.0);
+    double2 vF = make_double2(0.0, 0.0), vI = vF;
+    if (rr == 1) {
+      for (int q = 0; q < 4; ++q) {
+        vF.x += sRes[jl][q][0].x;
+        vF.y += sRes[jl][q][0].y;
+        vI.x += sRes[jl][q][1].x;
+        vI.y += sRes[jl][q][1].y;
+      }
+      vF.y = -vF.y;
+      vI.y = -vI.y;
+    }
+    Z[(int64_t)ii * ld + row] = vF;
+    Z[(int64_t)(T.Np + ii) * ld + row] = vI;
   }
 }
 
@@ -585,41 +619,10 @@ __global__ __launch_bounds__(NT) void k_form_load(DevTables T, ProbArgs P, Chunk
   }
   if (threadIdx.x < 64 && i < T.N) {
     const double* d = C.dscale + cell * (int64_t)T.nvp;
-    double2* Z = C.Z + cell * (int64_t)T.nrows * T.nvp;
-    Z[(int64_t)i * T.nrows + T.nvp + T.k] = make_double2(d[i] * acc.x, -d[i] * acc.y);
-  }
-}
-
-// r~_i = sum_a B~(i,a) x_a - l~_i for every test row i, from the conj-stored
-// RHS rows; one wave per test row, lanes striding over the unknowns.
-__global__ __launch_bounds__(NT) void k_resid(DevTables T, ChunkArgs C) {
-  const int per = NT / 64;
-  const int nb = (T.nvp + per - 1) / per;
-  int64_t cell;
-  int tile;
-  if (!decode_cell_tile(C.n, nb, cell, tile)) return;
-  const int64_t gc = C.cell_ids[cell];
-  const int col = tile * per + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (col >= T.nvp) return;
-  const double2* x = C.x + C.v_off[gc];
-  const double2* Zc = C.Z + cell * (int64_t)T.nrows * T.nvp + (int64_t)col * T.nrows + T.nvp;
-  double2 acc = make_double2(0.0, 0.0);
-  for (int a = lane; a < T.k; a += 64) {
-    const double2 b = cconj(Zc[a]);
-    const double2 xv = x[a];
-    acc.x += b.x * xv.x - b.y * xv.y;
-    acc.y += b.x * xv.y + b.y * xv.x;
-  }
-  for (int o = 32; o > 0; o >>= 1) {
-    acc.x += __shfl_xor(acc.x, o);
-    acc.y += __shfl_xor(acc.y, o);
-  }
-  if (lane == 0) {
-    const double2 lv = cconj(Zc[T.k]);
-    // store conj(r~)
-    C.Z[cell * (int64_t)T.nrows * T.nvp + (int64_t)col * T.nrows + T.nvp + T.k + 1] =
-        make_double2(acc.x - lv.x, -(acc.y - lv.y));
+    double2* Z = C.Z + cell * T.zstride;
+    double2* zc = Z + (int64_t)i * T.ldz + T.nvp + T.k;
+    zc[0] = make_double2(d[i] * acc.x, -d[i] * acc.y);           // conj(d l)
+    if (C.x) zc[1] = make_double2(zc[1].x - d[i] * acc.x, zc[1].y + d[i] * acc.y);   // conj(d (B x - l))
   }
 }
 
@@ -645,44 +648,60 @@ __device__ inline void acc_zero(Acc& c) {
     }
 }
 
+// Operand kinds of a tile product: both complex, complex x real (B exactly
+// real), real x real.  Rows of the factor that belong to the F test block are
+// exactly real (G_FF is real), so products with such rows skip the MFMAs
+// whose operands are exact zeros.
+enum { MM_CC = 0, MM_CR = 1, MM_RR = 2 };
+
+// One k-step of 4 for the wave's 2x2 blocks: re += Ar Br + Ai Bi, im += Ai Br - Ar Bi.
+template <int MODE>
+__device__ __forceinline__ void cmfma_step(const double* ar, const double* ai, const double* br, const double* bi,
+                                           Acc& c) {
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) c.re[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[u], br[v], c.re[u][v], 0, 0, 0);
+  if (MODE == MM_RR) return;
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) c.im[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[u], br[v], c.im[u][v], 0, 0, 0);
+  if (MODE == MM_CR) return;
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) c.re[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[u], bi[v], c.re[u][v], 0, 0, 0);
+  double nar[2] = {-ar[0], -ar[1]};
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) c.im[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(nar[u], bi[v], c.im[u][v], 0, 0, 0);
+}
+
+template <int MODE>
 __device__ inline void stage_compute(const Stage& s, Acc& c) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = w & 1, wc = w >> 1;
 #pragma unroll
   for (int ks = 0; ks < KC / 4; ++ks) {
     const int kk = ks * 4 + (lane >> 4);
-    double ar[2], ai[2], nar[2], br[2], bi[2];
+    double ar[2], ai[2] = {0.0, 0.0}, br[2], bi[2] = {0.0, 0.0};
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int row = wr * 32 + u * 16 + (lane & 15);
       ar[u] = s.Are[kk][row];
-      ai[u] = s.Aim[kk][row];
-      nar[u] = -ar[u];
+      if (MODE != MM_RR) ai[u] = s.Aim[kk][row];
       const int col = wc * 32 + u * 16 + (lane & 15);
       br[u] = s.Bre[kk][col];
-      bi[u] = s.Bim[kk][col];
+      if (MODE == MM_CC) bi[u] = s.Bim[kk][col];
     }
-    // A conj(B)^T: re += Ar Br + Ai Bi ; im += Ai Br - Ar Bi
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-      for (int v = 0; v < 2; ++v) c.re[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[u], br[v], c.re[u][v], 0, 0, 0);
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-      for (int v = 0; v < 2; ++v) c.im[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[u], br[v], c.im[u][v], 0, 0, 0);
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-      for (int v = 0; v < 2; ++v) c.re[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[u], bi[v], c.re[u][v], 0, 0, 0);
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-      for (int v = 0; v < 2; ++v) c.im[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(nar[u], bi[v], c.im[u][v], 0, 0, 0);
+    cmfma_step<MODE>(ar, ai, br, bi, c);
   }
 }
 
 // P += A[rowA:rowA+64, 0:K] * B[rowB:rowB+64, 0:K]^H ; A, B column-major with leading dim ld.
+template <int MODE = MM_CC>
 __device__ inline void gemm_abh(const double2* __restrict__ A, const double2* __restrict__ B, int64_t ld, int K,
                                 Stage* st, Acc& c) {
   if (K <= 0) return;
@@ -701,9 +720,9 @@ __device__ inline void gemm_abh(const double2* __restrict__ A, const double2* __
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       s.Are[lc * 4 + u][lr] = ra[u].x;
-      s.Aim[lc * 4 + u][lr] = ra[u].y;
+      if (MODE != MM_RR) s.Aim[lc * 4 + u][lr] = ra[u].y;
       s.Bre[lc * 4 + u][lr] = rb[u].x;
-      s.Bim[lc * 4 + u][lr] = rb[u].y;
+      if (MODE == MM_CC) s.Bim[lc * 4 + u][lr] = rb[u].y;
     }
   };
   gload(0);
@@ -713,7 +732,7 @@ __device__ inline void gemm_abh(const double2* __restrict__ A, const double2* __
   for (int sidx = 0; sidx < nst; ++sidx) {
     const bool more = sidx + 1 < nst;
     if (more) gload((sidx + 1) * KC);
-    stage_compute(st[sidx & 1], c);
+    stage_compute<MODE>(st[sidx & 1], c);
     if (more) lstore(st[(sidx + 1) & 1]);
     __syncthreads();
   }
@@ -875,8 +894,8 @@ __global__ __launch_bounds__(NT, 2) void k_form_SM(DevTables T, ProbArgs P, Chun
   const double cF = om2 * (eps.x * eps.x + eps.y * eps.y) + P.alpha;
   const double cI = om2 * (mu.x * mu.x + mu.y * mu.y) + P.alpha;
   const double* d = C.dscale + cell * (int64_t)T.nvp;
-  double2* Z = C.Z + cell * (int64_t)T.nrows * T.nvp;
-  const int64_t ld = T.nrows;
+  double2* Z = C.Z + cell * T.zstride;
+  const int64_t ld = T.ldz;
   // combine per item (same lane mapping for all four accumulators)
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = w & 1, wc = w >> 1;
@@ -899,39 +918,24 @@ __global__ __launch_bounds__(NT, 2) void k_form_SM(DevTables T, ProbArgs P, Chun
 // ================================================================ Cholesky
 // Product of two LDS-resident operands, P += A B^H over K columns: A and B
 // are stored as [k][row] planes (row pitch LDP), the same convention as Stage.
+template <int MODE = MM_CC>
 __device__ inline void lds_abh(const double* Ar, const double* Ai, const double* Br, const double* Bi, int K,
                                Acc& c) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = w & 1, wc = w >> 1;
   for (int ks = 0; ks < K / 4; ++ks) {
     const int kk = ks * 4 + (lane >> 4);
-    double ar[2], ai[2], nar[2], br[2], bi[2];
+    double ar[2], ai[2] = {0.0, 0.0}, br[2], bi[2] = {0.0, 0.0};
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int row = wr * 32 + u * 16 + (lane & 15);
       ar[u] = Ar[kk * LDP + row];
-      ai[u] = Ai[kk * LDP + row];
-      nar[u] = -ar[u];
+      if (MODE != MM_RR) ai[u] = Ai[kk * LDP + row];
       const int col = wc * 32 + u * 16 + (lane & 15);
       br[u] = Br[kk * LDP + col];
-      bi[u] = Bi[kk * LDP + col];
+      if (MODE == MM_CC) bi[u] = Bi[kk * LDP + col];
     }
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-      for (int v = 0; v < 2; ++v) c.re[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[u], br[v], c.re[u][v], 0, 0, 0);
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-      for (int v = 0; v < 2; ++v) c.im[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[u], br[v], c.im[u][v], 0, 0, 0);
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-      for (int v = 0; v < 2; ++v) c.re[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[u], bi[v], c.re[u][v], 0, 0, 0);
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-      for (int v = 0; v < 2; ++v) c.im[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(nar[u], bi[v], c.im[u][v], 0, 0, 0);
+    cmfma_step<MODE>(ar, ai, br, bi, c);
   }
 }
 
@@ -941,9 +945,10 @@ __device__ inline void lds_abh(const double* Ar, const double* Ai, const double*
 //   X Linv^H in k-halves    Xr, Xi [32][LDP] (k = column of X), Lr, Li [32][LDP]
 //   Y Y^H (lookahead)       Yr, Yi [64][LDP]
 //   Cholesky + inverse      Cr, Ci [64][65], Yd [64]
-constexpr size_t kFactorSmem = 2 * sizeof(Stage) > 4 * 32 * LDP * 8 ? 2 * sizeof(Stage) : 4 * 32 * LDP * 8;
-static_assert(2 * 64 * LDP * 8 <= kFactorSmem, "LDS plan");
-static_assert(2 * 64 * 65 * 8 + 64 * 8 <= kFactorSmem, "LDS plan");
+constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
+constexpr size_t kFactorSmem =
+    cmax(cmax(2 * sizeof(Stage), 4 * 32 * LDP * 8), cmax(2 * 64 * LDP * 8, 2 * 64 * 65 * 8 + 64 * 8));
+static_assert(kFactorSmem <= 80 * 1024, "two factorisation workgroups must fit one CU");
 
 // In-place Cholesky and inverse of the 64x64 Hermitian tile held (lower part)
 // in Cr/Ci[r*65+q]: on exit the lower part holds L and the strict upper part
@@ -1032,8 +1037,8 @@ __global__ __launch_bounds__(NT) void k_chol_diag0(DevTables T, ChunkArgs C) {
   double* Yd = Ci + 64 * 65;
   __shared__ double s_inv;
   __shared__ int s_fail;
-  const int64_t ld = T.nrows;
-  double2* tile = C.Z + cell * (int64_t)T.nrows * T.nvp;
+  const int64_t ld = T.ldz;
+  double2* tile = C.Z + cell * T.zstride;
   for (int e = threadIdx.x; e < 64 * 64; e += NT) {
     const int q = e >> 6, r = e & 63;
     if (q <= r) {
@@ -1056,20 +1061,42 @@ __global__ __launch_bounds__(NT) void k_chol_diag0(DevTables T, ChunkArgs C) {
 __global__ __launch_bounds__(NT, 2) void k_chol_step(DevTables T, ChunkArgs C, int j) {
   const int nrb = T.nrows / TB, nvb = T.nvp / TB;
   const int ntiles = nrb - j - 1;
+  // Workgroup ids [0, n8) carry the lookahead tile (tile 0) of every cell and
+  // are dispatched first, spread over all CUs (cell c on XCD c % 8); the other
+  // tiles follow with the usual XCD-aware (cell, tile) decode.  Interleaving
+  // the costlier lookahead tiles with a fixed period would pile them onto the
+  // same few CUs whenever the period divides the XCD's dispatch order.
+  const int64_t n8 = (C.n + 7) / 8 * 8;
   int64_t cell;
   int tile;
-  if (!decode_cell_tile(C.n, ntiles, cell, tile)) return;
+  if ((int64_t)blockIdx.x < n8) {
+    cell = blockIdx.x;
+    tile = 0;
+    if (cell >= C.n) return;
+  } else {
+    const int64_t w = (int64_t)blockIdx.x - n8;
+    const int64_t slot = w >> 3;
+    const int64_t cl = slot / (ntiles - 1);
+    tile = 1 + (int)(slot - cl * (ntiles - 1));
+    cell = cl * 8 + (w & 7);
+    if (cell >= C.n) return;
+  }
   const int i = j + 1 + tile;
   extern __shared__ double smem[];
   Stage* st = reinterpret_cast<Stage*>(smem);
-  const int64_t ld = T.nrows;
-  double2* Z = C.Z + cell * (int64_t)T.nrows * T.nvp;
+  const int64_t ld = T.ldz;
+  double2* Z = C.Z + cell * T.zstride;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wc = w >> 1;
 
+  // rows of tile i (resp. j) lie in the F test block and are exactly real?
+  const bool ireal = (i + 1) * TB <= T.Np, jreal = (j + 1) * TB <= T.Np;
+  const int mode = ireal ? MM_RR : (jreal ? MM_CR : MM_CC);
   Acc acc;
   acc_zero(acc);
-  gemm_abh(Z + i * TB, Z + j * TB, ld, j * TB, st, acc);
+  if (mode == MM_RR) gemm_abh<MM_RR>(Z + i * TB, Z + j * TB, ld, j * TB, st, acc);
+  else if (mode == MM_CR) gemm_abh<MM_CR>(Z + i * TB, Z + j * TB, ld, j * TB, st, acc);
+  else gemm_abh<MM_CC>(Z + i * TB, Z + j * TB, ld, j * TB, st, acc);
   // X = A_ij - P ; Y = X Linv_jj^H, in two k-halves through LDS
   double* Xr = smem;
   double* Xi = Xr + 32 * LDP;
@@ -1095,7 +1122,12 @@ __global__ __launch_bounds__(NT, 2) void k_chol_step(DevTables T, ChunkArgs C, i
       Li[kk * LDP + col] = v.y;
     }
     __syncthreads();
-    lds_abh(Xr, Xi, Lr, Li, 32, y);
+    // Linv_jj is lower triangular: columns c < 32 receive nothing from k >= 32
+    if (!(h == 1 && wc == 0)) {
+      if (mode == MM_RR) lds_abh<MM_RR>(Xr, Xi, Lr, Li, 32, y);
+      else if (mode == MM_CR) lds_abh<MM_CR>(Xr, Xi, Lr, Li, 32, y);
+      else lds_abh<MM_CC>(Xr, Xi, Lr, Li, 32, y);
+    }
   }
   double2* out = Z + (int64_t)(j * TB) * ld + i * TB;
   acc_for_each(y, [&](int r, int c, double vr, double vi) { out[(int64_t)c * ld + r] = make_double2(vr, vi); });
@@ -1105,7 +1137,8 @@ __global__ __launch_bounds__(NT, 2) void k_chol_step(DevTables T, ChunkArgs C, i
   const int64_t gc = C.cell_ids[cell];
   __syncthreads();
   acc_zero(acc);
-  gemm_abh(Z + i * TB, Z + i * TB, ld, j * TB, st, acc);
+  if (ireal) gemm_abh<MM_RR>(Z + i * TB, Z + i * TB, ld, j * TB, st, acc);
+  else gemm_abh<MM_CC>(Z + i * TB, Z + i * TB, ld, j * TB, st, acc);
   __syncthreads();
   double* Yr = smem;
   double* Yi = Yr + 64 * LDP;
@@ -1114,7 +1147,8 @@ __global__ __launch_bounds__(NT, 2) void k_chol_step(DevTables T, ChunkArgs C, i
     Yi[c * LDP + r] = vi;
   });
   __syncthreads();
-  lds_abh(Yr, Yi, Yr, Yi, 64, acc);
+  if (ireal) lds_abh<MM_RR>(Yr, Yi, Yr, Yi, 64, acc);
+  else lds_abh<MM_CC>(Yr, Yi, Yr, Yi, 64, acc);
   __syncthreads();
   double* Cr = smem;
   double* Ci = Cr + 64 * 65;
@@ -1150,8 +1184,8 @@ __global__ __launch_bounds__(NT, 2) void k_herk(DevTables T, ChunkArgs C) {
   const int64_t gc = C.cell_ids[cell];
   extern __shared__ double smem[];
   Stage* st = reinterpret_cast<Stage*>(smem);
-  const int64_t ld = T.nrows;
-  const double2* Z = C.Z + cell * (int64_t)T.nrows * T.nvp;
+  const int64_t ld = T.ldz;
+  const double2* Z = C.Z + cell * T.zstride;
   Acc acc;
   acc_zero(acc);
   gemm_abh(Z + T.nvp + a * TB, Z + T.nvp + b * TB, ld, T.nvp, st, acc);
@@ -1180,8 +1214,8 @@ __global__ __launch_bounds__(NT) void k_extract(DevTables T, ChunkArgs C, double
   if (cell >= C.n) return;
   const int nv = 2 * T.N;
   const double* d = C.dscale + cell * (int64_t)T.nvp;
-  const double2* Z = C.Z + cell * (int64_t)T.nrows * T.nvp;
-  const int64_t ld = T.nrows;
+  const double2* Z = C.Z + cell * T.zstride;
+  const int64_t ld = T.ldz;
   auto zrow = [&](int i) { return i < T.N ? i : T.Np + (i - T.N); };
   const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
   const int64_t nG = (int64_t)nv * nv, nB = (int64_t)nv * T.k;
@@ -1235,10 +1269,6 @@ hipError_t launch_formation(const DevTables& t, const ProbArgs& pa, const ChunkA
              st, t, pa, ca);
   DPG_LAUNCH(KC_FORM_LOAD, prof, st, k_form_load, dim3(grid_cells_tiles(ca.n, nt)), dim3(NT),
              sizeof(double2) * 3 * t.nfq, st, t, pa, ca);
-  if (ca.x) {
-    const int nb = (t.nvp + 3) / 4;
-    DPG_LAUNCH(KC_RESID, prof, st, k_resid, dim3(grid_cells_tiles(ca.n, nb)), dim3(NT), 0, st, t, ca);
-  }
   return hipGetLastError();
 }
 
