@@ -87,6 +87,7 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--precision", default="both", choices=["both", "fp64", "split"])
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -113,24 +114,32 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    for _ in range(args.warmup):
-        plan.local_solve(prob, xd, K, l, eta, info, stream=stream)
-    torch.cuda.synchronize()
-    plan.profile()                       # discard
-    plan.set_profiling(True)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.steps):
-        plan.local_solve(prob, xd, K, l, eta, info, stream=stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    plan.set_profiling(False)
-    ms = e0.elapsed_time(e1)
-    prof = plan.profile()
-    ms_step = ms / args.steps
+    def timed(precision):
+        for _ in range(args.warmup):
+            plan.local_solve(prob, xd, K, l, eta, info, precision=precision, stream=stream)
+        torch.cuda.synchronize()
+        plan.profile()                       # discard
+        plan.set_profiling(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            plan.local_solve(prob, xd, K, l, eta, info, precision=precision, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        plan.set_profiling(False)
+        ms = e0.elapsed_time(e1)
+        prof = plan.profile()
+        outs = (K.cpu().numpy(), l.cpu().numpy(), eta.cpu().numpy(), info.cpu().numpy())
+        return ms / args.steps, prof, outs
+
+    precisions = {"fp64": dpg.DPG_FP64, "split": dpg.DPG_SPLIT_FP32}
+    if args.precision != "both":
+        precisions = {args.precision: precisions[args.precision]}
+    runs = {name: timed(code) for name, code in precisions.items()}
+    head = "split" if "split" in runs else "fp64"
+    ms_step, prof, (Kh, lh, eh, info_h) = runs[head]
     value = w.n_cells / (ms_step * 1e-3)
-    info_h = info.cpu().numpy()
 
     # roofline of the dominant kernel class, from the live per-launch event timings
     fl = {}
@@ -138,35 +147,31 @@ def main():
         cnt = int(np.sum(w.degree == p))
         for key, v in algorithmic_flops(p, w.dp).items():
             fl[key] = fl.get(key, 0.0) + v * cnt
-    cls_flops = {"chol_panel": None, "herk": fl["herk"] + fl["vec"]}
-    # the factorisation sweep = k_chol_diag + k_chol_panel (Cholesky of G and W = L^{-1} B_f)
-    fac_ms = prof["chol_diag"][0] + prof["chol_panel"][0]
-    fac_launches = prof["chol_diag"][1] + prof["chol_panel"][1]
+    form_keys = ("scale", "form_SM", "form_IF", "form_pad", "form_B", "form_load")
     classes = {k: v for k, v in prof.items() if v[1] > 0}
     dominant = max(classes, key=lambda k: classes[k][0])
     if dominant in ("chol_diag", "chol_panel"):
-        dom_name = "chol_diag+chol_panel (blocked Cholesky + TRSM sweep)"
+        dom_name = "chol_diag+chol_panel (blocked Cholesky + TRSM sweep, FP64)"
         dom_flops = (fl["chol"] + fl["trsm"]) * args.steps
-        dom_ms = fac_ms
-        dom_launches = fac_launches
+        dom_ms = prof["chol_diag"][0] + prof["chol_panel"][0]
+        dom_launches = prof["chol_diag"][1] + prof["chol_panel"][1]
     elif dominant == "herk":
-        dom_name = "herk (K_e = W^H W, l_e, eta)"
-        dom_flops = cls_flops["herk"] * args.steps
-        dom_ms = prof["herk"][0]
-        dom_launches = prof["herk"][1]
+        dom_name = "herk (K_e = W^H W, l_e)"
+        dom_flops = (fl["herk"] + fl["vec"]) * args.steps
+        dom_ms, dom_launches = prof["herk"]
     else:
-        dom_name = dominant
+        dom_name = "formation"
         dom_flops = fl["form"] * args.steps
-        dom_ms = sum(prof[k][0] for k in ("scale", "form_SM", "form_IF", "form_pad", "form_B", "form_load"))
-        dom_launches = sum(prof[k][1] for k in ("scale", "form_SM", "form_IF", "form_pad", "form_B", "form_load"))
+        dom_ms = sum(prof[k][0] for k in form_keys)
+        dom_launches = sum(prof[k][1] for k in form_keys)
     achieved = dom_flops / (dom_ms * 1e-3) / 1e12
     total_alg = sum(fl.values())
     rec = {
         "metric": METRIC, "value": value, "unit": "elements/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f64+bf16x3" if head == "split" else "f64", "data": "synthetic",
         "config": {"workload": w.name, "cells": w.n_cells, "degrees": sorted(set(int(v) for v in w.degree)),
-                   "dp": w.dp, "freq_hz": w.freq_hz, "precision": "fp64", "parallelism": "single-gpu"},
+                   "dp": w.dp, "freq_hz": w.freq_hz, "precision": head, "parallelism": "single-gpu"},
         "roofline": {"bound": "mfma", "kernel": dom_name, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
                      "launches_per_step": dom_launches / args.steps,
@@ -175,20 +180,28 @@ def main():
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items() if v[1]},
         "failed_cells": int(np.sum(info_h != 0)),
     }
+    for name, (ms_n, prof_n, _) in runs.items():
+        rec[f"{name}_path"] = {"value": w.n_cells / (ms_n * 1e-3), "ms_per_step": ms_n,
+                               "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof_n.items() if v[1]}}
+    if "split" in runs and "fp64" in runs:
+        rec["speedup_split_vs_fp64"] = runs["fp64"][0] / runs["split"][0]
     if not args.no_cpu_baseline:
         base, outs = cpu_baseline(w, args.cpu_budget)
         rec["cpu_baseline"] = base
-        Kh, lh, eh = K.cpu().numpy(), l.cpu().numpy(), eta.cpu().numpy()
-        eK, el, ee = [], [], []
-        for c, (Ko, lo, eo) in outs.items():
-            k = int(off[c + 1] - off[c])
-            Kg = Kh[plan.K_off[c]:plan.K_off[c + 1]].reshape(k, k).T
-            eK.append(np.linalg.norm(Kg - Ko) / np.linalg.norm(Ko))
-            el.append(np.linalg.norm(lh[off[c]:off[c + 1]] - lo) / max(np.linalg.norm(lo), 1e-300))
-            ee.append(abs(eh[c] - eo) / eo)
-        rec["rel_err_vs_oracle"] = {"cells": len(outs), "K_e_max": float(np.max(eK)),
-                                    "K_e_median": float(np.median(eK)), "l_e_max": float(np.max(el)),
-                                    "eta_max": float(np.max(ee))}
+        errs = {}
+        for name, (_, _, (Kn, ln, en, _)) in runs.items():
+            eK, el, ee = [], [], []
+            for c, (Ko, lo, eo) in outs.items():
+                k = int(off[c + 1] - off[c])
+                Kg = Kn[plan.K_off[c]:plan.K_off[c + 1]].reshape(k, k).T
+                eK.append(np.linalg.norm(Kg - Ko) / np.linalg.norm(Ko))
+                if np.linalg.norm(lo) > 0:
+                    el.append(np.linalg.norm(ln[off[c]:off[c + 1]] - lo) / np.linalg.norm(lo))
+                ee.append(abs(en[c] - eo) / eo)
+            errs[name] = {"cells": len(outs), "K_e_max": float(np.max(eK)), "K_e_median": float(np.median(eK)),
+                          "l_e_max": float(np.max(el)) if el else None, "l_e_cells": len(el),
+                          "eta_max": float(np.max(ee))}
+        rec["rel_err_vs_oracle"] = errs
     print(json.dumps(rec), flush=True)
 
 

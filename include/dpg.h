@@ -82,7 +82,10 @@ typedef enum {
 
 typedef enum {
   DPG_FP64 = 0,              /* every step in FP64 */
-  DPG_SPLIT_FP32 = 1         /* reserved: split-FP32 contractions, FP64 Cholesky and eta */
+  DPG_SPLIT_FP32 = 1         /* split precision: formation, Cholesky and triangular solves in
+                                FP64; K_e = W^H W and l_e = W^H y from a three-term bf16 split of
+                                W (about 24 significant bits per operand, FP32 accumulation folded
+                                into FP64 every 64 terms) on bf16 MFMA; eta by an FP64 reduction */
 } dpg_precision;
 
 enum {
@@ -159,7 +162,7 @@ dpg_status dpg_plan_layout(dpg_plan plan, int32_t p, int64_t* n_test_padded, int
  *   l    [v_off[n]][2]  l_e per cell (output),
  *   eta  [n]            residual indicator per cell (output),
  *   info [n]            per-cell status (output, see above).
- * precision must be DPG_FP64 in this build (DPG_ERR_UNSUPPORTED otherwise).
+ * precision: DPG_FP64 or DPG_SPLIT_FP32 (DPG_ERR_ARG otherwise).
  * stream is a hipStream_t (NULL = the default stream). */
 dpg_status dpg_local_solve(dpg_plan plan, const dpg_problem* prob, const double* x, double* K,
                            double* l, double* eta, int32_t* info, int32_t precision, void* stream);

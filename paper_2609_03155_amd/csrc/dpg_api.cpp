@@ -42,6 +42,7 @@ struct dpg_plan_s {
   double2* Z = nullptr;
   double* dscale = nullptr;
   double* met = nullptr;
+  uint16_t* wsplit = nullptr;
   std::vector<void*> misc;            // other device allocations
   dpg::Prof prof;
 };
@@ -160,6 +161,7 @@ void free_plan(dpg_plan_s* p) {
   if (p->Z) (void)hipFree(p->Z);
   if (p->dscale) (void)hipFree(p->dscale);
   if (p->met) (void)hipFree(p->met);
+  if (p->wsplit) (void)hipFree(p->wsplit);
   delete p;
 }
 
@@ -261,16 +263,18 @@ dpg_status dpg_plan_create(int32_t device, const int8_t* degree_host, int64_t n_
     size_t free_b = 0, total_b = 0;
     HIP_CHECK(hipMemGetInfo(&free_b, &total_b));
     int64_t budget = max_workspace_bytes > 0 ? max_workspace_bytes : (int64_t)(0.4 * (double)free_b);
-    size_t zmax = 0, dmax = 0, mmax = 0;
+    size_t zmax = 0, dmax = 0, mmax = 0, smax = 0;
     for (auto& g : P->groups) {
       const int64_t mper = 12 * (int64_t)g.d.nq + 36 * (int64_t)g.d.nfq;
-      const int64_t per = g.dt.zstride * 16 + (int64_t)g.d.nvp * 8 + mper * 8;
+      const int64_t sper = dpg::split_elems(g.dt);
+      const int64_t per = g.dt.zstride * 16 + (int64_t)g.d.nvp * 8 + mper * 8 + sper * 2;
       int64_t ch = std::max<int64_t>(1, budget / per);
       ch = std::min<int64_t>(ch, (int64_t)g.cells.size());
       g.chunk = ch;
       zmax = std::max(zmax, (size_t)ch * g.dt.zstride * 16);
       dmax = std::max(dmax, (size_t)ch * g.d.nvp * 8);
       mmax = std::max(mmax, (size_t)(ch * mper * 8));
+      smax = std::max(smax, (size_t)(ch * sper * 2));
     }
     if (zmax) {
       if (hipMalloc(reinterpret_cast<void**>(&P->Z), zmax) != hipSuccess) {
@@ -278,7 +282,8 @@ dpg_status dpg_plan_create(int32_t device, const int8_t* degree_host, int64_t n_
         return DPG_ERR_ALLOC;
       }
       if (hipMalloc(reinterpret_cast<void**>(&P->dscale), dmax) != hipSuccess ||
-          hipMalloc(reinterpret_cast<void**>(&P->met), mmax) != hipSuccess) {
+          hipMalloc(reinterpret_cast<void**>(&P->met), mmax) != hipSuccess ||
+          hipMalloc(reinterpret_cast<void**>(&P->wsplit), smax) != hipSuccess) {
         free_plan(P);
         return DPG_ERR_ALLOC;
       }
@@ -327,7 +332,7 @@ dpg_status dpg_plan_layout(dpg_plan plan, int32_t p, int64_t* n_test_padded, int
 dpg_status dpg_local_solve(dpg_plan plan, const dpg_problem* prob, const double* x, double* K, double* l,
                            double* eta, int32_t* info, int32_t precision, void* stream) {
   if (!plan || !K || !l || !eta || !info) return DPG_ERR_ARG;
-  if (precision != DPG_FP64) return precision == DPG_SPLIT_FP32 ? DPG_ERR_UNSUPPORTED : DPG_ERR_ARG;
+  if (precision != DPG_FP64 && precision != DPG_SPLIT_FP32) return DPG_ERR_ARG;
   dpg::ProbArgs pa;
   if (!make_prob_args(prob, pa) || prob->n_cells != plan->n_cells) return DPG_ERR_ARG;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -341,6 +346,8 @@ dpg_status dpg_local_solve(dpg_plan plan, const dpg_problem* prob, const double*
       ca.Z = plan->Z;
       ca.dscale = plan->dscale;
       ca.met = plan->met;
+      ca.wsplit = plan->wsplit;
+      ca.split = precision == DPG_SPLIT_FP32 ? 1 : 0;
       ca.K_off = plan->K_off_dev;
       ca.v_off = plan->v_off_dev;
       ca.x = reinterpret_cast<const double2*>(x);

@@ -51,6 +51,8 @@ struct ChunkArgs {
   double2* Z;                // [n][nvp cols][nrows] augmented lower factor, column-major
   double* dscale;            // [n][nvp] Jacobi scaling of the test rows
   double* met;               // [n][12 nq + 36 nfq] point metrics: volume Gc|Gm, Robin-face Q
+  uint16_t* wsplit;          // split path: [n][6][kp][nvp] bf16 planes of W^H (re0,re1,re2,im0,im1,im2)
+  int split;                 // 1: K_aug from the bf16 split planes, eta by an FP64 reduction
   const int64_t* K_off;      // [n_cells+1] global output offsets (complex elements)
   const int64_t* v_off;
   const double2* x;          // trial+trace coefficients, or null
@@ -96,6 +98,8 @@ hipError_t launch_formation(const DevTables& t, const ProbArgs& pa, const ChunkA
                             Prof* prof = nullptr);
 hipError_t launch_factor(const DevTables& t, const ChunkArgs& ca, hipStream_t st, Prof* prof = nullptr);
 hipError_t launch_herk(const DevTables& t, const ChunkArgs& ca, hipStream_t st, Prof* prof = nullptr);
+// bf16 planes per cell of the split path
+__host__ __device__ inline int64_t split_elems(const DevTables& t) { return 6 * (int64_t)t.kp * t.nvp; }
 // Raise the dynamic-LDS limit of the kernels that stage whole tiles (once per process).
 hipError_t configure_kernels();
 // Unscaled G, B_f, l of `n` cells into dense per-cell arrays (parity entry).

@@ -141,6 +141,24 @@ __device__ inline double2 cmul(double2 a, double2 b) {
 }
 __device__ inline double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 
+// bf16 bits of a float, round to nearest even (finite inputs).
+__device__ inline uint16_t f32_to_bf16_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ inline double bf16_bits_to_f64(uint16_t h) { return (double)__uint_as_float((uint32_t)h << 16); }
+
+// v ~ h0 + h1 + h2 with bf16 terms: each term captures the remainder of the
+// previous ones (about 24 significant bits in total).
+__device__ inline void split3_bf16(double v, uint16_t h[3]) {
+  double rem = v;
+  for (int t = 0; t < 3; ++t) {
+    h[t] = f32_to_bf16_bits((float)rem);
+    rem -= bf16_bits_to_f64(h[t]);
+  }
+}
+
 // TE_mn fields of Sec. 4.1 at non-dimensional point x.
 __device__ inline void te_fields(const ProbArgs& P, double omega, const double x[3], double2 E[3], double2 H[3]) {
   const double c1 = cos(P.pk1 * x[0]), s1 = sin(P.pk1 * x[0]);
@@ -373,7 +391,9 @@ __global__ __launch_bounds__(NT, 2) void k_form_B(DevTables T, ProbArgs P, Chunk
   double2 rF = make_double2(0.0, 0.0), rI = rF;
   for (int ib = 0; ib < m1; ib += 4 * BIT) {
     double D[BIT][3], R[BIT][3], Dtr[BIT][3], Dti[BIT][3];
+#pragma unroll
     for (int u = 0; u < BIT; ++u)
+#pragma unroll
       for (int c = 0; c < 3; ++c) D[u][c] = R[u][c] = Dtr[u][c] = Dti[u][c] = 0.0;
     // ---- volume quadrature
     for (int q0 = 0; q0 < T.nq; q0 += BQC) {
@@ -406,15 +426,19 @@ __global__ __launch_bounds__(NT, 2) void k_form_B(DevTables T, ProbArgs P, Chunk
         }
       }
       __syncthreads();
-      for (int u = 0; u < BIT; ++u) {
-        const int m = ib + sub + 4 * u;
-        if (m >= m1) break;
-        for (int qq = 0; qq < nqc; ++qq) {
-          const double ph = sPhi[qq * m1 + m];
-          for (int cc = 0; cc < 3; ++cc) {
-            D[u][cc] += sP[qq][il][cc] * ph;
-            R[u][cc] += sQ[qq][il][cc] * ph;
-          }
+      for (int qq = 0; qq < nqc; ++qq) {
+        const double p0 = sP[qq][il][0], p1 = sP[qq][il][1], p2 = sP[qq][il][2];
+        const double q0v = sQ[qq][il][0], q1v = sQ[qq][il][1], q2v = sQ[qq][il][2];
+#pragma unroll
+        for (int u = 0; u < BIT; ++u) {
+          const int m = ib + sub + 4 * u;
+          const double ph = (m < m1) ? sPhi[qq * m1 + m] : 0.0;
+          D[u][0] += p0 * ph;
+          D[u][1] += p1 * ph;
+          D[u][2] += p2 * ph;
+          R[u][0] += q0v * ph;
+          R[u][1] += q1v * ph;
+          R[u][2] += q2v * ph;
         }
       }
     }
@@ -450,16 +474,18 @@ __global__ __launch_bounds__(NT, 2) void k_form_B(DevTables T, ProbArgs P, Chunk
             for (int cc = 0; cc < 3; ++cc) sP[qq][jl][cc] = v * sGeo[qq][a * 3 + cc];
           }
           __syncthreads();
-          for (int u = 0; u < BIT; ++u) {
-            const int m = ib + sub + 4 * u;
-            if (m >= m1) break;
-            for (int qq = 0; qq < nqc; ++qq) {
-              const double ph = sPhi[qq * m1 + m];
-              for (int cc = 0; cc < 3; ++cc) {
-                const double t = sP[qq][il][cc] * ph;
-                Dtr[u][cc] += zf[f].x * t;
-                Dti[u][cc] += zf[f].y * t;
-              }
+          for (int qq = 0; qq < nqc; ++qq) {
+            const double p0 = sP[qq][il][0], p1 = sP[qq][il][1], p2 = sP[qq][il][2];
+#pragma unroll
+            for (int u = 0; u < BIT; ++u) {
+              const int m = ib + sub + 4 * u;
+              const double ph = (m < m1) ? sPhi[qq * m1 + m] : 0.0;
+              Dtr[u][0] += zf[f].x * p0 * ph;
+              Dtr[u][1] += zf[f].x * p1 * ph;
+              Dtr[u][2] += zf[f].x * p2 * ph;
+              Dti[u][0] += zf[f].y * p0 * ph;
+              Dti[u][1] += zf[f].y * p1 * ph;
+              Dti[u][2] += zf[f].y * p2 * ph;
             }
           }
         }
@@ -467,9 +493,11 @@ __global__ __launch_bounds__(NT, 2) void k_form_B(DevTables T, ProbArgs P, Chunk
     }
     // ---- write the interior-unknown rows of (D B_f)^H and accumulate D B_f x
     if (inrange) {
+#pragma unroll
       for (int u = 0; u < BIT; ++u) {
         const int m = ib + sub + 4 * u;
-        if (m >= m1) break;
+        if (m >= m1) continue;
+#pragma unroll
         for (int cc = 0; cc < 3; ++cc) {
           const int rowE = nvp + cc * m1 + m, rowH = nvp + (3 + cc) * m1 + m;
           double2 bFE = make_double2(0, 0), bFH = bFE, bIE = bFE, bIH = bFE;
@@ -1131,6 +1159,26 @@ __global__ __launch_bounds__(NT, 2) void k_chol_step(DevTables T, ChunkArgs C, i
   }
   double2* out = Z + (int64_t)(j * TB) * ld + i * TB;
   acc_for_each(y, [&](int r, int c, double vr, double vi) { out[(int64_t)c * ld + r] = make_double2(vr, vi); });
+  if (C.split && i >= nvb) {
+    // final block (i, j) of W^H: three-term bf16 splits of re and im, [plane][row][k]
+    // layout [row][k / 32][plane][k % 32]: the six planes of a row's 32-column
+    // chunk are contiguous (384 B), planes re0, re1, re2, im0, im1, im2
+    uint16_t* wp = C.wsplit + cell * split_elems(T);
+    const int nkc = T.nvp / 32;
+    acc_for_each(y, [&](int r, int c, double vr, double vi) {
+      const int kk = j * TB + c;
+      const int64_t o = ((int64_t)((i - nvb) * TB + r) * nkc + kk / 32) * 192 + (kk % 32);
+      uint16_t h[3];
+      split3_bf16(vr, h);
+      wp[o] = h[0];
+      wp[o + 32] = h[1];
+      wp[o + 64] = h[2];
+      split3_bf16(vi, h);
+      wp[o + 96] = h[0];
+      wp[o + 128] = h[1];
+      wp[o + 160] = h[2];
+    });
+  }
 
   if (tile != 0 || i >= nvb) return;   // uniform per workgroup
   // ---- lookahead: diagonal block i
@@ -1204,6 +1252,202 @@ __global__ __launch_bounds__(NT, 2) void k_herk(DevTables T, ChunkArgs C) {
       C.eta[gc] = sqrt(fmax(vr, 0.0));
     }
   });
+}
+
+// ================================================================ split-precision K_aug
+// K_aug = W^H W from the three-term bf16 splits of W^H on bf16 MFMA
+// (v_mfma_f32_16x16x32_bf16): for each real product X Y^T the terms
+// X_s Y_t with s + t <= 2 are kept (six products, ~24-bit operands); the
+// FP32 accumulators are folded into FP64 every 64 columns.  eta is not taken
+// from here (FP64 reduction in k_eta).
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+constexpr int SKC = 32;              // k per stage
+constexpr int SPITCH = SKC + 8;      // bf16 row pitch in LDS (80 B: conflict-free 16-B row reads)
+
+struct SplitStage {
+  uint16_t A[6][64 * SPITCH];
+  uint16_t B[6][64 * SPITCH];
+};
+
+__device__ inline bf8 lds_frag(const uint16_t* plane, int row, int kq) {
+  const uint4 v = *reinterpret_cast<const uint4*>(plane + row * SPITCH + kq * 8);
+  return __builtin_bit_cast(bf8, v);
+}
+
+__device__ inline bf8 neg_frag(bf8 a) {
+  uint4 v = __builtin_bit_cast(uint4, a);
+  v.x ^= 0x80008000u;
+  v.y ^= 0x80008000u;
+  v.z ^= 0x80008000u;
+  v.w ^= 0x80008000u;
+  return __builtin_bit_cast(bf8, v);
+}
+
+__global__ __launch_bounds__(NT, 2) void k_herk_split(DevTables T, ChunkArgs C) {
+  const int kb = T.kp / TB;
+  const int ntiles = kb * (kb + 1) / 2;
+  int64_t cell;
+  int tile;
+  if (!decode_cell_tile(C.n, ntiles, cell, tile)) return;
+  int a = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
+  while ((a + 1) * (a + 2) / 2 <= tile) ++a;
+  while (a * (a + 1) / 2 > tile) --a;
+  const int b = tile - a * (a + 1) / 2;
+  const int64_t gc = C.cell_ids[cell];
+  extern __shared__ double smem[];
+  SplitStage* ss = reinterpret_cast<SplitStage*>(smem);
+  const uint16_t* wp = C.wsplit + cell * split_elems(T);
+  const int nkc = T.nvp / 32;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w & 1, wc = w >> 1;
+  // staging map: thread -> (row, 8-column chunk)
+  const int srow = threadIdx.x >> 2, skq = threadIdx.x & 3;
+  const uint16_t* pa = wp + (int64_t)(a * TB + srow) * nkc * 192 + skq * 8;
+  const uint16_t* pb = wp + (int64_t)(b * TB + srow) * nkc * 192 + skq * 8;
+  // prefetch registers (named individually: arrays of these were kept in scratch)
+  uint4 ra0, ra1, ra2, ra3, ra4, ra5, rb0, rb1, rb2, rb3, rb4, rb5;
+#define DPG_SPLIT_GLOAD(k0)                                                      \
+  do {                                                                           \
+    ra0 = *reinterpret_cast<const uint4*>(pa + (k0) * 6 + 0);                \
+    ra1 = *reinterpret_cast<const uint4*>(pa + (k0) * 6 + 32);                \
+    ra2 = *reinterpret_cast<const uint4*>(pa + (k0) * 6 + 64);                \
+    ra3 = *reinterpret_cast<const uint4*>(pa + (k0) * 6 + 96);                \
+    ra4 = *reinterpret_cast<const uint4*>(pa + (k0) * 6 + 128);                \
+    ra5 = *reinterpret_cast<const uint4*>(pa + (k0) * 6 + 160);                \
+    rb0 = *reinterpret_cast<const uint4*>(pb + (k0) * 6 + 0);                \
+    rb1 = *reinterpret_cast<const uint4*>(pb + (k0) * 6 + 32);                \
+    rb2 = *reinterpret_cast<const uint4*>(pb + (k0) * 6 + 64);                \
+    rb3 = *reinterpret_cast<const uint4*>(pb + (k0) * 6 + 96);                \
+    rb4 = *reinterpret_cast<const uint4*>(pb + (k0) * 6 + 128);                \
+    rb5 = *reinterpret_cast<const uint4*>(pb + (k0) * 6 + 160);                \
+  } while (0)
+#define DPG_SPLIT_LSTORE()                                                       \
+  do {                                                                           \
+    const int o_ = srow * SPITCH + skq * 8;                                      \
+    *reinterpret_cast<uint4*>(&ss->A[0][o_]) = ra0;                              \
+    *reinterpret_cast<uint4*>(&ss->A[1][o_]) = ra1;                              \
+    *reinterpret_cast<uint4*>(&ss->A[2][o_]) = ra2;                              \
+    *reinterpret_cast<uint4*>(&ss->A[3][o_]) = ra3;                              \
+    *reinterpret_cast<uint4*>(&ss->A[4][o_]) = ra4;                              \
+    *reinterpret_cast<uint4*>(&ss->A[5][o_]) = ra5;                              \
+    *reinterpret_cast<uint4*>(&ss->B[0][o_]) = rb0;                              \
+    *reinterpret_cast<uint4*>(&ss->B[1][o_]) = rb1;                              \
+    *reinterpret_cast<uint4*>(&ss->B[2][o_]) = rb2;                              \
+    *reinterpret_cast<uint4*>(&ss->B[3][o_]) = rb3;                              \
+    *reinterpret_cast<uint4*>(&ss->B[4][o_]) = rb4;                              \
+    *reinterpret_cast<uint4*>(&ss->B[5][o_]) = rb5;                              \
+  } while (0)
+  f4 fr[2][2], fi[2][2];
+  double dr[2][2][4], di[2][2][4];
+  for (int u = 0; u < 2; ++u)
+    for (int v = 0; v < 2; ++v) {
+      fr[u][v] = f4{0, 0, 0, 0};
+      fi[u][v] = f4{0, 0, 0, 0};
+      for (int e = 0; e < 4; ++e) dr[u][v][e] = di[u][v][e] = 0.0;
+    }
+  const int nst = T.nvp / SKC;
+  DPG_SPLIT_GLOAD(0);
+  for (int sidx = 0; sidx < nst; ++sidx) {
+    __syncthreads();
+    DPG_SPLIT_LSTORE();
+    __syncthreads();
+    if (sidx + 1 < nst) DPG_SPLIT_GLOAD((sidx + 1) * SKC);
+    const int kq = lane >> 4;
+    // B fragments of both column blocks once per stage; A per row block; the
+    // four accumulators of a row block alternate so that no MFMA waits on the
+    // previous one's result.
+    bf8 Br[2][3], Bi[2][3], nBi[2][3];
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const int brow = wc * 32 + v * 16 + (lane & 15);
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        Br[v][t] = lds_frag(ss->B[t], brow, kq);
+        Bi[v][t] = lds_frag(ss->B[3 + t], brow, kq);
+        nBi[v][t] = neg_frag(Bi[v][t]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int arow = wr * 32 + u * 16 + (lane & 15);
+      bf8 Ar[3], Ai[3];
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        Ar[t] = lds_frag(ss->A[t], arow, kq);
+        Ai[t] = lds_frag(ss->A[3 + t], arow, kq);
+      }
+      // re += Ar Br^T + Ai Bi^T ; im += Ai Br^T - Ar Bi^T   (terms with s + t <= 2)
+#pragma unroll
+      for (int s2 = 0; s2 < 3; ++s2)
+#pragma unroll
+        for (int t2 = 0; t2 + s2 < 3; ++t2) {
+#pragma unroll
+          for (int v = 0; v < 2; ++v) {
+            fr[u][v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ar[s2], Br[v][t2], fr[u][v], 0, 0, 0);
+            fi[u][v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ai[s2], Br[v][t2], fi[u][v], 0, 0, 0);
+          }
+#pragma unroll
+          for (int v = 0; v < 2; ++v) {
+            fr[u][v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ai[s2], Bi[v][t2], fr[u][v], 0, 0, 0);
+            fi[u][v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ar[s2], nBi[v][t2], fi[u][v], 0, 0, 0);
+          }
+        }
+    }
+    if ((sidx & 1) || sidx + 1 == nst) {
+      for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 2; ++v) {
+          for (int e = 0; e < 4; ++e) {
+            dr[u][v][e] += (double)fr[u][v][e];
+            di[u][v][e] += (double)fi[u][v][e];
+          }
+          fr[u][v] = f4{0, 0, 0, 0};
+          fi[u][v] = f4{0, 0, 0, 0};
+        }
+    }
+  }
+  const int k = T.k;
+  double2* K = C.K + C.K_off[gc];
+  double2* L = C.l + C.v_off[gc];
+  for (int u = 0; u < 2; ++u)
+    for (int v = 0; v < 2; ++v)
+      for (int e = 0; e < 4; ++e) {
+        // f32 16x16 accumulator layout: item e of lane l -> row 4(l>>4) + e, column l & 15
+        const int r = wr * 32 + u * 16 + 4 * (lane >> 4) + e, c = wc * 32 + v * 16 + (lane & 15);
+        const int al = a * TB + r, be = b * TB + c;
+        const double vr = dr[u][v][e], vi = di[u][v][e];
+        if (al < k && be < k) {
+          if (a == b && be > al) continue;
+          K[(int64_t)be * k + al] = make_double2(vr, vi);
+          if (al != be) K[(int64_t)al * k + be] = make_double2(vr, -vi);
+        } else if (al == k && be < k) {
+          L[be] = make_double2(vr, -vi);
+        }
+      }
+}
+
+#undef DPG_SPLIT_GLOAD
+#undef DPG_SPLIT_LSTORE
+
+// eta = ||L^{-1} D r|| in FP64: the residual row of W^H, reduced in a fixed order.
+__global__ __launch_bounds__(NT) void k_eta(DevTables T, ChunkArgs C) {
+  const int64_t cell = blockIdx.x;
+  if (cell >= C.n) return;
+  const int64_t gc = C.cell_ids[cell];
+  const double2* z = C.Z + cell * T.zstride + T.nvp + T.k + 1;
+  __shared__ double part[NT];
+  double s = 0.0;
+  for (int m = threadIdx.x; m < T.nvp; m += NT) {
+    const double2 v = z[(int64_t)m * T.ldz];
+    s += v.x * v.x + v.y * v.y;
+  }
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = NT / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) C.eta[gc] = sqrt(part[0]);
 }
 
 // ================================================================ parity extraction
@@ -1285,8 +1529,14 @@ hipError_t launch_factor(const DevTables& t, const ChunkArgs& ca, hipStream_t st
 hipError_t launch_herk(const DevTables& t, const ChunkArgs& ca, hipStream_t st, Prof* prof) {
   if (ca.n <= 0) return hipSuccess;
   const int kb = t.kp / TB;
-  DPG_LAUNCH(KC_HERK, prof, st, k_herk, dim3(grid_cells_tiles(ca.n, kb * (kb + 1) / 2)), dim3(NT),
-             2 * sizeof(Stage), st, t, ca);
+  if (ca.split) {
+    DPG_LAUNCH(KC_HERK, prof, st, k_herk_split, dim3(grid_cells_tiles(ca.n, kb * (kb + 1) / 2)), dim3(NT),
+               sizeof(SplitStage), st, t, ca);
+    DPG_LAUNCH(KC_RESID, prof, st, k_eta, dim3((unsigned)ca.n), dim3(NT), 0, st, t, ca);
+  } else {
+    DPG_LAUNCH(KC_HERK, prof, st, k_herk, dim3(grid_cells_tiles(ca.n, kb * (kb + 1) / 2)), dim3(NT),
+               2 * sizeof(Stage), st, t, ca);
+  }
   return hipGetLastError();
 }
 
@@ -1310,7 +1560,8 @@ hipError_t configure_kernels() {
   if (e != hipSuccess) return e;
   const void* fns[] = {reinterpret_cast<const void*>(&k_chol_diag0), reinterpret_cast<const void*>(&k_chol_step),
                        reinterpret_cast<const void*>(&k_cell_scale),
-                       reinterpret_cast<const void*>(&k_form_B), reinterpret_cast<const void*>(&k_herk)};
+                       reinterpret_cast<const void*>(&k_form_B), reinterpret_cast<const void*>(&k_herk),
+                       reinterpret_cast<const void*>(&k_herk_split)};
   for (const void* f : fns) {
     hipFuncAttributes fa;
     e = hipFuncGetAttributes(&fa, f);

@@ -244,6 +244,8 @@ def test_argument_errors_are_synchronous():
     with pytest.raises(dpg.DPGError):
         plan.local_solve(prob, None, K, l, eta, info, precision=7)
     with pytest.raises(dpg.DPGError):
+        plan.local_solve(prob, None, K, l, eta, info, precision=-1)
+    with pytest.raises(dpg.DPGError):
         plan.local_solve(prob, None, None, l, eta, info)
 
 
@@ -259,3 +261,47 @@ def test_empty_batch():
     _say("case: empty batch")
     plan.local_solve(prob, None, K, K, eta, info)
     torch.cuda.synchronize()
+
+
+# ------------------------------------------------------------ split precision
+SPLIT_TOL = 1e-6     # spec bar of the split path for K_e and l_e; eta stays FP64
+
+
+def _check_split(w, cells, plan, K, l, eta, x, off):
+    for c in cells:
+        Go, _, _, Ko, lo, eo = oracle_cell(w, c, x[off[c]:off[c + 1]])
+        Kg, lg = _cell_out(plan, K, l, c)
+        assert rel(Kg, Ko) < SPLIT_TOL, (c, rel(Kg, Ko))
+        if np.linalg.norm(lo) > 0:
+            assert rel(lg, lo) < SPLIT_TOL, (c, rel(lg, lo))
+        assert abs(eta[c] - eo) < fp64_tol(Go) * eo, (c, abs(eta[c] - eo) / eo)
+
+
+def test_split_precision_config1():
+    w = W.config1()
+    x, off = W.random_coefficients(w)
+    _say("case: dpg_local_solve split precision config1")
+    plan, K, l, eta, info = _run(w, x, precision=1)
+    assert np.all(info == 0)
+    _check_split(w, range(w.n_cells), plan, K, l, eta, x, off)
+
+
+def test_split_precision_config2_sampled():
+    w = W.config2()
+    x, off = W.random_coefficients(w)
+    _say("case: dpg_local_solve split precision config2 full (5120 cells)")
+    plan, K, l, eta, info = _run(w, x, precision=1)
+    assert np.all(info == 0)
+    rng = np.random.default_rng(W.SEED_BASE + 23)
+    _check_split(w, sorted(set([0, w.n_cells - 1] + list(rng.choice(w.n_cells, 4, replace=False)))), plan, K, l,
+                 eta, x, off)
+
+
+def test_split_precision_mixed_degrees():
+    w = W.config3(nx=3, ny=3, nz=4)
+    w.degree[:] = np.array([1, 2, 3, 4] * 9, np.int8)[: w.n_cells]
+    x, off = W.random_coefficients(w)
+    _say("case: dpg_local_solve split precision mixed p 1..4")
+    plan, K, l, eta, info = _run(w, x, precision=1)
+    assert np.all(info == 0)
+    _check_split(w, (0, 1, 2, 3), plan, K, l, eta, x, off)
