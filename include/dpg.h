@@ -167,6 +167,16 @@ dpg_status dpg_plan_layout(dpg_plan plan, int32_t p, int64_t* n_test_padded, int
 dpg_status dpg_local_solve(dpg_plan plan, const dpg_problem* prob, const double* x, double* K,
                            double* l, double* eta, int32_t* info, int32_t precision, void* stream);
 
+/* The local solve of the cells first .. first+count-1 only, for streaming
+ * through batches whose outputs do not fit in memory at once.  Output and
+ * coefficient pointers refer to the range: K_e of cell c starts at
+ * K + 2*(K_off[c] - K_off[first]) doubles, l_e and x of cell c at
+ * l + 2*(v_off[c] - v_off[first]), eta and info of cell c at index c - first.
+ * Same stream, precision and error behaviour as dpg_local_solve. */
+dpg_status dpg_local_solve_range(dpg_plan plan, const dpg_problem* prob, int64_t first, int64_t count,
+                                 const double* x, double* K, double* l, double* eta, int32_t* info,
+                                 int32_t precision, void* stream);
+
 /* Debug/parity entry: the unscaled local matrices of `count` consecutive
  * cells first, first+1, ... which must all have the plan's degree p.
  * Device outputs, complex, column-major per cell:

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <stdexcept>
@@ -329,20 +330,25 @@ dpg_status dpg_plan_layout(dpg_plan plan, int32_t p, int64_t* n_test_padded, int
   return DPG_ERR_ARG;
 }
 
-dpg_status dpg_local_solve(dpg_plan plan, const dpg_problem* prob, const double* x, double* K, double* l,
-                           double* eta, int32_t* info, int32_t precision, void* stream) {
-  if (!plan || !K || !l || !eta || !info) return DPG_ERR_ARG;
+dpg_status dpg_local_solve_range(dpg_plan plan, const dpg_problem* prob, int64_t first, int64_t count,
+                                 const double* x, double* K, double* l, double* eta, int32_t* info,
+                                 int32_t precision, void* stream) {
+  if (!plan || first < 0 || count < 0 || first + count > plan->n_cells) return DPG_ERR_ARG;
+  if (count > 0 && (!K || !l || !eta || !info)) return DPG_ERR_ARG;
   if (precision != DPG_FP64 && precision != DPG_SPLIT_FP32) return DPG_ERR_ARG;
   dpg::ProbArgs pa;
   if (!make_prob_args(prob, pa) || prob->n_cells != plan->n_cells) return DPG_ERR_ARG;
+  if (count == 0) return DPG_OK;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (hipSetDevice(plan->device) != hipSuccess) return DPG_ERR_HIP;
   for (auto& g : plan->groups) {
-    const int64_t cnt = (int64_t)g.cells.size();
-    for (int64_t s0 = 0; s0 < cnt; s0 += g.chunk) {
-      dpg::ChunkArgs ca;
+    // this degree's cells inside [first, first + count): a contiguous run of its sorted list
+    const int64_t lo = std::lower_bound(g.cells.begin(), g.cells.end(), first) - g.cells.begin();
+    const int64_t hi = std::lower_bound(g.cells.begin(), g.cells.end(), first + count) - g.cells.begin();
+    for (int64_t s0 = lo; s0 < hi; s0 += g.chunk) {
+      dpg::ChunkArgs ca{};
       ca.cell_ids = g.cells_dev + s0;
-      ca.n = std::min<int64_t>(g.chunk, cnt - s0);
+      ca.n = std::min<int64_t>(g.chunk, hi - s0);
       ca.Z = plan->Z;
       ca.dscale = plan->dscale;
       ca.met = plan->met;
@@ -350,6 +356,9 @@ dpg_status dpg_local_solve(dpg_plan plan, const dpg_problem* prob, const double*
       ca.split = precision == DPG_SPLIT_FP32 ? 1 : 0;
       ca.K_off = plan->K_off_dev;
       ca.v_off = plan->v_off_dev;
+      ca.cell_base = first;
+      ca.K_base = plan->K_off[first];
+      ca.v_base = plan->v_off[first];
       ca.x = reinterpret_cast<const double2*>(x);
       ca.K = reinterpret_cast<double2*>(K);
       ca.l = reinterpret_cast<double2*>(l);
@@ -366,6 +375,13 @@ dpg_status dpg_local_solve(dpg_plan plan, const dpg_problem* prob, const double*
     }
   }
   return DPG_OK;
+}
+
+dpg_status dpg_local_solve(dpg_plan plan, const dpg_problem* prob, const double* x, double* K, double* l,
+                           double* eta, int32_t* info, int32_t precision, void* stream) {
+  if (!plan) return DPG_ERR_ARG;
+  if (plan->n_cells > 0 && (!K || !l || !eta || !info)) return DPG_ERR_ARG;
+  return dpg_local_solve_range(plan, prob, 0, plan->n_cells, x, K, l, eta, info, precision, stream);
 }
 
 dpg_status dpg_plan_set_profiling(dpg_plan plan, int32_t enable) {

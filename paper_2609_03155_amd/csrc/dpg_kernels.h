@@ -55,6 +55,8 @@ struct ChunkArgs {
   int split;                 // 1: K_aug from the bf16 split planes, eta by an FP64 reduction
   const int64_t* K_off;      // [n_cells+1] global output offsets (complex elements)
   const int64_t* v_off;
+  int64_t cell_base;         // outputs are indexed relative to this cell (range solves)
+  int64_t K_base, v_base;    // K_off[cell_base], v_off[cell_base]
   const double2* x;          // trial+trace coefficients, or null
   double2* K;                // outputs
   double2* l;

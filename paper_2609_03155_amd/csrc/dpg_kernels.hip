@@ -267,7 +267,7 @@ __global__ __launch_bounds__(NT) void k_cell_scale(DevTables T, ProbArgs P, Chun
   // keep the point metrics for the formation kernels
   double* gm = C.met + cell * (int64_t)(12 * T.nq + 36 * T.nfq);
   for (int e = threadIdx.x; e < 12 * T.nq + 36 * T.nfq; e += NT) gm[e] = smem[e];
-  if (threadIdx.x == 0) C.info[gc] = s_bad ? -1 : 0;
+  if (threadIdx.x == 0) C.info[gc - C.cell_base] = s_bad ? -1 : 0;
 }
 
 // ================================================================ G_IF
@@ -366,7 +366,7 @@ __global__ __launch_bounds__(NT, 2) void k_form_B(DevTables T, ProbArgs P, Chunk
   extern __shared__ double smem[];
   double* sPhi = smem;                      // [BQC][m1]
   load_cell_vertices(P, gc, sX);
-  const double2* xc = C.x ? C.x + C.v_off[gc] : nullptr;
+  const double2* xc = C.x ? C.x + (C.v_off[gc] - C.v_base) : nullptr;
   int8_t fk[6];
   double2 zf[6];
   int nrobin = 0;
@@ -1078,7 +1078,7 @@ __global__ __launch_bounds__(NT) void k_chol_diag0(DevTables T, ChunkArgs C) {
   __syncthreads();
   tile_chol_inv(Cr, Ci, Yd, &s_fail, &s_inv);
   store_linv(Cr, Ci, Yd, tile, ld);
-  if (threadIdx.x == 0 && s_fail && C.info[gc] == 0) C.info[gc] = s_fail;
+  if (threadIdx.x == 0 && s_fail && C.info[gc - C.cell_base] == 0) C.info[gc - C.cell_base] = s_fail;
 }
 
 // Step j of the left-looking factorisation, one workgroup per row tile i > j:
@@ -1214,7 +1214,7 @@ __global__ __launch_bounds__(NT, 2) void k_chol_step(DevTables T, ChunkArgs C, i
   __syncthreads();
   tile_chol_inv(Cr, Ci, Yd, &s_fail, &s_inv);
   store_linv(Cr, Ci, Yd, tileD, ld);
-  if (threadIdx.x == 0 && s_fail && C.info[gc] == 0) C.info[gc] = i * TB + s_fail;
+  if (threadIdx.x == 0 && s_fail && C.info[gc - C.cell_base] == 0) C.info[gc - C.cell_base] = i * TB + s_fail;
   (void)lane;
 }
 
@@ -1238,8 +1238,8 @@ __global__ __launch_bounds__(NT, 2) void k_herk(DevTables T, ChunkArgs C) {
   acc_zero(acc);
   gemm_abh(Z + T.nvp + a * TB, Z + T.nvp + b * TB, ld, T.nvp, st, acc);
   const int k = T.k;
-  double2* K = C.K + C.K_off[gc];
-  double2* L = C.l + C.v_off[gc];
+  double2* K = C.K + (C.K_off[gc] - C.K_base);
+  double2* L = C.l + (C.v_off[gc] - C.v_base);
   acc_for_each(acc, [&](int r, int c, double vr, double vi) {
     const int al = a * TB + r, be = b * TB + c;
     if (al < k && be < k) {
@@ -1249,7 +1249,7 @@ __global__ __launch_bounds__(NT, 2) void k_herk(DevTables T, ChunkArgs C) {
     } else if (al == k && be < k) {
       L[be] = make_double2(vr, -vi);
     } else if (al == k + 1 && be == k + 1) {
-      C.eta[gc] = sqrt(fmax(vr, 0.0));
+      C.eta[gc - C.cell_base] = sqrt(fmax(vr, 0.0));
     }
   });
 }
@@ -1407,8 +1407,8 @@ __global__ __launch_bounds__(NT, 2) void k_herk_split(DevTables T, ChunkArgs C) 
     }
   }
   const int k = T.k;
-  double2* K = C.K + C.K_off[gc];
-  double2* L = C.l + C.v_off[gc];
+  double2* K = C.K + (C.K_off[gc] - C.K_base);
+  double2* L = C.l + (C.v_off[gc] - C.v_base);
   for (int u = 0; u < 2; ++u)
     for (int v = 0; v < 2; ++v)
       for (int e = 0; e < 4; ++e) {
@@ -1447,7 +1447,7 @@ __global__ __launch_bounds__(NT) void k_eta(DevTables T, ChunkArgs C) {
     if (threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) C.eta[gc] = sqrt(part[0]);
+  if (threadIdx.x == 0) C.eta[gc - C.cell_base] = sqrt(part[0]);
 }
 
 // ================================================================ parity extraction

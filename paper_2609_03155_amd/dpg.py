@@ -21,7 +21,7 @@ DPG_FP64, DPG_SPLIT_FP32 = 0, 1
 FACE_INTERIOR, FACE_PEC, FACE_PORT, FACE_ROBIN0 = 0, 1, 2, 3
 
 EXPORTS = ("dpg_local_dims", "dpg_plan_create", "dpg_plan_destroy", "dpg_plan_offsets", "dpg_plan_layout",
-           "dpg_local_solve", "dpg_form_local", "dpg_plan_set_profiling", "dpg_plan_profile", "dpg_status_string",
+           "dpg_local_solve", "dpg_local_solve_range", "dpg_form_local", "dpg_plan_set_profiling", "dpg_plan_profile", "dpg_status_string",
            "dpg_last_error")
 KERNEL_CLASSES = ("scale", "form_SM", "form_IF", "form_pad", "form_B", "form_load", "resid", "chol_diag",
                   "chol_panel", "herk")
@@ -60,6 +60,7 @@ def lib():
         L.dpg_plan_offsets.argtypes = [vp, vp, vp]
         L.dpg_plan_layout.argtypes = [vp, i32, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
         L.dpg_local_solve.argtypes = [vp, C.POINTER(dpg_problem), vp, vp, vp, vp, vp, i32, vp]
+        L.dpg_local_solve_range.argtypes = [vp, C.POINTER(dpg_problem), i64, i64, vp, vp, vp, vp, vp, i32, vp]
         L.dpg_form_local.argtypes = [vp, C.POINTER(dpg_problem), i64, i64, vp, vp, vp, vp, vp]
         L.dpg_plan_set_profiling.argtypes = [vp, i32]
         L.dpg_plan_profile.argtypes = [vp, vp, vp]
@@ -68,7 +69,8 @@ def lib():
         L.dpg_last_error.argtypes = []
         L.dpg_last_error.restype = C.c_char_p
         for name in ("dpg_local_dims", "dpg_plan_create", "dpg_plan_destroy", "dpg_plan_offsets",
-                     "dpg_plan_layout", "dpg_local_solve", "dpg_form_local", "dpg_plan_set_profiling",
+                     "dpg_plan_layout", "dpg_local_solve", "dpg_local_solve_range", "dpg_form_local",
+                     "dpg_plan_set_profiling",
                      "dpg_plan_profile"):
             getattr(L, name).restype = i32
         _lib = L
@@ -197,6 +199,18 @@ class Plan:
         s = prob.cstruct()
         _check(lib().dpg_local_solve(self._h, C.byref(s), _ptr(x), _ptr(K), _ptr(l), _ptr(eta), _ptr(info),
                                      int(precision), _stream(stream)), "dpg_local_solve")
+
+    def local_solve_range(self, prob: DeviceProblem, first: int, count: int, x, K, l, eta, info,
+                          precision: int = DPG_FP64, stream=None):
+        """dpg_local_solve_range: cells first..first+count-1, outputs relative to the range."""
+        s = prob.cstruct()
+        _check(lib().dpg_local_solve_range(self._h, C.byref(s), int(first), int(count), _ptr(x), _ptr(K), _ptr(l),
+                                           _ptr(eta), _ptr(info), int(precision), _stream(stream)),
+               "dpg_local_solve_range")
+
+    def range_sizes(self, first: int, count: int):
+        """(K elements, l/x elements) of the outputs of a range solve."""
+        return (int(self.K_off[first + count] - self.K_off[first]), int(self.v_off[first + count] - self.v_off[first]))
 
     def form_local(self, prob: DeviceProblem, first: int, count: int, stream=None):
         """dpg_form_local: unscaled G, B_f, l of cells first..first+count-1 (same degree)."""

@@ -203,6 +203,44 @@ def test_chunked_workspace_matches_single_chunk():
         assert np.array_equal(a, b)
 
 
+def test_range_solves_match_full_solve():
+    """dpg_local_solve_range over ragged consecutive ranges (mixed degrees,
+    one empty range) writes range-relative outputs that are bitwise equal to
+    the slices of one full solve, in both precisions."""
+    torch = _torch()
+    from paper_2609_03155_amd import dpg
+    w = W.config3(nx=3, ny=3, nz=4)
+    w.degree[:] = np.array([1, 2, 3, 4, 2, 1, 3] * 6, np.int8)[: w.n_cells]
+    x, off = W.random_coefficients(w)
+    plan = dpg.Plan(w.degree, w.dp)
+    prob = dpg.DeviceProblem.from_workload(w)
+    xd = torch.from_numpy(x).cuda()
+    bounds = [0, 5, 5, 17, 18, 36]
+    for precision in (dpg.DPG_FP64, dpg.DPG_SPLIT_FP32):
+        _say(f"case: range solves {bounds} precision {precision}")
+        K, l, eta, info = plan.alloc_outputs()
+        plan.local_solve(prob, xd, K, l, eta, info, precision)
+        torch.cuda.synchronize()
+        full = (K.cpu().numpy(), l.cpu().numpy(), eta.cpu().numpy(), info.cpu().numpy())
+        for a, b in zip(bounds[:-1], bounds[1:]):
+            nK, nv = plan.range_sizes(a, b - a)
+            Kr = torch.full((max(nK, 1),), float("nan"), dtype=torch.complex128, device="cuda")
+            lr = torch.full((max(nv, 1),), float("nan"), dtype=torch.complex128, device="cuda")
+            er = torch.full((max(b - a, 1),), float("nan"), dtype=torch.float64, device="cuda")
+            ir = torch.full((max(b - a, 1),), 99, dtype=torch.int32, device="cuda")
+            xr = torch.from_numpy(x[off[a]:off[b]].copy()).cuda()
+            plan.local_solve_range(prob, a, b - a, xr, Kr, lr, er, ir, precision)
+            torch.cuda.synchronize()
+            if b == a:
+                continue
+            assert np.array_equal(Kr.cpu().numpy()[:nK], full[0][plan.K_off[a]:plan.K_off[b]])
+            assert np.array_equal(lr.cpu().numpy()[:nv], full[1][plan.v_off[a]:plan.v_off[b]])
+            assert np.array_equal(er.cpu().numpy()[:b - a], full[2][a:b])
+            assert np.array_equal(ir.cpu().numpy()[:b - a], full[3][a:b])
+    with pytest.raises(dpg.DPGError):
+        plan.local_solve_range(prob, 30, 7, xd, K, l, eta, info)
+
+
 def test_repeat_is_bitwise_deterministic():
     w = W.config1()
     x, _ = W.random_coefficients(w)
