@@ -1081,40 +1081,231 @@ __global__ __launch_bounds__(NT) void k_chol_diag0(DevTables T, ChunkArgs C) {
   if (threadIdx.x == 0 && s_fail && C.info[gc - C.cell_base] == 0) C.info[gc - C.cell_base] = s_fail;
 }
 
-// Step j of the left-looking factorisation, one workgroup per row tile i > j:
+// ---------------------------------------------------------------- one wave, half a tile
+// Register-direct tile product for one wave, which owns the 32 rows
+// [32h, 32h + 32) of a 64x64 output tile: Q -= conj(B_j) A_i^T with B_j the
+// 64-row panel of the tile's columns and A_i the wave's 32 rows, over columns
+// [0, K) of the panels.  No LDS and no barriers: every operand goes from
+// memory to the MFMA source registers.  Block (u, v) of Q (u: rows from panel
+// j, v: rows from the wave's half of panel i) is one 16x16 f64 MFMA
+// accumulator; item t of lane l holds Q[16u + (l >> 4) + 4t][16v + (l & 15)].
+// With that layout item t is at once the B operand (k = row of Q) of a
+// following product  M Q, which is how the triangular epilogue consumes it
+// without a transpose.  Two waves per SIMD (256 registers each) hide each
+// other's load latency.
+struct WAcc {
+  d4 re[4][2], im[4][2];
+};
+
+struct WOps {
+  double2 a[2], b[4];
+};
+
+// Register buffers of the k-step pipeline (prefetch distance NB - 1): the
+// fewer MFMAs a k-step has, the deeper the prefetch; sized to what the
+// register file holds next to the accumulators without spilling.
+template <int MODE>
+struct WPipe {
+  static constexpr int NB = MODE == MM_RR ? 6 : (MODE == MM_CR ? 2 : 2);
+};
+
+template <int MODE>
+__device__ __forceinline__ void wave_load(const double2* __restrict__ Ai, const double2* __restrict__ Bj, int64_t ld,
+                                          int ks, WOps& o) {
+  const int lane = threadIdx.x & 63;
+  const int64_t off = (int64_t)(4 * ks + (lane >> 4)) * ld + (lane & 15);
+#pragma unroll
+  for (int v = 0; v < 2; ++v) {
+    if (MODE == MM_RR) o.a[v].x = reinterpret_cast<const double*>(Ai + off + 16 * v)[0];
+    else o.a[v] = Ai[off + 16 * v];
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    if (MODE == MM_CC) o.b[u] = Bj[off + 16 * u];
+    else o.b[u].x = reinterpret_cast<const double*>(Bj + off + 16 * u)[0];
+  }
+}
+
+// re -= br ar + bi ai,  im -= br ai - bi ar   (Q -= conj(b) a)
+template <int MODE>
+__device__ __forceinline__ void wave_step(const WOps& o, WAcc& q) {
+  double nbr[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) nbr[u] = -o.b[u].x;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) q.re[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(nbr[u], o.a[v].x, q.re[u][v], 0, 0, 0);
+  if (MODE == MM_RR) return;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) q.im[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(nbr[u], o.a[v].y, q.im[u][v], 0, 0, 0);
+  if (MODE == MM_CR) return;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const double nbi = -o.b[u].y;
+#pragma unroll
+    for (int v = 0; v < 2; ++v) q.re[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(nbi, o.a[v].y, q.re[u][v], 0, 0, 0);
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) q.im[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(o.b[u].y, o.a[v].x, q.im[u][v], 0, 0, 0);
+}
+
+// The steady-state loop has no branch in its unrolled body (loads past the
+// end re-read the last k-step), so the wait before each k-step leaves the
+// younger prefetches in flight; the last nks % NB k-steps, already loaded,
+// follow the loop.
+template <int MODE>
+__device__ __forceinline__ void wave_gemm_t(const double2* __restrict__ Ai, const double2* __restrict__ Bj, int64_t ld,
+                                            int K, WAcc& q) {
+  constexpr int NB = WPipe<MODE>::NB;
+  const int nks = K / 4;
+  if (nks <= 0) return;
+  const int nfull = nks - nks % NB;
+  WOps o[NB];
+#pragma unroll
+  for (int s = 0; s < NB - 1; ++s) wave_load<MODE>(Ai, Bj, ld, min(s, nks - 1), o[s]);
+  for (int k0 = 0; k0 < nfull; k0 += NB) {
+#pragma unroll
+    for (int s = 0; s < NB; ++s) {
+      wave_load<MODE>(Ai, Bj, ld, min(k0 + s + NB - 1, nks - 1), o[(s + NB - 1) % NB]);
+      __builtin_amdgcn_sched_barrier(0);   // keep each prefetch in its slot (bounded live ranges)
+      wave_step<MODE>(o[s], q);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < NB - 1; ++s)
+    if (s < nks - nfull) wave_step<MODE>(o[s], q);
+}
+
+// Rows [32h, 32h + 32) of the regular tile (i, j) of step j, one wave:
+// X = A_ij - L_i,<j L_j,<j^H, then L_ij = X Linv_jj^H, computed transposed as
+// L_ij^T = conj(Linv_jj) X^T with the lower-triangular Linv_jj (16x16 blocks
+// above its diagonal skipped).  Row halves are independent: row r of L_ij
+// needs row r of X only.
+template <int MODE>
+__device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __restrict__ Z, int64_t cell, int i, int j,
+                          int h) {
+  const int64_t ld = T.ldz;
+  const int lane = threadIdx.x & 63;
+  double2* tile = Z + (int64_t)(j * TB) * ld + i * TB + 32 * h;   // rows of A_ij in, of L_ij out
+  // the accumulators start as A_ij^T, so that they end as X^T
+  WAcc q;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int r = 16 * v + (lane & 15), c = 16 * u + 4 * t + (lane >> 4);
+        const double2 a = tile[(int64_t)c * ld + r];
+        q.re[u][v][t] = a.x;
+        q.im[u][v][t] = MODE == MM_RR ? 0.0 : a.y;
+      }
+  __builtin_amdgcn_sched_barrier(0);
+  wave_gemm_t<MODE>(Z + i * TB + 32 * h, Z + j * TB, ld, j * TB, q);
+  __builtin_amdgcn_sched_barrier(0);
+  const double2* tL = Z + (int64_t)(j * TB) * ld + j * TB;   // Linv_jj, lower
+  const int nvb = T.nvp / TB;
+  const bool wsplit = C.split && i >= nvb;
+  uint16_t* wp = wsplit ? C.wsplit + cell * split_elems(T) : nullptr;
+  const int nkc = T.nvp / 32;
+#pragma unroll
+  for (int mb = 3; mb >= 0; --mb) {
+    d4 yr[2], yi[2];
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+      yr[nb] = d4{0, 0, 0, 0};
+      yi[nb] = d4{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int kb = 0; kb <= mb; ++kb)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        // A operand conj(Linv)[16 mb + (l & 15)][16 kb + 4 t + (l >> 4)]
+        const double2 L = tL[(int64_t)(16 * kb + 4 * t + (lane >> 4)) * ld + 16 * mb + (lane & 15)];
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+          yr[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(L.x, q.re[kb][nb][t], yr[nb], 0, 0, 0);
+          if (MODE != MM_RR) yi[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(L.x, q.im[kb][nb][t], yi[nb], 0, 0, 0);
+          if (MODE == MM_CC) {
+            yr[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(L.y, q.im[kb][nb][t], yr[nb], 0, 0, 0);
+            yi[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-L.y, q.re[kb][nb][t], yi[nb], 0, 0, 0);
+          }
+        }
+      }
+    // item t of block (mb, nb): L_ij[row 32h + 16 nb + (l & 15)][column 16 mb + 4 t + (l >> 4)]
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int r = 16 * nb + (lane & 15), c = 16 * mb + 4 * t + (lane >> 4);
+        const double vr = yr[nb][t], vi = MODE == MM_RR ? 0.0 : yi[nb][t];
+        tile[(int64_t)c * ld + r] = make_double2(vr, vi);
+        if (wsplit) {
+          // final block (i, j) of W^H as three-term bf16 splits, layout
+          // [row][k / 32][plane][k % 32], planes re0, re1, re2, im0, im1, im2
+          const int kk = j * TB + c;
+          const int64_t o = ((int64_t)((i - nvb) * TB + 32 * h + r) * nkc + kk / 32) * 192 + (kk % 32);
+          uint16_t hb[3];
+          split3_bf16(vr, hb);
+          wp[o] = hb[0];
+          wp[o + 32] = hb[1];
+          wp[o + 64] = hb[2];
+          split3_bf16(vi, hb);
+          wp[o + 96] = hb[0];
+          wp[o + 128] = hb[1];
+          wp[o + 160] = hb[2];
+        }
+      }
+  }
+}
+
+// Step j of the left-looking factorisation over the row tiles i > j:
 //   L_ij = (A_ij - sum_{m<j} L_im L_jm^H) Linv_jj^H .
-// Lookahead: the workgroup of tile i = j+1 (< number of test tiles) then forms
-//   A_ii - sum_{m<=j} L_im L_im^H  and factorises it (Cholesky + inverse),
-// storing Linv_ii for step j+1, so no separate launch factors diagonal blocks.
+// Tile i = j+1 (while it is a test tile) is the lookahead tile: its
+// workgroup (four waves through LDS) also forms A_ii - sum_{m<=j} L_im L_im^H
+// and factorises it (Cholesky + inverse), storing Linv_ii for step j+1, so no
+// separate launch factors diagonal blocks.  Every other tile is two waves
+// (wave_tile, one row half each), two tiles per workgroup.
 __global__ __launch_bounds__(NT, 2) void k_chol_step(DevTables T, ChunkArgs C, int j) {
   const int nrb = T.nrows / TB, nvb = T.nvp / TB;
-  const int ntiles = nrb - j - 1;
-  // Workgroup ids [0, n8) carry the lookahead tile (tile 0) of every cell and
-  // are dispatched first, spread over all CUs (cell c on XCD c % 8); the other
-  // tiles follow with the usual XCD-aware (cell, tile) decode.  Interleaving
-  // the costlier lookahead tiles with a fixed period would pile them onto the
-  // same few CUs whenever the period divides the XCD's dispatch order.
-  const int64_t n8 = (C.n + 7) / 8 * 8;
-  int64_t cell;
-  int tile;
-  if ((int64_t)blockIdx.x < n8) {
-    cell = blockIdx.x;
-    tile = 0;
-    if (cell >= C.n) return;
-  } else {
+  const bool la = j + 1 < nvb;
+  const int nreg = nrb - j - 1 - (la ? 1 : 0);   // tiles done by wave pairs
+  // Workgroup ids [0, n8) carry the lookahead tile of every cell and are
+  // dispatched first, spread over all CUs (cell c on XCD c % 8).  The wave
+  // tiles follow: per XCD x the (cell, tile) pairs of its cells c = 8 m + x
+  // form one list in (m, tile) order, two per workgroup, so that no
+  // workgroup is left partly empty at the end of a cell.
+  const int64_t n8 = la ? (C.n + 7) / 8 * 8 : 0;
+  if ((int64_t)blockIdx.x >= n8) {
     const int64_t w = (int64_t)blockIdx.x - n8;
-    const int64_t slot = w >> 3;
-    const int64_t cl = slot / (ntiles - 1);
-    tile = 1 + (int)(slot - cl * (ntiles - 1));
-    cell = cl * 8 + (w & 7);
-    if (cell >= C.n) return;
+    const int wave = (int)(threadIdx.x >> 6);
+    const int64_t item = (w >> 3) * 2 + (wave >> 1);
+    const int64_t m = item / nreg;
+    const int t = (int)(item - m * nreg);
+    const int64_t cell = m * 8 + (w & 7);
+    if (cell >= C.n) return;   // whole waves: no barrier follows on this path
+    const int i = j + 1 + (la ? 1 : 0) + t;
+    double2* Z = C.Z + cell * T.zstride;
+    const bool ireal = (i + 1) * TB <= T.Np, jreal = (j + 1) * TB <= T.Np;
+    if (ireal) wave_tile<MM_RR>(T, C, Z, cell, i, j, wave & 1);
+    else if (jreal) wave_tile<MM_CR>(T, C, Z, cell, i, j, wave & 1);
+    else wave_tile<MM_CC>(T, C, Z, cell, i, j, wave & 1);
+    return;
   }
-  const int i = j + 1 + tile;
+  const int64_t cell = blockIdx.x;
+  if (cell >= C.n) return;
+  const int i = j + 1;
   extern __shared__ double smem[];
   Stage* st = reinterpret_cast<Stage*>(smem);
   const int64_t ld = T.ldz;
   double2* Z = C.Z + cell * T.zstride;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int w = threadIdx.x >> 6;
   const int wc = w >> 1;
 
   // rows of tile i (resp. j) lie in the F test block and are exactly real?
@@ -1159,28 +1350,7 @@ __global__ __launch_bounds__(NT, 2) void k_chol_step(DevTables T, ChunkArgs C, i
   }
   double2* out = Z + (int64_t)(j * TB) * ld + i * TB;
   acc_for_each(y, [&](int r, int c, double vr, double vi) { out[(int64_t)c * ld + r] = make_double2(vr, vi); });
-  if (C.split && i >= nvb) {
-    // final block (i, j) of W^H: three-term bf16 splits of re and im, [plane][row][k]
-    // layout [row][k / 32][plane][k % 32]: the six planes of a row's 32-column
-    // chunk are contiguous (384 B), planes re0, re1, re2, im0, im1, im2
-    uint16_t* wp = C.wsplit + cell * split_elems(T);
-    const int nkc = T.nvp / 32;
-    acc_for_each(y, [&](int r, int c, double vr, double vi) {
-      const int kk = j * TB + c;
-      const int64_t o = ((int64_t)((i - nvb) * TB + r) * nkc + kk / 32) * 192 + (kk % 32);
-      uint16_t h[3];
-      split3_bf16(vr, h);
-      wp[o] = h[0];
-      wp[o + 32] = h[1];
-      wp[o + 64] = h[2];
-      split3_bf16(vi, h);
-      wp[o + 96] = h[0];
-      wp[o + 128] = h[1];
-      wp[o + 160] = h[2];
-    });
-  }
 
-  if (tile != 0 || i >= nvb) return;   // uniform per workgroup
   // ---- lookahead: diagonal block i
   const int64_t gc = C.cell_ids[cell];
   __syncthreads();
@@ -1215,7 +1385,6 @@ __global__ __launch_bounds__(NT, 2) void k_chol_step(DevTables T, ChunkArgs C, i
   tile_chol_inv(Cr, Ci, Yd, &s_fail, &s_inv);
   store_linv(Cr, Ci, Yd, tileD, ld);
   if (threadIdx.x == 0 && s_fail && C.info[gc - C.cell_base] == 0) C.info[gc - C.cell_base] = i * TB + s_fail;
-  (void)lane;
 }
 
 // ================================================================ K_aug = W^H W
@@ -1520,9 +1689,14 @@ hipError_t launch_factor(const DevTables& t, const ChunkArgs& ca, hipStream_t st
   if (ca.n <= 0) return hipSuccess;
   const int nvb = t.nvp / TB, nrb = t.nrows / TB;
   DPG_LAUNCH(KC_CHOL_DIAG, prof, st, k_chol_diag0, dim3((unsigned)ca.n), dim3(NT), kFactorSmem, st, t, ca);
-  for (int j = 0; j < nvb; ++j)
-    DPG_LAUNCH(KC_CHOL_PANEL, prof, st, k_chol_step, dim3(grid_cells_tiles(ca.n, nrb - j - 1)), dim3(NT),
-               kFactorSmem, st, t, ca, j);
+  const int64_t n8 = (ca.n + 7) / 8 * 8;
+  for (int j = 0; j < nvb; ++j) {
+    // lookahead workgroups (one per cell) + two wave-pair tiles per workgroup
+    const bool la = j + 1 < nvb;
+    const int nreg = nrb - j - 1 - (la ? 1 : 0);
+    const unsigned grid = (unsigned)((la ? n8 : 0) + 8 * ((n8 / 8 * nreg + 1) / 2));
+    DPG_LAUNCH(KC_CHOL_PANEL, prof, st, k_chol_step, dim3(grid), dim3(NT), kFactorSmem, st, t, ca, j);
+  }
   return hipGetLastError();
 }
 
