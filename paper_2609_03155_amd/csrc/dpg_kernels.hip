@@ -944,114 +944,94 @@ __global__ __launch_bounds__(NT, 2) void k_form_SM(DevTables T, ProbArgs P, Chun
 }
 
 // ================================================================ Cholesky
-// Product of two LDS-resident operands, P += A B^H over K columns: A and B
-// are stored as [k][row] planes (row pitch LDP), the same convention as Stage.
-template <int MODE = MM_CC>
-__device__ inline void lds_abh(const double* Ar, const double* Ai, const double* Br, const double* Bi, int K,
-                               Acc& c) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wr = w & 1, wc = w >> 1;
-  for (int ks = 0; ks < K / 4; ++ks) {
-    const int kk = ks * 4 + (lane >> 4);
-    double ar[2], ai[2] = {0.0, 0.0}, br[2], bi[2] = {0.0, 0.0};
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int row = wr * 32 + u * 16 + (lane & 15);
-      ar[u] = Ar[kk * LDP + row];
-      if (MODE != MM_RR) ai[u] = Ai[kk * LDP + row];
-      const int col = wc * 32 + u * 16 + (lane & 15);
-      br[u] = Br[kk * LDP + col];
-      if (MODE == MM_CC) bi[u] = Bi[kk * LDP + col];
-    }
-    cmfma_step<MODE>(ar, ai, br, bi, c);
-  }
-}
-
-// LDS layout of the factorisation kernels (aliased phases, <= 68 KB so that
-// two workgroups fit one CU):
-//   GEMM staging            2 x Stage
-//   X Linv^H in k-halves    Xr, Xi [32][LDP] (k = column of X), Lr, Li [32][LDP]
-//   Y Y^H (lookahead)       Yr, Yi [64][LDP]
-//   Cholesky + inverse      Cr, Ci [64][65], Yd [64]
+// LDS of the factorisation kernels (aliased phases, two workgroups per CU):
+//   diagonal block          Cr, Ci [64][65] (then broadcast slots in Cr)
+//   split regrouping        one slab of WSP_BYTES per wave
 constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
-constexpr size_t kFactorSmem =
-    cmax(cmax(2 * sizeof(Stage), 4 * 32 * LDP * 8), cmax(2 * 64 * LDP * 8, 2 * 64 * 65 * 8 + 64 * 8));
+constexpr size_t kFactorSmem = 2 * 64 * 65 * 8;
 static_assert(kFactorSmem <= 80 * 1024, "two factorisation workgroups must fit one CU");
 
-// In-place Cholesky and inverse of the 64x64 Hermitian tile held (lower part)
-// in Cr/Ci[r*65+q]: on exit the lower part holds L and the strict upper part
-// holds L^{-1} transposed (Linv[r][q] at [q*65+r]); the (real) diagonal of
-// L^{-1} is in Yd.  Returns the first failing column + 1 (0 if none) in s_fail.
-__device__ inline void tile_chol_inv(double* Cr, double* Ci, double* Yd, int* s_fail, double* s_inv) {
-  for (int e = threadIdx.x; e < 64 * 64; e += NT) {
-    const int r = e >> 6, q = e & 63;
-    if (q > r) {
-      Cr[r * 65 + q] = 0.0;
-      Ci[r * 65 + q] = 0.0;
-    }
+// Cholesky factor and inverse of the 64x64 Hermitian tile whose lower part
+// is in Cr/Ci[r*65+q]; writes L^{-1} (lower, zero upper) to the column-major
+// tile `out` and returns the first failing column + 1 (0 if none), the same
+// value in every thread.  Registers carry the work: thread (r, g) = (t & 63,
+// t >> 6) owns columns [16g, 16g + 16) of row r of both A (updated in place)
+// and X = L^{-1} (from the identity).  Step c broadcasts column c of A (its
+// owner wave; zero above the diagonal) and row c of X (lane c of every wave)
+// through a double-buffered LDS slot, one barrier per step, and every thread
+// applies
+//   A_rq -= L_rc conj(L_qc)   and   X_rq -= L_rc X_cq ,   L_rc = 0 for r <= c,
+// then X_c. /= L_cc.  A wave skips the A update once all its columns are
+// done (16g + 15 < c) and the X update while X_cq = 0 for all its columns
+// (16g > c); entries of A left of column c or above the diagonal take
+// meaningless updates but are never read again.  Cr/Ci are reused as the
+// broadcast slots.
+__device__ __forceinline__ int chol_inv_tile(double* Cr, const double* Ci, double2* __restrict__ out, int64_t ld) {
+  const int r = threadIdx.x & 63;
+  const int g = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
+  double ar[16], ai[16], xr[16], xi[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int q = 16 * g + u;
+    ar[u] = q <= r ? Cr[r * 65 + q] : 0.0;
+    ai[u] = q <= r ? Ci[r * 65 + q] : 0.0;
+    xr[u] = q == r ? 1.0 : 0.0;
+    xi[u] = 0.0;
   }
-  if (threadIdx.x == 0) *s_fail = 0;
   __syncthreads();
-  for (int c = 0; c < 64; ++c) {
-    if (threadIdx.x == 0) {
-      double dd = Cr[c * 65 + c];
-      if (!(dd > 0.0) || !isfinite(dd)) {
-        if (!*s_fail) *s_fail = c + 1;
-        dd = 1.0;
+  double2* cb = reinterpret_cast<double2*>(Cr);   // [2][64]: column c of A
+  double2* rb = cb + 128;                          // [2][64]: row c of X (before its scaling)
+  int fail = 0;
+  for (int kb = 0; kb < 4; ++kb) {
+#pragma unroll
+    for (int uc = 0; uc < 16; ++uc) {
+      const int c = 16 * kb + uc;
+      const int par = (uc & 1) * 64;
+      if (g == kb) cb[par + r] = r >= c ? make_double2(ar[uc], ai[uc]) : make_double2(0.0, 0.0);
+      if (r == c) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) rb[par + 16 * g + u] = make_double2(xr[u], xi[u]);
       }
-      const double l = sqrt(dd);
-      Cr[c * 65 + c] = l;
-      Ci[c * 65 + c] = 0.0;
-      *s_inv = 1.0 / l;
-      Yd[c] = 1.0 / l;
-    }
-    __syncthreads();
-    const double inv = *s_inv;
-    // column c of L below the diagonal; row c of L^{-1} left of the diagonal (stored at [q][c])
-    for (int r = c + 1 + threadIdx.x; r < 64; r += NT) {
-      Cr[r * 65 + c] *= inv;
-      Ci[r * 65 + c] *= inv;
-    }
-    for (int q = threadIdx.x; q < c; q += NT) {
-      Cr[q * 65 + c] *= inv;
-      Ci[q * 65 + c] *= inv;
-    }
-    __syncthreads();
-    const int q = threadIdx.x & 63;
-    for (int r = c + 1 + (threadIdx.x >> 6); r < 64; r += NT / 64) {
-      const double lr = Cr[r * 65 + c], li = Ci[r * 65 + c];
-      if (q > c && q <= r) {
-        const double mr = Cr[q * 65 + c], mi = -Ci[q * 65 + c];   // conj(L_qc)
-        Cr[r * 65 + q] -= lr * mr - li * mi;
-        Ci[r * 65 + q] -= lr * mi + li * mr;
-      } else if (q <= c) {
-        // Linv[r][q] -= L[r][c] Linv[c][q]
-        double yr, yi;
-        if (q == c) {
-          yr = Yd[c];
-          yi = 0.0;
-        } else {
-          yr = Cr[q * 65 + c];
-          yi = Ci[q * 65 + c];
+      __syncthreads();
+      const double2 own = cb[par + r];
+      double d = cb[par + c].x;
+      if (!(d > 0.0) || !isfinite(d)) {
+        if (!fail) fail = c + 1;
+        d = 1.0;
+      }
+      const double inv = 1.0 / sqrt(d);
+      const double lr = r > c ? own.x * inv * inv : 0.0, li = r > c ? own.y * inv * inv : 0.0;   // L_rc / L_cc
+      if (g >= kb) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const double2 m = cb[par + 16 * g + u];   // A_qc (broadcast)
+          ar[u] -= lr * m.x + li * m.y;
+          ai[u] -= li * m.x - lr * m.y;
         }
-        Cr[q * 65 + r] -= lr * yr - li * yi;
-        Ci[q * 65 + r] -= lr * yi + li * yr;
+      }
+      if (g <= kb) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const double2 y = rb[par + 16 * g + u];   // X_cq before scaling (broadcast)
+          xr[u] -= lr * y.x - li * y.y;
+          xi[u] -= lr * y.y + li * y.x;
+        }
+      }
+      if (r == c) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          xr[u] *= inv;
+          xi[u] *= inv;
+        }
       }
     }
-    __syncthreads();
   }
-}
-
-// Writes L^{-1} (lower, zero upper) from the tile_chol_inv layout into a
-// column-major global tile.
-__device__ inline void store_linv(const double* Cr, const double* Ci, const double* Yd, double2* tile, int64_t ld) {
-  for (int e = threadIdx.x; e < 64 * 64; e += NT) {
-    const int q = e >> 6, r = e & 63;   // column q, row r
-    double2 v = make_double2(0.0, 0.0);
-    if (r == q) v = make_double2(Yd[r], 0.0);
-    else if (r > q) v = make_double2(Cr[q * 65 + r], Ci[q * 65 + r]);
-    tile[(int64_t)q * ld + r] = v;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int q = 16 * g + u;
+    out[(int64_t)q * ld + r] = q <= r ? make_double2(xr[u], xi[u]) : make_double2(0.0, 0.0);
   }
+  return fail;
 }
 
 // Step 0 diagonal block: A_00 = L L^H, store L^{-1}.
@@ -1062,9 +1042,6 @@ __global__ __launch_bounds__(NT) void k_chol_diag0(DevTables T, ChunkArgs C) {
   extern __shared__ double smem[];
   double* Cr = smem;
   double* Ci = Cr + 64 * 65;
-  double* Yd = Ci + 64 * 65;
-  __shared__ double s_inv;
-  __shared__ int s_fail;
   const int64_t ld = T.ldz;
   double2* tile = C.Z + cell * T.zstride;
   for (int e = threadIdx.x; e < 64 * 64; e += NT) {
@@ -1076,9 +1053,8 @@ __global__ __launch_bounds__(NT) void k_chol_diag0(DevTables T, ChunkArgs C) {
     }
   }
   __syncthreads();
-  tile_chol_inv(Cr, Ci, Yd, &s_fail, &s_inv);
-  store_linv(Cr, Ci, Yd, tile, ld);
-  if (threadIdx.x == 0 && s_fail && C.info[gc - C.cell_base] == 0) C.info[gc - C.cell_base] = s_fail;
+  const int fail = chol_inv_tile(Cr, Ci, tile, ld);
+  if (threadIdx.x == 0 && fail && C.info[gc - C.cell_base] == 0) C.info[gc - C.cell_base] = fail;
 }
 
 // ---------------------------------------------------------------- one wave, half a tile
@@ -1096,6 +1072,13 @@ __global__ __launch_bounds__(NT) void k_chol_diag0(DevTables T, ChunkArgs C) {
 struct WAcc {
   d4 re[4][2], im[4][2];
 };
+
+// Per-wave LDS slab that regroups the bf16 split planes of a 32 x 16 block of
+// W^H into 16-byte column runs: [32 rows][6 planes][16 columns], row pitch
+// 208 bytes (16-byte aligned rows; 2-way bank aliasing at most).
+constexpr int WSP_PITCH = 208;
+constexpr int WSP_BYTES = 32 * WSP_PITCH;
+static_assert(4 * WSP_BYTES <= kFactorSmem, "four wave slabs fit the step kernel's LDS");
 
 struct WOps {
   double2 a[2], b[4];
@@ -1189,7 +1172,7 @@ __device__ __forceinline__ void wave_gemm_t(const double2* __restrict__ Ai, cons
 // needs row r of X only.
 template <int MODE>
 __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __restrict__ Z, int64_t cell, int i, int j,
-                          int h) {
+                          int h, unsigned char* slab) {
   const int64_t ld = T.ldz;
   const int lane = threadIdx.x & 63;
   double2* tile = Z + (int64_t)(j * TB) * ld + i * TB + 32 * h;   // rows of A_ij in, of L_ij out
@@ -1247,31 +1230,90 @@ __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __res
         const double vr = yr[nb][t], vi = MODE == MM_RR ? 0.0 : yi[nb][t];
         tile[(int64_t)c * ld + r] = make_double2(vr, vi);
         if (wsplit) {
-          // final block (i, j) of W^H as three-term bf16 splits, layout
-          // [row][k / 32][plane][k % 32], planes re0, re1, re2, im0, im1, im2
-          const int kk = j * TB + c;
-          const int64_t o = ((int64_t)((i - nvb) * TB + 32 * h + r) * nkc + kk / 32) * 192 + (kk % 32);
+          // three-term bf16 splits of re and im into the wave's LDS slab
+          // [32 rows][6 planes][16 columns] (row pitch WSP_PITCH bytes)
+          uint16_t* sl = reinterpret_cast<uint16_t*>(slab + r * WSP_PITCH) + 4 * t + (lane >> 4);
           uint16_t hb[3];
           split3_bf16(vr, hb);
-          wp[o] = hb[0];
-          wp[o + 32] = hb[1];
-          wp[o + 64] = hb[2];
+          sl[0] = hb[0];
+          sl[16] = hb[1];
+          sl[32] = hb[2];
           split3_bf16(vi, hb);
-          wp[o + 96] = hb[0];
-          wp[o + 128] = hb[1];
-          wp[o + 160] = hb[2];
+          sl[48] = hb[0];
+          sl[64] = hb[1];
+          sl[80] = hb[2];
         }
       }
+    if (wsplit) {
+      // W^H block (i, j) in the split layout [row][k / 32][plane][k % 32]
+      // (planes re0, re1, re2, im0, im1, im2): each lane stores 16-byte runs
+      // of 8 columns, gathered from the slab written above by the same wave.
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+      for (int e = 0; e < 6; ++e) {
+        const int id = e * 64 + lane;            // (row, plane, half) of 32 x 6 x 2
+        const int r = id / 12, pl = (id % 12) >> 1, hf = id & 1;
+        const uint4 v = *reinterpret_cast<const uint4*>(slab + r * WSP_PITCH + pl * 32 + hf * 16);
+        const int kk = j * TB + 16 * mb + 8 * hf;
+        const int64_t o = ((int64_t)((i - nvb) * TB + 32 * h + r) * nkc + kk / 32) * 192 + pl * 32 + (kk % 32);
+        *reinterpret_cast<uint4*>(wp + o) = v;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
   }
+}
+
+// Rows [32h, 32h + 32) of a diagonal block update, one wave:
+//   S = S0 - P_h P^H ,  P the 64-row panel (columns [0, K) at P), P_h its rows [32h, 32h + 32),
+// with S0 the column-major tile S0g (FROM_TILE) or the LDS block
+// Sr/Si[r*65 + c] itself; the whole 32 x 64 result is written to
+// Sr/Si[r*65 + c] (only its lower part is meaningful).
+template <int MODE, bool FROM_TILE>
+__device__ __forceinline__ void diag_update(const double2* __restrict__ S0g, const double2* __restrict__ P, int64_t ld,
+                                            int K, int h, double* Sr, double* Si) {
+  const int lane = threadIdx.x & 63;
+  WAcc q;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int r = 32 * h + 16 * v + (lane & 15), c = 16 * u + 4 * t + (lane >> 4);
+        if (FROM_TILE) {
+          const double2 a = S0g[(int64_t)c * ld + r];
+          q.re[u][v][t] = a.x;
+          q.im[u][v][t] = MODE == MM_RR ? 0.0 : a.y;
+        } else {
+          q.re[u][v][t] = Sr[r * 65 + c];
+          q.im[u][v][t] = MODE == MM_RR ? 0.0 : Si[r * 65 + c];
+        }
+      }
+  wave_gemm_t<MODE>(P + 32 * h, P, ld, K, q);
+  // item t of block (u, v): S[row 32h + 16v + (l & 15)][column 16u + 4t + (l >> 4)]
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int r = 32 * h + 16 * v + (lane & 15), c = 16 * u + 4 * t + (lane >> 4);
+        Sr[r * 65 + c] = q.re[u][v][t];
+        Si[r * 65 + c] = q.im[u][v][t];
+      }
 }
 
 // Step j of the left-looking factorisation over the row tiles i > j:
 //   L_ij = (A_ij - sum_{m<j} L_im L_jm^H) Linv_jj^H .
 // Tile i = j+1 (while it is a test tile) is the lookahead tile: its
-// workgroup (four waves through LDS) also forms A_ii - sum_{m<=j} L_im L_im^H
-// and factorises it (Cholesky + inverse), storing Linv_ii for step j+1, so no
-// separate launch factors diagonal blocks.  Every other tile is two waves
-// (wave_tile, one row half each), two tiles per workgroup.
+// workgroup also forms A_ii - sum_{m<=j} L_im L_im^H and factorises it
+// (Cholesky + inverse), storing Linv_ii for step j+1, so no separate launch
+// factors diagonal blocks.  Every other tile is two waves (wave_tile, one row
+// half each), two tiles per workgroup.
 __global__ __launch_bounds__(NT, 2) void k_chol_step(DevTables T, ChunkArgs C, int j) {
   const int nrb = T.nrows / TB, nvb = T.nvp / TB;
   const bool la = j + 1 < nvb;
@@ -1293,98 +1335,47 @@ __global__ __launch_bounds__(NT, 2) void k_chol_step(DevTables T, ChunkArgs C, i
     const int i = j + 1 + (la ? 1 : 0) + t;
     double2* Z = C.Z + cell * T.zstride;
     const bool ireal = (i + 1) * TB <= T.Np, jreal = (j + 1) * TB <= T.Np;
-    if (ireal) wave_tile<MM_RR>(T, C, Z, cell, i, j, wave & 1);
-    else if (jreal) wave_tile<MM_CR>(T, C, Z, cell, i, j, wave & 1);
-    else wave_tile<MM_CC>(T, C, Z, cell, i, j, wave & 1);
+    extern __shared__ double smem[];
+    unsigned char* slab = reinterpret_cast<unsigned char*>(smem) + wave * WSP_BYTES;
+    if (ireal) wave_tile<MM_RR>(T, C, Z, cell, i, j, wave & 1, slab);
+    else if (jreal) wave_tile<MM_CR>(T, C, Z, cell, i, j, wave & 1, slab);
+    else wave_tile<MM_CC>(T, C, Z, cell, i, j, wave & 1, slab);
     return;
   }
+  // ---- lookahead workgroup: tile (i, j), i = j + 1, on waves 0 and 1 (one
+  // row half each); meanwhile waves 2 and 3 form the two row halves of
+  // A_ii - sum_{m<j} L_im L_im^H in LDS, add the new term -L_ij L_ij^H once
+  // L_ij is stored, and all four waves factorise the result (Cholesky +
+  // inverse).
   const int64_t cell = blockIdx.x;
   if (cell >= C.n) return;
   const int i = j + 1;
-  extern __shared__ double smem[];
-  Stage* st = reinterpret_cast<Stage*>(smem);
   const int64_t ld = T.ldz;
+  const int wave = (int)(threadIdx.x >> 6);
   double2* Z = C.Z + cell * T.zstride;
-  const int w = threadIdx.x >> 6;
-  const int wc = w >> 1;
-
-  // rows of tile i (resp. j) lie in the F test block and are exactly real?
   const bool ireal = (i + 1) * TB <= T.Np, jreal = (j + 1) * TB <= T.Np;
-  const int mode = ireal ? MM_RR : (jreal ? MM_CR : MM_CC);
-  Acc acc;
-  acc_zero(acc);
-  if (mode == MM_RR) gemm_abh<MM_RR>(Z + i * TB, Z + j * TB, ld, j * TB, st, acc);
-  else if (mode == MM_CR) gemm_abh<MM_CR>(Z + i * TB, Z + j * TB, ld, j * TB, st, acc);
-  else gemm_abh<MM_CC>(Z + i * TB, Z + j * TB, ld, j * TB, st, acc);
-  // X = A_ij - P ; Y = X Linv_jj^H, in two k-halves through LDS
-  double* Xr = smem;
-  double* Xi = Xr + 32 * LDP;
-  double* Lr = Xi + 32 * LDP;
-  double* Li = Lr + 32 * LDP;
-  const double2* tileA = Z + (int64_t)(j * TB) * ld + i * TB;
-  const double2* tileL = Z + (int64_t)(j * TB) * ld + j * TB;
-  Acc y;
-  acc_zero(y);
-  for (int h = 0; h < 2; ++h) {
-    __syncthreads();
-    if (wc == h) {
-      acc_for_each(acc, [&](int r, int c, double pr, double pi) {
-        const double2 a = tileA[(int64_t)c * ld + r];
-        Xr[(c - 32 * h) * LDP + r] = a.x - pr;
-        Xi[(c - 32 * h) * LDP + r] = a.y - pi;
-      });
-    }
-    for (int e = threadIdx.x; e < 32 * 64; e += NT) {
-      const int kk = e >> 6, col = e & 63;
-      const double2 v = tileL[(int64_t)(32 * h + kk) * ld + col];
-      Lr[kk * LDP + col] = v.x;
-      Li[kk * LDP + col] = v.y;
-    }
-    __syncthreads();
-    // Linv_jj is lower triangular: columns c < 32 receive nothing from k >= 32
-    if (!(h == 1 && wc == 0)) {
-      if (mode == MM_RR) lds_abh<MM_RR>(Xr, Xi, Lr, Li, 32, y);
-      else if (mode == MM_CR) lds_abh<MM_CR>(Xr, Xi, Lr, Li, 32, y);
-      else lds_abh<MM_CC>(Xr, Xi, Lr, Li, 32, y);
-    }
-  }
-  double2* out = Z + (int64_t)(j * TB) * ld + i * TB;
-  acc_for_each(y, [&](int r, int c, double vr, double vi) { out[(int64_t)c * ld + r] = make_double2(vr, vi); });
-
-  // ---- lookahead: diagonal block i
-  const int64_t gc = C.cell_ids[cell];
-  __syncthreads();
-  acc_zero(acc);
-  if (ireal) gemm_abh<MM_RR>(Z + i * TB, Z + i * TB, ld, j * TB, st, acc);
-  else gemm_abh<MM_CC>(Z + i * TB, Z + i * TB, ld, j * TB, st, acc);
-  __syncthreads();
-  double* Yr = smem;
-  double* Yi = Yr + 64 * LDP;
-  acc_for_each(y, [&](int r, int c, double vr, double vi) {
-    Yr[c * LDP + r] = vr;
-    Yi[c * LDP + r] = vi;
-  });
-  __syncthreads();
-  if (ireal) lds_abh<MM_RR>(Yr, Yi, Yr, Yi, 64, acc);
-  else lds_abh<MM_CC>(Yr, Yi, Yr, Yi, 64, acc);
-  __syncthreads();
+  extern __shared__ double smem[];
   double* Cr = smem;
   double* Ci = Cr + 64 * 65;
-  double* Yd = Ci + 64 * 65;
-  __shared__ double s_inv;
-  __shared__ int s_fail;
   double2* tileD = Z + (int64_t)(i * TB) * ld + i * TB;
-  acc_for_each(acc, [&](int r, int c, double pr, double pi) {
-    if (c <= r) {
-      const double2 a = tileD[(int64_t)c * ld + r];
-      Cr[r * 65 + c] = a.x - pr;
-      Ci[r * 65 + c] = a.y - pi;
-    }
-  });
+  if (wave < 2) {
+    if (ireal) wave_tile<MM_RR>(T, C, Z, cell, i, j, wave, nullptr);
+    else if (jreal) wave_tile<MM_CR>(T, C, Z, cell, i, j, wave, nullptr);
+    else wave_tile<MM_CC>(T, C, Z, cell, i, j, wave, nullptr);
+  } else {
+    if (ireal) diag_update<MM_RR, true>(tileD, Z + i * TB, ld, j * TB, wave - 2, Cr, Ci);
+    else diag_update<MM_CC, true>(tileD, Z + i * TB, ld, j * TB, wave - 2, Cr, Ci);
+  }
+  __syncthreads();   // L_ij stored (workgroup scope); partial diagonal block in LDS
+  if (wave >= 2) {
+    const double2* Lij = Z + (int64_t)(j * TB) * ld + i * TB;   // column block j of panel i
+    if (ireal) diag_update<MM_RR, false>(nullptr, Lij, ld, TB, wave - 2, Cr, Ci);
+    else diag_update<MM_CC, false>(nullptr, Lij, ld, TB, wave - 2, Cr, Ci);
+  }
   __syncthreads();
-  tile_chol_inv(Cr, Ci, Yd, &s_fail, &s_inv);
-  store_linv(Cr, Ci, Yd, tileD, ld);
-  if (threadIdx.x == 0 && s_fail && C.info[gc - C.cell_base] == 0) C.info[gc - C.cell_base] = i * TB + s_fail;
+  const int fail = chol_inv_tile(Cr, Ci, tileD, ld);
+  const int64_t gc = C.cell_ids[cell];
+  if (threadIdx.x == 0 && fail && C.info[gc - C.cell_base] == 0) C.info[gc - C.cell_base] = i * TB + fail;
 }
 
 // ================================================================ K_aug = W^H W
