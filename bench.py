@@ -26,6 +26,7 @@ from paper_2609_03155_amd import workloads as W  # noqa: E402
 METRIC = "DPG local-solve elements/s (B^H G^{-1} B + eta) mixed-prec vs FP64; rel err"
 PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 matrix peak
 PEAK_HBM_GBS = 8000.0
+STREAM_CELLS = 8192          # cells per range when the outputs are streamed
 
 
 def algorithmic_flops(p: int, dp: int) -> dict:
@@ -90,6 +91,9 @@ def main():
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "split"])
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (calibrates HBM byte counters)")
+    ap.add_argument("--no-graph", action="store_true", help="time eager solves instead of HIP-graph replays")
+    ap.add_argument("--no-autotune", action="store_true", help="skip the batching autotuner")
+    ap.add_argument("--sequential", action="store_true", help="degree groups one after the other (no branches)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (requested --gpus {args.gpus}); the per-cell local solve needs no "
@@ -103,9 +107,33 @@ def main():
     x, off = W.random_coefficients(w)
     plan = dpg.Plan(w.degree, w.dp)
     prob = dpg.DeviceProblem.from_workload(w)
-    K, l, eta, info = plan.alloc_outputs()
     xd = torch.from_numpy(x).cuda()
     stream = torch.cuda.current_stream()
+    # Outputs larger than about a third of the device are streamed: the step
+    # solves consecutive ranges of STREAM_CELLS cells into one reused output
+    # buffer (eta and info for all cells stay resident).
+    free_b, _ = torch.cuda.mem_get_info()
+    streaming = int(plan.K_off[-1]) * 16 > free_b // 3
+    if streaming:
+        ranges = [(a, min(STREAM_CELLS, w.n_cells - a)) for a in range(0, w.n_cells, STREAM_CELLS)]
+        nK = max(plan.range_sizes(a, n)[0] for a, n in ranges)
+        nv = max(plan.range_sizes(a, n)[1] for a, n in ranges)
+        K = torch.empty(nK, dtype=torch.complex128, device="cuda")
+        l = torch.empty(nv, dtype=torch.complex128, device="cuda")
+        eta = torch.empty(w.n_cells, dtype=torch.float64, device="cuda")
+        info = torch.empty(w.n_cells, dtype=torch.int32, device="cuda")
+        args.no_graph = True
+        args.no_autotune = True
+    else:
+        K, l, eta, info = plan.alloc_outputs()
+
+    def solve(precision):
+        if not streaming:
+            plan.local_solve(prob, xd, K, l, eta, info, precision=precision, stream=stream)
+            return
+        for a, n in ranges:
+            plan.local_solve_range(prob, a, n, xd[int(off[a]):], K, l, eta[a:], info[a:], precision=precision,
+                                   stream=stream)
 
     if args.copy_calib_mib > 0:
         n = args.copy_calib_mib * (1 << 20) // 8
@@ -114,31 +142,78 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.sequential:
+        plan.set_concurrency(False)
+
     def timed(precision):
+        """(ms per step, per-class kernel profile of eager steps, outputs, replay stats)."""
+        if not args.no_autotune:
+            t_at = plan.autotune(prob, xd, K, l, eta, info, precision=precision, stream=stream)
+            print(f"[bench] precision {precision}: autotuned, solve {t_at:.1f} ms", file=sys.stderr, flush=True)
+        # eager steps with per-launch HIP events: kernel classes and the roofline
         for _ in range(args.warmup):
-            plan.local_solve(prob, xd, K, l, eta, info, precision=precision, stream=stream)
+            solve(precision)
         torch.cuda.synchronize()
         plan.profile()                       # discard
+        # per-launch durations are taken on the sequential schedule, where
+        # kernels of different degree groups do not share the device
+        conc = plan.tuning(int(w.degree[0]))[1]
+        plan.set_concurrency(False)
         plan.set_profiling(True)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         e0.record(stream)
         for _ in range(args.steps):
-            plan.local_solve(prob, xd, K, l, eta, info, precision=precision, stream=stream)
+            solve(precision)
         e1.record(stream)
         torch.cuda.synchronize()
         plan.set_profiling(False)
-        ms = e0.elapsed_time(e1)
+        plan.set_concurrency(conc)
+        eager_ms = e0.elapsed_time(e1) / args.steps
         prof = plan.profile()
-        outs = (K.cpu().numpy(), l.cpu().numpy(), eta.cpu().numpy(), info.cpu().numpy())
-        return ms / args.steps, prof, outs
+        print(f"[bench] precision {precision}: eager {eager_ms:.1f} ms/step", file=sys.stderr, flush=True)
+        rep = None
+        ms = eager_ms
+        if not args.no_graph:
+            # the headline: K replays of the captured solve, bracketed by synchronisation
+            g = plan.graph(prob, xd, K, l, eta, info, precision)
+            for _ in range(args.warmup):
+                g.launch(stream)
+            torch.cuda.synchronize()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+            ev[0].record(stream)
+            for k in range(args.steps):
+                g.launch(stream)
+                ev[k + 1].record(stream)
+            torch.cuda.synchronize()
+            per = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
+            ms = ev[0].elapsed_time(ev[-1]) / args.steps
+            rep = {"median_ms": float(np.median(per)), "min_ms": float(np.min(per)), "max_ms": float(np.max(per)),
+                   "eager_ms_per_step": eager_ms}
+            g.close()
+        return ms, prof, precision, rep
+
+    def cell_outputs(precision, c):
+        """(K_e, l_e, eta) of cell c from the last solve, or from a one-cell range solve when streaming."""
+        k = int(off[c + 1] - off[c])
+        if not streaming:
+            Kc = K[int(plan.K_off[c]):int(plan.K_off[c + 1])].cpu().numpy().reshape(k, k).T
+            return Kc, l[int(off[c]):int(off[c + 1])].cpu().numpy(), float(eta[c])
+        Kc = torch.empty(k * k, dtype=torch.complex128, device="cuda")
+        lc = torch.empty(k, dtype=torch.complex128, device="cuda")
+        ec = torch.empty(1, dtype=torch.float64, device="cuda")
+        ic = torch.empty(1, dtype=torch.int32, device="cuda")
+        plan.local_solve_range(prob, c, 1, xd[int(off[c]):], Kc, lc, ec, ic, precision=precision, stream=stream)
+        torch.cuda.synchronize()
+        return Kc.cpu().numpy().reshape(k, k).T, lc.cpu().numpy(), float(ec[0])
 
     precisions = {"fp64": dpg.DPG_FP64, "split": dpg.DPG_SPLIT_FP32}
     if args.precision != "both":
         precisions = {args.precision: precisions[args.precision]}
     runs = {name: timed(code) for name, code in precisions.items()}
     head = "split" if "split" in runs else "fp64"
-    ms_step, prof, (Kh, lh, eh, info_h) = runs[head]
+    ms_step, prof, _, _ = runs[head]
+    info_h = info.cpu().numpy()
     value = w.n_cells / (ms_step * 1e-3)
 
     # roofline of the dominant kernel class, from the live per-launch event timings
@@ -180,24 +255,32 @@ def main():
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items() if v[1]},
         "failed_cells": int(np.sum(info_h != 0)),
     }
-    for name, (ms_n, prof_n, _) in runs.items():
+    for name, (ms_n, prof_n, _, rep_n) in runs.items():
         rec[f"{name}_path"] = {"value": w.n_cells / (ms_n * 1e-3), "ms_per_step": ms_n,
                                "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof_n.items() if v[1]}}
+        if rep_n:
+            rec[f"{name}_path"]["graph_replays"] = rep_n
+    degs = sorted(set(int(v) for v in w.degree))
+    rec["batching"] = {"timed": "eager" if args.no_graph else "hip-graph replays",
+                       "concurrent_degree_branches": plan.tuning(degs[0])[1],
+                       "cells_per_launch": {str(p): plan.tuning(p)[0] for p in degs}}
     if "split" in runs and "fp64" in runs:
         rec["speedup_split_vs_fp64"] = runs["fp64"][0] / runs["split"][0]
     if not args.no_cpu_baseline:
         base, outs = cpu_baseline(w, args.cpu_budget)
         rec["cpu_baseline"] = base
         errs = {}
-        for name, (_, _, (Kn, ln, en, _)) in runs.items():
+        for name, (_, _, code, _) in runs.items():
             eK, el, ee = [], [], []
+            if not streaming:
+                solve(code)                  # outputs of this precision
+                torch.cuda.synchronize()
             for c, (Ko, lo, eo) in outs.items():
-                k = int(off[c + 1] - off[c])
-                Kg = Kn[plan.K_off[c]:plan.K_off[c + 1]].reshape(k, k).T
+                Kg, lg, eg = cell_outputs(code, c)
                 eK.append(np.linalg.norm(Kg - Ko) / np.linalg.norm(Ko))
                 if np.linalg.norm(lo) > 0:
-                    el.append(np.linalg.norm(ln[off[c]:off[c + 1]] - lo) / np.linalg.norm(lo))
-                ee.append(abs(en[c] - eo) / eo)
+                    el.append(np.linalg.norm(lg - lo) / np.linalg.norm(lo))
+                ee.append(abs(eg - eo) / eo)
             errs[name] = {"cells": len(outs), "K_e_max": float(np.max(eK)), "K_e_median": float(np.median(eK)),
                           "l_e_max": float(np.max(el)) if el else None, "l_e_cells": len(el),
                           "eta_max": float(np.max(ee))}

@@ -126,6 +126,7 @@ typedef struct {
 } dpg_problem;
 
 typedef struct dpg_plan_s* dpg_plan;
+typedef struct dpg_graph_s* dpg_graph;
 
 /* Local sizes of a (p, dp) cell (Sec. 2.3 spaces): n_test = 6 s (s+1)^2
  * (F and I), n_interior = 6 (p+1)^3 (E and H), n_trace = 24 (p+1)^2
@@ -135,10 +136,17 @@ dpg_status dpg_local_dims(int32_t p, int32_t dp, int32_t* n_test, int32_t* n_int
 
 /* Creates a plan for a batch of cells on HIP device `device`.
  * degree_host: HOST array [n_cells] of trial degrees p (1..4); dp: the test
- * enrichment (1..2) used for every cell.  The plan groups cells by degree,
- * builds the reference tables of each degree on the device and sizes its
- * workspace so that it stays below max_workspace_bytes (0 = 40% of the
- * device memory free at creation).  Synchronous. */
+ * enrichment (1..2) used for every cell.  The plan groups cells by degree
+ * (the batching of the mixed-degree cells of Sec. 3's workloads, which the
+ * per-cell solve of Sec. 2.3 leaves free), orders the groups by decreasing
+ * algorithmic cost (the work queue), builds the reference tables of each
+ * degree on the device and gives each group its own workspace: room for
+ * min(cells, 1024) cells, plus a share of the rest of max_workspace_bytes
+ * (0 = 40% of the device memory free at creation) proportional to the
+ * group's cost and capped at what all its cells need (all scaled down if
+ * the budget is short); a group with more cells than its workspace holds
+ * is solved in chunks.  Each
+ * group also gets a branch stream of default priority.  Synchronous. */
 dpg_status dpg_plan_create(int32_t device, const int8_t* degree_host, int64_t n_cells, int32_t dp,
                            int64_t max_workspace_bytes, dpg_plan* plan);
 
@@ -177,6 +185,46 @@ dpg_status dpg_local_solve_range(dpg_plan plan, const dpg_problem* prob, int64_t
                                  const double* x, double* K, double* l, double* eta, int32_t* info,
                                  int32_t precision, void* stream);
 
+/* Degree groups of one solve run on parallel branches (enable = 1, the
+ * default): each group's launches go to its own stream, forked from and
+ * joined back into the caller's stream with events; with enable = 0 the
+ * groups run one after the other on the caller's stream.  Results are the
+ * same bit for bit either way.  Host only; affects later solves and graphs. */
+dpg_status dpg_plan_set_concurrency(dpg_plan plan, int32_t enable);
+
+/* Autotuner of the batching: after one warm-up solve, for each degree group
+ * (queue order) it times whole solves of all n_cells cells with 1, 1/2 and
+ * 1/4 of the group's chunk per launch sequence and keeps the fastest, then
+ * times the concurrent schedule against the sequential one and keeps the
+ * faster.
+ * Arguments as dpg_local_solve (all cells); the outputs hold a complete
+ * solve with the chosen settings on return.  *best_ms (may be NULL)
+ * receives the time of that last solve.  Synchronises `stream`. */
+dpg_status dpg_plan_autotune(dpg_plan plan, const dpg_problem* prob, const double* x, double* K, double* l,
+                             double* eta, int32_t* info, int32_t precision, void* stream, double* best_ms);
+
+/* Current batching of degree p: cells per launch sequence and whether the
+ * concurrent schedule is on.  Host only. */
+dpg_status dpg_plan_tuning(dpg_plan plan, int32_t p, int64_t* run_chunk, int32_t* concurrent);
+
+/* Captures dpg_local_solve_range(plan, prob, first, count, x, K, l, eta,
+ * info, precision) into a HIP graph (degree groups as parallel branches when
+ * concurrency is on) for replay with dpg_graph_launch.  The graph keeps the
+ * pointers it was captured with and the plan's workspace: the plan and the
+ * buffers must outlive it, and replays, solves and other graphs of the same
+ * plan must not overlap in time (they share the workspace).  Profiling is
+ * not recorded inside graphs.  Synchronous (capture happens on a private
+ * stream; nothing runs until a launch).  count = 0 gives an empty graph. */
+dpg_status dpg_graph_create(dpg_plan plan, const dpg_problem* prob, int64_t first, int64_t count,
+                            const double* x, double* K, double* l, double* eta, int32_t* info,
+                            int32_t precision, dpg_graph* graph);
+
+/* Enqueues one replay of the graph on `stream` (a hipStream_t, NULL = the
+ * default stream). */
+dpg_status dpg_graph_launch(dpg_graph graph, void* stream);
+
+dpg_status dpg_graph_destroy(dpg_graph graph);
+
 /* Debug/parity entry: the unscaled local matrices of `count` consecutive
  * cells first, first+1, ... which must all have the plan's degree p.
  * Device outputs, complex, column-major per cell:
@@ -184,7 +232,8 @@ dpg_status dpg_local_solve_range(dpg_plan plan, const dpg_problem* prob, int64_t
  *   contiguous: Bf[c][a][i] = B_f(i, a)), lvec [count][n_test].
  * Row order of the test space: F functions (3 s (s+1)^2, component-major,
  * then x-, y-, z-degree with x fastest, orthonormal shifted Legendre factors),
- * then I functions in the same order. */
+ * then I functions in the same order.  info [count]: geometry status of cell
+ * first + c at index c.  Synchronises `stream`. */
 dpg_status dpg_form_local(dpg_plan plan, const dpg_problem* prob, int64_t first, int64_t count,
                           double* G, double* Bf, double* lvec, int32_t* info, void* stream);
 
@@ -205,7 +254,9 @@ enum {
 
 /* Enables (1) or disables (0) per-kernel timing: while enabled, every kernel
  * launch of dpg_local_solve is bracketed by HIP events recorded on the
- * caller's stream.  Host only; takes effect for later solves. */
+ * stream it runs on (a group's branch stream under the concurrent schedule,
+ * where concurrent kernels share the device).  Host only; takes effect for
+ * later solves. */
 dpg_status dpg_plan_set_profiling(dpg_plan plan, int32_t enable);
 
 /* Waits for the recorded events and returns, per kernel class, the summed

@@ -27,8 +27,30 @@ struct DegreeGroup {
   std::vector<void*> bufs;            // device table allocations
   std::vector<int64_t> cells;         // global cell ids of this degree, ascending
   int64_t* cells_dev = nullptr;
-  int64_t chunk = 0;                  // cells per chunk
+  int64_t chunk = 0;                  // cells per chunk (workspace capacity)
+  int64_t run_chunk = 0;              // cells per launch sequence (<= chunk; autotuned)
+  double cost = 0.0;                  // algorithmic flops of all its cells (queue order)
+  int64_t per_cell = 0;               // workspace bytes per cell
+  // workspace of this group alone, so that groups can run concurrently
+  double2* Z = nullptr;
+  double* dscale = nullptr;
+  double* met = nullptr;
+  uint16_t* wsplit = nullptr;
+  hipStream_t stream = nullptr;       // branch stream of the concurrent schedule
+  hipEvent_t done = nullptr;
 };
+
+// Algorithmic flops of one cell (structure-aware counts: formation of the
+// real S, M, C, D, R, T contractions, complex Cholesky, triangular solves,
+// HERK and the two GEMVs); only their ratios matter here (queue order and
+// workspace shares).
+double cell_flops(int p, int dp) {
+  const double s = p + dp + 1, r = p + 1, n1 = p + dp + 2;
+  const double N = 3 * s * (s + 1) * (s + 1), nv = 2 * N, m1 = (p + 1.0) * (p + 1) * (p + 1);
+  const double nq = n1 * n1 * n1, nu = 6 * m1, nt = 24 * r * r, k = nu + nt;
+  return 12 * N * N * nq + 12 * N * m1 * nq + 48 * N * r * (r + 1) * n1 * n1 + 4.0 / 3.0 * nv * nv * nv +
+         4 * nv * nv * nu + 2 * nv * nv * nt + 4 * k * k * nv + 32 * nv * k;
+}
 
 }  // namespace
 
@@ -39,13 +61,17 @@ struct dpg_plan_s {
   std::vector<int64_t> K_off, v_off;
   int64_t* K_off_dev = nullptr;
   int64_t* v_off_dev = nullptr;
-  std::vector<DegreeGroup> groups;
-  double2* Z = nullptr;
-  double* dscale = nullptr;
-  double* met = nullptr;
-  uint16_t* wsplit = nullptr;
+  std::vector<DegreeGroup> groups;    // in queue order: decreasing total cost
   std::vector<void*> misc;            // other device allocations
+  hipEvent_t fork = nullptr;
+  bool concurrent = true;             // degree groups on parallel branches
   dpg::Prof prof;
+};
+
+struct dpg_graph_s {
+  int device = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
 
 namespace {
@@ -152,17 +178,20 @@ void free_plan(dpg_plan_s* p) {
   for (auto& g : p->groups) {
     for (void* b : g.bufs) (void)hipFree(b);
     if (g.cells_dev) (void)hipFree(g.cells_dev);
+    if (g.Z) (void)hipFree(g.Z);
+    if (g.dscale) (void)hipFree(g.dscale);
+    if (g.met) (void)hipFree(g.met);
+    if (g.wsplit) (void)hipFree(g.wsplit);
+    if (g.stream) (void)hipStreamDestroy(g.stream);
+    if (g.done) (void)hipEventDestroy(g.done);
   }
+  if (p->fork) (void)hipEventDestroy(p->fork);
   for (void* b : p->misc) (void)hipFree(b);
   for (auto& r : p->prof.recs) {
     (void)hipEventDestroy(r.b);
     (void)hipEventDestroy(r.e);
   }
   for (auto e : p->prof.pool) (void)hipEventDestroy(e);
-  if (p->Z) (void)hipFree(p->Z);
-  if (p->dscale) (void)hipFree(p->dscale);
-  if (p->met) (void)hipFree(p->met);
-  if (p->wsplit) (void)hipFree(p->wsplit);
   delete p;
 }
 
@@ -196,6 +225,79 @@ bool make_prob_args(const dpg_problem* pr, dpg::ProbArgs& pa) {
     pa.has_port = 1;
   }
   return true;
+}
+
+dpg_status check_solve_args(dpg_plan plan, const dpg_problem* prob, int64_t first, int64_t count, const double* K,
+                            const double* l, const double* eta, const int32_t* info, int32_t precision,
+                            dpg::ProbArgs& pa) {
+  if (!plan || first < 0 || count < 0 || first + count > plan->n_cells) return DPG_ERR_ARG;
+  if (count > 0 && (!K || !l || !eta || !info)) return DPG_ERR_ARG;
+  if (precision != DPG_FP64 && precision != DPG_SPLIT_FP32) return DPG_ERR_ARG;
+  if (!make_prob_args(prob, pa) || prob->n_cells != plan->n_cells) return DPG_ERR_ARG;
+  return DPG_OK;
+}
+
+// Enqueues the local solve of cells [first, first + count) on `st`.  Degree
+// groups are taken in queue order (decreasing cost); with concurrency on and
+// more than one group in the range, each group runs on its own branch
+// stream, forked from and joined back into `st` with events, so that the
+// launches of cheap degrees fill the tails of the expensive ones.  Under
+// stream capture the branches become parallel branches of the graph.
+dpg_status enqueue_solve(dpg_plan P, const dpg::ProbArgs& pa, int64_t first, int64_t count, const double* x,
+                         double* K, double* l, double* eta, int32_t* info, int32_t precision, hipStream_t st,
+                         bool profile) {
+  struct Job {
+    DegreeGroup* g;
+    int64_t lo, hi;
+  };
+  std::vector<Job> jobs;
+  for (auto& g : P->groups) {
+    // this degree's cells inside [first, first + count): a contiguous run of its sorted list
+    const int64_t lo = std::lower_bound(g.cells.begin(), g.cells.end(), first) - g.cells.begin();
+    const int64_t hi = std::lower_bound(g.cells.begin(), g.cells.end(), first + count) - g.cells.begin();
+    if (hi > lo) jobs.push_back({&g, lo, hi});
+  }
+  const bool par = P->concurrent && jobs.size() > 1;
+  hipError_t e = hipSuccess;
+  if (par) e = hipEventRecord(P->fork, st);
+  for (const Job& jb : jobs) {
+    DegreeGroup& g = *jb.g;
+    hipStream_t s = par ? g.stream : st;
+    if (par && e == hipSuccess) e = hipStreamWaitEvent(s, P->fork, 0);
+    for (int64_t s0 = jb.lo; s0 < jb.hi && e == hipSuccess; s0 += g.run_chunk) {
+      dpg::ChunkArgs ca{};
+      ca.cell_ids = g.cells_dev + s0;
+      ca.n = std::min<int64_t>(g.run_chunk, jb.hi - s0);
+      ca.Z = g.Z;
+      ca.dscale = g.dscale;
+      ca.met = g.met;
+      ca.wsplit = g.wsplit;
+      ca.split = precision == DPG_SPLIT_FP32 ? 1 : 0;
+      ca.K_off = P->K_off_dev;
+      ca.v_off = P->v_off_dev;
+      ca.cell_base = first;
+      ca.K_base = P->K_off[first];
+      ca.v_base = P->v_off[first];
+      ca.x = reinterpret_cast<const double2*>(x);
+      ca.K = reinterpret_cast<double2*>(K);
+      ca.l = reinterpret_cast<double2*>(l);
+      ca.eta = eta;
+      ca.info = info;
+      dpg::Prof* pr = profile ? &P->prof : nullptr;
+      e = dpg::launch_formation(g.dt, pa, ca, s, pr);
+      if (e == hipSuccess) e = dpg::launch_factor(g.dt, ca, s, pr);
+      if (e == hipSuccess) e = dpg::launch_herk(g.dt, ca, s, pr);
+    }
+    if (par && e == hipSuccess) e = hipEventRecord(g.done, s);
+  }
+  if (par)
+    for (const Job& jb : jobs)
+      if (e == hipSuccess) e = hipStreamWaitEvent(st, jb.g->done, 0);
+  if (e != hipSuccess) {
+    set_error("dpg local solve enqueue", e);
+    return DPG_ERR_HIP;
+  }
+  return DPG_OK;
 }
 
 }  // namespace
@@ -261,34 +363,73 @@ dpg_status dpg_plan_create(int32_t device, const int8_t* degree_host, int64_t n_
       g.cells_dev = upload(tmp, g.cells);
       P->groups.push_back(std::move(g));
     }
+    // queue order: most expensive degree first
+    for (auto& g : P->groups) g.cost = cell_flops(g.p, dp) * (double)g.cells.size();
+    std::stable_sort(P->groups.begin(), P->groups.end(),
+                     [](const DegreeGroup& a, const DegreeGroup& b) { return a.cost > b.cost; });
     size_t free_b = 0, total_b = 0;
     HIP_CHECK(hipMemGetInfo(&free_b, &total_b));
-    int64_t budget = max_workspace_bytes > 0 ? max_workspace_bytes : (int64_t)(0.4 * (double)free_b);
-    size_t zmax = 0, dmax = 0, mmax = 0, smax = 0;
+    const double budget = max_workspace_bytes > 0 ? (double)max_workspace_bytes : 0.4 * (double)free_b;
     for (auto& g : P->groups) {
       const int64_t mper = 12 * (int64_t)g.d.nq + 36 * (int64_t)g.d.nfq;
-      const int64_t sper = dpg::split_elems(g.dt);
-      const int64_t per = g.dt.zstride * 16 + (int64_t)g.d.nvp * 8 + mper * 8 + sper * 2;
-      int64_t ch = std::max<int64_t>(1, budget / per);
-      ch = std::min<int64_t>(ch, (int64_t)g.cells.size());
-      g.chunk = ch;
-      zmax = std::max(zmax, (size_t)ch * g.dt.zstride * 16);
-      dmax = std::max(dmax, (size_t)ch * g.d.nvp * 8);
-      mmax = std::max(mmax, (size_t)(ch * mper * 8));
-      smax = std::max(smax, (size_t)(ch * sper * 2));
+      g.per_cell = g.dt.zstride * 16 + (int64_t)g.d.nvp * 8 + mper * 8 + dpg::split_elems(g.dt) * 2;
     }
-    if (zmax) {
-      if (hipMalloc(reinterpret_cast<void**>(&P->Z), zmax) != hipSuccess) {
+    // Each group first gets room for min(cells, kMinChunk) cells, so that even
+    // a cheap degree's launches fill the device; the rest of the budget is
+    // shared in proportion to cost, capped at what all a group's cells need
+    // (water filling over the remaining groups).
+    constexpr int64_t kMinChunk = 1024;
+    double base = 0.0;
+    for (auto& g : P->groups) base += (double)g.per_cell * (double)std::min<int64_t>(kMinChunk, g.cells.size());
+    const double bscale = base > budget ? budget / base : 1.0;
+    std::vector<int64_t> base_cells(P->groups.size());
+    for (size_t q = 0; q < P->groups.size(); ++q)
+      base_cells[q] = (int64_t)(bscale * (double)std::min<int64_t>(kMinChunk, P->groups[q].cells.size()));
+    std::vector<int> open(P->groups.size());
+    for (size_t q = 0; q < open.size(); ++q) open[q] = (int)q;
+    double left = std::max(0.0, budget - bscale * base);
+    for (bool capped = true; capped && !open.empty();) {
+      capped = false;
+      double csum = 0.0;
+      for (int q : open) csum += P->groups[q].cost;
+      std::vector<int> keep;
+      double used = 0.0;
+      for (int q : open) {
+        DegreeGroup& g = P->groups[q];
+        const double need = (double)g.per_cell * (double)(g.cells.size() - base_cells[q]);
+        if (left * g.cost / csum >= need) {
+          g.chunk = (int64_t)g.cells.size();
+          used += need;
+          capped = true;
+        } else {
+          keep.push_back(q);
+        }
+      }
+      if (capped) {
+        left -= used;
+        open.swap(keep);
+      } else {
+        for (int q : open) {
+          DegreeGroup& g = P->groups[q];
+          const int64_t ch = base_cells[q] + (int64_t)(left * g.cost / csum / (double)g.per_cell);
+          g.chunk = std::max<int64_t>(1, std::min<int64_t>(ch, (int64_t)g.cells.size()));
+        }
+      }
+    }
+    for (auto& g : P->groups) {
+      g.run_chunk = g.chunk;
+      const int64_t mper = 12 * (int64_t)g.d.nq + 36 * (int64_t)g.d.nfq;
+      if (hipMalloc(reinterpret_cast<void**>(&g.Z), (size_t)g.chunk * g.dt.zstride * 16) != hipSuccess ||
+          hipMalloc(reinterpret_cast<void**>(&g.dscale), (size_t)g.chunk * g.d.nvp * 8) != hipSuccess ||
+          hipMalloc(reinterpret_cast<void**>(&g.met), (size_t)g.chunk * mper * 8) != hipSuccess ||
+          hipMalloc(reinterpret_cast<void**>(&g.wsplit), (size_t)g.chunk * dpg::split_elems(g.dt) * 2) != hipSuccess) {
         free_plan(P);
         return DPG_ERR_ALLOC;
       }
-      if (hipMalloc(reinterpret_cast<void**>(&P->dscale), dmax) != hipSuccess ||
-          hipMalloc(reinterpret_cast<void**>(&P->met), mmax) != hipSuccess ||
-          hipMalloc(reinterpret_cast<void**>(&P->wsplit), smax) != hipSuccess) {
-        free_plan(P);
-        return DPG_ERR_ALLOC;
-      }
+      HIP_CHECK(hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking));
+      HIP_CHECK(hipEventCreateWithFlags(&g.done, hipEventDisableTiming));
     }
+    HIP_CHECK(hipEventCreateWithFlags(&P->fork, hipEventDisableTiming));
     *plan = P;
     return DPG_OK;
   } catch (const HipError&) {
@@ -333,48 +474,12 @@ dpg_status dpg_plan_layout(dpg_plan plan, int32_t p, int64_t* n_test_padded, int
 dpg_status dpg_local_solve_range(dpg_plan plan, const dpg_problem* prob, int64_t first, int64_t count,
                                  const double* x, double* K, double* l, double* eta, int32_t* info,
                                  int32_t precision, void* stream) {
-  if (!plan || first < 0 || count < 0 || first + count > plan->n_cells) return DPG_ERR_ARG;
-  if (count > 0 && (!K || !l || !eta || !info)) return DPG_ERR_ARG;
-  if (precision != DPG_FP64 && precision != DPG_SPLIT_FP32) return DPG_ERR_ARG;
   dpg::ProbArgs pa;
-  if (!make_prob_args(prob, pa) || prob->n_cells != plan->n_cells) return DPG_ERR_ARG;
-  if (count == 0) return DPG_OK;
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const dpg_status rc = check_solve_args(plan, prob, first, count, K, l, eta, info, precision, pa);
+  if (rc != DPG_OK || count == 0) return rc;
   if (hipSetDevice(plan->device) != hipSuccess) return DPG_ERR_HIP;
-  for (auto& g : plan->groups) {
-    // this degree's cells inside [first, first + count): a contiguous run of its sorted list
-    const int64_t lo = std::lower_bound(g.cells.begin(), g.cells.end(), first) - g.cells.begin();
-    const int64_t hi = std::lower_bound(g.cells.begin(), g.cells.end(), first + count) - g.cells.begin();
-    for (int64_t s0 = lo; s0 < hi; s0 += g.chunk) {
-      dpg::ChunkArgs ca{};
-      ca.cell_ids = g.cells_dev + s0;
-      ca.n = std::min<int64_t>(g.chunk, hi - s0);
-      ca.Z = plan->Z;
-      ca.dscale = plan->dscale;
-      ca.met = plan->met;
-      ca.wsplit = plan->wsplit;
-      ca.split = precision == DPG_SPLIT_FP32 ? 1 : 0;
-      ca.K_off = plan->K_off_dev;
-      ca.v_off = plan->v_off_dev;
-      ca.cell_base = first;
-      ca.K_base = plan->K_off[first];
-      ca.v_base = plan->v_off[first];
-      ca.x = reinterpret_cast<const double2*>(x);
-      ca.K = reinterpret_cast<double2*>(K);
-      ca.l = reinterpret_cast<double2*>(l);
-      ca.eta = eta;
-      ca.info = info;
-      dpg::Prof* pr = plan->prof.on ? &plan->prof : nullptr;
-      hipError_t e = dpg::launch_formation(g.dt, pa, ca, st, pr);
-      if (e == hipSuccess) e = dpg::launch_factor(g.dt, ca, st, pr);
-      if (e == hipSuccess) e = dpg::launch_herk(g.dt, ca, st, pr);
-      if (e != hipSuccess) {
-        set_error("dpg_local_solve launch", e);
-        return DPG_ERR_HIP;
-      }
-    }
-  }
-  return DPG_OK;
+  return enqueue_solve(plan, pa, first, count, x, K, l, eta, info, precision,
+                       reinterpret_cast<hipStream_t>(stream), plan->prof.on);
 }
 
 dpg_status dpg_local_solve(dpg_plan plan, const dpg_problem* prob, const double* x, double* K, double* l,
@@ -382,6 +487,146 @@ dpg_status dpg_local_solve(dpg_plan plan, const dpg_problem* prob, const double*
   if (!plan) return DPG_ERR_ARG;
   if (plan->n_cells > 0 && (!K || !l || !eta || !info)) return DPG_ERR_ARG;
   return dpg_local_solve_range(plan, prob, 0, plan->n_cells, x, K, l, eta, info, precision, stream);
+}
+
+dpg_status dpg_plan_set_concurrency(dpg_plan plan, int32_t enable) {
+  if (!plan) return DPG_ERR_ARG;
+  plan->concurrent = enable != 0;
+  return DPG_OK;
+}
+
+dpg_status dpg_plan_autotune(dpg_plan plan, const dpg_problem* prob, const double* x, double* K, double* l,
+                             double* eta, int32_t* info, int32_t precision, void* stream, double* best_ms) {
+  dpg::ProbArgs pa;
+  dpg_status rc = check_solve_args(plan, prob, 0, plan ? plan->n_cells : 0, K, l, eta, info, precision, pa);
+  if (rc != DPG_OK) return rc;
+  if (hipSetDevice(plan->device) != hipSuccess) return DPG_ERR_HIP;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) return DPG_ERR_HIP;
+  // Times one whole solve with the plan's current settings.
+  auto timed = [&](float& ms) -> dpg_status {
+    ms = 0.f;
+    if (hipEventRecord(t0, st) != hipSuccess) return DPG_ERR_HIP;
+    const dpg_status r = enqueue_solve(plan, pa, 0, plan->n_cells, x, K, l, eta, info, precision, st, false);
+    if (r != DPG_OK) return r;
+    if (hipEventRecord(t1, st) != hipSuccess || hipEventSynchronize(t1) != hipSuccess ||
+        hipEventElapsedTime(&ms, t0, t1) != hipSuccess)
+      return DPG_ERR_HIP;
+    return DPG_OK;
+  };
+  const bool conc0 = plan->concurrent;
+  float best = 0.f;
+  {
+    float warm = 0.f;   // first touch of tables, workspace and outputs
+    rc = timed(warm);
+  }
+  // 1. cells per launch sequence of each degree group, the others fixed
+  plan->concurrent = false;
+  for (auto& g : plan->groups) {
+    if (rc != DPG_OK) break;
+    int64_t cand[3] = {g.chunk, (g.chunk + 1) / 2, (g.chunk + 3) / 4};
+    int64_t pick = g.chunk;
+    float pick_ms = 0.f;
+    for (int c = 0; c < 3 && rc == DPG_OK; ++c) {
+      if (c > 0 && cand[c] == cand[c - 1]) continue;
+      g.run_chunk = cand[c];
+      float ms = 0.f;
+      rc = timed(ms);
+      if (rc == DPG_OK && (c == 0 || ms < pick_ms)) {
+        pick_ms = ms;
+        pick = cand[c];
+      }
+    }
+    g.run_chunk = pick;
+    best = pick_ms;
+  }
+  // 2. concurrent degree branches or one stream
+  if (rc == DPG_OK && plan->groups.size() > 1) {
+    plan->concurrent = true;
+    float ms = 0.f;
+    rc = timed(ms);
+    if (rc == DPG_OK) {
+      if (ms < best) best = ms;
+      else plan->concurrent = false;
+    }
+  }
+  if (rc != DPG_OK) plan->concurrent = conc0;
+  // leave the outputs of the chosen settings
+  float ms = 0.f;
+  if (rc == DPG_OK) rc = timed(ms);
+  if (best_ms) *best_ms = rc == DPG_OK ? (double)ms : 0.0;
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  return rc;
+}
+
+dpg_status dpg_plan_tuning(dpg_plan plan, int32_t p, int64_t* run_chunk, int32_t* concurrent) {
+  if (!plan || !run_chunk || !concurrent) return DPG_ERR_ARG;
+  for (auto& g : plan->groups)
+    if (g.p == p) {
+      *run_chunk = g.run_chunk;
+      *concurrent = plan->concurrent ? 1 : 0;
+      return DPG_OK;
+    }
+  return DPG_ERR_ARG;
+}
+
+dpg_status dpg_graph_create(dpg_plan plan, const dpg_problem* prob, int64_t first, int64_t count, const double* x,
+                            double* K, double* l, double* eta, int32_t* info, int32_t precision, dpg_graph* out) {
+  if (!out) return DPG_ERR_ARG;
+  *out = nullptr;
+  dpg::ProbArgs pa;
+  dpg_status rc = check_solve_args(plan, prob, first, count, K, l, eta, info, precision, pa);
+  if (rc != DPG_OK) return rc;
+  if (hipSetDevice(plan->device) != hipSuccess) return DPG_ERR_HIP;
+  dpg_graph_s* G = new (std::nothrow) dpg_graph_s();
+  if (!G) return DPG_ERR_ALLOC;
+  G->device = plan->device;
+  if (count > 0) {
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      rc = enqueue_solve(plan, pa, first, count, x, K, l, eta, info, precision, cs, false);
+      hipGraph_t g = nullptr;
+      e = hipStreamEndCapture(cs, &g);   // always ends the capture
+      G->graph = g;
+      if (e == hipSuccess && rc == DPG_OK) e = hipGraphInstantiate(&G->exec, g, nullptr, nullptr, 0);
+    }
+    if (cs) (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+      set_error("dpg_graph_create", e);
+      if (rc == DPG_OK) rc = DPG_ERR_HIP;
+    }
+  }
+  if (rc != DPG_OK) {
+    (void)dpg_graph_destroy(G);
+    return rc;
+  }
+  *out = G;
+  return DPG_OK;
+}
+
+dpg_status dpg_graph_launch(dpg_graph graph, void* stream) {
+  if (!graph) return DPG_ERR_ARG;
+  if (!graph->exec) return DPG_OK;   // empty range
+  if (hipSetDevice(graph->device) != hipSuccess) return DPG_ERR_HIP;
+  const hipError_t e = hipGraphLaunch(graph->exec, reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) {
+    set_error("dpg_graph_launch", e);
+    return DPG_ERR_HIP;
+  }
+  return DPG_OK;
+}
+
+dpg_status dpg_graph_destroy(dpg_graph graph) {
+  if (!graph) return DPG_ERR_ARG;
+  (void)hipSetDevice(graph->device);
+  if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+  if (graph->graph) (void)hipGraphDestroy(graph->graph);
+  delete graph;
+  return DPG_OK;
 }
 
 dpg_status dpg_plan_set_profiling(dpg_plan plan, int32_t enable) {
@@ -445,11 +690,12 @@ dpg_status dpg_form_local(dpg_plan plan, const dpg_problem* prob, int64_t first,
     dpg::ChunkArgs ca{};
     ca.cell_ids = ids_dev + s0;
     ca.n = std::min<int64_t>(grp->chunk, count - s0);
-    ca.Z = plan->Z;
-    ca.dscale = plan->dscale;
-    ca.met = plan->met;
+    ca.Z = grp->Z;
+    ca.dscale = grp->dscale;
+    ca.met = grp->met;
     ca.K_off = plan->K_off_dev;
     ca.v_off = plan->v_off_dev;
+    ca.cell_base = first;
     ca.x = nullptr;
     ca.info = info;
     if (dpg::launch_formation(grp->dt, pa, ca, st) != hipSuccess ||

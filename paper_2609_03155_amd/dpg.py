@@ -21,8 +21,9 @@ DPG_FP64, DPG_SPLIT_FP32 = 0, 1
 FACE_INTERIOR, FACE_PEC, FACE_PORT, FACE_ROBIN0 = 0, 1, 2, 3
 
 EXPORTS = ("dpg_local_dims", "dpg_plan_create", "dpg_plan_destroy", "dpg_plan_offsets", "dpg_plan_layout",
-           "dpg_local_solve", "dpg_local_solve_range", "dpg_form_local", "dpg_plan_set_profiling", "dpg_plan_profile", "dpg_status_string",
-           "dpg_last_error")
+           "dpg_local_solve", "dpg_local_solve_range", "dpg_plan_set_concurrency", "dpg_plan_autotune",
+           "dpg_plan_tuning", "dpg_graph_create", "dpg_graph_launch", "dpg_graph_destroy", "dpg_form_local",
+           "dpg_plan_set_profiling", "dpg_plan_profile", "dpg_status_string", "dpg_last_error")
 KERNEL_CLASSES = ("scale", "form_SM", "form_IF", "form_pad", "form_B", "form_load", "resid", "chol_diag",
                   "chol_panel", "herk")
 
@@ -61,6 +62,12 @@ def lib():
         L.dpg_plan_layout.argtypes = [vp, i32, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
         L.dpg_local_solve.argtypes = [vp, C.POINTER(dpg_problem), vp, vp, vp, vp, vp, i32, vp]
         L.dpg_local_solve_range.argtypes = [vp, C.POINTER(dpg_problem), i64, i64, vp, vp, vp, vp, vp, i32, vp]
+        L.dpg_plan_set_concurrency.argtypes = [vp, i32]
+        L.dpg_plan_autotune.argtypes = [vp, C.POINTER(dpg_problem), vp, vp, vp, vp, vp, i32, vp, C.POINTER(dp_)]
+        L.dpg_plan_tuning.argtypes = [vp, i32, C.POINTER(i64), C.POINTER(i32)]
+        L.dpg_graph_create.argtypes = [vp, C.POINTER(dpg_problem), i64, i64, vp, vp, vp, vp, vp, i32, C.POINTER(vp)]
+        L.dpg_graph_launch.argtypes = [vp, vp]
+        L.dpg_graph_destroy.argtypes = [vp]
         L.dpg_form_local.argtypes = [vp, C.POINTER(dpg_problem), i64, i64, vp, vp, vp, vp, vp]
         L.dpg_plan_set_profiling.argtypes = [vp, i32]
         L.dpg_plan_profile.argtypes = [vp, vp, vp]
@@ -68,11 +75,9 @@ def lib():
         L.dpg_status_string.restype = C.c_char_p
         L.dpg_last_error.argtypes = []
         L.dpg_last_error.restype = C.c_char_p
-        for name in ("dpg_local_dims", "dpg_plan_create", "dpg_plan_destroy", "dpg_plan_offsets",
-                     "dpg_plan_layout", "dpg_local_solve", "dpg_local_solve_range", "dpg_form_local",
-                     "dpg_plan_set_profiling",
-                     "dpg_plan_profile"):
-            getattr(L, name).restype = i32
+        for name in EXPORTS:
+            if name not in ("dpg_status_string", "dpg_last_error"):
+                getattr(L, name).restype = i32
         _lib = L
     return _lib
 
@@ -208,6 +213,34 @@ class Plan:
                                            _ptr(eta), _ptr(info), int(precision), _stream(stream)),
                "dpg_local_solve_range")
 
+    def set_concurrency(self, enable: bool):
+        _check(lib().dpg_plan_set_concurrency(self._h, int(bool(enable))), "dpg_plan_set_concurrency")
+
+    def autotune(self, prob: DeviceProblem, x, K, l, eta, info, precision: int = DPG_FP64, stream=None) -> float:
+        """dpg_plan_autotune: returns the time (ms) of a solve with the chosen batching."""
+        s = prob.cstruct()
+        ms = C.c_double()
+        _check(lib().dpg_plan_autotune(self._h, C.byref(s), _ptr(x), _ptr(K), _ptr(l), _ptr(eta), _ptr(info),
+                                       int(precision), _stream(stream), C.byref(ms)), "dpg_plan_autotune")
+        return ms.value
+
+    def tuning(self, p: int):
+        """(cells per launch sequence of degree p, concurrent schedule on?)"""
+        a, b = C.c_int64(), C.c_int32()
+        _check(lib().dpg_plan_tuning(self._h, int(p), C.byref(a), C.byref(b)), "dpg_plan_tuning")
+        return a.value, bool(b.value)
+
+    def graph(self, prob: DeviceProblem, x, K, l, eta, info, precision: int = DPG_FP64, first: int = 0,
+              count: int = None) -> "Graph":
+        """dpg_graph_create: the solve of cells first..first+count-1 as a replayable HIP graph."""
+        if count is None:
+            count = self.n_cells - first
+        s = prob.cstruct()
+        h = C.c_void_p()
+        _check(lib().dpg_graph_create(self._h, C.byref(s), int(first), int(count), _ptr(x), _ptr(K), _ptr(l),
+                                      _ptr(eta), _ptr(info), int(precision), C.byref(h)), "dpg_graph_create")
+        return Graph(h, (self, prob, x, K, l, eta, info))
+
     def range_sizes(self, first: int, count: int):
         """(K elements, l/x elements) of the outputs of a range solve."""
         return (int(self.K_off[first + count] - self.K_off[first]), int(self.v_off[first + count] - self.v_off[first]))
@@ -222,12 +255,34 @@ class Plan:
         G = torch.empty((count, nt, nt), dtype=torch.complex128, device=dev)
         Bf = torch.empty((count, k, nt), dtype=torch.complex128, device=dev)
         lv = torch.empty((count, nt), dtype=torch.complex128, device=dev)
-        info = torch.zeros(self.n_cells, dtype=torch.int32, device=dev)
+        info = torch.zeros(count, dtype=torch.int32, device=dev)
         s = prob.cstruct()
         _check(lib().dpg_form_local(self._h, C.byref(s), int(first), int(count), _ptr(G), _ptr(Bf), _ptr(lv),
                                     _ptr(info), _stream(stream)), "dpg_form_local")
         # column-major per cell: G[c][col][row] -> transpose to [row][col]
         return G.transpose(1, 2), Bf.transpose(1, 2), lv, info
+
+
+class Graph:
+    """A captured solve (dpg_graph_create); keeps the plan and buffers it references alive."""
+
+    def __init__(self, handle, keep):
+        self._h = handle
+        self._keep = keep
+
+    def launch(self, stream=None):
+        _check(lib().dpg_graph_launch(self._h, _stream(stream)), "dpg_graph_launch")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().dpg_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def cell_view(plan: Plan, K, l, c: int):

@@ -343,3 +343,111 @@ def test_split_precision_mixed_degrees():
     plan, K, l, eta, info = _run(w, x, precision=1)
     assert np.all(info == 0)
     _check_split(w, (0, 1, 2, 3), plan, K, l, eta, x, off)
+
+
+# ------------------------------------------------------------ batching, graphs, autotuner
+def _mixed36():
+    w = W.config3(nx=3, ny=3, nz=4)
+    w.degree[:] = np.array([1, 2, 3, 4, 2, 1, 3] * 6, np.int8)[: w.n_cells]
+    return w
+
+
+def _host(*ts):
+    return tuple(t.cpu().numpy() for t in ts)
+
+
+def test_concurrent_and_sequential_schedules_agree_bitwise():
+    torch = _torch()
+    from paper_2609_03155_amd import dpg
+    w = _mixed36()
+    x, off = W.random_coefficients(w)
+    plan = dpg.Plan(w.degree, w.dp)
+    prob = dpg.DeviceProblem.from_workload(w)
+    xd = torch.from_numpy(x).cuda()
+    outs = []
+    for conc in (True, False):
+        _say(f"case: mixed degrees, concurrent schedule {conc}")
+        plan.set_concurrency(conc)
+        K, l, eta, info = plan.alloc_outputs()
+        plan.local_solve(prob, xd, K, l, eta, info, dpg.DPG_SPLIT_FP32)
+        torch.cuda.synchronize()
+        outs.append(_host(K, l, eta, info))
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+    assert np.all(outs[0][3] == 0)
+
+
+@pytest.mark.parametrize("concurrent", [True, False])
+def test_graph_replays_match_eager_solve(concurrent):
+    """Every replay (with eager work and synchronisations in between) equals
+    the eager solve bit for bit; both precisions, a sub-range graph too."""
+    torch = _torch()
+    from paper_2609_03155_amd import dpg
+    w = _mixed36()
+    x, off = W.random_coefficients(w)
+    plan = dpg.Plan(w.degree, w.dp)
+    plan.set_concurrency(concurrent)
+    prob = dpg.DeviceProblem.from_workload(w)
+    xd = torch.from_numpy(x).cuda()
+    for precision in (dpg.DPG_FP64, dpg.DPG_SPLIT_FP32):
+        _say(f"case: graph replays, concurrent {concurrent}, precision {precision}")
+        K, l, eta, info = plan.alloc_outputs()
+        plan.local_solve(prob, xd, K, l, eta, info, precision)
+        torch.cuda.synchronize()
+        ref = _host(K, l, eta, info)
+        Kg, lg, eg, ig = plan.alloc_outputs()
+        g = plan.graph(prob, xd, Kg, lg, eg, ig, precision)
+        for rep in range(3):
+            for t in (Kg, lg, eg):
+                t.fill_(float("nan"))
+            ig.fill_(77)
+            torch.cuda.synchronize()
+            g.launch()
+            torch.cuda.synchronize()
+            got = _host(Kg, lg, eg, ig)
+            for a, b in zip(ref, got):
+                assert np.array_equal(a, b), rep
+            # eager work between replays
+            plan.local_solve(prob, xd, K, l, eta, info, precision)
+            torch.cuda.synchronize()
+        g.close()
+    # a graph of a sub-range writes range-relative outputs
+    a, b = 7, 29
+    nK, nv = plan.range_sizes(a, b - a)
+    Kr = torch.empty(nK, dtype=torch.complex128, device="cuda")
+    lr = torch.empty(nv, dtype=torch.complex128, device="cuda")
+    er = torch.empty(b - a, dtype=torch.float64, device="cuda")
+    ir = torch.empty(b - a, dtype=torch.int32, device="cuda")
+    xr = torch.from_numpy(x[off[a]:off[b]].copy()).cuda()
+    g = plan.graph(prob, xr, Kr, lr, er, ir, dpg.DPG_SPLIT_FP32, first=a, count=b - a)
+    g.launch()
+    torch.cuda.synchronize()
+    assert np.array_equal(Kr.cpu().numpy(), ref[0][plan.K_off[a]:plan.K_off[b]])
+    assert np.array_equal(er.cpu().numpy(), ref[2][a:b])
+    g.close()
+
+
+def test_autotune_keeps_results_and_reports_choice():
+    torch = _torch()
+    from paper_2609_03155_amd import dpg
+    w = _mixed36()
+    x, off = W.random_coefficients(w)
+    # a small budget forces several chunks per degree
+    plan = dpg.Plan(w.degree, w.dp, max_workspace_bytes=600 * 2 ** 20)
+    prob = dpg.DeviceProblem.from_workload(w)
+    xd = torch.from_numpy(x).cuda()
+    K, l, eta, info = plan.alloc_outputs()
+    plan.local_solve(prob, xd, K, l, eta, info)
+    torch.cuda.synchronize()
+    ref = _host(K, l, eta, info)
+    _say("case: autotune mixed degrees")
+    K2, l2, eta2, info2 = plan.alloc_outputs()
+    ms = plan.autotune(prob, xd, K2, l2, eta2, info2)
+    torch.cuda.synchronize()
+    assert ms > 0.0
+    for a, b in zip(ref, _host(K2, l2, eta2, info2)):
+        assert np.array_equal(a, b)
+    for p in (1, 2, 3, 4):
+        run, conc = plan.tuning(p)
+        cap = plan.layout(p)[2]
+        assert 1 <= run <= cap
