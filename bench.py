@@ -47,6 +47,27 @@ def algorithmic_flops(p: int, dp: int) -> dict:
                 vec=32 * nv * k)
 
 
+def measured_traffic(workload: str, precision: str, kernel: str):
+    """HBM bytes per launch of the dominant kernel class from the committed
+    rocprofv3 counter summaries (profiles/*.md), or None when none matches or
+    the kernel source has changed since the counters were taken."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_2609_03155_amd", "csrc", "dpg_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        kv = {}
+        for line in open(path):
+            line = line.strip()
+            if line.startswith("traffic_") and " = " in line:
+                k, v = line.split(" = ", 1)
+                kv[k] = v.strip()
+        if (kv.get("traffic_workload") == workload and kv.get("traffic_precision") == precision
+                and kv.get("traffic_kernel") == kernel and kv.get("traffic_source_sha256_prefix") == sha):
+            return float(kv["traffic_bytes_per_launch"])
+    return None
+
+
 def cpu_baseline(w, budget_s: float = 20.0):
     """The oracle, as it stands, on a bounded seeded sample of the workload's
     cells; returns (record, per-cell oracle outputs)."""
@@ -225,7 +246,9 @@ def main():
     form_keys = ("scale", "form_SM", "form_IF", "form_pad", "form_B", "form_load")
     classes = {k: v for k, v in prof.items() if v[1] > 0}
     dominant = max(classes, key=lambda k: classes[k][0])
+    dom_key = dominant
     if dominant in ("chol_diag", "chol_panel"):
+        dom_key = "chol_diag+chol_panel"
         dom_name = "chol_diag+chol_panel (blocked Cholesky + TRSM sweep, FP64)"
         dom_flops = (fl["chol"] + fl["trsm"]) * args.steps
         dom_ms = prof["chol_diag"][0] + prof["chol_panel"][0]
@@ -248,7 +271,8 @@ def main():
         "config": {"workload": w.name, "cells": w.n_cells, "degrees": sorted(set(int(v) for v in w.degree)),
                    "dp": w.dp, "freq_hz": w.freq_hz, "precision": head, "parallelism": "single-gpu"},
         "roofline": {"bound": "mfma", "kernel": dom_name, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                     "traffic": measured_traffic(w.name, head, dom_key), "traffic_unit": "HBM bytes per launch",
                      "launches_per_step": dom_launches / args.steps,
                      "avg_launch_ms": dom_ms / max(1, dom_launches)},
         "whole_step_tflops": total_alg / (ms_step * 1e-3) / 1e12,
