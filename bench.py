@@ -130,11 +130,12 @@ def main():
     prob = dpg.DeviceProblem.from_workload(w)
     xd = torch.from_numpy(x).cuda()
     stream = torch.cuda.current_stream()
-    # Outputs larger than about a third of the device are streamed: the step
-    # solves consecutive ranges of STREAM_CELLS cells into one reused output
-    # buffer (eta and info for all cells stay resident).
+    # Outputs that do not fit in 80% of the memory left after the plan's
+    # workspace are streamed: the step solves consecutive ranges of
+    # STREAM_CELLS cells into one reused output buffer (eta and info for all
+    # cells stay resident).
     free_b, _ = torch.cuda.mem_get_info()
-    streaming = int(plan.K_off[-1]) * 16 > free_b // 3
+    streaming = int(plan.K_off[-1]) * 16 > 0.8 * free_b
     if streaming:
         ranges = [(a, min(STREAM_CELLS, w.n_cells - a)) for a in range(0, w.n_cells, STREAM_CELLS)]
         nK = max(plan.range_sizes(a, n)[0] for a, n in ranges)

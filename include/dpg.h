@@ -141,7 +141,9 @@ dpg_status dpg_local_dims(int32_t p, int32_t dp, int32_t* n_test, int32_t* n_int
  * per-cell solve of Sec. 2.3 leaves free), orders the groups by decreasing
  * algorithmic cost (the work queue), builds the reference tables of each
  * degree on the device and gives each group its own workspace: room for
- * min(cells, 1024) cells, plus a share of the rest of max_workspace_bytes
+ * enough cells that a factorisation step has about 16384 row tiles (at
+ * least 64 cells, at most all of them), plus a share of the rest of
+ * max_workspace_bytes
  * (0 = 40% of the device memory free at creation) proportional to the
  * group's cost and capped at what all its cells need (all scaled down if
  * the budget is short); a group with more cells than its workspace holds

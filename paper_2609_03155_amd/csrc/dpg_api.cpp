@@ -374,17 +374,22 @@ dpg_status dpg_plan_create(int32_t device, const int8_t* degree_host, int64_t n_
       const int64_t mper = 12 * (int64_t)g.d.nq + 36 * (int64_t)g.d.nfq;
       g.per_cell = g.dt.zstride * 16 + (int64_t)g.d.nvp * 8 + mper * 8 + dpg::split_elems(g.dt) * 2;
     }
-    // Each group first gets room for min(cells, kMinChunk) cells, so that even
-    // a cheap degree's launches fill the device; the rest of the budget is
-    // shared in proportion to cost, capped at what all a group's cells need
-    // (water filling over the remaining groups).
-    constexpr int64_t kMinChunk = 1024;
-    double base = 0.0;
-    for (auto& g : P->groups) base += (double)g.per_cell * (double)std::min<int64_t>(kMinChunk, g.cells.size());
-    const double bscale = base > budget ? budget / base : 1.0;
+    // Each group first gets room for enough cells that one factorisation step
+    // has about kFillTiles row tiles (a few waves of workgroups on every CU),
+    // so that even a cheap degree's launches fill the device; the rest of the
+    // budget is shared in proportion to cost, capped at what all a group's
+    // cells need (water filling over the remaining groups).
+    constexpr int64_t kFillTiles = 16384;
     std::vector<int64_t> base_cells(P->groups.size());
-    for (size_t q = 0; q < P->groups.size(); ++q)
-      base_cells[q] = (int64_t)(bscale * (double)std::min<int64_t>(kMinChunk, P->groups[q].cells.size()));
+    double base = 0.0;
+    for (size_t q = 0; q < P->groups.size(); ++q) {
+      const DegreeGroup& g = P->groups[q];
+      const int64_t fill = std::max<int64_t>(64, kFillTiles / (g.d.nrows / 64));
+      base_cells[q] = std::min<int64_t>(fill, (int64_t)g.cells.size());
+      base += (double)g.per_cell * (double)base_cells[q];
+    }
+    const double bscale = base > budget ? budget / base : 1.0;
+    for (auto& b : base_cells) b = (int64_t)(bscale * (double)b);
     std::vector<int> open(P->groups.size());
     for (size_t q = 0; q < open.size(); ++q) open[q] = (int)q;
     double left = std::max(0.0, budget - bscale * base);
