@@ -118,7 +118,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (requested --gpus {args.gpus}); the per-cell local solve needs no "
-              "communication, see DESIGN.md for how it shards.", file=sys.stderr)
+              "communication: each GPU would run the same plan on its own contiguous, cost-balanced share of the cells.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -24,7 +24,7 @@ No block decomposition of G or B is used here; the solve is the plain
 definition X = G^{-1}[B_f l] via LU (numpy.linalg.solve), with a Cholesky route
 offered only as a cross-check.
 
-Readings of points the paper leaves open (each is listed in the design doc):
+Readings of points the paper leaves open:
   * spaces (§2.3): trial E,H = discontinuous tensor Lagrange of degree p per
     Cartesian component at Gauss-Lobatto nodes; trace = tangential traces of
     first-kind Nedelec functions of FEEC index r=p+1 with interior functions

@@ -302,7 +302,7 @@ def test_empty_batch():
 
 
 # ------------------------------------------------------------ split precision
-SPLIT_TOL = 1e-6     # spec bar of the split path for K_e and l_e; eta stays FP64
+SPLIT_TOL = 1e-6     # required bar of the split path for K_e and l_e; eta stays FP64
 
 
 def _check_split(w, cells, plan, K, l, eta, x, off):
