@@ -127,6 +127,7 @@ typedef struct {
 
 typedef struct dpg_plan_s* dpg_plan;
 typedef struct dpg_graph_s* dpg_graph;
+typedef struct dpg_trace_system_s* dpg_trace_system;
 
 /* Local sizes of a (p, dp) cell (Sec. 2.3 spaces): n_test = 6 s (s+1)^2
  * (F and I), n_interior = 6 (p+1)^3 (E and H), n_trace = 24 (p+1)^2
@@ -238,6 +239,83 @@ dpg_status dpg_graph_destroy(dpg_graph graph);
  * first + c at index c.  Synchronises `stream`. */
 dpg_status dpg_form_local(dpg_plan plan, const dpg_problem* prob, int64_t first, int64_t count,
                           double* G, double* Bf, double* lvec, int32_t* info, void* stream);
+
+/* ---------------------------------------------------------------------
+ * Condensed trace system (Sec. 2.3: static condensation of the interior
+ * unknowns; the global system in the trace unknowns that the paper solves
+ * by CG).  Cell matrices are ordered as K_e: interior [E, H] (n_u = 6 (p+1)^3)
+ * then trace [Ehat, Hhat] (n_t = 24 (p+1)^2), so
+ *   K_e = [[M1, M2], [M2^H, M3]],  l_e = [l_u ; l_t].
+ * --------------------------------------------------------------------- */
+
+/* Offsets, in complex elements, of the condensed cell outputs, written to
+ * HOST arrays of n_cells+1 entries: A_K of cell c occupies
+ * A[A_off[c] .. A_off[c+1]) (n_t x n_t, column-major, full Hermitian), b_K
+ * occupies b[b_off[c] .. b_off[c+1]) (n_t entries). */
+dpg_status dpg_plan_trace_offsets(dpg_plan plan, int64_t* A_off, int64_t* b_off);
+
+/* Condensation of every cell (Sec. 2.3):
+ *   A_K = M3 - M2^H M1^{-1} M2,   b_K = l_t - M2^H M1^{-1} l_u,
+ * from the K_e, l_e a dpg_local_solve of the same plan wrote (device, its
+ * layout).  On the GPU: a Jacobi-scaled blocked Cholesky of M1 with the rows
+ * (D M2)^H, (D l_u)^H appended (the local solve's factorisation kernels),
+ * a HERK of those rows, and the subtraction.  A, b: device outputs at the
+ * dpg_plan_trace_offsets offsets; info [n_cells]: 0, or the failing pivot
+ * column + 1 of M1.  Uses the plan's workspace (do not overlap with a solve
+ * of the same plan).  Stream-ordered. */
+dpg_status dpg_condense(dpg_plan plan, const double* K, const double* l, double* A, double* b, int32_t* info,
+                        void* stream);
+
+/* Numbering of the global trace unknowns and the CSR structure of
+ *   A = sum_K P_K^T A_K P_K,  b = sum_K P_K^T b_K
+ * for the plan's cells.  cells_host [n][8] (vertex ids, v(i,j,k) at 4k+2j+i)
+ * and face_kind_host [n][6] are HOST arrays.  Rules:
+ *   - local trace functions of a cell (Ehat then Hhat, 12 r^2 each) live on
+ *     its 12 edges (r each; edges along x at (y,z) = (0,0),(1,0),(0,1),(1,1),
+ *     then along y, then z) or 6 faces (2 r (r-1) each; faces x-,x+,y-,y+,
+ *     z-,z+; first the functions whose component is the lower tangential
+ *     axis, then the other; bubble degree 2..r; along-degree fastest);
+ *   - edges are identified by their (start, end) vertices along the local
+ *     component axis and faces by their vertex sets; all cells must agree on
+ *     edge directions and face axes (structured meshes do), else DPG_ERR_ARG;
+ *   - minimum rule for mixed degrees: an edge or face keeps the functions of
+ *     the smallest r among its cells, higher ones are constrained to zero;
+ *   - removed (homogeneous Dirichlet) unknowns: Ehat on every edge or face
+ *     inside a PEC face; Hhat face functions of Robin faces and Hhat edge
+ *     functions whose cell faces are all Robin (they have zero rows, the
+ *     pairing excludes Hhat there, Sec. 2.2);
+ *   - kept unknowns are numbered in order of first appearance (cells in
+ *     order, local functions in order); CSR columns ascend within a row.
+ * Builds on the host (synchronous) and uploads the structure and the gather
+ * lists of the assembly to the plan's device. */
+dpg_status dpg_trace_system_create(dpg_plan plan, const int64_t* cells_host, const int8_t* face_kind_host,
+                                   dpg_trace_system* sys);
+/* The same numbering without a device: HOST arrays; glob receives
+ * sum_c 24 (p_c+1)^2 ids (cell by cell, Ehat then Hhat), *n_dofs the number
+ * of kept unknowns.  DPG_ERR_ARG for degrees outside 1..4 or inconsistent
+ * orientations. */
+dpg_status dpg_trace_numbering(const int64_t* cells_host, const int8_t* face_kind_host, const int8_t* degree_host,
+                               int64_t n_cells, int64_t* glob, int64_t* n_dofs);
+dpg_status dpg_trace_system_destroy(dpg_trace_system sys);
+/* Number of unknowns and of stored nonzeros (host). */
+dpg_status dpg_trace_system_info(dpg_trace_system sys, int64_t* n_dofs, int64_t* nnz);
+/* HOST copy of the global id of every local trace function, laid out like b
+ * (b_off), -1 where removed or constrained. */
+dpg_status dpg_trace_system_numbering(dpg_trace_system sys, int64_t* glob);
+/* DEVICE pointers to the CSR structure (row_ptr [n_dofs+1], col [nnz]),
+ * owned by the system. */
+dpg_status dpg_trace_system_csr(dpg_trace_system sys, const int64_t** row_ptr, const int32_t** col);
+
+/* Assembly by gathering: vals [nnz] (complex) and rhs [n_dofs] (complex)
+ * from the condensed cell outputs A, b (device); each entry is the sum of its
+ * cell contributions in a fixed order (deterministic).  Stream-ordered. */
+dpg_status dpg_assemble(dpg_trace_system sys, const double* A, const double* b, double* vals, double* rhs,
+                        void* stream);
+
+/* y = A x for a complex CSR matrix (the CG matvec); all device pointers,
+ * x and y complex [n_rows].  Stream-ordered. */
+dpg_status dpg_csr_matvec(int64_t n_rows, const int64_t* row_ptr, const int32_t* col, const double* vals,
+                          const double* x, double* y, void* stream);
 
 /* Kernel classes timed by the plan's optional profiler. */
 enum {

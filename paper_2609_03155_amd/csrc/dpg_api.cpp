@@ -15,6 +15,7 @@
 
 #include "dpg_kernels.h"
 #include "dpg_tables.h"
+#include "dpg_trace.h"
 
 namespace {
 
@@ -38,6 +39,7 @@ struct DegreeGroup {
   uint16_t* wsplit = nullptr;
   hipStream_t stream = nullptr;       // branch stream of the concurrent schedule
   hipEvent_t done = nullptr;
+  dpg::DevTables ct{};                // condensation: factorisation tables of the K_e-based matrix
 };
 
 // Algorithmic flops of one cell (structure-aware counts: formation of the
@@ -62,10 +64,27 @@ struct dpg_plan_s {
   int64_t* K_off_dev = nullptr;
   int64_t* v_off_dev = nullptr;
   std::vector<DegreeGroup> groups;    // in queue order: decreasing total cost
+  std::vector<int8_t> degree;         // per cell (host)
+  std::vector<int64_t> A_off, b_off;  // condensed cell matrices / right-hand sides (complex elements)
+  int64_t* A_off_dev = nullptr;
+  int64_t* b_off_dev = nullptr;
+  double* cond_eta = nullptr;         // [n_cells] scratch of the condensation HERK
   std::vector<void*> misc;            // other device allocations
   hipEvent_t fork = nullptr;
   bool concurrent = true;             // degree groups on parallel branches
   dpg::Prof prof;
+};
+
+struct dpg_trace_system_s {
+  int device = 0;
+  int64_t n_cells = 0, n_dofs = 0, nnz = 0;
+  std::vector<int64_t> glob;          // [b_off[n]] global id per local trace function, -1 removed
+  int64_t* row_ptr = nullptr;         // device CSR structure
+  int32_t* col = nullptr;
+  int64_t* contrib_ptr = nullptr;     // device gather lists of the values and of the right-hand side
+  int64_t* contrib = nullptr;
+  int64_t* rhs_ptr = nullptr;
+  int64_t* rhs_contrib = nullptr;
 };
 
 struct dpg_graph_s {
@@ -352,6 +371,17 @@ dpg_status dpg_plan_create(int32_t device, const int8_t* degree_host, int64_t n_
     }
     P->K_off_dev = upload(P->misc, P->K_off);
     P->v_off_dev = upload(P->misc, P->v_off);
+    P->degree.assign(degree_host, degree_host + n_cells);
+    P->A_off.assign(n_cells + 1, 0);
+    P->b_off.assign(n_cells + 1, 0);
+    for (int64_t c = 0; c < n_cells; ++c) {
+      const int64_t r = degree_host[c] + 1, nt = 24 * r * r;
+      P->A_off[c + 1] = P->A_off[c] + nt * nt;
+      P->b_off[c + 1] = P->b_off[c] + nt;
+    }
+    P->A_off_dev = upload(P->misc, P->A_off);
+    P->b_off_dev = upload(P->misc, P->b_off);
+    P->cond_eta = upload(P->misc, std::vector<double>(std::max<int64_t>(1, n_cells), 0.0));
     for (int p = 1; p <= 4; ++p) {
       DegreeGroup g;
       g.p = p;
@@ -359,6 +389,21 @@ dpg_status dpg_plan_create(int32_t device, const int8_t* degree_host, int64_t n_
         if (degree_host[c] == p) g.cells.push_back(c);
       if (g.cells.empty()) continue;
       build_group(g, dp);
+      {
+        // condensation matrix: columns = interior unknowns (padded to 64),
+        // rows below = (D M2)^H, (D l_u)^H; every tile complex (Np = 0)
+        dpg::DevTables& c = g.ct;
+        c = g.dt;
+        const int nt = g.d.nt;
+        c.Np = 0;
+        c.nvp = (g.d.nu + 63) / 64 * 64;
+        c.k = nt;
+        c.kp = (nt + 2 + 63) / 64 * 64;
+        c.nrows = c.nvp + c.kp;
+        c.ldz = c.nrows + 4;
+        c.zstride = c.ldz * c.nvp + 36;
+        if (c.zstride > g.dt.zstride) throw std::bad_alloc();
+      }
       std::vector<void*> tmp;
       g.cells_dev = upload(tmp, g.cells);
       P->groups.push_back(std::move(g));
@@ -631,6 +676,170 @@ dpg_status dpg_graph_destroy(dpg_graph graph) {
   if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
   if (graph->graph) (void)hipGraphDestroy(graph->graph);
   delete graph;
+  return DPG_OK;
+}
+
+dpg_status dpg_plan_trace_offsets(dpg_plan plan, int64_t* A_off, int64_t* b_off) {
+  if (!plan || !A_off || !b_off) return DPG_ERR_ARG;
+  std::memcpy(A_off, plan->A_off.data(), sizeof(int64_t) * plan->A_off.size());
+  std::memcpy(b_off, plan->b_off.data(), sizeof(int64_t) * plan->b_off.size());
+  return DPG_OK;
+}
+
+dpg_status dpg_condense(dpg_plan plan, const double* K, const double* l, double* A, double* b, int32_t* info,
+                        void* stream) {
+  if (!plan) return DPG_ERR_ARG;
+  if (plan->n_cells == 0) return DPG_OK;
+  if (!K || !l || !A || !b || !info) return DPG_ERR_ARG;
+  if (hipSetDevice(plan->device) != hipSuccess) return DPG_ERR_HIP;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = hipSuccess;
+  for (auto& g : plan->groups) {
+    const int64_t nc = (int64_t)g.cells.size();
+    for (int64_t s0 = 0; s0 < nc && e == hipSuccess; s0 += g.chunk) {
+      dpg::ChunkArgs ca{};
+      ca.cell_ids = g.cells_dev + s0;
+      ca.n = std::min<int64_t>(g.chunk, nc - s0);
+      ca.Z = g.Z;
+      ca.split = 0;
+      ca.K_off = plan->A_off_dev;
+      ca.v_off = plan->b_off_dev;
+      ca.K = reinterpret_cast<double2*>(A);
+      ca.l = reinterpret_cast<double2*>(b);
+      ca.eta = plan->cond_eta;
+      ca.info = info;
+      dpg::CondArgs cg{};
+      cg.Ke = reinterpret_cast<const double2*>(K);
+      cg.le = reinterpret_cast<const double2*>(l);
+      cg.Ke_off = plan->K_off_dev;
+      cg.le_off = plan->v_off_dev;
+      cg.nu = g.d.nu;
+      cg.kfull = g.d.k;
+      e = dpg::launch_cond_load(g.ct, ca, cg, st);
+      if (e == hipSuccess) e = dpg::launch_factor(g.ct, ca, st, nullptr);
+      if (e == hipSuccess) e = dpg::launch_herk(g.ct, ca, st, nullptr);
+      if (e == hipSuccess) e = dpg::launch_cond_finish(g.ct, ca, cg, st);
+    }
+  }
+  if (e != hipSuccess) {
+    set_error("dpg_condense", e);
+    return DPG_ERR_HIP;
+  }
+  return DPG_OK;
+}
+
+dpg_status dpg_trace_numbering(const int64_t* cells_host, const int8_t* face_kind_host, const int8_t* degree_host,
+                               int64_t n_cells, int64_t* glob, int64_t* n_dofs) {
+  if (n_cells < 0 || !n_dofs || (n_cells > 0 && (!cells_host || !face_kind_host || !degree_host || !glob)))
+    return DPG_ERR_ARG;
+  for (int64_t c = 0; c < n_cells; ++c)
+    if (degree_host[c] < 1 || degree_host[c] > 4) return DPG_ERR_ARG;
+  try {
+    std::vector<int64_t> toff, g;
+    dpg::trace_numbering(cells_host, face_kind_host, degree_host, n_cells, toff, g, *n_dofs);
+    if (!g.empty()) std::memcpy(glob, g.data(), sizeof(int64_t) * g.size());
+    return DPG_OK;
+  } catch (const std::invalid_argument&) {
+    return DPG_ERR_ARG;
+  } catch (const std::bad_alloc&) {
+    return DPG_ERR_ALLOC;
+  }
+}
+
+dpg_status dpg_trace_system_create(dpg_plan plan, const int64_t* cells_host, const int8_t* face_kind_host,
+                                   dpg_trace_system* out) {
+  if (!plan || !out || (plan->n_cells > 0 && (!cells_host || !face_kind_host))) return DPG_ERR_ARG;
+  *out = nullptr;
+  dpg_trace_system_s* S = nullptr;
+  try {
+    if (hipSetDevice(plan->device) != hipSuccess) return DPG_ERR_HIP;
+    S = new dpg_trace_system_s();
+    S->device = plan->device;
+    S->n_cells = plan->n_cells;
+    std::vector<int64_t> toff;
+    dpg::trace_numbering(cells_host, face_kind_host, plan->degree.data(), plan->n_cells, toff, S->glob, S->n_dofs);
+    std::vector<int64_t> row_ptr, cptr, contrib, rptr, rcontrib;
+    std::vector<int32_t> col;
+    dpg::trace_csr(toff, S->glob, plan->A_off, plan->b_off, S->n_dofs, row_ptr, col, cptr, contrib, rptr, rcontrib);
+    S->nnz = (int64_t)col.size();
+    std::vector<void*> own;
+    S->row_ptr = upload(own, row_ptr);
+    S->col = upload(own, col);
+    S->contrib_ptr = upload(own, cptr);
+    S->contrib = upload(own, contrib);
+    S->rhs_ptr = upload(own, rptr);
+    S->rhs_contrib = upload(own, rcontrib);
+    *out = S;
+    return DPG_OK;
+  } catch (const std::invalid_argument&) {
+    (void)dpg_trace_system_destroy(S);
+    return DPG_ERR_ARG;
+  } catch (const HipError&) {
+    (void)dpg_trace_system_destroy(S);
+    return DPG_ERR_HIP;
+  } catch (const std::bad_alloc&) {
+    (void)dpg_trace_system_destroy(S);
+    return DPG_ERR_ALLOC;
+  }
+}
+
+dpg_status dpg_trace_system_destroy(dpg_trace_system sys) {
+  if (!sys) return DPG_ERR_ARG;
+  (void)hipSetDevice(sys->device);
+  for (void* p : {(void*)sys->row_ptr, (void*)sys->col, (void*)sys->contrib_ptr, (void*)sys->contrib,
+                  (void*)sys->rhs_ptr, (void*)sys->rhs_contrib})
+    if (p) (void)hipFree(p);
+  delete sys;
+  return DPG_OK;
+}
+
+dpg_status dpg_trace_system_info(dpg_trace_system sys, int64_t* n_dofs, int64_t* nnz) {
+  if (!sys || !n_dofs || !nnz) return DPG_ERR_ARG;
+  *n_dofs = sys->n_dofs;
+  *nnz = sys->nnz;
+  return DPG_OK;
+}
+
+dpg_status dpg_trace_system_numbering(dpg_trace_system sys, int64_t* glob) {
+  if (!sys || !glob) return DPG_ERR_ARG;
+  std::memcpy(glob, sys->glob.data(), sizeof(int64_t) * sys->glob.size());
+  return DPG_OK;
+}
+
+dpg_status dpg_trace_system_csr(dpg_trace_system sys, const int64_t** row_ptr, const int32_t** col) {
+  if (!sys || !row_ptr || !col) return DPG_ERR_ARG;
+  *row_ptr = sys->row_ptr;
+  *col = sys->col;
+  return DPG_OK;
+}
+
+dpg_status dpg_assemble(dpg_trace_system sys, const double* A, const double* b, double* vals, double* rhs,
+                        void* stream) {
+  if (!sys || (sys->nnz > 0 && (!A || !vals)) || (sys->n_dofs > 0 && (!b || !rhs))) return DPG_ERR_ARG;
+  if (hipSetDevice(sys->device) != hipSuccess) return DPG_ERR_HIP;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = dpg::launch_gather(sys->nnz, sys->contrib_ptr, sys->contrib, reinterpret_cast<const double2*>(A),
+                                    reinterpret_cast<double2*>(vals), st);
+  if (e == hipSuccess)
+    e = dpg::launch_gather(sys->n_dofs, sys->rhs_ptr, sys->rhs_contrib, reinterpret_cast<const double2*>(b),
+                           reinterpret_cast<double2*>(rhs), st);
+  if (e != hipSuccess) {
+    set_error("dpg_assemble", e);
+    return DPG_ERR_HIP;
+  }
+  return DPG_OK;
+}
+
+dpg_status dpg_csr_matvec(int64_t n_rows, const int64_t* row_ptr, const int32_t* col, const double* vals,
+                          const double* x, double* y, void* stream) {
+  if (n_rows < 0 || (n_rows > 0 && (!row_ptr || !col || !vals || !x || !y))) return DPG_ERR_ARG;
+  const hipError_t e = dpg::launch_csr_matvec(n_rows, row_ptr, col, reinterpret_cast<const double2*>(vals),
+                                              reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y),
+                                              reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) {
+    set_error("dpg_csr_matvec", e);
+    return DPG_ERR_HIP;
+  }
   return DPG_OK;
 }
 

@@ -64,6 +64,17 @@ struct ChunkArgs {
   int32_t* info;
 };
 
+// Inputs of the condensation kernels: the local solve's K_e and l_e.
+struct CondArgs {
+  const double2* Ke;         // K_e of all cells (output layout of the local solve)
+  const double2* le;
+  const int64_t* Ke_off;     // [n_cells+1] K_off, v_off of the plan
+  const int64_t* le_off;
+  int64_t Ke_base, le_base;  // Ke_off[first], le_off[first] of the buffers' first cell
+  int nu;                    // interior unknowns (first nu rows/columns of K_e)
+  int kfull;                 // K_e dimension, nu + n_t
+};
+
 // Optional per-kernel timing: when `on`, each launch is bracketed by two HIP
 // events recorded on the launch stream; `recs` keeps (class, begin, end).
 struct Prof {
@@ -100,6 +111,18 @@ hipError_t launch_formation(const DevTables& t, const ProbArgs& pa, const ChunkA
                             Prof* prof = nullptr);
 hipError_t launch_factor(const DevTables& t, const ChunkArgs& ca, hipStream_t st, Prof* prof = nullptr);
 hipError_t launch_herk(const DevTables& t, const ChunkArgs& ca, hipStream_t st, Prof* prof = nullptr);
+// Condensation A_K = M3 - M2^H M1^{-1} M2, b_K = l_t - M2^H M1^{-1} l_u: load of the
+// augmented matrix into the workspace, and the final subtraction (the
+// factorisation and HERK in between are launch_factor / launch_herk on the
+// condensation tables).
+hipError_t launch_cond_load(const DevTables& t, const ChunkArgs& ca, const CondArgs& a, hipStream_t st);
+hipError_t launch_cond_finish(const DevTables& t, const ChunkArgs& ca, const CondArgs& a, hipStream_t st);
+// to[z] = sum_{k in [ptr[z], ptr[z+1])} from[src[k]]  (assembly by gathering)
+hipError_t launch_gather(int64_t n, const int64_t* ptr, const int64_t* src, const double2* from, double2* to,
+                         hipStream_t st);
+// y = A x for a complex CSR matrix
+hipError_t launch_csr_matvec(int64_t n_rows, const int64_t* row_ptr, const int32_t* col, const double2* val,
+                             const double2* x, double2* y, hipStream_t st);
 // bf16 planes per cell of the split path
 __host__ __device__ inline int64_t split_elems(const DevTables& t) { return 6 * (int64_t)t.kp * t.nvp; }
 // Raise the dynamic-LDS limit of the kernels that stage whole tiles (once per process).

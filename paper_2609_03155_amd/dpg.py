@@ -23,6 +23,9 @@ FACE_INTERIOR, FACE_PEC, FACE_PORT, FACE_ROBIN0 = 0, 1, 2, 3
 EXPORTS = ("dpg_local_dims", "dpg_plan_create", "dpg_plan_destroy", "dpg_plan_offsets", "dpg_plan_layout",
            "dpg_local_solve", "dpg_local_solve_range", "dpg_plan_set_concurrency", "dpg_plan_autotune",
            "dpg_plan_tuning", "dpg_graph_create", "dpg_graph_launch", "dpg_graph_destroy", "dpg_form_local",
+           "dpg_plan_trace_offsets", "dpg_condense", "dpg_trace_numbering", "dpg_trace_system_create",
+           "dpg_trace_system_destroy", "dpg_trace_system_info", "dpg_trace_system_numbering", "dpg_trace_system_csr",
+           "dpg_assemble", "dpg_csr_matvec",
            "dpg_plan_set_profiling", "dpg_plan_profile", "dpg_status_string", "dpg_last_error")
 KERNEL_CLASSES = ("scale", "form_SM", "form_IF", "form_pad", "form_B", "form_load", "resid", "chol_diag",
                   "chol_panel", "herk")
@@ -69,6 +72,16 @@ def lib():
         L.dpg_graph_launch.argtypes = [vp, vp]
         L.dpg_graph_destroy.argtypes = [vp]
         L.dpg_form_local.argtypes = [vp, C.POINTER(dpg_problem), i64, i64, vp, vp, vp, vp, vp]
+        L.dpg_plan_trace_offsets.argtypes = [vp, vp, vp]
+        L.dpg_condense.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.dpg_trace_numbering.argtypes = [vp, vp, vp, i64, vp, C.POINTER(i64)]
+        L.dpg_trace_system_create.argtypes = [vp, vp, vp, C.POINTER(vp)]
+        L.dpg_trace_system_destroy.argtypes = [vp]
+        L.dpg_trace_system_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i64)]
+        L.dpg_trace_system_numbering.argtypes = [vp, vp]
+        L.dpg_trace_system_csr.argtypes = [vp, C.POINTER(vp), C.POINTER(vp)]
+        L.dpg_assemble.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.dpg_csr_matvec.argtypes = [i64, vp, vp, vp, vp, vp, vp]
         L.dpg_plan_set_profiling.argtypes = [vp, i32]
         L.dpg_plan_profile.argtypes = [vp, vp, vp]
         L.dpg_status_string.argtypes = [i32]
@@ -241,6 +254,25 @@ class Plan:
                                       _ptr(eta), _ptr(info), int(precision), C.byref(h)), "dpg_graph_create")
         return Graph(h, (self, prob, x, K, l, eta, info))
 
+    def trace_offsets(self):
+        """(A_off, b_off): offsets of the condensed cell matrices and right-hand sides."""
+        A_off = np.zeros(self.n_cells + 1, np.int64)
+        b_off = np.zeros(self.n_cells + 1, np.int64)
+        _check(lib().dpg_plan_trace_offsets(self._h, A_off.ctypes.data, b_off.ctypes.data), "dpg_plan_trace_offsets")
+        return A_off, b_off
+
+    def condense(self, K, l, stream=None):
+        """dpg_condense: (A, b, info) device tensors from a solve's K_e, l_e."""
+        import torch
+        A_off, b_off = self.trace_offsets()
+        dev = K.device
+        A = torch.empty(max(int(A_off[-1]), 1), dtype=torch.complex128, device=dev)
+        b = torch.empty(max(int(b_off[-1]), 1), dtype=torch.complex128, device=dev)
+        info = torch.empty(max(self.n_cells, 1), dtype=torch.int32, device=dev)
+        _check(lib().dpg_condense(self._h, _ptr(K), _ptr(l), _ptr(A), _ptr(b), _ptr(info), _stream(stream)),
+               "dpg_condense")
+        return A, b, info
+
     def range_sizes(self, first: int, count: int):
         """(K elements, l/x elements) of the outputs of a range solve."""
         return (int(self.K_off[first + count] - self.K_off[first]), int(self.v_off[first + count] - self.v_off[first]))
@@ -261,6 +293,67 @@ class Plan:
                                     _ptr(info), _stream(stream)), "dpg_form_local")
         # column-major per cell: G[c][col][row] -> transpose to [row][col]
         return G.transpose(1, 2), Bf.transpose(1, 2), lv, info
+
+
+def trace_numbering(cells, face_kind, degree):
+    """dpg_trace_numbering (host): (glob, n_dofs), glob laid out cell by cell."""
+    cells = np.ascontiguousarray(np.asarray(cells, np.int64))
+    fk = np.ascontiguousarray(np.asarray(face_kind, np.int8))
+    deg = np.ascontiguousarray(np.asarray(degree, np.int8))
+    total = int(np.sum(24 * (deg.astype(np.int64) + 1) ** 2))
+    glob = np.zeros(max(total, 1), np.int64)
+    n = C.c_int64()
+    _check(lib().dpg_trace_numbering(cells.ctypes.data, fk.ctypes.data, deg.ctypes.data, int(deg.shape[0]),
+                                     glob.ctypes.data, C.byref(n)), "dpg_trace_numbering")
+    return glob[:total], n.value
+
+
+class TraceSystem:
+    """dpg_trace_system_*: numbering, CSR structure and gather assembly of the condensed system."""
+
+    def __init__(self, plan: "Plan", cells, face_kind):
+        self._plan = plan
+        cells = np.ascontiguousarray(np.asarray(cells, np.int64))
+        fk = np.ascontiguousarray(np.asarray(face_kind, np.int8))
+        h = C.c_void_p()
+        _check(lib().dpg_trace_system_create(plan._h, cells.ctypes.data, fk.ctypes.data, C.byref(h)),
+               "dpg_trace_system_create")
+        self._h = h
+        a, b = C.c_int64(), C.c_int64()
+        _check(lib().dpg_trace_system_info(self._h, C.byref(a), C.byref(b)), "dpg_trace_system_info")
+        self.n_dofs, self.nnz = a.value, b.value
+        rp, cl = C.c_void_p(), C.c_void_p()
+        _check(lib().dpg_trace_system_csr(self._h, C.byref(rp), C.byref(cl)), "dpg_trace_system_csr")
+        self.row_ptr_ptr, self.col_ptr = rp.value, cl.value
+
+    def numbering(self):
+        total = int(self._plan.trace_offsets()[1][-1])
+        glob = np.zeros(max(total, 1), np.int64)
+        _check(lib().dpg_trace_system_numbering(self._h, glob.ctypes.data), "dpg_trace_system_numbering")
+        return glob[:total]
+
+    def assemble(self, A, b, stream=None):
+        """(vals, rhs) device tensors of the assembled CSR matrix and right-hand side."""
+        import torch
+        vals = torch.empty(max(self.nnz, 1), dtype=torch.complex128, device=A.device)
+        rhs = torch.empty(max(self.n_dofs, 1), dtype=torch.complex128, device=A.device)
+        _check(lib().dpg_assemble(self._h, _ptr(A), _ptr(b), _ptr(vals), _ptr(rhs), _stream(stream)), "dpg_assemble")
+        return vals, rhs
+
+    def matvec(self, vals, x, y, stream=None):
+        _check(lib().dpg_csr_matvec(self.n_dofs, self.row_ptr_ptr, self.col_ptr, _ptr(vals), _ptr(x), _ptr(y),
+                                    _stream(stream)), "dpg_csr_matvec")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().dpg_trace_system_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Graph:
