@@ -68,6 +68,70 @@ def measured_traffic(workload: str, precision: str, kernel: str):
     return None
 
 
+def trace_system_timings(w, plan, prob, xd, K, l, eta, info, solve, stream, reps: int = 5, mv_reps: int = 50):
+    """Condensation (A_K, b_K), gather assembly and complex CSR matvec of the
+    condensed trace system on the workload, timed with HIP events."""
+    import torch
+    from paper_2609_03155_amd import dpg
+    solve(dpg.DPG_FP64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ts = dpg.TraceSystem(plan, w.cells, w.face_kind)
+    build_s = time.perf_counter() - t0
+    print(f"[bench] trace system: {ts.n_dofs} unknowns, {ts.nnz} nonzeros, built in {build_s:.1f} s",
+          file=sys.stderr, flush=True)
+
+    def timed_ms(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(n):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    out = {}
+    cond = {}
+
+    def do_cond():
+        cond["r"] = plan.condense(K, l, stream=stream)
+    cond_ms = timed_ms(do_cond, reps)
+    A, b, cinfo = cond["r"]
+    asm = {}
+
+    def do_asm():
+        asm["r"] = ts.assemble(A, b, stream=stream)
+    asm_ms = timed_ms(do_asm, reps)
+    vals, rhs = asm["r"]
+    x = torch.ones(ts.n_dofs, dtype=torch.complex128, device="cuda")
+    y = torch.empty_like(x)
+    mv_ms = timed_ms(lambda: ts.matvec(vals, x, y, stream=stream), mv_reps)
+    fl = 0.0
+    contrib = 0
+    for p in sorted(set(int(v) for v in w.degree)):
+        cnt = int(np.sum(w.degree == p))
+        nu, nt = 6 * (p + 1) ** 3, 24 * (p + 1) ** 2
+        fl += cnt * (4.0 / 3.0 * nu ** 3 + 4.0 * nu * nu * nt + 4.0 * nt * nt * nu)
+        contrib += cnt * nt * nt
+    mv_bytes = ts.nnz * (16 + 4) + (ts.n_dofs + 1) * 8 + 2 * ts.n_dofs * 16
+    out.update({
+        "n_dofs": ts.n_dofs, "nnz": ts.nnz, "build_s": build_s,
+        "condense_ms": cond_ms, "condense_tflops": fl / (cond_ms * 1e-3) / 1e12,
+        "condense_failed_cells": int(np.sum(cinfo.cpu().numpy()[:w.n_cells] != 0)),
+        "assemble_ms": asm_ms,
+        "assemble_GBps": (contrib * 24 + ts.nnz * 24) / (asm_ms * 1e-3) / 1e9,
+        "spmv_ms": mv_ms, "spmv_nnz_per_s": ts.nnz / (mv_ms * 1e-3),
+        "spmv_GBps": mv_bytes / (mv_ms * 1e-3) / 1e9,
+        "spmv_frac_hbm": mv_bytes / (mv_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+        "spmv_bytes_note": "algorithmic: 16 B value + 4 B column per nonzero, row pointers, x and y once",
+    })
+    ts.close()
+    del A, b, vals, rhs
+    return out
+
+
 def cpu_baseline(w, budget_s: float = 20.0):
     """The oracle, as it stands, on a bounded seeded sample of the workload's
     cells; returns (record, per-cell oracle outputs)."""
@@ -115,6 +179,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="time eager solves instead of HIP-graph replays")
     ap.add_argument("--no-autotune", action="store_true", help="skip the batching autotuner")
     ap.add_argument("--sequential", action="store_true", help="degree groups one after the other (no branches)")
+    ap.add_argument("--no-trace-system", action="store_true",
+                    help="skip the condensation / assembly / CSR matvec measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (requested --gpus {args.gpus}); the per-cell local solve needs no "
@@ -291,6 +357,8 @@ def main():
                        "cells_per_launch": {str(p): plan.tuning(p)[0] for p in degs}}
     if "split" in runs and "fp64" in runs:
         rec["speedup_split_vs_fp64"] = runs["fp64"][0] / runs["split"][0]
+    if not args.no_trace_system and not streaming:
+        rec["trace_system"] = trace_system_timings(w, plan, prob, xd, K, l, eta, info, solve, stream)
     if not args.no_cpu_baseline:
         base, outs = cpu_baseline(w, args.cpu_budget)
         rec["cpu_baseline"] = base
