@@ -416,7 +416,7 @@ dpg_status dpg_plan_create(int32_t device, const int8_t* degree_host, int64_t n_
     HIP_CHECK(hipMemGetInfo(&free_b, &total_b));
     const double budget = max_workspace_bytes > 0 ? (double)max_workspace_bytes : 0.4 * (double)free_b;
     for (auto& g : P->groups) {
-      const int64_t mper = 12 * (int64_t)g.d.nq + 36 * (int64_t)g.d.nfq;
+      const int64_t mper = dpg::met_stride(g.dt);
       g.per_cell = g.dt.zstride * 16 + (int64_t)g.d.nvp * 8 + mper * 8 + dpg::split_elems(g.dt) * 2;
     }
     // Each group first gets room for enough cells that one factorisation step
@@ -468,7 +468,7 @@ dpg_status dpg_plan_create(int32_t device, const int8_t* degree_host, int64_t n_
     }
     for (auto& g : P->groups) {
       g.run_chunk = g.chunk;
-      const int64_t mper = 12 * (int64_t)g.d.nq + 36 * (int64_t)g.d.nfq;
+      const int64_t mper = dpg::met_stride(g.dt);
       if (hipMalloc(reinterpret_cast<void**>(&g.Z), (size_t)g.chunk * g.dt.zstride * 16) != hipSuccess ||
           hipMalloc(reinterpret_cast<void**>(&g.dscale), (size_t)g.chunk * g.d.nvp * 8) != hipSuccess ||
           hipMalloc(reinterpret_cast<void**>(&g.met), (size_t)g.chunk * mper * 8) != hipSuccess ||

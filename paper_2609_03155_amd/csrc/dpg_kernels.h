@@ -50,7 +50,8 @@ struct ChunkArgs {
   int64_t n;                 // cells in the chunk
   double2* Z;                // [n][nvp cols][nrows] augmented lower factor, column-major
   double* dscale;            // [n][nvp] Jacobi scaling of the test rows
-  double* met;               // [n][12 nq + 36 nfq] point metrics: volume Gc|Gm, Robin-face Q
+  double* met;               // [n][met_stride] point metrics: volume Gc|Gm (6 nq each), Robin-face Q (36 nfq),
+                             // volume w det J^{-T} (9 nq, [a][c] = w det (J^{-1})_{ac}) and w J (9 nq)
   uint16_t* wsplit;          // split path: [n][6][kp][nvp] bf16 planes of W^H (re0,re1,re2,im0,im1,im2)
   int split;                 // 1: K_aug from the bf16 split planes, eta by an FP64 reduction
   const int64_t* K_off;      // [n_cells+1] global output offsets (complex elements)
@@ -123,6 +124,8 @@ hipError_t launch_gather(int64_t n, const int64_t* ptr, const int64_t* src, cons
 // y = A x for a complex CSR matrix
 hipError_t launch_csr_matvec(int64_t n_rows, const int64_t* row_ptr, const int32_t* col, const double2* val,
                              const double2* x, double2* y, hipStream_t st);
+// doubles of per-point metrics kept per cell (ChunkArgs::met)
+__host__ __device__ inline int64_t met_stride(const DevTables& t) { return 30 * (int64_t)t.nq + 36 * (int64_t)t.nfq; }
 // bf16 planes per cell of the split path
 __host__ __device__ inline int64_t split_elems(const DevTables& t) { return 6 * (int64_t)t.kp * t.nvp; }
 // Raise the dynamic-LDS limit of the kernels that stage whole tiles (once per process).

@@ -203,11 +203,21 @@ __global__ __launch_bounds__(NT) void k_cell_scale(DevTables T, ProbArgs P, Chun
   load_cell_vertices(P, gc, sX);
   if (threadIdx.x == 0) s_bad = 0;
   __syncthreads();
+  double* gm = C.met + cell * met_stride(T);
   for (int q = threadIdx.x; q < T.nq; q += NT) {
     Geo g;
     trilinear(sX, T.vol_pts[3 * q], T.vol_pts[3 * q + 1], T.vol_pts[3 * q + 2], g);
     if (!(g.det > 0.0) || !isfinite(g.det)) atomicOr(&s_bad, 1);
     vol_metrics(g, T.vol_w[q], &sGc[6 * q], &sGm[6 * q]);
+    // the maps of the trial-to-test contractions: w det J^{-T} (covariant test
+    // functions times the volume element) and w J (their curls times det J)
+    double* pj = gm + 12 * T.nq + 36 * T.nfq + 9 * q;
+    double* qj = gm + 21 * T.nq + 36 * T.nfq + 9 * q;
+    const double wd = T.vol_w[q] * g.det, w = T.vol_w[q];
+    for (int e = 0; e < 9; ++e) {
+      pj[e] = wd * g.Ji[e / 3][e % 3];
+      qj[e] = w * g.J[e / 3][e % 3];
+    }
   }
   int8_t fk[6];
   for (int f = 0; f < 6; ++f) fk[f] = P.face_kind[gc * 6 + f];
@@ -265,7 +275,6 @@ __global__ __launch_bounds__(NT) void k_cell_scale(DevTables T, ProbArgs P, Chun
     d[T.Np + i] = dI;
   }
   // keep the point metrics for the formation kernels
-  double* gm = C.met + cell * (int64_t)(12 * T.nq + 36 * T.nfq);
   for (int e = threadIdx.x; e < 12 * T.nq + 36 * T.nfq; e += NT) gm[e] = smem[e];
   if (threadIdx.x == 0) C.info[gc - C.cell_base] = s_bad ? -1 : 0;
 }
@@ -359,7 +368,7 @@ __global__ __launch_bounds__(NT, 2) void k_form_B(DevTables T, ProbArgs P, Chunk
   const int64_t gc = C.cell_ids[cell];
   const int i0 = tile * 64;
   __shared__ double sX[8][3];
-  __shared__ double sGeo[BQC][21];          // J (9), Ji (9), w det, w
+  __shared__ double sGeo[BQC][21];          // w J (9), w det J^{-T} (9) | Robin: tangential maps
   __shared__ double sP[BQC][64][3];         // w det (J^{-T} psi_hat_i)_c
   __shared__ double sQ[BQC][64][3];         // w (J chat_i)_c
   __shared__ double2 sRes[64][4][2];        // per-thread shares of (D B_f x): [row][share][F/I]
@@ -381,6 +390,7 @@ __global__ __launch_bounds__(NT, 2) void k_form_B(DevTables T, ProbArgs P, Chunk
   const double om = P.omega;
   const double* d = C.dscale + cell * (int64_t)T.nvp;
   double2* Z = C.Z + cell * T.zstride;
+  const double* gmet = C.met + cell * met_stride(T);
   const int64_t ld = T.ldz;
   const int nvp = T.nvp;
   const int m1 = T.m1;
@@ -399,16 +409,11 @@ __global__ __launch_bounds__(NT, 2) void k_form_B(DevTables T, ProbArgs P, Chunk
     for (int q0 = 0; q0 < T.nq; q0 += BQC) {
       const int nqc = min(BQC, T.nq - q0);
       __syncthreads();
-      for (int qq = threadIdx.x; qq < nqc; qq += NT) {
-        const int q = q0 + qq;
-        Geo g;
-        trilinear(sX, T.vol_pts[3 * q], T.vol_pts[3 * q + 1], T.vol_pts[3 * q + 2], g);
-        for (int e = 0; e < 9; ++e) {
-          sGeo[qq][e] = g.J[e / 3][e % 3];
-          sGeo[qq][9 + e] = g.Ji[e / 3][e % 3];
-        }
-        sGeo[qq][18] = T.vol_w[q] * g.det;
-        sGeo[qq][19] = T.vol_w[q];
+      for (int e = threadIdx.x; e < nqc * 18; e += NT) {
+        const int qq = e / 18, k = e % 18;
+        // [0, 9): w J ; [9, 18): w det J^{-T} (row a of J^{-1} at 9 + 3a)
+        sGeo[qq][k] = k < 9 ? gmet[21 * T.nq + 36 * T.nfq + 9 * (q0 + qq) + k]
+                            : gmet[12 * T.nq + 36 * T.nfq + 9 * (q0 + qq) + (k - 9)];
       }
       for (int e = threadIdx.x; e < nqc * m1; e += NT) sPhi[e] = T.vol_phi[(size_t)(q0 + e / m1) * m1 + e % m1];
       __syncthreads();
@@ -421,8 +426,8 @@ __global__ __launch_bounds__(NT, 2) void k_form_B(DevTables T, ProbArgs P, Chunk
         const double* c = &T.vol_c[((size_t)q * T.Np + ii) * 3];
         const double* G = sGeo[qq];
         for (int cc = 0; cc < 3; ++cc) {
-          sP[qq][jl][cc] = G[18] * G[9 + a * 3 + cc] * v;                     // (J^{-T})_{c a} = Ji[a][c]
-          sQ[qq][jl][cc] = G[19] * (G[cc * 3] * c[0] + G[cc * 3 + 1] * c[1] + G[cc * 3 + 2] * c[2]);
+          sP[qq][jl][cc] = G[9 + a * 3 + cc] * v;                             // w det (J^{-T})_{c a}
+          sQ[qq][jl][cc] = G[cc * 3] * c[0] + G[cc * 3 + 1] * c[1] + G[cc * 3 + 2] * c[2];   // w (J chat)_c
         }
       }
       __syncthreads();
@@ -491,70 +496,115 @@ __global__ __launch_bounds__(NT, 2) void k_form_B(DevTables T, ProbArgs P, Chunk
         }
       }
     }
-    // ---- write the interior-unknown rows of (D B_f)^H and accumulate D B_f x
-    if (inrange) {
+    // ---- interior-unknown rows of (D B_f)^H: accumulate D B_f x, then write
+    // through LDS (sP/sQ are free until the next batch) so that every store
+    // instruction covers runs of 16 consecutive rows of one column
+    const int nm = min(4 * BIT, m1 - ib);   // DG functions of this batch
+    double2* sb = reinterpret_cast<double2*>(&sP[0][0][0]);   // [2 rows E/H][16 m][64 columns]
 #pragma unroll
-      for (int u = 0; u < BIT; ++u) {
-        const int m = ib + sub + 4 * u;
-        if (m >= m1) continue;
+    for (int cc = 0; cc < 3; ++cc)
 #pragma unroll
-        for (int cc = 0; cc < 3; ++cc) {
-          const int rowE = nvp + cc * m1 + m, rowH = nvp + (3 + cc) * m1 + m;
-          double2 bFE = make_double2(0, 0), bFH = bFE, bIE = bFE, bIH = bFE;
-          if (ok) {
-            // B(F,E) = i w eps D - z Dt  -> stored conj(dF B)
-            const double2 fe =
-                make_double2(-om * eps.y * D[u][cc] - Dtr[u][cc], om * eps.x * D[u][cc] - Dti[u][cc]);
-            bFE = make_double2(dF * fe.x, -dF * fe.y);
-            bFH = make_double2(dF * R[u][cc], 0.0);
-            bIE = make_double2(dI * R[u][cc], 0.0);
-            // B(I,H) = -i w mu D -> conj = i w conj(mu) D = w (mu.y, mu.x) D
-            bIH = make_double2(dI * om * mu.y * D[u][cc], dI * om * mu.x * D[u][cc]);
+      for (int side = 0; side < 2; ++side) {
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < BIT; ++u) {
+          const int m = ib + sub + 4 * u;
+          double2 bE = make_double2(0, 0), bH = bE;
+          if (inrange && ok && m < m1) {
+            if (side == 0) {
+              // B(F,E) = i w eps D - z Dt -> stored conj(dF B);  B(F,H) = R
+              const double2 fe =
+                  make_double2(-om * eps.y * D[u][cc] - Dtr[u][cc], om * eps.x * D[u][cc] - Dti[u][cc]);
+              bE = make_double2(dF * fe.x, -dF * fe.y);
+              bH = make_double2(dF * R[u][cc], 0.0);
+            } else {
+              // B(I,E) = R;  B(I,H) = -i w mu D -> conj = w (mu.y, mu.x) D
+              bE = make_double2(dI * R[u][cc], 0.0);
+              bH = make_double2(dI * om * mu.y * D[u][cc], dI * om * mu.x * D[u][cc]);
+            }
+            if (xc) {
+              // (d B x) += conj(stored) x
+              const double2 xe = xc[cc * m1 + m], xh = xc[(3 + cc) * m1 + m];
+              const double px = bE.x * xe.x + bE.y * xe.y + bH.x * xh.x + bH.y * xh.y;
+              const double py = bE.x * xe.y - bE.y * xe.x + bH.x * xh.y - bH.y * xh.x;
+              if (side == 0) {
+                rF.x += px;
+                rF.y += py;
+              } else {
+                rI.x += px;
+                rI.y += py;
+              }
+            }
           }
-          Z[(int64_t)i * ld + rowE] = bFE;
-          Z[(int64_t)i * ld + rowH] = bFH;
-          Z[(int64_t)(T.Np + i) * ld + rowE] = bIE;
-          Z[(int64_t)(T.Np + i) * ld + rowH] = bIH;
-          if (xc && ok) {
-            // (d B x) += conj(stored) x
-            const double2 xe = xc[rowE - nvp], xh = xc[rowH - nvp];
-            rF.x += bFE.x * xe.x + bFE.y * xe.y + bFH.x * xh.x + bFH.y * xh.y;
-            rF.y += bFE.x * xe.y - bFE.y * xe.x + bFH.x * xh.y - bFH.y * xh.x;
-            rI.x += bIE.x * xe.x + bIE.y * xe.y + bIH.x * xh.x + bIH.y * xh.y;
-            rI.y += bIE.x * xe.y - bIE.y * xe.x + bIH.x * xh.y - bIH.y * xh.x;
-          }
+          sb[(0 * 16 + sub + 4 * u) * 64 + il] = bE;
+          sb[(1 * 16 + sub + 4 * u) * 64 + il] = bH;
+        }
+        __syncthreads();
+        // column i0 + e / 32 of this side, rows (E or H, cc, m) for m < nm
+        for (int e = threadIdx.x; e < 64 * 32; e += NT) {
+          const int jl = e >> 5, hr = (e >> 4) & 1, ml = e & 15;
+          const int ii = i0 + jl;
+          if (ml >= nm || ii >= T.Np) continue;
+          const int row = nvp + (3 * hr + cc) * m1 + ib + ml;
+          Z[(int64_t)(side * T.Np + ii) * ld + row] = sb[(hr * 16 + ml) * 64 + jl];
         }
       }
-    }
-  }
-  // ---- trace unknowns (real, geometry free)
-  if (inrange) {
-    for (int jt = sub; jt < T.nt1; jt += 4) {
-      double tI = 0.0, tF = 0.0;
-      if (ok) {
-        for (int f = 0; f < 6; ++f) {
-          const double t = T.T[((size_t)f * T.N + i) * T.nt1 + jt];
-          tI += t;
-          if (!is_robin(fk[f])) tF += t;
-        }
-      }
-      const int rowEh = nvp + T.nu + jt, rowHh = nvp + T.nu + T.nt1 + jt;
-      const double tf = dF * tF, ti = dI * tI;
-      Z[(int64_t)i * ld + rowEh] = make_double2(0.0, 0.0);
-      Z[(int64_t)i * ld + rowHh] = make_double2(tf, 0.0);
-      Z[(int64_t)(T.Np + i) * ld + rowEh] = make_double2(ti, 0.0);
-      Z[(int64_t)(T.Np + i) * ld + rowHh] = make_double2(0.0, 0.0);
-      if (xc && ok) {
-        const double2 xe = xc[T.nu + jt], xh = xc[T.nu + T.nt1 + jt];
-        rF.x += tf * xh.x;
-        rF.y += tf * xh.y;
-        rI.x += ti * xe.x;
-        rI.y += ti * xe.y;
-      }
-    }
   }
   sRes[il][sub][0] = rF;
   sRes[il][sub][1] = rI;
+  // ---- trace unknowns (real, geometry free): one wave per (column, chunk of
+  // 64 trace functions), lanes along the rows (coalesced); the wave's part of
+  // D B_f x is reduced in a fixed order and added per column chunk by chunk
+  __shared__ double2 sTr[64][2];
+  {
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (threadIdx.x < 64) sTr[threadIdx.x][0] = sTr[threadIdx.x][1] = make_double2(0.0, 0.0);
+    __syncthreads();
+    for (int c0 = 0; c0 < T.nt1; c0 += 64) {
+      for (int jl0 = 0; jl0 < 64; jl0 += NT / 64) {
+        const int jl = jl0 + wv, ii = i0 + jl, jt = c0 + lane;
+        if (ii >= T.Np) continue;   // uniform per wave
+        const bool okc = ii < T.N && jt < T.nt1;
+        double tI = 0.0, tF = 0.0;
+        if (okc) {
+          for (int f = 0; f < 6; ++f) {
+            const double t = T.T[((size_t)f * T.N + ii) * T.nt1 + jt];
+            tI += t;
+            if (!is_robin(fk[f])) tF += t;
+          }
+        }
+        const double tf = d[ii] * tF, ti = d[T.Np + ii] * tI;
+        if (jt < T.nt1) {
+          const int rowEh = nvp + T.nu + jt, rowHh = nvp + T.nu + T.nt1 + jt;
+          Z[(int64_t)ii * ld + rowEh] = make_double2(0.0, 0.0);
+          Z[(int64_t)ii * ld + rowHh] = make_double2(tf, 0.0);
+          Z[(int64_t)(T.Np + ii) * ld + rowEh] = make_double2(ti, 0.0);
+          Z[(int64_t)(T.Np + ii) * ld + rowHh] = make_double2(0.0, 0.0);
+        }
+        if (xc) {
+          double2 pF = make_double2(0.0, 0.0), pI = pF;
+          if (okc) {
+            const double2 xe = xc[T.nu + jt], xh = xc[T.nu + T.nt1 + jt];
+            pF = make_double2(tf * xh.x, tf * xh.y);
+            pI = make_double2(ti * xe.x, ti * xe.y);
+          }
+#pragma unroll
+          for (int off = 32; off > 0; off >>= 1) {
+            pF.x += __shfl_xor(pF.x, off, 64);
+            pF.y += __shfl_xor(pF.y, off, 64);
+            pI.x += __shfl_xor(pI.x, off, 64);
+            pI.y += __shfl_xor(pI.y, off, 64);
+          }
+          if (lane == 0) {
+            sTr[jl][0].x += pF.x;
+            sTr[jl][0].y += pF.y;
+            sTr[jl][1].x += pI.x;
+            sTr[jl][1].y += pI.y;
+          }
+        }
+      }
+    }
+  }
   __syncthreads();
   // ---- padding rows of the RHS block, zero load row, residual row conj(D B_f x)
   // (k_form_load subtracts the load on port cells)
@@ -571,6 +621,10 @@ __global__ __launch_bounds__(NT, 2) void k_form_B(DevTables T, ProbArgs P, Chunk
         vI.x += sRes[jl][q][1].x;
         vI.y += sRes[jl][q][1].y;
       }
+      vF.x += sTr[jl][0].x;
+      vF.y += sTr[jl][0].y;
+      vI.x += sTr[jl][1].x;
+      vI.y += sTr[jl][1].y;
       vF.y = -vF.y;
       vI.y = -vI.y;
     }
@@ -857,7 +911,7 @@ __global__ __launch_bounds__(NT, 2) void k_form_SM(DevTables T, ProbArgs P, Chun
   racc_zero(MF);
   racc_zero(MI);
   __syncthreads();
-  const double* gmet = C.met + cell * (int64_t)(12 * T.nq + 36 * T.nfq);
+  const double* gmet = C.met + cell * met_stride(T);
   // ---- volume points
   for (int q0 = 0; q0 < T.nq; q0 += SQC) {
     if (threadIdx.x < SQC * 12) {
