@@ -123,6 +123,7 @@ def c2_full():
     x, off = W.random_coefficients(w)
     _say("case: dpg_local_solve config2 full (5120 cells, p=2, dp=1)")
     plan, K, l, eta, info = _run(w, x)
+    plan.close()      # keeps the offsets, frees the workspace for the later full-size cases
     return w, x, off, plan, K, l, eta, info
 
 
@@ -531,3 +532,81 @@ def test_assembly_and_matvec_match_oracle():
         yo = Ao @ xv
         assert np.abs(yd.cpu().numpy() - yo).max() <= 1e-12 * np.abs(yo).max()
         sys_.close()
+
+
+# ------------------------------------------------------------ full-size workloads (sampled)
+def _sampled_full(w, cells):
+    torch = _torch()
+    from paper_2609_03155_amd import dpg
+    torch.cuda.empty_cache()
+    x, off = W.random_coefficients(w)
+    plan = dpg.Plan(w.degree, w.dp)
+    prob = dpg.DeviceProblem.from_workload(w)
+    K, l, eta, info = plan.alloc_outputs()
+    xd = torch.from_numpy(x).cuda()
+    plan.local_solve(prob, xd, K, l, eta, info)
+    torch.cuda.synchronize()
+    ih = info.cpu().numpy()
+    assert np.all(ih == 0)
+    eh = eta.cpu().numpy()
+    assert np.all(np.isfinite(eh)) and np.all(eh >= 0)
+    for c in cells:
+        Go, _, _, Ko, lo, eo = oracle_cell(w, c, x[off[c]:off[c + 1]])
+        tol = fp64_tol(Go)
+        k = int(off[c + 1] - off[c])
+        Kg = K[int(plan.K_off[c]):int(plan.K_off[c + 1])].cpu().numpy().reshape(k, k).T
+        lg = l[int(off[c]):int(off[c + 1])].cpu().numpy()
+        assert rel(Kg, Ko) < tol, (c, rel(Kg, Ko), tol)
+        if np.linalg.norm(lo) > 0:
+            assert rel(lg, lo) < tol, (c, rel(lg, lo), tol)
+        assert abs(eh[c] - eo) < tol * eo, (c, abs(eh[c] - eo) / eo, tol)
+    del K, l
+
+
+def test_config3_full_size_sampled():
+    w = W.config3()
+    rng = np.random.default_rng(W.SEED_BASE + 33)
+    cells = sorted(set([0, w.n_cells - 1] + [int(c) for c in rng.choice(w.n_cells, 3, replace=False)]
+                       + [int(np.nonzero(w.degree == 4)[0][0])]))
+    _say(f"case: config3 full size (20000 cells, p 1..4), oracle on cells {cells}")
+    _sampled_full(w, cells)
+
+
+def test_config4_full_size_sampled():
+    w = W.config4()
+    rng = np.random.default_rng(W.SEED_BASE + 34)
+    cells = sorted(set([w.n_cells - 1] + [int(c) for c in rng.choice(w.n_cells, 1, replace=False)]))
+    _say(f"case: config4 full size (4096 cells, p=4 dp=2), oracle on cells {cells}")
+    _sampled_full(w, cells)
+
+
+def test_config5_streamed_range_sampled():
+    """The 262144-cell curved workload is solved in ranges (its K_e do not
+    fit); one 8192-cell range at the end of the mesh, sampled against the oracle."""
+    torch = _torch()
+    from paper_2609_03155_amd import dpg
+    w = W.config5()
+    x, off = W.random_coefficients(w)
+    torch.cuda.empty_cache()
+    plan = dpg.Plan(w.degree, w.dp)
+    prob = dpg.DeviceProblem.from_workload(w)
+    first, count = w.n_cells - 8192, 8192
+    nK, nv = plan.range_sizes(first, count)
+    K = torch.empty(nK, dtype=torch.complex128, device="cuda")
+    l = torch.empty(nv, dtype=torch.complex128, device="cuda")
+    eta = torch.empty(count, dtype=torch.float64, device="cuda")
+    info = torch.empty(count, dtype=torch.int32, device="cuda")
+    xr = torch.from_numpy(x[off[first]:off[first + count]].copy()).cuda()
+    _say("case: config5 range solve of the last 8192 cells (p 2/3, curved)")
+    plan.local_solve_range(prob, first, count, xr, K, l, eta, info)
+    torch.cuda.synchronize()
+    assert np.all(info.cpu().numpy() == 0)
+    rng = np.random.default_rng(W.SEED_BASE + 35)
+    for c in sorted(set([w.n_cells - 1] + [first + int(q) for q in rng.choice(count, 1, replace=False)])):
+        Go, _, _, Ko, lo, eo = oracle_cell(w, c, x[off[c]:off[c + 1]])
+        tol = fp64_tol(Go)
+        k = int(off[c + 1] - off[c])
+        a = int(plan.K_off[c] - plan.K_off[first])
+        Kg = K[a:a + k * k].cpu().numpy().reshape(k, k).T
+        assert rel(Kg, Ko) < tol, (c, rel(Kg, Ko), tol)
+        assert abs(float(eta[c - first]) - eo) < tol * eo
