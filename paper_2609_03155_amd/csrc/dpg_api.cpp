@@ -188,6 +188,13 @@ void build_group(DegreeGroup& g, int dp) {
   t.CrefT = upload(g.bufs, CT);
   t.RtT = upload(g.bufs, RtT);
   t.T = upload(g.bufs, rt.T);
+  {
+    // the trace pairing summed over the six faces (cells without Robin faces use it as is)
+    std::vector<double> ts((size_t)d.N * d.nt1, 0.0);
+    for (int f = 0; f < 6; ++f)
+      for (size_t e = 0; e < ts.size(); ++e) ts[e] += rt.T[(size_t)f * ts.size() + e];
+    t.Tsum = upload(g.bufs, ts);
+  }
   t.sm_tiles = upload(g.bufs, tiles);
   t.n_sm_tiles = (int)tiles.size();
 }

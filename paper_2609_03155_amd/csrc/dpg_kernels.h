@@ -26,6 +26,7 @@ struct DevTables {
   const double* CrefT;     // [N][N] transpose
   const double* RtT;       // [6][N][N]  RtT[f][j][i] = Rt_f[i][j]
   const double* T;         // [6][N][nt1]
+  const double* Tsum;      // [N][nt1] sum of T over the faces
   const int4* sm_tiles;    // formation tiles (a, b, I, J) of the S/M kernel
   int n_sm_tiles;
 };

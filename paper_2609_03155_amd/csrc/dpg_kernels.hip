@@ -554,40 +554,42 @@ __global__ __launch_bounds__(NT, 2) void k_form_B(DevTables T, ProbArgs P, Chunk
   sRes[il][sub][1] = rI;
   // ---- trace unknowns (real, geometry free): one wave per (column, chunk of
   // 64 trace functions), lanes along the rows (coalesced); the wave's part of
-  // D B_f x is reduced in a fixed order and added per column chunk by chunk
+  // D B_f x is reduced in a fixed order and added per column chunk by chunk.
+  // The pairing summed over all faces is a table; Robin faces are taken off
+  // it for the F rows.
   __shared__ double2 sTr[64][2];
   {
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (threadIdx.x < 64) sTr[threadIdx.x][0] = sTr[threadIdx.x][1] = make_double2(0.0, 0.0);
     __syncthreads();
+    const int ncol = min(64, T.Np - i0);   // columns of this tile
     for (int c0 = 0; c0 < T.nt1; c0 += 64) {
-      for (int jl0 = 0; jl0 < 64; jl0 += NT / 64) {
-        const int jl = jl0 + wv, ii = i0 + jl, jt = c0 + lane;
-        if (ii >= T.Np) continue;   // uniform per wave
-        const bool okc = ii < T.N && jt < T.nt1;
-        double tI = 0.0, tF = 0.0;
-        if (okc) {
-          for (int f = 0; f < 6; ++f) {
-            const double t = T.T[((size_t)f * T.N + ii) * T.nt1 + jt];
-            tI += t;
-            if (!is_robin(fk[f])) tF += t;
-          }
+      const int jt = c0 + lane;
+      const bool okt = jt < T.nt1;
+      const int rowEh = nvp + T.nu + jt, rowHh = nvp + T.nu + T.nt1 + jt;
+      double2 xe = make_double2(0.0, 0.0), xh = xe;
+      if (xc && okt) {
+        xe = xc[T.nu + jt];
+        xh = xc[T.nu + T.nt1 + jt];
+      }
+#pragma unroll 4
+      for (int jl = wv; jl < ncol; jl += NT / 64) {
+        const int ii = i0 + jl;
+        const bool okc = ii < T.N && okt;
+        double tI = okc ? T.Tsum[(size_t)ii * T.nt1 + jt] : 0.0, tF = tI;
+        if (nrobin && okc) {
+          for (int f = 0; f < 6; ++f)
+            if (is_robin(fk[f])) tF -= T.T[((size_t)f * T.N + ii) * T.nt1 + jt];
         }
         const double tf = d[ii] * tF, ti = d[T.Np + ii] * tI;
-        if (jt < T.nt1) {
-          const int rowEh = nvp + T.nu + jt, rowHh = nvp + T.nu + T.nt1 + jt;
+        if (okt) {
           Z[(int64_t)ii * ld + rowEh] = make_double2(0.0, 0.0);
           Z[(int64_t)ii * ld + rowHh] = make_double2(tf, 0.0);
           Z[(int64_t)(T.Np + ii) * ld + rowEh] = make_double2(ti, 0.0);
           Z[(int64_t)(T.Np + ii) * ld + rowHh] = make_double2(0.0, 0.0);
         }
         if (xc) {
-          double2 pF = make_double2(0.0, 0.0), pI = pF;
-          if (okc) {
-            const double2 xe = xc[T.nu + jt], xh = xc[T.nu + T.nt1 + jt];
-            pF = make_double2(tf * xh.x, tf * xh.y);
-            pI = make_double2(ti * xe.x, ti * xe.y);
-          }
+          double2 pF = make_double2(tf * xh.x, tf * xh.y), pI = make_double2(ti * xe.x, ti * xe.y);
 #pragma unroll
           for (int off = 32; off > 0; off >>= 1) {
             pF.x += __shfl_xor(pF.x, off, 64);
@@ -912,31 +914,53 @@ __global__ __launch_bounds__(NT, 2) void k_form_SM(DevTables T, ProbArgs P, Chun
   racc_zero(MI);
   __syncthreads();
   const double* gmet = C.met + cell * met_stride(T);
-  // ---- volume points
-  for (int q0 = 0; q0 < T.nq; q0 += SQC) {
-    if (threadIdx.x < SQC * 12) {
-      const int qq = threadIdx.x / 12, e = threadIdx.x % 12, q = q0 + qq;
-      // gmet layout: Gc[nq][6] then Gm[nq][6]
-      sMet[qq][e] = (q < T.nq) ? gmet[(e < 6 ? 0 : 6 * T.nq) + 6 * q + (e % 6)] : 0.0;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < SQC * 64; e += NT) {
+  // ---- volume points, in chunks of SQC; the table values and metrics of
+  // the next chunk are fetched into registers while the current one is
+  // multiplied, so the load latency hides behind the MFMAs
+  constexpr int PER = SQC * 64 / NT;   // staged elements per thread and chunk
+  double pv[PER], pc1[PER], pc2[PER], qv[PER], qc1[PER], qc2[PER];
+  double pm = 0.0;
+  auto fetch = [&](int q0) {
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int e = threadIdx.x + k * NT;
       const int qq = e >> 6, il = e & 63;
       const int q = min(q0 + qq, T.nq - 1);
       const int i = a * T.nc + min(tl.z * 64 + il, T.nc - 1);
       const int jj = b * T.nc + min(tl.w * 64 + il, T.nc - 1);
-      const double* m = sMet[qq];
       const double* ci = &T.vol_c[((size_t)q * T.Np + i) * 3];
       const double* cj = &T.vol_c[((size_t)q * T.Np + jj) * 3];
-      Av[qq * LDP + il] = T.vol_v[(size_t)q * T.Np + i];
-      Ac1[qq * LDP + il] = ci[a1];
-      Ac2[qq * LDP + il] = ci[a2];
-      const double cj1 = cj[b1], cj2 = cj[b2];
-      Bv[qq * LDP + il] = m[6 + sab] * T.vol_v[(size_t)q * T.Np + jj];
-      By1[qq * LDP + il] = m[s11] * cj1 + m[s12] * cj2;
-      By2[qq * LDP + il] = m[s21] * cj1 + m[s22] * cj2;
+      pv[k] = T.vol_v[(size_t)q * T.Np + i];
+      pc1[k] = ci[a1];
+      pc2[k] = ci[a2];
+      qv[k] = T.vol_v[(size_t)q * T.Np + jj];
+      qc1[k] = cj[b1];
+      qc2[k] = cj[b2];
+    }
+    if (threadIdx.x < SQC * 12) {
+      const int qq = threadIdx.x / 12, e = threadIdx.x % 12, q = q0 + qq;
+      // gmet layout: Gc[nq][6] then Gm[nq][6]
+      pm = (q < T.nq) ? gmet[(e < 6 ? 0 : 6 * T.nq) + 6 * q + (e % 6)] : 0.0;
+    }
+  };
+  fetch(0);
+  for (int q0 = 0; q0 < T.nq; q0 += SQC) {
+    if (threadIdx.x < SQC * 12) sMet[threadIdx.x / 12][threadIdx.x % 12] = pm;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int e = threadIdx.x + k * NT;
+      const int qq = e >> 6, il = e & 63;
+      const double* m = sMet[qq];
+      Av[qq * LDP + il] = pv[k];
+      Ac1[qq * LDP + il] = pc1[k];
+      Ac2[qq * LDP + il] = pc2[k];
+      Bv[qq * LDP + il] = m[6 + sab] * qv[k];
+      By1[qq * LDP + il] = m[s11] * qc1[k] + m[s12] * qc2[k];
+      By2[qq * LDP + il] = m[s21] * qc1[k] + m[s22] * qc2[k];
     }
     __syncthreads();
+    if (q0 + SQC < T.nq) fetch(q0 + SQC);
     lds_atb(Av, Bv, SQC, M);
     lds_atb(Ac1, By1, SQC, S);
     lds_atb(Ac2, By2, SQC, S);
@@ -1005,6 +1029,20 @@ constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
 constexpr size_t kFactorSmem = 2 * 64 * 65 * 8;
 static_assert(kFactorSmem <= 80 * 1024, "two factorisation workgroups must fit one CU");
 
+// 1/sqrt(d) for the pivots of the tile factorisation (d > 0 and finite, of
+// order one after the diagonal scaling): the hardware estimate refined by two
+// Newton steps y <- y + y (1 - d y^2) / 2, about one ulp, with a dependency
+// chain a quarter as long as an IEEE square root followed by a division.
+__device__ __forceinline__ double pivot_rsqrt(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-d * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
 // Cholesky factor and inverse of the 64x64 Hermitian tile whose lower part
 // is in Cr/Ci[r*65+q]; writes L^{-1} (lower, zero upper) to the column-major
 // tile `out` and returns the first failing column + 1 (0 if none), the same
@@ -1015,75 +1053,110 @@ static_assert(kFactorSmem <= 80 * 1024, "two factorisation workgroups must fit o
 // through a double-buffered LDS slot, one barrier per step, and every thread
 // applies
 //   A_rq -= L_rc conj(L_qc)   and   X_rq -= L_rc X_cq ,   L_rc = 0 for r <= c,
-// then X_c. /= L_cc.  A wave skips the A update once all its columns are
+// and row c of X is scaled by 1/L_cc (deferred to the end: the row is not
+// read again after step c, and the other rows use it before the scaling).
+// A wave skips the A update once all its columns are
 // done (16g + 15 < c) and the X update while X_cq = 0 for all its columns
 // (16g > c); entries of A left of column c or above the diagonal take
 // meaningless updates but are never read again.  Cr/Ci are reused as the
-// broadcast slots.
+// broadcast slots.  REAL: the tile is real (Ci is not read), and the
+// imaginary parts are dropped from the arithmetic and the broadcasts.
+template <bool REAL>
 __device__ __forceinline__ int chol_inv_tile(double* Cr, const double* Ci, double2* __restrict__ out, int64_t ld) {
-  const int r = threadIdx.x & 63;
+  int r = threadIdx.x & 63;
+  __asm__ volatile("" : "+v"(r));   // not hoisted out of a caller's loop (as in wave_tile)
   const int g = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   double ar[16], ai[16], xr[16], xi[16];
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int q = 16 * g + u;
     ar[u] = q <= r ? Cr[r * 65 + q] : 0.0;
-    ai[u] = q <= r ? Ci[r * 65 + q] : 0.0;
+    ai[u] = !REAL && q <= r ? Ci[r * 65 + q] : 0.0;
     xr[u] = q == r ? 1.0 : 0.0;
     xi[u] = 0.0;
   }
   __syncthreads();
-  double2* cb = reinterpret_cast<double2*>(Cr);   // [2][64]: column c of A
-  double2* rb = cb + 128;                          // [2][64]: row c of X (before its scaling)
+  // broadcast slots [2][64] of column c of A and of row c of X (before its scaling)
+  double2* cb = reinterpret_cast<double2*>(Cr);
+  double2* rb = cb + 128;
+  double* cbr = Cr;
+  double* rbr = Cr + 128;
   int fail = 0;
+  double pinv = 1.0;   // 1 / L_rr of this thread's row
   for (int kb = 0; kb < 4; ++kb) {
 #pragma unroll
     for (int uc = 0; uc < 16; ++uc) {
       const int c = 16 * kb + uc;
       const int par = (uc & 1) * 64;
-      if (g == kb) cb[par + r] = r >= c ? make_double2(ar[uc], ai[uc]) : make_double2(0.0, 0.0);
+      if (g == kb) {
+        if (REAL) cbr[par + r] = r >= c ? ar[uc] : 0.0;
+        else cb[par + r] = r >= c ? make_double2(ar[uc], ai[uc]) : make_double2(0.0, 0.0);
+      }
       if (r == c) {
 #pragma unroll
-        for (int u = 0; u < 16; ++u) rb[par + 16 * g + u] = make_double2(xr[u], xi[u]);
+        for (int u = 0; u < 16; ++u) {
+          if (REAL) rbr[par + 16 * g + u] = xr[u];
+          else rb[par + 16 * g + u] = make_double2(xr[u], xi[u]);
+        }
       }
       __syncthreads();
-      const double2 own = cb[par + r];
-      double d = cb[par + c].x;
+      double ownr, owni = 0.0, d;
+      if (REAL) {
+        ownr = cbr[par + r];
+        d = cbr[par + c];
+      } else {
+        const double2 own = cb[par + r];
+        ownr = own.x;
+        owni = own.y;
+        d = cb[par + c].x;
+      }
       if (!(d > 0.0) || !isfinite(d)) {
         if (!fail) fail = c + 1;
         d = 1.0;
       }
-      const double inv = 1.0 / sqrt(d);
-      const double lr = r > c ? own.x * inv * inv : 0.0, li = r > c ? own.y * inv * inv : 0.0;   // L_rc / L_cc
+      const double inv = pivot_rsqrt(d);
+      const double inv2 = inv * inv;
+      const double lr = r > c ? ownr * inv2 : 0.0, li = r > c ? owni * inv2 : 0.0;   // L_rc / L_cc
       if (g >= kb) {
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
-          const double2 m = cb[par + 16 * g + u];   // A_qc (broadcast)
-          ar[u] -= lr * m.x + li * m.y;
-          ai[u] -= li * m.x - lr * m.y;
+          if (REAL) {
+            ar[u] = fma(-lr, cbr[par + 16 * g + u], ar[u]);
+          } else {
+            const double2 m = cb[par + 16 * g + u];   // A_qc (broadcast)
+            ar[u] = fma(-lr, m.x, ar[u]);
+            ar[u] = fma(-li, m.y, ar[u]);
+            ai[u] = fma(-li, m.x, ai[u]);
+            ai[u] = fma(lr, m.y, ai[u]);
+          }
         }
       }
       if (g <= kb) {
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
-          const double2 y = rb[par + 16 * g + u];   // X_cq before scaling (broadcast)
-          xr[u] -= lr * y.x - li * y.y;
-          xi[u] -= lr * y.y + li * y.x;
+          if (REAL) {
+            xr[u] = fma(-lr, rbr[par + 16 * g + u], xr[u]);
+          } else {
+            const double2 y = rb[par + 16 * g + u];   // X_cq before scaling (broadcast)
+            xr[u] = fma(-lr, y.x, xr[u]);
+            xr[u] = fma(li, y.y, xr[u]);
+            xi[u] = fma(-lr, y.y, xi[u]);
+            xi[u] = fma(-li, y.x, xi[u]);
+          }
         }
       }
-      if (r == c) {
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-          xr[u] *= inv;
-          xi[u] *= inv;
-        }
-      }
+      if (r == c) pinv = inv;
     }
   }
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
+    xr[u] *= pinv;
+    if (!REAL) xi[u] *= pinv;
+  }
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
     const int q = 16 * g + u;
-    out[(int64_t)q * ld + r] = q <= r ? make_double2(xr[u], xi[u]) : make_double2(0.0, 0.0);
+    out[(int64_t)q * ld + r] = q <= r ? make_double2(xr[u], REAL ? 0.0 : xi[u]) : make_double2(0.0, 0.0);
   }
   return fail;
 }
@@ -1107,7 +1180,7 @@ __global__ __launch_bounds__(NT) void k_chol_diag0(DevTables T, ChunkArgs C) {
     }
   }
   __syncthreads();
-  const int fail = chol_inv_tile(Cr, Ci, tile, ld);
+  const int fail = T.Np >= TB ? chol_inv_tile<true>(Cr, Ci, tile, ld) : chol_inv_tile<false>(Cr, Ci, tile, ld);
   if (threadIdx.x == 0 && fail && C.info[gc - C.cell_base] == 0) C.info[gc - C.cell_base] = fail;
 }
 
@@ -1144,6 +1217,9 @@ struct WOps {
 template <int MODE>
 struct WPipe {
   static constexpr int NB = MODE == MM_RR ? 6 : (MODE == MM_CR ? 2 : 2);
+  // k-steps per buffer: a complex x real k-step has half the MFMAs of a
+  // complex one, so its buffers take two, to keep as much work in flight
+  static constexpr int KS = MODE == MM_CR ? 1 : 1;
 };
 
 template <int MODE>
@@ -1198,25 +1274,33 @@ __device__ __forceinline__ void wave_step(const WOps& o, WAcc& q) {
 template <int MODE>
 __device__ __forceinline__ void wave_gemm_t(const double2* __restrict__ Ai, const double2* __restrict__ Bj, int64_t ld,
                                             int K, WAcc& q) {
-  constexpr int NB = WPipe<MODE>::NB;
-  const int nks = K / 4;
+  constexpr int NB = WPipe<MODE>::NB, KS = WPipe<MODE>::KS;
+  const int nks = K / (4 * KS);   // buffers' worth of k-steps (K is a multiple of 64)
   if (nks <= 0) return;
   const int nfull = nks - nks % NB;
-  WOps o[NB];
+  WOps o[NB][KS];
 #pragma unroll
-  for (int s = 0; s < NB - 1; ++s) wave_load<MODE>(Ai, Bj, ld, min(s, nks - 1), o[s]);
+  for (int s = 0; s < NB - 1; ++s)
+#pragma unroll
+    for (int u = 0; u < KS; ++u) wave_load<MODE>(Ai, Bj, ld, min(s, nks - 1) * KS + u, o[s][u]);
   for (int k0 = 0; k0 < nfull; k0 += NB) {
 #pragma unroll
     for (int s = 0; s < NB; ++s) {
-      wave_load<MODE>(Ai, Bj, ld, min(k0 + s + NB - 1, nks - 1), o[(s + NB - 1) % NB]);
+#pragma unroll
+      for (int u = 0; u < KS; ++u)
+        wave_load<MODE>(Ai, Bj, ld, min(k0 + s + NB - 1, nks - 1) * KS + u, o[(s + NB - 1) % NB][u]);
       __builtin_amdgcn_sched_barrier(0);   // keep each prefetch in its slot (bounded live ranges)
-      wave_step<MODE>(o[s], q);
+#pragma unroll
+      for (int u = 0; u < KS; ++u) wave_step<MODE>(o[s][u], q);
       __builtin_amdgcn_sched_barrier(0);
     }
   }
 #pragma unroll
   for (int s = 0; s < NB - 1; ++s)
-    if (s < nks - nfull) wave_step<MODE>(o[s], q);
+    if (s < nks - nfull) {
+#pragma unroll
+      for (int u = 0; u < KS; ++u) wave_step<MODE>(o[s][u], q);
+    }
 }
 
 // Rows [32h, 32h + 32) of the regular tile (i, j) of step j, one wave:
@@ -1227,8 +1311,13 @@ __device__ __forceinline__ void wave_gemm_t(const double2* __restrict__ Ai, cons
 template <int MODE>
 __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __restrict__ Z, int64_t cell, int i, int j,
                           int h, unsigned char* slab) {
-  const int64_t ld = T.ldz;
-  const int lane = threadIdx.x & 63;
+  // ld and lane pass through empty asm so that, in a loop over tiles, the
+  // compiler recomputes the lane addresses per tile instead of keeping them
+  // all live across the loop (which spills)
+  int64_t ld = T.ldz;
+  __asm__ volatile("" : "+s"(ld));
+  int lane = threadIdx.x & 63;
+  __asm__ volatile("" : "+v"(lane));
   double2* tile = Z + (int64_t)(j * TB) * ld + i * TB + 32 * h;   // rows of A_ij in, of L_ij out
   // the accumulators start as A_ij^T, so that they end as X^T
   WAcc q;
@@ -1329,7 +1418,9 @@ __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __res
 template <int MODE, bool FROM_TILE>
 __device__ __forceinline__ void diag_update(const double2* __restrict__ S0g, const double2* __restrict__ P, int64_t ld,
                                             int K, int h, double* Sr, double* Si) {
-  const int lane = threadIdx.x & 63;
+  int lane = threadIdx.x & 63;
+  __asm__ volatile("" : "+v"(lane));   // not hoisted out of a caller's loop (as in wave_tile)
+  __asm__ volatile("" : "+s"(ld));
   WAcc q;
 #pragma unroll
   for (int u = 0; u < 4; ++u)
@@ -1362,12 +1453,13 @@ __device__ __forceinline__ void diag_update(const double2* __restrict__ S0g, con
 }
 
 // Step j of the left-looking factorisation over the row tiles i > j:
-//   L_ij = (A_ij - sum_{m<j} L_im L_jm^H) Linv_jj^H .
-// Tile i = j+1 (while it is a test tile) is the lookahead tile: its
-// workgroup also forms A_ii - sum_{m<=j} L_im L_im^H and factorises it
-// (Cholesky + inverse), storing Linv_ii for step j+1, so no separate launch
-// factors diagonal blocks.  Every other tile is two waves (wave_tile, one row
-// half each), two tiles per workgroup.
+//   L_ij = (A_ij - sum_{m<j} L_im L_jm^H) Linv_jj^H ,
+// for the columns after the real F block (all of them when there is none),
+// where every tile is complex.  Tile i = j+1 (while it is a test tile) is
+// the lookahead tile: its workgroup also forms A_ii - sum_{m<=j} L_im L_im^H
+// and factorises it (Cholesky + inverse), storing Linv_ii for step j+1, so
+// no separate launch factors diagonal blocks.  Every other tile is two waves
+// (wave_tile, one row half each), two tiles per workgroup.
 __global__ __launch_bounds__(NT, 2) void k_chol_step(DevTables T, ChunkArgs C, int j) {
   const int nrb = T.nrows / TB, nvb = T.nvp / TB;
   const bool la = j + 1 < nvb;
@@ -1388,12 +1480,9 @@ __global__ __launch_bounds__(NT, 2) void k_chol_step(DevTables T, ChunkArgs C, i
     if (cell >= C.n) return;   // whole waves: no barrier follows on this path
     const int i = j + 1 + (la ? 1 : 0) + t;
     double2* Z = C.Z + cell * T.zstride;
-    const bool ireal = (i + 1) * TB <= T.Np, jreal = (j + 1) * TB <= T.Np;
     extern __shared__ double smem[];
     unsigned char* slab = reinterpret_cast<unsigned char*>(smem) + wave * WSP_BYTES;
-    if (ireal) wave_tile<MM_RR>(T, C, Z, cell, i, j, wave & 1, slab);
-    else if (jreal) wave_tile<MM_CR>(T, C, Z, cell, i, j, wave & 1, slab);
-    else wave_tile<MM_CC>(T, C, Z, cell, i, j, wave & 1, slab);
+    wave_tile<MM_CC>(T, C, Z, cell, i, j, wave & 1, slab);
     return;
   }
   // ---- lookahead workgroup: tile (i, j), i = j + 1, on waves 0 and 1 (one
@@ -1407,27 +1496,117 @@ __global__ __launch_bounds__(NT, 2) void k_chol_step(DevTables T, ChunkArgs C, i
   const int64_t ld = T.ldz;
   const int wave = (int)(threadIdx.x >> 6);
   double2* Z = C.Z + cell * T.zstride;
-  const bool ireal = (i + 1) * TB <= T.Np, jreal = (j + 1) * TB <= T.Np;
   extern __shared__ double smem[];
   double* Cr = smem;
   double* Ci = Cr + 64 * 65;
   double2* tileD = Z + (int64_t)(i * TB) * ld + i * TB;
-  if (wave < 2) {
-    if (ireal) wave_tile<MM_RR>(T, C, Z, cell, i, j, wave, nullptr);
-    else if (jreal) wave_tile<MM_CR>(T, C, Z, cell, i, j, wave, nullptr);
-    else wave_tile<MM_CC>(T, C, Z, cell, i, j, wave, nullptr);
-  } else {
-    if (ireal) diag_update<MM_RR, true>(tileD, Z + i * TB, ld, j * TB, wave - 2, Cr, Ci);
-    else diag_update<MM_CC, true>(tileD, Z + i * TB, ld, j * TB, wave - 2, Cr, Ci);
-  }
+  if (wave < 2) wave_tile<MM_CC>(T, C, Z, cell, i, j, wave, nullptr);
+  else diag_update<MM_CC, true>(tileD, Z + i * TB, ld, j * TB, wave - 2, Cr, Ci);
   __syncthreads();   // L_ij stored (workgroup scope); partial diagonal block in LDS
   if (wave >= 2) {
     const double2* Lij = Z + (int64_t)(j * TB) * ld + i * TB;   // column block j of panel i
-    if (ireal) diag_update<MM_RR, false>(nullptr, Lij, ld, TB, wave - 2, Cr, Ci);
-    else diag_update<MM_CC, false>(nullptr, Lij, ld, TB, wave - 2, Cr, Ci);
+    diag_update<MM_CC, false>(nullptr, Lij, ld, TB, wave - 2, Cr, Ci);
   }
   __syncthreads();
-  const int fail = chol_inv_tile(Cr, Ci, tileD, ld);
+  const int fail = chol_inv_tile<false>(Cr, Ci, tileD, ld);
+  const int64_t gc = C.cell_ids[cell];
+  if (threadIdx.x == 0 && fail && C.info[gc - C.cell_base] == 0) C.info[gc - C.cell_base] = i * TB + fail;
+}
+
+// Factorisation of the real F block (row and column tiles < nF) of every
+// cell in one launch, one workgroup per cell:
+//   Linv_00 = chol(A_00)^{-1};  for j = 0 .. nF-2:
+//     L_ij = (A_ij - sum_{m<j} L_im L_jm^T) Linv_jj^T   for j < i < nF
+//            (two tiles at a time, one per wave pair),
+//     Linv_{j+1,j+1} = chol(A_{j+1,j+1} - sum_{m<=j} L_{j+1,m} L_{j+1,m}^T)^{-1} .
+// The block is small, so its cost is the latency of the chain, which one
+// workgroup walks without a launch (and a pass over all cells) per step.
+__global__ __launch_bounds__(NT, 2) void k_chol_fblock(DevTables T, ChunkArgs C, int nF) {
+  const int64_t cell = blockIdx.x;
+  if (cell >= C.n) return;
+  const int64_t gc = C.cell_ids[cell];
+  const int64_t ld = T.ldz;
+  const int wave = (int)(threadIdx.x >> 6);
+  double2* Z = C.Z + cell * T.zstride;
+  extern __shared__ double smem[];
+  double* Cr = smem;
+  double* Ci = Cr + 64 * 65;
+  int fail = 0;
+  for (int j = 0;; ++j) {
+    // diagonal block j, updated by the columns before it, into LDS
+    double2* tileD = Z + (int64_t)(j * TB) * ld + j * TB;
+    if (j == 0) {
+      for (int e = threadIdx.x; e < 64 * 64; e += NT) {
+        const int q = e >> 6, r = e & 63;
+        if (q <= r) Cr[r * 65 + q] = tileD[(int64_t)q * ld + r].x;
+      }
+    } else if (wave < 2) {
+      diag_update<MM_RR, true>(tileD, Z + j * TB, ld, j * TB, wave, Cr, Ci);
+    }
+    __syncthreads();
+    const int f = chol_inv_tile<true>(Cr, Ci, tileD, ld);
+    if (f && !fail) fail = j * TB + f;
+    if (j + 1 == nF) break;
+    __syncthreads();   // Linv_jj stored (workgroup scope); LDS free
+    for (int i = j + 1 + (wave >> 1); i < nF; i += 2) wave_tile<MM_RR>(T, C, Z, cell, i, j, wave & 1, nullptr);
+    __syncthreads();   // column block j stored
+  }
+  if (threadIdx.x == 0 && fail && C.info[gc - C.cell_base] == 0) C.info[gc - C.cell_base] = fail;
+}
+
+// The real F columns of all remaining rows in one launch.  Once the F block
+// (row and column tiles < nF, all real) is factorised, the rows i >= nF need
+// nothing else for their F columns: a wave pair walks its row tile through
+// j = 0 .. nF-1,
+//   L_ij = (A_ij - sum_{m<j} L_im L_jm^T) Linv_jj^T ,
+// and reads back the row panel L_i,<j it has just written, which is still
+// in the caches, instead of every step re-reading it from HBM in a launch of
+// its own.  Row tile nF is taken by the first workgroups (one per cell):
+// waves 0 and 1 walk it while waves 2 and 3 subtract each finished
+// L_{nF,j} L_{nF,j}^H from the diagonal block in LDS, and all four
+// factorise the result, storing Linv_{nF,nF} for the step nF.
+__global__ __launch_bounds__(NT, 2) void k_chol_fpanel(DevTables T, ChunkArgs C, int nF) {
+  const int nrb = T.nrows / TB;
+  const int nreg = nrb - nF - 1;   // row tiles after nF, two per workgroup
+  const int64_t n8 = (C.n + 7) / 8 * 8;
+  const int wave = (int)(threadIdx.x >> 6);
+  extern __shared__ double smem[];
+  if ((int64_t)blockIdx.x >= n8) {
+    // per XCD x the (cell, tile) pairs of its cells c = 8 m + x in (m, tile) order, two per workgroup
+    const int64_t w = (int64_t)blockIdx.x - n8;
+    const int64_t item = (w >> 3) * 2 + (wave >> 1);
+    const int64_t m = item / nreg;
+    const int t = (int)(item - m * nreg);
+    const int64_t cell = m * 8 + (w & 7);
+    if (cell >= C.n) return;   // whole waves: no barrier on this path
+    const int i = nF + 1 + t;
+    double2* Z = C.Z + cell * T.zstride;
+    unsigned char* slab = reinterpret_cast<unsigned char*>(smem) + wave * WSP_BYTES;
+    for (int j = 0; j < nF; ++j) {
+      wave_tile<MM_CR>(T, C, Z, cell, i, j, wave & 1, slab);
+      // L_ij (stored by all lanes) feeds the loads of step j + 1
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+    return;
+  }
+  const int64_t cell = blockIdx.x;
+  if (cell >= C.n) return;
+  const int i = nF;
+  const int64_t ld = T.ldz;
+  double2* Z = C.Z + cell * T.zstride;
+  double* Cr = smem;
+  double* Ci = Cr + 64 * 65;
+  double2* tileD = Z + (int64_t)(i * TB) * ld + i * TB;
+  if (wave >= 2) diag_update<MM_CC, true>(tileD, Z + i * TB, ld, 0, wave - 2, Cr, Ci);   // A_ii into LDS
+  for (int j = 0; j < nF; ++j) {
+    if (wave < 2) wave_tile<MM_CR>(T, C, Z, cell, i, j, wave, nullptr);
+    __syncthreads();   // L_ij stored (workgroup scope)
+    if (wave >= 2) diag_update<MM_CC, false>(nullptr, Z + (int64_t)(j * TB) * ld + i * TB, ld, TB, wave - 2, Cr, Ci);
+  }
+  __syncthreads();
+  const int fail = chol_inv_tile<false>(Cr, Ci, tileD, ld);
   const int64_t gc = C.cell_ids[cell];
   if (threadIdx.x == 0 && fail && C.info[gc - C.cell_base] == 0) C.info[gc - C.cell_base] = i * TB + fail;
 }
@@ -1554,10 +1733,13 @@ __global__ __launch_bounds__(NT, 2) void k_herk_split(DevTables T, ChunkArgs C) 
   } while (0)
   f4 fr[2][2], fi[2][2];
   double dr[2][2][4], di[2][2][4];
+#pragma unroll
   for (int u = 0; u < 2; ++u)
+#pragma unroll
     for (int v = 0; v < 2; ++v) {
       fr[u][v] = f4{0, 0, 0, 0};
       fi[u][v] = f4{0, 0, 0, 0};
+#pragma unroll
       for (int e = 0; e < 4; ++e) dr[u][v][e] = di[u][v][e] = 0.0;
     }
   const int nst = T.nvp / SKC;
@@ -1571,7 +1753,7 @@ __global__ __launch_bounds__(NT, 2) void k_herk_split(DevTables T, ChunkArgs C) 
     // B fragments of both column blocks once per stage; A per row block; the
     // four accumulators of a row block alternate so that no MFMA waits on the
     // previous one's result.
-    bf8 Br[2][3], Bi[2][3], nBi[2][3];
+    bf8 Br[2][3], Bi[2][3];
 #pragma unroll
     for (int v = 0; v < 2; ++v) {
       const int brow = wc * 32 + v * 16 + (lane & 15);
@@ -1579,17 +1761,17 @@ __global__ __launch_bounds__(NT, 2) void k_herk_split(DevTables T, ChunkArgs C) 
       for (int t = 0; t < 3; ++t) {
         Br[v][t] = lds_frag(ss->B[t], brow, kq);
         Bi[v][t] = lds_frag(ss->B[3 + t], brow, kq);
-        nBi[v][t] = neg_frag(Bi[v][t]);
       }
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int arow = wr * 32 + u * 16 + (lane & 15);
-      bf8 Ar[3], Ai[3];
+      bf8 Ar[3], Ai[3], nAr[3];
 #pragma unroll
       for (int t = 0; t < 3; ++t) {
         Ar[t] = lds_frag(ss->A[t], arow, kq);
         Ai[t] = lds_frag(ss->A[3 + t], arow, kq);
+        nAr[t] = neg_frag(Ar[t]);
       }
       // re += Ar Br^T + Ai Bi^T ; im += Ai Br^T - Ar Bi^T   (terms with s + t <= 2)
 #pragma unroll
@@ -1604,13 +1786,16 @@ __global__ __launch_bounds__(NT, 2) void k_herk_split(DevTables T, ChunkArgs C) 
 #pragma unroll
           for (int v = 0; v < 2; ++v) {
             fr[u][v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ai[s2], Bi[v][t2], fr[u][v], 0, 0, 0);
-            fi[u][v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ar[s2], nBi[v][t2], fi[u][v], 0, 0, 0);
+            fi[u][v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nAr[s2], Bi[v][t2], fi[u][v], 0, 0, 0);
           }
         }
     }
     if ((sidx & 1) || sidx + 1 == nst) {
+#pragma unroll
       for (int u = 0; u < 2; ++u)
+#pragma unroll
         for (int v = 0; v < 2; ++v) {
+#pragma unroll
           for (int e = 0; e < 4; ++e) {
             dr[u][v][e] += (double)fr[u][v][e];
             di[u][v][e] += (double)fi[u][v][e];
@@ -1620,24 +1805,51 @@ __global__ __launch_bounds__(NT, 2) void k_herk_split(DevTables T, ChunkArgs C) 
         }
     }
   }
+  // The tile leaves through LDS, 32 columns at a time, so that both its
+  // stores (column runs of K) and those of its conjugate mirror (row runs)
+  // are coalesced.
   const int k = T.k;
   double2* K = C.K + (C.K_off[gc] - C.K_base);
   double2* L = C.l + (C.v_off[gc] - C.v_base);
-  for (int u = 0; u < 2; ++u)
-    for (int v = 0; v < 2; ++v)
-      for (int e = 0; e < 4; ++e) {
-        // f32 16x16 accumulator layout: item e of lane l -> row 4(l>>4) + e, column l & 15
-        const int r = wr * 32 + u * 16 + 4 * (lane >> 4) + e, c = wc * 32 + v * 16 + (lane & 15);
-        const int al = a * TB + r, be = b * TB + c;
-        const double vr = dr[u][v][e], vi = di[u][v][e];
-        if (al < k && be < k) {
-          if (a == b && be > al) continue;
-          K[(int64_t)be * k + al] = make_double2(vr, vi);
-          if (al != be) K[(int64_t)al * k + be] = make_double2(vr, -vi);
-        } else if (al == k && be < k) {
-          L[be] = make_double2(vr, -vi);
-        }
+  constexpr int OP = 33;   // double2 pitch of the staged [64][32] half tile
+  static_assert(64 * OP * sizeof(double2) <= sizeof(SplitStage), "staged half tile fits the stage buffer");
+  double2* so = reinterpret_cast<double2*>(smem);
+#pragma unroll
+  for (int hc = 0; hc < 2; ++hc) {
+    __syncthreads();   // stage buffer free
+    if (wc == hc) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            // f32 16x16 accumulator layout: item e of lane l -> row 4(l>>4) + e, column l & 15
+            const int r = wr * 32 + u * 16 + 4 * (lane >> 4) + e, cl = v * 16 + (lane & 15);
+            so[r * OP + cl] = make_double2(dr[u][v][e], di[u][v][e]);
+          }
+    }
+    __syncthreads();
+    // element (al, be) of the tile: al = a TB + row, be = b TB + 32 hc + column
+    for (int e = threadIdx.x; e < 64 * 32; e += NT) {
+      const int cl = e >> 6, rl = e & 63;
+      const int al = a * TB + rl, be = b * TB + 32 * hc + cl;
+      const double2 v = so[rl * OP + cl];
+      if (al < k && be < k) {
+        if (!(a == b && be > al)) K[(int64_t)be * k + al] = v;
+      } else if (al == k && be < k) {
+        L[be] = make_double2(v.x, -v.y);
       }
+    }
+    for (int e = threadIdx.x; e < 64 * 32; e += NT) {
+      const int rl = e >> 5, cl = e & 31;
+      const int al = a * TB + rl, be = b * TB + 32 * hc + cl;
+      if (al < k && be < k && al != be && !(a == b && be > al)) {
+        const double2 v = so[rl * OP + cl];
+        K[(int64_t)al * k + be] = make_double2(v.x, -v.y);
+      }
+    }
+  }
 }
 
 #undef DPG_SPLIT_GLOAD
@@ -1733,14 +1945,24 @@ hipError_t launch_formation(const DevTables& t, const ProbArgs& pa, const ChunkA
 hipError_t launch_factor(const DevTables& t, const ChunkArgs& ca, hipStream_t st, Prof* prof) {
   if (ca.n <= 0) return hipSuccess;
   const int nvb = t.nvp / TB, nrb = t.nrows / TB;
-  DPG_LAUNCH(KC_CHOL_DIAG, prof, st, k_chol_diag0, dim3((unsigned)ca.n), dim3(NT), kFactorSmem, st, t, ca);
   const int64_t n8 = (ca.n + 7) / 8 * 8;
-  for (int j = 0; j < nvb; ++j) {
-    // lookahead workgroups (one per cell) + two wave-pair tiles per workgroup
+  // lookahead workgroups (one per cell) + two wave-pair tiles per workgroup
+  auto grid_of = [&](bool la, int nreg) { return (unsigned)((la ? n8 : 0) + 8 * ((n8 / 8 * nreg + 1) / 2)); };
+  int j0 = 0;
+  const int nF = t.Np / TB;   // leading column tiles that are real
+  if (nF >= 1) {
+    // F block first (one workgroup per cell), then the F columns of every other row in one launch
+    DPG_LAUNCH(KC_CHOL_DIAG, prof, st, k_chol_fblock, dim3((unsigned)ca.n), dim3(NT), kFactorSmem, st, t, ca, nF);
+    DPG_LAUNCH(KC_CHOL_PANEL, prof, st, k_chol_fpanel, dim3(grid_of(true, nrb - nF - 1)), dim3(NT), kFactorSmem, st,
+               t, ca, nF);
+    j0 = nF;
+  } else {
+    DPG_LAUNCH(KC_CHOL_DIAG, prof, st, k_chol_diag0, dim3((unsigned)ca.n), dim3(NT), kFactorSmem, st, t, ca);
+  }
+  for (int j = j0; j < nvb; ++j) {
     const bool la = j + 1 < nvb;
     const int nreg = nrb - j - 1 - (la ? 1 : 0);
-    const unsigned grid = (unsigned)((la ? n8 : 0) + 8 * ((n8 / 8 * nreg + 1) / 2));
-    DPG_LAUNCH(KC_CHOL_PANEL, prof, st, k_chol_step, dim3(grid), dim3(NT), kFactorSmem, st, t, ca, j);
+    DPG_LAUNCH(KC_CHOL_PANEL, prof, st, k_chol_step, dim3(grid_of(la, nreg)), dim3(NT), kFactorSmem, st, t, ca, j);
   }
   return hipGetLastError();
 }
@@ -1778,6 +2000,7 @@ hipError_t configure_kernels() {
   e = hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev);
   if (e != hipSuccess) return e;
   const void* fns[] = {reinterpret_cast<const void*>(&k_chol_diag0), reinterpret_cast<const void*>(&k_chol_step),
+                       reinterpret_cast<const void*>(&k_chol_fpanel), reinterpret_cast<const void*>(&k_chol_fblock),
                        reinterpret_cast<const void*>(&k_cell_scale),
                        reinterpret_cast<const void*>(&k_form_B), reinterpret_cast<const void*>(&k_herk),
                        reinterpret_cast<const void*>(&k_herk_split)};
