@@ -376,14 +376,9 @@ __global__ __launch_bounds__(NT, 2) void k_form_B(DevTables T, ProbArgs P, Chunk
   double* sPhi = smem;                      // [BQC][m1]
   load_cell_vertices(P, gc, sX);
   const double2* xc = C.x ? C.x + (C.v_off[gc] - C.v_base) : nullptr;
-  int8_t fk[6];
-  double2 zf[6];
-  int nrobin = 0;
-  for (int f = 0; f < 6; ++f) {
-    fk[f] = P.face_kind[gc * 6 + f];
-    zf[f] = make_double2(P.zinv[(gc * 6 + f) * 2], P.zinv[(gc * 6 + f) * 2 + 1]);
-    nrobin += is_robin(fk[f]);
-  }
+  int rmask = 0;   // bit f: face f is a Robin face (a mask, not a per-face array: no scratch)
+  for (int f = 0; f < 6; ++f) rmask |= is_robin(P.face_kind[gc * 6 + f]) ? 1 << f : 0;
+  const int nrobin = __builtin_popcount(rmask);
   __syncthreads();
   const double2 eps = make_double2(P.eps[2 * gc], P.eps[2 * gc + 1]);
   const double2 mu = make_double2(P.mu[2 * gc], P.mu[2 * gc + 1]);
@@ -450,7 +445,8 @@ __global__ __launch_bounds__(NT, 2) void k_form_B(DevTables T, ProbArgs P, Chunk
     // ---- Robin faces: Dt weighted by z (complex)
     if (nrobin) {
       for (int f = 0; f < 6; ++f) {
-        if (!is_robin(fk[f])) continue;
+        if (!((rmask >> f) & 1)) continue;
+        const double2 zf = make_double2(P.zinv[(gc * 6 + f) * 2], P.zinv[(gc * 6 + f) * 2 + 1]);
         for (int q0 = 0; q0 < T.nfq; q0 += BQC) {
           const int nqc = min(BQC, T.nfq - q0);
           __syncthreads();
@@ -485,12 +481,12 @@ __global__ __launch_bounds__(NT, 2) void k_form_B(DevTables T, ProbArgs P, Chunk
             for (int u = 0; u < BIT; ++u) {
               const int m = ib + sub + 4 * u;
               const double ph = (m < m1) ? sPhi[qq * m1 + m] : 0.0;
-              Dtr[u][0] += zf[f].x * p0 * ph;
-              Dtr[u][1] += zf[f].x * p1 * ph;
-              Dtr[u][2] += zf[f].x * p2 * ph;
-              Dti[u][0] += zf[f].y * p0 * ph;
-              Dti[u][1] += zf[f].y * p1 * ph;
-              Dti[u][2] += zf[f].y * p2 * ph;
+              Dtr[u][0] += zf.x * p0 * ph;
+              Dtr[u][1] += zf.x * p1 * ph;
+              Dtr[u][2] += zf.x * p2 * ph;
+              Dti[u][0] += zf.y * p0 * ph;
+              Dti[u][1] += zf.y * p1 * ph;
+              Dti[u][2] += zf.y * p2 * ph;
             }
           }
         }
@@ -579,7 +575,7 @@ __global__ __launch_bounds__(NT, 2) void k_form_B(DevTables T, ProbArgs P, Chunk
         double tI = okc ? T.Tsum[(size_t)ii * T.nt1 + jt] : 0.0, tF = tI;
         if (nrobin && okc) {
           for (int f = 0; f < 6; ++f)
-            if (is_robin(fk[f])) tF -= T.T[((size_t)f * T.N + ii) * T.nt1 + jt];
+            if ((rmask >> f) & 1) tF -= T.T[((size_t)f * T.N + ii) * T.nt1 + jt];
         }
         const double tf = d[ii] * tF, ti = d[T.Np + ii] * tI;
         if (okt) {
@@ -1303,14 +1299,28 @@ __device__ __forceinline__ void wave_gemm_t(const double2* __restrict__ Ai, cons
     }
 }
 
+// Structure of the 32 augmented rows [r0, r0 + 32) in the F columns: the
+// rows of the E-hat trace unknowns pair with no F test function (zero there,
+// so are the padding rows), those of H-hat only through the real trace table
+// (real); the interior, load and residual rows and the I test rows are complex.
+enum { FROWS_COMPLEX = 0, FROWS_REAL = 1, FROWS_ZERO = 2 };
+__device__ inline int frows_class(const DevTables& T, int r0) {
+  const int eh0 = T.nvp + T.nu, hh0 = eh0 + T.nt1, lr0 = T.nvp + T.k, pad0 = lr0 + 2;
+  const int r1 = r0 + 32;
+  if (r0 < eh0 || (r0 < pad0 && r1 > lr0)) return FROWS_COMPLEX;
+  if (r0 < lr0 && r1 > hh0) return FROWS_REAL;
+  return FROWS_ZERO;
+}
+
 // Rows [32h, 32h + 32) of the regular tile (i, j) of step j, one wave:
-// X = A_ij - L_i,<j L_j,<j^H, then L_ij = X Linv_jj^H, computed transposed as
+// X = A_ij - L_i,<j L_j,<j^H, then L_ij = X Linv_jj^H (the sum over columns
+// from k0, the caller's bound below which the rows are zero), computed transposed as
 // L_ij^T = conj(Linv_jj) X^T with the lower-triangular Linv_jj (16x16 blocks
 // above its diagonal skipped).  Row halves are independent: row r of L_ij
 // needs row r of X only.
 template <int MODE>
 __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __restrict__ Z, int64_t cell, int i, int j,
-                          int h, unsigned char* slab) {
+                          int h, unsigned char* slab, int k0 = 0) {
   // ld and lane pass through empty asm so that, in a loop over tiles, the
   // compiler recomputes the lane addresses per tile instead of keeping them
   // all live across the loop (which spills)
@@ -1333,7 +1343,7 @@ __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __res
         q.im[u][v][t] = MODE == MM_RR ? 0.0 : a.y;
       }
   __builtin_amdgcn_sched_barrier(0);
-  wave_gemm_t<MODE>(Z + i * TB + 32 * h, Z + j * TB, ld, j * TB, q);
+  wave_gemm_t<MODE>(Z + (int64_t)k0 * ld + i * TB + 32 * h, Z + (int64_t)k0 * ld + j * TB, ld, j * TB - k0, q);
   __builtin_amdgcn_sched_barrier(0);
   const double2* tL = Z + (int64_t)(j * TB) * ld + j * TB;   // Linv_jj, lower
   const int nvb = T.nvp / TB;
@@ -1482,7 +1492,9 @@ __global__ __launch_bounds__(NT, 2) void k_chol_step(DevTables T, ChunkArgs C, i
     double2* Z = C.Z + cell * T.zstride;
     extern __shared__ double smem[];
     unsigned char* slab = reinterpret_cast<unsigned char*>(smem) + wave * WSP_BYTES;
-    wave_tile<MM_CC>(T, C, Z, cell, i, j, wave & 1, slab);
+    // rows that are zero in the F columns stay zero there (k_chol_fpanel leaves them), so their sum starts after
+    const int k0 = frows_class(T, i * TB + 32 * (wave & 1)) == FROWS_ZERO ? (T.Np / TB) * TB : 0;
+    wave_tile<MM_CC>(T, C, Z, cell, i, j, wave & 1, slab, k0);
     return;
   }
   // ---- lookahead workgroup: tile (i, j), i = j + 1, on waves 0 and 1 (one
@@ -1580,10 +1592,27 @@ __global__ __launch_bounds__(NT, 2) void k_chol_fpanel(DevTables T, ChunkArgs C,
     const int64_t cell = m * 8 + (w & 7);
     if (cell >= C.n) return;   // whole waves: no barrier on this path
     const int i = nF + 1 + t;
+    const int h = wave & 1;
     double2* Z = C.Z + cell * T.zstride;
     unsigned char* slab = reinterpret_cast<unsigned char*>(smem) + wave * WSP_BYTES;
+    const int cls = frows_class(T, i * TB + 32 * h);
+    if (cls == FROWS_ZERO) {
+      // L_i,F = 0 (A_i,F = 0, already so in the workspace); only the bf16
+      // planes of these W rows need their zeros for the F columns
+      if (C.split) {
+        const int nkc = T.nvp / 32;
+        uint16_t* wp = C.wsplit + cell * split_elems(T) + (int64_t)((i - T.nvp / TB) * TB + 32 * h) * nkc * 192;
+        const int per_row = 2 * nF * 192 / 8;   // 16-byte runs of the F columns in one row
+        for (int e = (int)(threadIdx.x & 63); e < 32 * per_row; e += 64) {
+          const int rr = e / per_row, o = e - rr * per_row;
+          *reinterpret_cast<uint4*>(wp + (int64_t)rr * nkc * 192 + 8 * o) = make_uint4(0u, 0u, 0u, 0u);
+        }
+      }
+      return;
+    }
     for (int j = 0; j < nF; ++j) {
-      wave_tile<MM_CR>(T, C, Z, cell, i, j, wave & 1, slab);
+      if (cls == FROWS_REAL) wave_tile<MM_RR>(T, C, Z, cell, i, j, h, slab);
+      else wave_tile<MM_CR>(T, C, Z, cell, i, j, h, slab);
       // L_ij (stored by all lanes) feeds the loads of step j + 1
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
       __builtin_amdgcn_wave_barrier();
