@@ -37,6 +37,7 @@ struct DegreeGroup {
   double* dscale = nullptr;
   double* met = nullptr;
   uint16_t* wsplit = nullptr;
+  double* fr = nullptr;               // real copy of each cell's factorised F block
   hipStream_t stream = nullptr;       // branch stream of the concurrent schedule
   hipEvent_t done = nullptr;
   dpg::DevTables ct{};                // condensation: factorisation tables of the K_e-based matrix
@@ -208,6 +209,7 @@ void free_plan(dpg_plan_s* p) {
     if (g.dscale) (void)hipFree(g.dscale);
     if (g.met) (void)hipFree(g.met);
     if (g.wsplit) (void)hipFree(g.wsplit);
+    if (g.fr) (void)hipFree(g.fr);
     if (g.stream) (void)hipStreamDestroy(g.stream);
     if (g.done) (void)hipEventDestroy(g.done);
   }
@@ -298,6 +300,7 @@ dpg_status enqueue_solve(dpg_plan P, const dpg::ProbArgs& pa, int64_t first, int
       ca.dscale = g.dscale;
       ca.met = g.met;
       ca.wsplit = g.wsplit;
+      ca.fr = g.fr;
       ca.split = precision == DPG_SPLIT_FP32 ? 1 : 0;
       ca.K_off = P->K_off_dev;
       ca.v_off = P->v_off_dev;
@@ -424,7 +427,8 @@ dpg_status dpg_plan_create(int32_t device, const int8_t* degree_host, int64_t n_
     const double budget = max_workspace_bytes > 0 ? (double)max_workspace_bytes : 0.4 * (double)free_b;
     for (auto& g : P->groups) {
       const int64_t mper = dpg::met_stride(g.dt);
-      g.per_cell = g.dt.zstride * 16 + (int64_t)g.d.nvp * 8 + mper * 8 + dpg::split_elems(g.dt) * 2;
+      g.per_cell = g.dt.zstride * 16 + (int64_t)g.d.nvp * 8 + mper * 8 + dpg::split_elems(g.dt) * 2 +
+                   dpg::fr_stride(g.dt) * 8;
     }
     // Each group first gets room for enough cells that one factorisation step
     // has about kFillTiles row tiles (a few waves of workgroups on every CU),
@@ -479,7 +483,8 @@ dpg_status dpg_plan_create(int32_t device, const int8_t* degree_host, int64_t n_
       if (hipMalloc(reinterpret_cast<void**>(&g.Z), (size_t)g.chunk * g.dt.zstride * 16) != hipSuccess ||
           hipMalloc(reinterpret_cast<void**>(&g.dscale), (size_t)g.chunk * g.d.nvp * 8) != hipSuccess ||
           hipMalloc(reinterpret_cast<void**>(&g.met), (size_t)g.chunk * mper * 8) != hipSuccess ||
-          hipMalloc(reinterpret_cast<void**>(&g.wsplit), (size_t)g.chunk * dpg::split_elems(g.dt) * 2) != hipSuccess) {
+          hipMalloc(reinterpret_cast<void**>(&g.wsplit), (size_t)g.chunk * dpg::split_elems(g.dt) * 2) != hipSuccess ||
+          hipMalloc(reinterpret_cast<void**>(&g.fr), (size_t)g.chunk * dpg::fr_stride(g.dt) * 8) != hipSuccess) {
         free_plan(P);
         return DPG_ERR_ALLOC;
       }

@@ -54,6 +54,7 @@ struct ChunkArgs {
   double* met;               // [n][met_stride] point metrics: volume Gc|Gm (6 nq each), Robin-face Q (36 nfq),
                              // volume w det J^{-T} (9 nq, [a][c] = w det (J^{-1})_{ac}) and w J (9 nq)
   uint16_t* wsplit;          // split path: [n][6][kp][nvp] bf16 planes of W^H (re0,re1,re2,im0,im1,im2)
+  double* fr;                // [n][fr_stride] real copy of the factorised F block (column-major, fr_ld), or null
   int split;                 // 1: K_aug from the bf16 split planes, eta by an FP64 reduction
   const int64_t* K_off;      // [n_cells+1] global output offsets (complex elements)
   const int64_t* v_off;
@@ -127,6 +128,10 @@ hipError_t launch_csr_matvec(int64_t n_rows, const int64_t* row_ptr, const int32
                              const double2* x, double2* y, hipStream_t st);
 // doubles of per-point metrics kept per cell (ChunkArgs::met)
 __host__ __device__ inline int64_t met_stride(const DevTables& t) { return 30 * (int64_t)t.nq + 36 * (int64_t)t.nfq; }
+// real copy of the factorised F block (the leading 64 floor(Np/64) rows and
+// columns): leading dimension (padded off a power of two) and doubles per cell
+__host__ __device__ inline int64_t fr_ld(const DevTables& t) { return (int64_t)(t.Np / 64) * 64 + 4; }
+__host__ __device__ inline int64_t fr_stride(const DevTables& t) { return fr_ld(t) * (t.Np / 64) * 64; }
 // bf16 planes per cell of the split path
 __host__ __device__ inline int64_t split_elems(const DevTables& t) { return 6 * (int64_t)t.kp * t.nvp; }
 // Raise the dynamic-LDS limit of the kernels that stage whole tiles (once per process).

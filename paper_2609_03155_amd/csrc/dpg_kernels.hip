@@ -1056,9 +1056,11 @@ __device__ __forceinline__ double pivot_rsqrt(double d) {
 // (16g > c); entries of A left of column c or above the diagonal take
 // meaningless updates but are never read again.  Cr/Ci are reused as the
 // broadcast slots.  REAL: the tile is real (Ci is not read), and the
-// imaginary parts are dropped from the arithmetic and the broadcasts.
+// imaginary parts are dropped from the arithmetic and the broadcasts; L^{-1}
+// also goes to the real column-major tile rout (leading dimension ldr) if given.
 template <bool REAL>
-__device__ __forceinline__ int chol_inv_tile(double* Cr, const double* Ci, double2* __restrict__ out, int64_t ld) {
+__device__ __forceinline__ int chol_inv_tile(double* Cr, const double* Ci, double2* __restrict__ out, int64_t ld,
+                                             double* __restrict__ rout = nullptr, int64_t ldr = 0) {
   int r = threadIdx.x & 63;
   __asm__ volatile("" : "+v"(r));   // not hoisted out of a caller's loop (as in wave_tile)
   const int g = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
@@ -1153,6 +1155,7 @@ __device__ __forceinline__ int chol_inv_tile(double* Cr, const double* Ci, doubl
   for (int u = 0; u < 16; ++u) {
     const int q = 16 * g + u;
     out[(int64_t)q * ld + r] = q <= r ? make_double2(xr[u], REAL ? 0.0 : xi[u]) : make_double2(0.0, 0.0);
+    if (REAL && rout) rout[(int64_t)q * ldr + r] = q <= r ? xr[u] : 0.0;
   }
   return fail;
 }
@@ -1218,20 +1221,25 @@ struct WPipe {
   static constexpr int KS = MODE == MM_CR ? 1 : 1;
 };
 
-template <int MODE>
-__device__ __forceinline__ void wave_load(const double2* __restrict__ Ai, const double2* __restrict__ Bj, int64_t ld,
-                                          int ks, WOps& o) {
+// Operands of one k-step: A from the complex panel Ai (leading dimension
+// lda), B from the complex panel Bj or, when FRB, from a real matrix (the
+// compact copy of the factorised F block, leading dimension ldb).
+template <int MODE, bool FRB>
+__device__ __forceinline__ void wave_load(const double2* __restrict__ Ai, int64_t lda, const void* __restrict__ Bj,
+                                          int64_t ldb, int ks, WOps& o) {
   const int lane = threadIdx.x & 63;
-  const int64_t off = (int64_t)(4 * ks + (lane >> 4)) * ld + (lane & 15);
+  const int64_t offa = (int64_t)(4 * ks + (lane >> 4)) * lda + (lane & 15);
 #pragma unroll
   for (int v = 0; v < 2; ++v) {
-    if (MODE == MM_RR) o.a[v].x = reinterpret_cast<const double*>(Ai + off + 16 * v)[0];
-    else o.a[v] = Ai[off + 16 * v];
+    if (MODE == MM_RR) o.a[v].x = reinterpret_cast<const double*>(Ai + offa + 16 * v)[0];
+    else o.a[v] = Ai[offa + 16 * v];
   }
+  const int64_t offb = (int64_t)(4 * ks + (lane >> 4)) * ldb + (lane & 15);
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    if (MODE == MM_CC) o.b[u] = Bj[off + 16 * u];
-    else o.b[u].x = reinterpret_cast<const double*>(Bj + off + 16 * u)[0];
+    if (FRB) o.b[u].x = reinterpret_cast<const double*>(Bj)[offb + 16 * u];
+    else if (MODE == MM_CC) o.b[u] = reinterpret_cast<const double2*>(Bj)[offb + 16 * u];
+    else o.b[u].x = reinterpret_cast<const double*>(reinterpret_cast<const double2*>(Bj) + offb + 16 * u)[0];
   }
 }
 
@@ -1267,9 +1275,9 @@ __device__ __forceinline__ void wave_step(const WOps& o, WAcc& q) {
 // end re-read the last k-step), so the wait before each k-step leaves the
 // younger prefetches in flight; the last nks % NB k-steps, already loaded,
 // follow the loop.
-template <int MODE>
-__device__ __forceinline__ void wave_gemm_t(const double2* __restrict__ Ai, const double2* __restrict__ Bj, int64_t ld,
-                                            int K, WAcc& q) {
+template <int MODE, bool FRB = false>
+__device__ __forceinline__ void wave_gemm_t(const double2* __restrict__ Ai, int64_t lda, const void* __restrict__ Bj,
+                                            int64_t ldb, int K, WAcc& q) {
   constexpr int NB = WPipe<MODE>::NB, KS = WPipe<MODE>::KS;
   const int nks = K / (4 * KS);   // buffers' worth of k-steps (K is a multiple of 64)
   if (nks <= 0) return;
@@ -1278,13 +1286,13 @@ __device__ __forceinline__ void wave_gemm_t(const double2* __restrict__ Ai, cons
 #pragma unroll
   for (int s = 0; s < NB - 1; ++s)
 #pragma unroll
-    for (int u = 0; u < KS; ++u) wave_load<MODE>(Ai, Bj, ld, min(s, nks - 1) * KS + u, o[s][u]);
+    for (int u = 0; u < KS; ++u) wave_load<MODE, FRB>(Ai, lda, Bj, ldb, min(s, nks - 1) * KS + u, o[s][u]);
   for (int k0 = 0; k0 < nfull; k0 += NB) {
 #pragma unroll
     for (int s = 0; s < NB; ++s) {
 #pragma unroll
       for (int u = 0; u < KS; ++u)
-        wave_load<MODE>(Ai, Bj, ld, min(k0 + s + NB - 1, nks - 1) * KS + u, o[(s + NB - 1) % NB][u]);
+        wave_load<MODE, FRB>(Ai, lda, Bj, ldb, min(k0 + s + NB - 1, nks - 1) * KS + u, o[(s + NB - 1) % NB][u]);
       __builtin_amdgcn_sched_barrier(0);   // keep each prefetch in its slot (bounded live ranges)
 #pragma unroll
       for (int u = 0; u < KS; ++u) wave_step<MODE>(o[s][u], q);
@@ -1318,7 +1326,11 @@ __device__ inline int frows_class(const DevTables& T, int r0) {
 // L_ij^T = conj(Linv_jj) X^T with the lower-triangular Linv_jj (16x16 blocks
 // above its diagonal skipped).  Row halves are independent: row r of L_ij
 // needs row r of X only.
-template <int MODE>
+// Use of the compact real copy of the F block by a tile: none, its operands
+// (panel j and Linv_jj) from it, or the tile's real output written to it too.
+enum { FR_NONE = 0, FR_READ = 1, FR_WRITE = 2 };
+
+template <int MODE, int FR = FR_NONE>
 __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __restrict__ Z, int64_t cell, int i, int j,
                           int h, unsigned char* slab, int k0 = 0) {
   // ld and lane pass through empty asm so that, in a loop over tiles, the
@@ -1343,9 +1355,18 @@ __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __res
         q.im[u][v][t] = MODE == MM_RR ? 0.0 : a.y;
       }
   __builtin_amdgcn_sched_barrier(0);
-  wave_gemm_t<MODE>(Z + (int64_t)k0 * ld + i * TB + 32 * h, Z + (int64_t)k0 * ld + j * TB, ld, j * TB - k0, q);
+  // panel j and Linv_jj: from Z, or from the real copy of the F block
+  constexpr bool FRB = FR == FR_READ;
+  const int64_t ldf = fr_ld(T);
+  double* Fr = FR != FR_NONE ? C.fr + cell * fr_stride(T) : nullptr;
+  if (FRB)
+    wave_gemm_t<MODE, true>(Z + (int64_t)k0 * ld + i * TB + 32 * h, ld, Fr + (int64_t)k0 * ldf + j * TB, ldf,
+                            j * TB - k0, q);
+  else
+    wave_gemm_t<MODE>(Z + (int64_t)k0 * ld + i * TB + 32 * h, ld, Z + (int64_t)k0 * ld + j * TB, ld, j * TB - k0, q);
   __builtin_amdgcn_sched_barrier(0);
   const double2* tL = Z + (int64_t)(j * TB) * ld + j * TB;   // Linv_jj, lower
+  const double* tLr = FRB ? Fr + (int64_t)(j * TB) * ldf + j * TB : nullptr;
   const int nvb = T.nvp / TB;
   const bool wsplit = C.split && i >= nvb;
   uint16_t* wp = wsplit ? C.wsplit + cell * split_elems(T) : nullptr;
@@ -1363,7 +1384,9 @@ __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __res
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         // A operand conj(Linv)[16 mb + (l & 15)][16 kb + 4 t + (l >> 4)]
-        const double2 L = tL[(int64_t)(16 * kb + 4 * t + (lane >> 4)) * ld + 16 * mb + (lane & 15)];
+        double2 L;
+        if (FRB) L = make_double2(tLr[(int64_t)(16 * kb + 4 * t + (lane >> 4)) * ldf + 16 * mb + (lane & 15)], 0.0);
+        else L = tL[(int64_t)(16 * kb + 4 * t + (lane >> 4)) * ld + 16 * mb + (lane & 15)];
 #pragma unroll
         for (int nb = 0; nb < 2; ++nb) {
           yr[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(L.x, q.re[kb][nb][t], yr[nb], 0, 0, 0);
@@ -1382,6 +1405,7 @@ __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __res
         const int r = 16 * nb + (lane & 15), c = 16 * mb + 4 * t + (lane >> 4);
         const double vr = yr[nb][t], vi = MODE == MM_RR ? 0.0 : yi[nb][t];
         tile[(int64_t)c * ld + r] = make_double2(vr, vi);
+        if (FR == FR_WRITE) Fr[(int64_t)(j * TB + c) * ldf + i * TB + 32 * h + r] = vr;
         if (wsplit) {
           // three-term bf16 splits of re and im into the wave's LDS slab
           // [32 rows][6 planes][16 columns] (row pitch WSP_PITCH bytes)
@@ -1448,7 +1472,7 @@ __device__ __forceinline__ void diag_update(const double2* __restrict__ S0g, con
           q.im[u][v][t] = MODE == MM_RR ? 0.0 : Si[r * 65 + c];
         }
       }
-  wave_gemm_t<MODE>(P + 32 * h, P, ld, K, q);
+  wave_gemm_t<MODE>(P + 32 * h, ld, P, ld, K, q);
   // item t of block (u, v): S[row 32h + 16v + (l & 15)][column 16u + 4t + (l >> 4)]
 #pragma unroll
   for (int u = 0; u < 4; ++u)
@@ -1543,6 +1567,10 @@ __global__ __launch_bounds__(NT, 2) void k_chol_fblock(DevTables T, ChunkArgs C,
   extern __shared__ double smem[];
   double* Cr = smem;
   double* Ci = Cr + 64 * 65;
+  // the factorised block is also kept as a compact real copy (L_ij below the
+  // diagonal, Linv_jj on it), the real operands of the F-column launch
+  double* fr = C.fr + cell * fr_stride(T);
+  const int64_t ldf = fr_ld(T);
   int fail = 0;
   for (int j = 0;; ++j) {
     // diagonal block j, updated by the columns before it, into LDS
@@ -1556,13 +1584,15 @@ __global__ __launch_bounds__(NT, 2) void k_chol_fblock(DevTables T, ChunkArgs C,
       diag_update<MM_RR, true>(tileD, Z + j * TB, ld, j * TB, wave, Cr, Ci);
     }
     __syncthreads();
-    const int f = chol_inv_tile<true>(Cr, Ci, tileD, ld);
+    const int f = chol_inv_tile<true>(Cr, Ci, tileD, ld, fr + (int64_t)(j * TB) * ldf + j * TB, ldf);
     if (f && !fail) fail = j * TB + f;
     if (j + 1 == nF) break;
     __syncthreads();   // Linv_jj stored (workgroup scope); LDS free
-    for (int i = j + 1 + (wave >> 1); i < nF; i += 2) wave_tile<MM_RR>(T, C, Z, cell, i, j, wave & 1, nullptr);
+    for (int i = j + 1 + (wave >> 1); i < nF; i += 2)
+      wave_tile<MM_RR, FR_WRITE>(T, C, Z, cell, i, j, wave & 1, nullptr);
     __syncthreads();   // column block j stored
   }
+
   if (threadIdx.x == 0 && fail && C.info[gc - C.cell_base] == 0) C.info[gc - C.cell_base] = fail;
 }
 
@@ -1611,8 +1641,8 @@ __global__ __launch_bounds__(NT, 2) void k_chol_fpanel(DevTables T, ChunkArgs C,
       return;
     }
     for (int j = 0; j < nF; ++j) {
-      if (cls == FROWS_REAL) wave_tile<MM_RR>(T, C, Z, cell, i, j, h, slab);
-      else wave_tile<MM_CR>(T, C, Z, cell, i, j, h, slab);
+      if (cls == FROWS_REAL) wave_tile<MM_RR, FR_READ>(T, C, Z, cell, i, j, h, slab);
+      else wave_tile<MM_CR, FR_READ>(T, C, Z, cell, i, j, h, slab);
       // L_ij (stored by all lanes) feeds the loads of step j + 1
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
       __builtin_amdgcn_wave_barrier();
@@ -1630,7 +1660,7 @@ __global__ __launch_bounds__(NT, 2) void k_chol_fpanel(DevTables T, ChunkArgs C,
   double2* tileD = Z + (int64_t)(i * TB) * ld + i * TB;
   if (wave >= 2) diag_update<MM_CC, true>(tileD, Z + i * TB, ld, 0, wave - 2, Cr, Ci);   // A_ii into LDS
   for (int j = 0; j < nF; ++j) {
-    if (wave < 2) wave_tile<MM_CR>(T, C, Z, cell, i, j, wave, nullptr);
+    if (wave < 2) wave_tile<MM_CR, FR_READ>(T, C, Z, cell, i, j, wave, nullptr);
     __syncthreads();   // L_ij stored (workgroup scope)
     if (wave >= 2) diag_update<MM_CC, false>(nullptr, Z + (int64_t)(j * TB) * ld + i * TB, ld, TB, wave - 2, Cr, Ci);
   }
