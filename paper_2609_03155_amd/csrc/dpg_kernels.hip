@@ -1195,9 +1195,11 @@ __global__ __launch_bounds__(NT) void k_chol_diag0(DevTables T, ChunkArgs C) {
 // following product  M Q, which is how the triangular epilogue consumes it
 // without a transpose.  Two waves per SIMD (256 registers each) hide each
 // other's load latency.
-struct WAcc {
-  d4 re[4][2], im[4][2];
+template <int NV = 2>
+struct WAccT {
+  d4 re[4][NV], im[4][NV];
 };
+using WAcc = WAccT<2>;
 
 // Per-wave LDS slab that regroups the bf16 split planes of a 32 x 16 block of
 // W^H into 16-byte column runs: [32 rows][6 planes][16 columns], row pitch
@@ -1206,16 +1208,18 @@ constexpr int WSP_PITCH = 208;
 constexpr int WSP_BYTES = 32 * WSP_PITCH;
 static_assert(4 * WSP_BYTES <= kFactorSmem, "four wave slabs fit the step kernel's LDS");
 
-struct WOps {
-  double2 a[2], b[4];
+template <int NV = 2>
+struct WOpsT {
+  double2 a[NV], b[4];
 };
 
 // Register buffers of the k-step pipeline (prefetch distance NB - 1): the
 // fewer MFMAs a k-step has, the deeper the prefetch; sized to what the
 // register file holds next to the accumulators without spilling.
-template <int MODE>
+template <int MODE, int NV = 2>
 struct WPipe {
-  static constexpr int NB = MODE == MM_RR ? 6 : (MODE == MM_CR ? 2 : 2);
+  // a wave of 16 rows (NV = 1) has half the accumulators, so room for twice the buffers
+  static constexpr int NB = NV == 2 ? (MODE == MM_RR ? 6 : 2) : (MODE == MM_RR ? 8 : 4);
   // k-steps per buffer: a complex x real k-step has half the MFMAs of a
   // complex one, so its buffers take two, to keep as much work in flight
   static constexpr int KS = MODE == MM_CR ? 1 : 1;
@@ -1224,13 +1228,13 @@ struct WPipe {
 // Operands of one k-step: A from the complex panel Ai (leading dimension
 // lda), B from the complex panel Bj or, when FRB, from a real matrix (the
 // compact copy of the factorised F block, leading dimension ldb).
-template <int MODE, bool FRB>
+template <int MODE, bool FRB, int NV>
 __device__ __forceinline__ void wave_load(const double2* __restrict__ Ai, int64_t lda, const void* __restrict__ Bj,
-                                          int64_t ldb, int ks, WOps& o) {
+                                          int64_t ldb, int ks, WOpsT<NV>& o) {
   const int lane = threadIdx.x & 63;
   const int64_t offa = (int64_t)(4 * ks + (lane >> 4)) * lda + (lane & 15);
 #pragma unroll
-  for (int v = 0; v < 2; ++v) {
+  for (int v = 0; v < NV; ++v) {
     if (MODE == MM_RR) o.a[v].x = reinterpret_cast<const double*>(Ai + offa + 16 * v)[0];
     else o.a[v] = Ai[offa + 16 * v];
   }
@@ -1244,58 +1248,58 @@ __device__ __forceinline__ void wave_load(const double2* __restrict__ Ai, int64_
 }
 
 // re -= br ar + bi ai,  im -= br ai - bi ar   (Q -= conj(b) a)
-template <int MODE>
-__device__ __forceinline__ void wave_step(const WOps& o, WAcc& q) {
+template <int MODE, int NV>
+__device__ __forceinline__ void wave_step(const WOpsT<NV>& o, WAccT<NV>& q) {
   double nbr[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) nbr[u] = -o.b[u].x;
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int v = 0; v < 2; ++v) q.re[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(nbr[u], o.a[v].x, q.re[u][v], 0, 0, 0);
+    for (int v = 0; v < NV; ++v) q.re[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(nbr[u], o.a[v].x, q.re[u][v], 0, 0, 0);
   if (MODE == MM_RR) return;
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int v = 0; v < 2; ++v) q.im[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(nbr[u], o.a[v].y, q.im[u][v], 0, 0, 0);
+    for (int v = 0; v < NV; ++v) q.im[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(nbr[u], o.a[v].y, q.im[u][v], 0, 0, 0);
   if (MODE == MM_CR) return;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const double nbi = -o.b[u].y;
 #pragma unroll
-    for (int v = 0; v < 2; ++v) q.re[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(nbi, o.a[v].y, q.re[u][v], 0, 0, 0);
+    for (int v = 0; v < NV; ++v) q.re[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(nbi, o.a[v].y, q.re[u][v], 0, 0, 0);
   }
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int v = 0; v < 2; ++v) q.im[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(o.b[u].y, o.a[v].x, q.im[u][v], 0, 0, 0);
+    for (int v = 0; v < NV; ++v) q.im[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(o.b[u].y, o.a[v].x, q.im[u][v], 0, 0, 0);
 }
 
 // The steady-state loop has no branch in its unrolled body (loads past the
 // end re-read the last k-step), so the wait before each k-step leaves the
 // younger prefetches in flight; the last nks % NB k-steps, already loaded,
 // follow the loop.
-template <int MODE, bool FRB = false>
+template <int MODE, bool FRB = false, int NV = 2>
 __device__ __forceinline__ void wave_gemm_t(const double2* __restrict__ Ai, int64_t lda, const void* __restrict__ Bj,
-                                            int64_t ldb, int K, WAcc& q) {
-  constexpr int NB = WPipe<MODE>::NB, KS = WPipe<MODE>::KS;
+                                            int64_t ldb, int K, WAccT<NV>& q) {
+  constexpr int NB = WPipe<MODE, NV>::NB, KS = WPipe<MODE, NV>::KS;
   const int nks = K / (4 * KS);   // buffers' worth of k-steps (K is a multiple of 64)
   if (nks <= 0) return;
   const int nfull = nks - nks % NB;
-  WOps o[NB][KS];
+  WOpsT<NV> o[NB][KS];
 #pragma unroll
   for (int s = 0; s < NB - 1; ++s)
 #pragma unroll
-    for (int u = 0; u < KS; ++u) wave_load<MODE, FRB>(Ai, lda, Bj, ldb, min(s, nks - 1) * KS + u, o[s][u]);
+    for (int u = 0; u < KS; ++u) wave_load<MODE, FRB, NV>(Ai, lda, Bj, ldb, min(s, nks - 1) * KS + u, o[s][u]);
   for (int k0 = 0; k0 < nfull; k0 += NB) {
 #pragma unroll
     for (int s = 0; s < NB; ++s) {
 #pragma unroll
       for (int u = 0; u < KS; ++u)
-        wave_load<MODE, FRB>(Ai, lda, Bj, ldb, min(k0 + s + NB - 1, nks - 1) * KS + u, o[(s + NB - 1) % NB][u]);
+        wave_load<MODE, FRB, NV>(Ai, lda, Bj, ldb, min(k0 + s + NB - 1, nks - 1) * KS + u, o[(s + NB - 1) % NB][u]);
       __builtin_amdgcn_sched_barrier(0);   // keep each prefetch in its slot (bounded live ranges)
 #pragma unroll
-      for (int u = 0; u < KS; ++u) wave_step<MODE>(o[s][u], q);
+      for (int u = 0; u < KS; ++u) wave_step<MODE, NV>(o[s][u], q);
       __builtin_amdgcn_sched_barrier(0);
     }
   }
@@ -1303,21 +1307,31 @@ __device__ __forceinline__ void wave_gemm_t(const double2* __restrict__ Ai, int6
   for (int s = 0; s < NB - 1; ++s)
     if (s < nks - nfull) {
 #pragma unroll
-      for (int u = 0; u < KS; ++u) wave_step<MODE>(o[s][u], q);
+      for (int u = 0; u < KS; ++u) wave_step<MODE, NV>(o[s][u], q);
     }
 }
 
-// Structure of the 32 augmented rows [r0, r0 + 32) in the F columns: the
+// Structure of the augmented rows [r0, r0 + nr) in the F columns: the
 // rows of the E-hat trace unknowns pair with no F test function (zero there,
 // so are the padding rows), those of H-hat only through the real trace table
 // (real); the interior, load and residual rows and the I test rows are complex.
 enum { FROWS_COMPLEX = 0, FROWS_REAL = 1, FROWS_ZERO = 2 };
-__device__ inline int frows_class(const DevTables& T, int r0) {
+__device__ inline int frows_class(const DevTables& T, int r0, int nr = 32) {
   const int eh0 = T.nvp + T.nu, hh0 = eh0 + T.nt1, lr0 = T.nvp + T.k, pad0 = lr0 + 2;
-  const int r1 = r0 + 32;
+  const int r1 = r0 + nr;
   if (r0 < eh0 || (r0 < pad0 && r1 > lr0)) return FROWS_COMPLEX;
   if (r0 < lr0 && r1 > hh0) return FROWS_REAL;
   return FROWS_ZERO;
+}
+
+// First column of the sum W_a^H W_b over the test columns: the F columns
+// contribute nothing when either 64-row block of W^H is zero there.
+__device__ inline int herk_k0(const DevTables& T, int a, int b) {
+  auto zero_f = [&](int blk) {
+    const int r0 = T.nvp + blk * TB;
+    return frows_class(T, r0) == FROWS_ZERO && frows_class(T, r0 + 32) == FROWS_ZERO;
+  };
+  return zero_f(a) || zero_f(b) ? (T.Np / TB) * TB : 0;
 }
 
 // Rows [32h, 32h + 32) of the regular tile (i, j) of step j, one wave:
@@ -1326,13 +1340,23 @@ __device__ inline int frows_class(const DevTables& T, int r0) {
 // L_ij^T = conj(Linv_jj) X^T with the lower-triangular Linv_jj (16x16 blocks
 // above its diagonal skipped).  Row halves are independent: row r of L_ij
 // needs row r of X only.
+// Regular tiles of the sweep run on waves of 16 RNV rows, 64 / (16 RNV) waves
+// per tile and 4 / that tiles per workgroup.  Waves of 16 rows (one tile per
+// workgroup, a deeper prefetch in the registers the smaller accumulators
+// free) were measured on the WR340 workload: no faster than 32-row waves.
+constexpr int RNV = 2;                    // 16-row blocks per wave of a regular tile
+constexpr int RWPT = TB / (16 * RNV);   // waves per regular tile
+static_assert(RWPT * 16 * RNV == TB, "the waves of a regular tile cover its rows");
+constexpr int RTPW = 4 / RWPT;            // regular tiles per workgroup
+
 // Use of the compact real copy of the F block by a tile: none, its operands
 // (panel j and Linv_jj) from it, or the tile's real output written to it too.
 enum { FR_NONE = 0, FR_READ = 1, FR_WRITE = 2 };
 
-template <int MODE, int FR = FR_NONE>
+template <int MODE, int FR = FR_NONE, int NV = 2>
 __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __restrict__ Z, int64_t cell, int i, int j,
                           int h, unsigned char* slab, int k0 = 0) {
+  constexpr int RW = 16 * NV;   // rows of the wave: [RW h, RW h + RW) of the tile
   // ld and lane pass through empty asm so that, in a loop over tiles, the
   // compiler recomputes the lane addresses per tile instead of keeping them
   // all live across the loop (which spills)
@@ -1340,13 +1364,13 @@ __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __res
   __asm__ volatile("" : "+s"(ld));
   int lane = threadIdx.x & 63;
   __asm__ volatile("" : "+v"(lane));
-  double2* tile = Z + (int64_t)(j * TB) * ld + i * TB + 32 * h;   // rows of A_ij in, of L_ij out
+  double2* tile = Z + (int64_t)(j * TB) * ld + i * TB + RW * h;   // rows of A_ij in, of L_ij out
   // the accumulators start as A_ij^T, so that they end as X^T
-  WAcc q;
+  WAccT<NV> q;
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int v = 0; v < 2; ++v)
+    for (int v = 0; v < NV; ++v)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int r = 16 * v + (lane & 15), c = 16 * u + 4 * t + (lane >> 4);
@@ -1360,10 +1384,11 @@ __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __res
   const int64_t ldf = fr_ld(T);
   double* Fr = FR != FR_NONE ? C.fr + cell * fr_stride(T) : nullptr;
   if (FRB)
-    wave_gemm_t<MODE, true>(Z + (int64_t)k0 * ld + i * TB + 32 * h, ld, Fr + (int64_t)k0 * ldf + j * TB, ldf,
+    wave_gemm_t<MODE, true, NV>(Z + (int64_t)k0 * ld + i * TB + RW * h, ld, Fr + (int64_t)k0 * ldf + j * TB, ldf,
                             j * TB - k0, q);
   else
-    wave_gemm_t<MODE>(Z + (int64_t)k0 * ld + i * TB + 32 * h, ld, Z + (int64_t)k0 * ld + j * TB, ld, j * TB - k0, q);
+    wave_gemm_t<MODE, false, NV>(Z + (int64_t)k0 * ld + i * TB + RW * h, ld, Z + (int64_t)k0 * ld + j * TB, ld,
+                              j * TB - k0, q);
   __builtin_amdgcn_sched_barrier(0);
   const double2* tL = Z + (int64_t)(j * TB) * ld + j * TB;   // Linv_jj, lower
   const double* tLr = FRB ? Fr + (int64_t)(j * TB) * ldf + j * TB : nullptr;
@@ -1373,9 +1398,9 @@ __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __res
   const int nkc = T.nvp / 32;
 #pragma unroll
   for (int mb = 3; mb >= 0; --mb) {
-    d4 yr[2], yi[2];
+    d4 yr[NV], yi[NV];
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb) {
+    for (int nb = 0; nb < NV; ++nb) {
       yr[nb] = d4{0, 0, 0, 0};
       yi[nb] = d4{0, 0, 0, 0};
     }
@@ -1388,7 +1413,7 @@ __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __res
         if (FRB) L = make_double2(tLr[(int64_t)(16 * kb + 4 * t + (lane >> 4)) * ldf + 16 * mb + (lane & 15)], 0.0);
         else L = tL[(int64_t)(16 * kb + 4 * t + (lane >> 4)) * ld + 16 * mb + (lane & 15)];
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb) {
+        for (int nb = 0; nb < NV; ++nb) {
           yr[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(L.x, q.re[kb][nb][t], yr[nb], 0, 0, 0);
           if (MODE != MM_RR) yi[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(L.x, q.im[kb][nb][t], yi[nb], 0, 0, 0);
           if (MODE == MM_CC) {
@@ -1397,18 +1422,18 @@ __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __res
           }
         }
       }
-    // item t of block (mb, nb): L_ij[row 32h + 16 nb + (l & 15)][column 16 mb + 4 t + (l >> 4)]
+    // item t of block (mb, nb): L_ij[row RW h + 16 nb + (l & 15)][column 16 mb + 4 t + (l >> 4)]
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb)
+    for (int nb = 0; nb < NV; ++nb)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int r = 16 * nb + (lane & 15), c = 16 * mb + 4 * t + (lane >> 4);
         const double vr = yr[nb][t], vi = MODE == MM_RR ? 0.0 : yi[nb][t];
         tile[(int64_t)c * ld + r] = make_double2(vr, vi);
-        if (FR == FR_WRITE) Fr[(int64_t)(j * TB + c) * ldf + i * TB + 32 * h + r] = vr;
+        if (FR == FR_WRITE) Fr[(int64_t)(j * TB + c) * ldf + i * TB + RW * h + r] = vr;
         if (wsplit) {
           // three-term bf16 splits of re and im into the wave's LDS slab
-          // [32 rows][6 planes][16 columns] (row pitch WSP_PITCH bytes)
+          // [RW rows][6 planes][16 columns] (row pitch WSP_PITCH bytes)
           uint16_t* sl = reinterpret_cast<uint16_t*>(slab + r * WSP_PITCH) + 4 * t + (lane >> 4);
           uint16_t hb[3];
           split3_bf16(vr, hb);
@@ -1429,12 +1454,12 @@ __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __res
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-      for (int e = 0; e < 6; ++e) {
-        const int id = e * 64 + lane;            // (row, plane, half) of 32 x 6 x 2
+      for (int e = 0; e < 3 * NV; ++e) {
+        const int id = e * 64 + lane;            // (row, plane, half) of RW x 6 x 2
         const int r = id / 12, pl = (id % 12) >> 1, hf = id & 1;
         const uint4 v = *reinterpret_cast<const uint4*>(slab + r * WSP_PITCH + pl * 32 + hf * 16);
         const int kk = j * TB + 16 * mb + 8 * hf;
-        const int64_t o = ((int64_t)((i - nvb) * TB + 32 * h + r) * nkc + kk / 32) * 192 + pl * 32 + (kk % 32);
+        const int64_t o = ((int64_t)((i - nvb) * TB + RW * h + r) * nkc + kk / 32) * 192 + pl * 32 + (kk % 32);
         *reinterpret_cast<uint4*>(wp + o) = v;
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1499,15 +1524,15 @@ __global__ __launch_bounds__(NT, 2) void k_chol_step(DevTables T, ChunkArgs C, i
   const bool la = j + 1 < nvb;
   const int nreg = nrb - j - 1 - (la ? 1 : 0);   // tiles done by wave pairs
   // Workgroup ids [0, n8) carry the lookahead tile of every cell and are
-  // dispatched first, spread over all CUs (cell c on XCD c % 8).  The wave
+  // dispatched first, spread over all CUs (cell c on XCD c % 8).  The regular
   // tiles follow: per XCD x the (cell, tile) pairs of its cells c = 8 m + x
-  // form one list in (m, tile) order, two per workgroup, so that no
-  // workgroup is left partly empty at the end of a cell.
+  // form one list in (m, tile) order, RTPW per workgroup.
   const int64_t n8 = la ? (C.n + 7) / 8 * 8 : 0;
   if ((int64_t)blockIdx.x >= n8) {
     const int64_t w = (int64_t)blockIdx.x - n8;
     const int wave = (int)(threadIdx.x >> 6);
-    const int64_t item = (w >> 3) * 2 + (wave >> 1);
+    const int64_t item = (w >> 3) * RTPW + wave / RWPT;
+    const int h = wave % RWPT;
     const int64_t m = item / nreg;
     const int t = (int)(item - m * nreg);
     const int64_t cell = m * 8 + (w & 7);
@@ -1517,8 +1542,9 @@ __global__ __launch_bounds__(NT, 2) void k_chol_step(DevTables T, ChunkArgs C, i
     extern __shared__ double smem[];
     unsigned char* slab = reinterpret_cast<unsigned char*>(smem) + wave * WSP_BYTES;
     // rows that are zero in the F columns stay zero there (k_chol_fpanel leaves them), so their sum starts after
-    const int k0 = frows_class(T, i * TB + 32 * (wave & 1)) == FROWS_ZERO ? (T.Np / TB) * TB : 0;
-    wave_tile<MM_CC>(T, C, Z, cell, i, j, wave & 1, slab, k0);
+    const int r0 = i * TB + 16 * RNV * h;
+    const int k0 = frows_class(T, r0, 16 * RNV) == FROWS_ZERO ? (T.Np / TB) * TB : 0;
+    wave_tile<MM_CC, FR_NONE, RNV>(T, C, Z, cell, i, j, h, slab, k0);
     return;
   }
   // ---- lookahead workgroup: tile (i, j), i = j + 1, on waves 0 and 1 (one
@@ -1609,31 +1635,32 @@ __global__ __launch_bounds__(NT, 2) void k_chol_fblock(DevTables T, ChunkArgs C,
 // factorise the result, storing Linv_{nF,nF} for the step nF.
 __global__ __launch_bounds__(NT, 2) void k_chol_fpanel(DevTables T, ChunkArgs C, int nF) {
   const int nrb = T.nrows / TB;
-  const int nreg = nrb - nF - 1;   // row tiles after nF, two per workgroup
+  const int nreg = nrb - nF - 1;   // row tiles after nF, RTPW per workgroup
   const int64_t n8 = (C.n + 7) / 8 * 8;
   const int wave = (int)(threadIdx.x >> 6);
   extern __shared__ double smem[];
   if ((int64_t)blockIdx.x >= n8) {
-    // per XCD x the (cell, tile) pairs of its cells c = 8 m + x in (m, tile) order, two per workgroup
+    // per XCD x the (cell, tile) pairs of its cells c = 8 m + x in (m, tile) order, RTPW per workgroup
     const int64_t w = (int64_t)blockIdx.x - n8;
-    const int64_t item = (w >> 3) * 2 + (wave >> 1);
+    const int64_t item = (w >> 3) * RTPW + wave / RWPT;
+    const int h = wave % RWPT;
     const int64_t m = item / nreg;
     const int t = (int)(item - m * nreg);
     const int64_t cell = m * 8 + (w & 7);
     if (cell >= C.n) return;   // whole waves: no barrier on this path
     const int i = nF + 1 + t;
-    const int h = wave & 1;
+    constexpr int RW = 16 * RNV;
     double2* Z = C.Z + cell * T.zstride;
     unsigned char* slab = reinterpret_cast<unsigned char*>(smem) + wave * WSP_BYTES;
-    const int cls = frows_class(T, i * TB + 32 * h);
+    const int cls = frows_class(T, i * TB + RW * h, RW);
     if (cls == FROWS_ZERO) {
       // L_i,F = 0 (A_i,F = 0, already so in the workspace); only the bf16
       // planes of these W rows need their zeros for the F columns
       if (C.split) {
         const int nkc = T.nvp / 32;
-        uint16_t* wp = C.wsplit + cell * split_elems(T) + (int64_t)((i - T.nvp / TB) * TB + 32 * h) * nkc * 192;
+        uint16_t* wp = C.wsplit + cell * split_elems(T) + (int64_t)((i - T.nvp / TB) * TB + RW * h) * nkc * 192;
         const int per_row = 2 * nF * 192 / 8;   // 16-byte runs of the F columns in one row
-        for (int e = (int)(threadIdx.x & 63); e < 32 * per_row; e += 64) {
+        for (int e = (int)(threadIdx.x & 63); e < RW * per_row; e += 64) {
           const int rr = e / per_row, o = e - rr * per_row;
           *reinterpret_cast<uint4*>(wp + (int64_t)rr * nkc * 192 + 8 * o) = make_uint4(0u, 0u, 0u, 0u);
         }
@@ -1641,8 +1668,8 @@ __global__ __launch_bounds__(NT, 2) void k_chol_fpanel(DevTables T, ChunkArgs C,
       return;
     }
     for (int j = 0; j < nF; ++j) {
-      if (cls == FROWS_REAL) wave_tile<MM_RR, FR_READ>(T, C, Z, cell, i, j, h, slab);
-      else wave_tile<MM_CR, FR_READ>(T, C, Z, cell, i, j, h, slab);
+      if (cls == FROWS_REAL) wave_tile<MM_RR, FR_READ, RNV>(T, C, Z, cell, i, j, h, slab);
+      else wave_tile<MM_CR, FR_READ, RNV>(T, C, Z, cell, i, j, h, slab);
       // L_ij (stored by all lanes) feeds the loads of step j + 1
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
       __builtin_amdgcn_wave_barrier();
@@ -1688,7 +1715,8 @@ __global__ __launch_bounds__(NT, 2) void k_herk(DevTables T, ChunkArgs C) {
   const double2* Z = C.Z + cell * T.zstride;
   Acc acc;
   acc_zero(acc);
-  gemm_abh(Z + T.nvp + a * TB, Z + T.nvp + b * TB, ld, T.nvp, st, acc);
+  const int k0 = herk_k0(T, a, b);
+  gemm_abh(Z + (int64_t)k0 * ld + T.nvp + a * TB, Z + (int64_t)k0 * ld + T.nvp + b * TB, ld, T.nvp - k0, st, acc);
   const int k = T.k;
   double2* K = C.K + (C.K_off[gc] - C.K_base);
   double2* L = C.l + (C.v_off[gc] - C.v_base);
@@ -1802,8 +1830,9 @@ __global__ __launch_bounds__(NT, 2) void k_herk_split(DevTables T, ChunkArgs C) 
       for (int e = 0; e < 4; ++e) dr[u][v][e] = di[u][v][e] = 0.0;
     }
   const int nst = T.nvp / SKC;
-  DPG_SPLIT_GLOAD(0);
-  for (int sidx = 0; sidx < nst; ++sidx) {
+  const int s0 = herk_k0(T, a, b) / SKC;   // stages of the F columns skipped where they contribute nothing
+  DPG_SPLIT_GLOAD(s0 * SKC);
+  for (int sidx = s0; sidx < nst; ++sidx) {
     __syncthreads();
     DPG_SPLIT_LSTORE();
     __syncthreads();
@@ -2006,7 +2035,9 @@ hipError_t launch_factor(const DevTables& t, const ChunkArgs& ca, hipStream_t st
   const int nvb = t.nvp / TB, nrb = t.nrows / TB;
   const int64_t n8 = (ca.n + 7) / 8 * 8;
   // lookahead workgroups (one per cell) + two wave-pair tiles per workgroup
-  auto grid_of = [&](bool la, int nreg) { return (unsigned)((la ? n8 : 0) + 8 * ((n8 / 8 * nreg + 1) / 2)); };
+  auto grid_of = [&](bool la, int nreg) {
+    return (unsigned)((la ? n8 : 0) + 8 * ((n8 / 8 * nreg + RTPW - 1) / RTPW));
+  };
   int j0 = 0;
   const int nF = t.Np / TB;   // leading column tiles that are real
   if (nF >= 1) {
