@@ -1743,16 +1743,20 @@ __global__ __launch_bounds__(NT, 2) void k_herk(DevTables T, ChunkArgs C) {
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 constexpr int SKC = 32;              // k per stage
-constexpr int SPITCH = SKC + 8;      // bf16 row pitch in LDS (80 B: conflict-free 16-B row reads)
 
+// Staged planes: per row the four 16-byte chunks of its 32 k, chunk c at
+// position c ^ swz(row).  Reads (one chunk of 16 consecutive rows per lane
+// group) and stores (the four chunks of consecutive rows) then touch distinct
+// banks in every cycle with 32 as with 64 four-byte LDS banks, as 128-bit
+// accesses.
 struct SplitStage {
-  uint16_t A[6][64 * SPITCH];
-  uint16_t B[6][64 * SPITCH];
+  uint4 A[6][64 * 4];
+  uint4 B[6][64 * 4];
 };
+__device__ __forceinline__ int swz(int row) { return ((row >> 1) ^ (row >> 3)) & 3; }
 
-__device__ inline bf8 lds_frag(const uint16_t* plane, int row, int kq) {
-  const uint4 v = *reinterpret_cast<const uint4*>(plane + row * SPITCH + kq * 8);
-  return __builtin_bit_cast(bf8, v);
+__device__ inline bf8 lds_frag(const uint4* plane, int row, int kq) {
+  return __builtin_bit_cast(bf8, plane[row * 4 + (kq ^ swz(row))]);
 }
 
 __device__ inline bf8 neg_frag(bf8 a) {
@@ -1804,19 +1808,19 @@ __global__ __launch_bounds__(NT, 2) void k_herk_split(DevTables T, ChunkArgs C) 
   } while (0)
 #define DPG_SPLIT_LSTORE()                                                       \
   do {                                                                           \
-    const int o_ = srow * SPITCH + skq * 8;                                      \
-    *reinterpret_cast<uint4*>(&ss->A[0][o_]) = ra0;                              \
-    *reinterpret_cast<uint4*>(&ss->A[1][o_]) = ra1;                              \
-    *reinterpret_cast<uint4*>(&ss->A[2][o_]) = ra2;                              \
-    *reinterpret_cast<uint4*>(&ss->A[3][o_]) = ra3;                              \
-    *reinterpret_cast<uint4*>(&ss->A[4][o_]) = ra4;                              \
-    *reinterpret_cast<uint4*>(&ss->A[5][o_]) = ra5;                              \
-    *reinterpret_cast<uint4*>(&ss->B[0][o_]) = rb0;                              \
-    *reinterpret_cast<uint4*>(&ss->B[1][o_]) = rb1;                              \
-    *reinterpret_cast<uint4*>(&ss->B[2][o_]) = rb2;                              \
-    *reinterpret_cast<uint4*>(&ss->B[3][o_]) = rb3;                              \
-    *reinterpret_cast<uint4*>(&ss->B[4][o_]) = rb4;                              \
-    *reinterpret_cast<uint4*>(&ss->B[5][o_]) = rb5;                              \
+    const int o_ = srow * 4 + (skq ^ swz(srow));                                 \
+    ss->A[0][o_] = ra0;                                                          \
+    ss->A[1][o_] = ra1;                                                          \
+    ss->A[2][o_] = ra2;                                                          \
+    ss->A[3][o_] = ra3;                                                          \
+    ss->A[4][o_] = ra4;                                                          \
+    ss->A[5][o_] = ra5;                                                          \
+    ss->B[0][o_] = rb0;                                                          \
+    ss->B[1][o_] = rb1;                                                          \
+    ss->B[2][o_] = rb2;                                                          \
+    ss->B[3][o_] = rb3;                                                          \
+    ss->B[4][o_] = rb4;                                                          \
+    ss->B[5][o_] = rb5;                                                          \
   } while (0)
   f4 fr[2][2], fi[2][2];
   double dr[2][2][4], di[2][2][4];
