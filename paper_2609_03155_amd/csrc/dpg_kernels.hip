@@ -369,8 +369,11 @@ __global__ __launch_bounds__(NT, 2) void k_form_B(DevTables T, ProbArgs P, Chunk
   const int i0 = tile * 64;
   __shared__ double sX[8][3];
   __shared__ double sGeo[BQC][21];          // w J (9), w det J^{-T} (9) | Robin: tangential maps
-  __shared__ double sP[BQC][64][3];         // w det (J^{-T} psi_hat_i)_c
-  __shared__ double sQ[BQC][64][3];         // w (J chat_i)_c
+  // sP = sPQ[0]: w det (J^{-T} psi_hat_i)_c;  sQ = sPQ[1]: w (J chat_i)_c.  One
+  // array, so that the write-out staging below may span both.
+  __shared__ double sPQ[2][BQC][64][3];
+  auto& sP = sPQ[0];
+  auto& sQ = sPQ[1];
   __shared__ double2 sRes[64][4][2];        // per-thread shares of (D B_f x): [row][share][F/I]
   extern __shared__ double smem[];
   double* sPhi = smem;                      // [BQC][m1]
@@ -496,7 +499,11 @@ __global__ __launch_bounds__(NT, 2) void k_form_B(DevTables T, ProbArgs P, Chunk
     // through LDS (sP/sQ are free until the next batch) so that every store
     // instruction covers runs of 16 consecutive rows of one column
     const int nm = min(4 * BIT, m1 - ib);   // DG functions of this batch
-    double2* sb = reinterpret_cast<double2*>(&sP[0][0][0]);   // [2 rows E/H][16 m][64 columns]
+    // [2 rows E/H][16 m][SBP columns]; the pitch of SBP = 66 16-byte slots puts the
+    // eight lanes of one 128-bit access (two columns x four m) in distinct banks
+    constexpr int SBP = 66;
+    static_assert(2 * 16 * SBP * sizeof(double2) <= sizeof(double) * 2 * BQC * 64 * 3, "staging fits sP and sQ");
+    double2* sb = reinterpret_cast<double2*>(&sPQ[0][0][0][0]);
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc)
 #pragma unroll
@@ -532,8 +539,8 @@ __global__ __launch_bounds__(NT, 2) void k_form_B(DevTables T, ProbArgs P, Chunk
               }
             }
           }
-          sb[(0 * 16 + sub + 4 * u) * 64 + il] = bE;
-          sb[(1 * 16 + sub + 4 * u) * 64 + il] = bH;
+          sb[(0 * 16 + sub + 4 * u) * SBP + il] = bE;
+          sb[(1 * 16 + sub + 4 * u) * SBP + il] = bH;
         }
         __syncthreads();
         // column i0 + e / 32 of this side, rows (E or H, cc, m) for m < nm
@@ -542,7 +549,7 @@ __global__ __launch_bounds__(NT, 2) void k_form_B(DevTables T, ProbArgs P, Chunk
           const int ii = i0 + jl;
           if (ml >= nm || ii >= T.Np) continue;
           const int row = nvp + (3 * hr + cc) * m1 + ib + ml;
-          Z[(int64_t)(side * T.Np + ii) * ld + row] = sb[(hr * 16 + ml) * 64 + jl];
+          Z[(int64_t)(side * T.Np + ii) * ld + row] = sb[(hr * 16 + ml) * SBP + jl];
         }
       }
   }
