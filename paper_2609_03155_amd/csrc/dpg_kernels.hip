@@ -555,58 +555,54 @@ __global__ __launch_bounds__(NT, 2) void k_form_B(DevTables T, ProbArgs P, Chunk
   }
   sRes[il][sub][0] = rF;
   sRes[il][sub][1] = rI;
-  // ---- trace unknowns (real, geometry free): one wave per (column, chunk of
-  // 64 trace functions), lanes along the rows (coalesced); the wave's part of
-  // D B_f x is reduced in a fixed order and added per column chunk by chunk.
-  // The pairing summed over all faces is a table; Robin faces are taken off
-  // it for the F rows.
+  // ---- trace unknowns (real, geometry free): one wave per column, its lanes
+  // along the trace rows in chunks of 64 (coalesced stores); each lane sums
+  // its rows' part of D B_f x over the chunks, and the wave reduces the
+  // column's sum once, in a fixed order.  The pairing summed over all faces
+  // is a table; Robin faces are taken off it for the F rows.
   __shared__ double2 sTr[64][2];
   {
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (threadIdx.x < 64) sTr[threadIdx.x][0] = sTr[threadIdx.x][1] = make_double2(0.0, 0.0);
-    __syncthreads();
     const int ncol = min(64, T.Np - i0);   // columns of this tile
-    for (int c0 = 0; c0 < T.nt1; c0 += 64) {
-      const int jt = c0 + lane;
-      const bool okt = jt < T.nt1;
-      const int rowEh = nvp + T.nu + jt, rowHh = nvp + T.nu + T.nt1 + jt;
-      double2 xe = make_double2(0.0, 0.0), xh = xe;
-      if (xc && okt) {
-        xe = xc[T.nu + jt];
-        xh = xc[T.nu + T.nt1 + jt];
-      }
-#pragma unroll 4
-      for (int jl = wv; jl < ncol; jl += NT / 64) {
-        const int ii = i0 + jl;
-        const bool okc = ii < T.N && okt;
+#pragma unroll 2
+    for (int jl = wv; jl < ncol; jl += NT / 64) {
+      const int ii = i0 + jl;
+      const double dF = d[ii], dI = d[T.Np + ii];
+      double2 aF = make_double2(0.0, 0.0), aI = aF;
+      for (int c0 = 0; c0 < T.nt1; c0 += 64) {
+        const int jt = c0 + lane;
+        const bool okt = jt < T.nt1, okc = ii < T.N && okt;
         double tI = okc ? T.Tsum[(size_t)ii * T.nt1 + jt] : 0.0, tF = tI;
         if (nrobin && okc) {
           for (int f = 0; f < 6; ++f)
             if ((rmask >> f) & 1) tF -= T.T[((size_t)f * T.N + ii) * T.nt1 + jt];
         }
-        const double tf = d[ii] * tF, ti = d[T.Np + ii] * tI;
+        const double tf = dF * tF, ti = dI * tI;
         if (okt) {
+          const int rowEh = nvp + T.nu + jt, rowHh = nvp + T.nu + T.nt1 + jt;
           Z[(int64_t)ii * ld + rowEh] = make_double2(0.0, 0.0);
           Z[(int64_t)ii * ld + rowHh] = make_double2(tf, 0.0);
           Z[(int64_t)(T.Np + ii) * ld + rowEh] = make_double2(ti, 0.0);
           Z[(int64_t)(T.Np + ii) * ld + rowHh] = make_double2(0.0, 0.0);
+          if (xc) {
+            const double2 xe = xc[T.nu + jt], xh = xc[T.nu + T.nt1 + jt];
+            aF.x += tf * xh.x;
+            aF.y += tf * xh.y;
+            aI.x += ti * xe.x;
+            aI.y += ti * xe.y;
+          }
         }
-        if (xc) {
-          double2 pF = make_double2(tf * xh.x, tf * xh.y), pI = make_double2(ti * xe.x, ti * xe.y);
+      }
 #pragma unroll
-          for (int off = 32; off > 0; off >>= 1) {
-            pF.x += __shfl_xor(pF.x, off, 64);
-            pF.y += __shfl_xor(pF.y, off, 64);
-            pI.x += __shfl_xor(pI.x, off, 64);
-            pI.y += __shfl_xor(pI.y, off, 64);
-          }
-          if (lane == 0) {
-            sTr[jl][0].x += pF.x;
-            sTr[jl][0].y += pF.y;
-            sTr[jl][1].x += pI.x;
-            sTr[jl][1].y += pI.y;
-          }
-        }
+      for (int off = 32; off > 0; off >>= 1) {
+        aF.x += __shfl_xor(aF.x, off, 64);
+        aF.y += __shfl_xor(aF.y, off, 64);
+        aI.x += __shfl_xor(aI.x, off, 64);
+        aI.y += __shfl_xor(aI.y, off, 64);
+      }
+      if (lane == 0) {
+        sTr[jl][0] = aF;
+        sTr[jl][1] = aI;
       }
     }
   }
