@@ -890,7 +890,7 @@ __device__ inline void lds_atb(const double* A, const double* B, int K, RAcc& c)
   }
 }
 
-__global__ __launch_bounds__(NT, 2) void k_form_SM(DevTables T, ProbArgs P, ChunkArgs C) {
+__global__ __launch_bounds__(NT, 3) void k_form_SM(DevTables T, ProbArgs P, ChunkArgs C) {
   int64_t cell;
   int tile;
   if (!decode_cell_tile(C.n, T.n_sm_tiles, cell, tile)) return;
@@ -906,11 +906,12 @@ __global__ __launch_bounds__(NT, 2) void k_form_SM(DevTables T, ProbArgs P, Chun
   const int b1 = (b == 0) ? 1 : 0, b2 = (b == 2) ? 1 : 2;
   const int sab = sym3(a, b);
   const int s11 = sym3(a1, b1), s12 = sym3(a1, b2), s21 = sym3(a2, b1), s22 = sym3(a2, b2);
-  RAcc S, M, MF, MI;
+  // S and M over the volume points; then S + cF M and S + cI M, to which the
+  // Robin-face masses add (two accumulators live at a time: three workgroups
+  // fit a CU)
+  RAcc S, M;
   racc_zero(S);
   racc_zero(M);
-  racc_zero(MF);
-  racc_zero(MI);
   __syncthreads();
   const double* gmet = C.met + cell * met_stride(T);
   // ---- volume points, in chunks of SQC; the table values and metrics of
@@ -965,6 +966,22 @@ __global__ __launch_bounds__(NT, 2) void k_form_SM(DevTables T, ProbArgs P, Chun
     lds_atb(Ac2, By2, SQC, S);
     __syncthreads();
   }
+  const double2 eps = make_double2(P.eps[2 * gc], P.eps[2 * gc + 1]);
+  const double2 mu = make_double2(P.mu[2 * gc], P.mu[2 * gc + 1]);
+  const double om2 = P.omega * P.omega;
+  const double cF = om2 * (eps.x * eps.x + eps.y * eps.y) + P.alpha;
+  const double cI = om2 * (mu.x * mu.x + mu.y * mu.y) + P.alpha;
+  // S <- S + cF M (G_FF),  M <- S + cI M (G_II)
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int it = 0; it < 4; ++it) {
+        const double sv = S.b[u][v][it], mv = M.b[u][v][it];
+        S.b[u][v][it] = sv + cF * mv;
+        M.b[u][v][it] = sv + cI * mv;
+      }
   // ---- Robin faces
   for (int f = 0; f < 6; ++f) {
     if (!is_robin(fk[f])) continue;
@@ -988,16 +1005,11 @@ __global__ __launch_bounds__(NT, 2) void k_form_SM(DevTables T, ProbArgs P, Chun
         By1[qq * LDP + il] = z2 * bq;
       }
       __syncthreads();
-      lds_atb(Av, Bv, SQC, MI);
-      lds_atb(Av, By1, SQC, MF);
+      lds_atb(Av, Bv, SQC, M);    // G_II part
+      lds_atb(Av, By1, SQC, S);   // G_FF part
       __syncthreads();
     }
   }
-  const double2 eps = make_double2(P.eps[2 * gc], P.eps[2 * gc + 1]);
-  const double2 mu = make_double2(P.mu[2 * gc], P.mu[2 * gc + 1]);
-  const double om2 = P.omega * P.omega;
-  const double cF = om2 * (eps.x * eps.x + eps.y * eps.y) + P.alpha;
-  const double cI = om2 * (mu.x * mu.x + mu.y * mu.y) + P.alpha;
   const double* d = C.dscale + cell * (int64_t)T.nvp;
   double2* Z = C.Z + cell * T.zstride;
   const int64_t ld = T.ldz;
@@ -1012,9 +1024,7 @@ __global__ __launch_bounds__(NT, 2) void k_form_SM(DevTables T, ProbArgs P, Chun
         if (li >= T.nc || lj >= T.nc) continue;
         const int i = a * T.nc + li, j = b * T.nc + lj;
         if (a == b && j > i) continue;
-        const double sv = S.b[u][v][it], mv = M.b[u][v][it];
-        const double gff = sv + cF * mv + MF.b[u][v][it];
-        const double gii = sv + cI * mv + MI.b[u][v][it];
+        const double gff = S.b[u][v][it], gii = M.b[u][v][it];
         Z[(int64_t)j * ld + i] = make_double2(d[i] * d[j] * gff, 0.0);
         Z[(int64_t)(T.Np + j) * ld + T.Np + i] = make_double2(d[T.Np + i] * d[T.Np + j] * gii, 0.0);
       }
