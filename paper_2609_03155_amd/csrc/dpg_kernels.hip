@@ -1036,6 +1036,7 @@ __global__ __launch_bounds__(NT, 3) void k_form_SM(DevTables T, ProbArgs P, Chun
 //   split regrouping        one slab of WSP_BYTES per wave
 constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
 constexpr size_t kFactorSmem = 2 * 64 * 65 * 8;
+constexpr size_t kFblockSmem = 64 * 65 * 8;   // the real F block needs no imaginary parts: three workgroups per CU
 static_assert(kFactorSmem <= 80 * 1024, "two factorisation workgroups must fit one CU");
 
 // 1/sqrt(d) for the pivots of the tile factorisation (d > 0 and finite, of
@@ -1232,7 +1233,7 @@ struct WOpsT {
 template <int MODE, int NV = 2>
 struct WPipe {
   // a wave of 16 rows (NV = 1) has half the accumulators, so room for twice the buffers
-  static constexpr int NB = NV == 2 ? (MODE == MM_RR ? 6 : 2) : (MODE == MM_RR ? 8 : 4);
+  static constexpr int NB = NV == 2 ? (MODE == MM_RR ? 4 : 2) : (MODE == MM_RR ? 8 : 4);
   // k-steps per buffer: a complex x real k-step has half the MFMAs of a
   // complex one, so its buffers take two, to keep as much work in flight
   static constexpr int KS = MODE == MM_CR ? 1 : 1;
@@ -1520,7 +1521,7 @@ __device__ __forceinline__ void diag_update(const double2* __restrict__ S0g, con
       for (int t = 0; t < 4; ++t) {
         const int r = 32 * h + 16 * v + (lane & 15), c = 16 * u + 4 * t + (lane >> 4);
         Sr[r * 65 + c] = q.re[u][v][t];
-        Si[r * 65 + c] = q.im[u][v][t];
+        if (MODE != MM_RR) Si[r * 65 + c] = q.im[u][v][t];   // a real block has no Si
       }
 }
 
@@ -1596,7 +1597,7 @@ __global__ __launch_bounds__(NT, 2) void k_chol_step(DevTables T, ChunkArgs C, i
 //     Linv_{j+1,j+1} = chol(A_{j+1,j+1} - sum_{m<=j} L_{j+1,m} L_{j+1,m}^T)^{-1} .
 // The block is small, so its cost is the latency of the chain, which one
 // workgroup walks without a launch (and a pass over all cells) per step.
-__global__ __launch_bounds__(NT, 2) void k_chol_fblock(DevTables T, ChunkArgs C, int nF) {
+__global__ __launch_bounds__(NT, 3) void k_chol_fblock(DevTables T, ChunkArgs C, int nF) {
   const int64_t cell = blockIdx.x;
   if (cell >= C.n) return;
   const int64_t gc = C.cell_ids[cell];
@@ -2059,7 +2060,7 @@ hipError_t launch_factor(const DevTables& t, const ChunkArgs& ca, hipStream_t st
   const int nF = t.Np / TB;   // leading column tiles that are real
   if (nF >= 1) {
     // F block first (one workgroup per cell), then the F columns of every other row in one launch
-    DPG_LAUNCH(KC_CHOL_DIAG, prof, st, k_chol_fblock, dim3((unsigned)ca.n), dim3(NT), kFactorSmem, st, t, ca, nF);
+    DPG_LAUNCH(KC_CHOL_DIAG, prof, st, k_chol_fblock, dim3((unsigned)ca.n), dim3(NT), kFblockSmem, st, t, ca, nF);
     DPG_LAUNCH(KC_CHOL_PANEL, prof, st, k_chol_fpanel, dim3(grid_of(true, nrb - nF - 1)), dim3(NT), kFactorSmem, st,
                t, ca, nF);
     j0 = nF;
