@@ -1408,6 +1408,7 @@ __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __res
   const double* tLr = FRB ? Fr + (int64_t)(j * TB) * ldf + j * TB : nullptr;
   const int nvb = T.nvp / TB;
   const bool wsplit = C.split && i >= nvb;
+  const bool last_w = j + 1 == nvb;
   uint16_t* wp = wsplit ? C.wsplit + cell * split_elems(T) : nullptr;
   const int nkc = T.nvp / 32;
 #pragma unroll
@@ -1443,7 +1444,10 @@ __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __res
       for (int t = 0; t < 4; ++t) {
         const int r = 16 * nb + (lane & 15), c = 16 * mb + 4 * t + (lane >> 4);
         const double vr = yr[nb][t], vi = MODE == MM_RR ? 0.0 : yi[nb][t];
-        tile[(int64_t)c * ld + r] = make_double2(vr, vi);
+        // in the split path the last column block of W^H is read only through its
+        // bf16 planes, except the residual row (eta is formed from it in FP64)
+        const bool keep = !(wsplit && last_w) || i * TB + RW * h + r == T.nvp + T.k + 1;
+        if (keep) tile[(int64_t)c * ld + r] = make_double2(vr, vi);
         if (FR == FR_WRITE) Fr[(int64_t)(j * TB + c) * ldf + i * TB + RW * h + r] = vr;
         if (wsplit) {
           // three-term bf16 splits of re and im into the wave's LDS slab
@@ -1669,8 +1673,11 @@ __global__ __launch_bounds__(NT, 2) void k_chol_fpanel(DevTables T, ChunkArgs C,
     const int cls = frows_class(T, i * TB + RW * h, RW);
     if (cls == FROWS_ZERO) {
       // L_i,F = 0 (A_i,F = 0, already so in the workspace); only the bf16
-      // planes of these W rows need their zeros for the F columns
-      if (C.split) {
+      // planes of these W rows need their zeros for the F columns, and only
+      // if the HERK reads them (it skips the F columns of a block of W that
+      // is zero there)
+      const int wblk = i - T.nvp / TB;
+      if (C.split && herk_k0(T, wblk, wblk) == 0) {
         const int nkc = T.nvp / 32;
         uint16_t* wp = C.wsplit + cell * split_elems(T) + (int64_t)((i - T.nvp / TB) * TB + RW * h) * nkc * 192;
         const int per_row = 2 * nF * 192 / 8;   // 16-byte runs of the F columns in one row
