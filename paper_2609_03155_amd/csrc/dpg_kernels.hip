@@ -1234,9 +1234,9 @@ template <int MODE, int NV = 2>
 struct WPipe {
   // a wave of 16 rows (NV = 1) has half the accumulators, so room for twice the buffers
   static constexpr int NB = NV == 2 ? (MODE == MM_RR ? 4 : 2) : (MODE == MM_RR ? 8 : 4);
-  // k-steps per buffer: a complex x real k-step has half the MFMAs of a
-  // complex one, so its buffers take two, to keep as much work in flight
-  static constexpr int KS = MODE == MM_CR ? 1 : 1;
+  // k-steps per buffer (more than one lets a mode with few MFMAs per k-step
+  // keep more work in flight; two for the complex x real mode spilled, so one)
+  static constexpr int KS = 1;
 };
 
 // Operands of one k-step: A from the complex panel Ai (leading dimension
