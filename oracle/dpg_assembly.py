@@ -10,6 +10,14 @@ no code with the HIP library or its host code.
                    and l_e = [M4 l ; M5 l]  (§2.3, the condensed system).
 * trace_numbering: global trace unknowns of a conforming hexahedral mesh.
 * assemble:        A = sum_K P_K^T A_K P_K,  b = sum_K P_K^T b_K  (scipy.sparse).
+* cg:              the condensed system A t = b solved by conjugate gradients
+                   without a preconditioner (§2.3; A is Hermitian positive
+                   definite); textbook Hestenes-Stiefel recursion.
+* scatter:         t_K = P_K t, the cell's local trace coefficients (zero where
+                   removed or constrained).
+* reconstruct:     the interior unknowns recovered cell by cell,
+                   u_K = M1^{-1} (M4 l - M2 t_K)  (§2.3), returned with t_K as
+                   the cell's whole coefficient vector [u_K ; t_K].
 
 Numbering rule (the library's host numbering follows the same rule, written
 independently):
@@ -184,3 +192,54 @@ def assemble(A_cells, b_cells, glob, n_dofs):
     A.sum_duplicates()
     A.sort_indices()
     return A, b
+
+
+def cg(A, b, tol: float, max_iter: int, x0=None):
+    """Conjugate gradients for the Hermitian positive definite A (any object
+    with ``@``), as the condensed trace system is solved in §2.3: no
+    preconditioner, start x0 (zero if None), stop once the recursively updated
+    residual satisfies ||r||_2 <= tol ||b||_2 or after max_iter iterations.
+    Each iteration:
+        q = A p,  alpha = (r^H r) / (p^H q),  x += alpha p,  r -= alpha q,
+        beta = (r_new^H r_new) / (r^H r),     p = r + beta p.
+    Returns (x, iterations, history of ||r||_2 / ||b||_2, one entry per
+    iteration plus the initial one)."""
+    b = np.asarray(b, complex)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, complex)
+    bn = float(np.linalg.norm(b))
+    r = b - A @ x
+    p = r.copy()
+    rr = float(np.real(np.vdot(r, r)))
+    hist = [np.sqrt(rr) / bn if bn > 0 else 0.0]
+    it = 0
+    while it < max_iter and bn > 0 and np.sqrt(rr) > tol * bn:
+        q = A @ p
+        alpha = rr / float(np.real(np.vdot(p, q)))
+        x = x + alpha * p
+        r = r - alpha * q
+        rr_new = float(np.real(np.vdot(r, r)))
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+        it += 1
+        hist.append(np.sqrt(rr) / bn)
+    return x, it, np.array(hist)
+
+
+def scatter(t, glob_cell):
+    """P_K t: the cell's local trace coefficients from the global ones."""
+    g = np.asarray(glob_cell)
+    out = np.zeros(len(g), complex)
+    keep = g >= 0
+    out[keep] = np.asarray(t, complex)[g[keep]]
+    return out
+
+
+def reconstruct(K, le, nu: int, t_local):
+    """The cell's interior unknowns from its traces (§2.3),
+    u = M1^{-1} (M4 l - M2 t), with M1 = K_e[:nu, :nu], M2 = K_e[:nu, nu:] and
+    M4 l = l_e[:nu]; returns [u ; t]."""
+    K = np.asarray(K, complex)
+    le = np.asarray(le, complex)
+    t_local = np.asarray(t_local, complex)
+    u = np.linalg.solve(K[:nu, :nu], le[:nu] - K[:nu, nu:] @ t_local)
+    return np.concatenate([u, t_local])
