@@ -68,9 +68,12 @@ def measured_traffic(workload: str, precision: str, kernel: str):
     return None
 
 
-def trace_system_timings(w, plan, prob, xd, K, l, eta, info, solve, stream, reps: int = 5, mv_reps: int = 50):
-    """Condensation (A_K, b_K), gather assembly and complex CSR matvec of the
-    condensed trace system on the workload, timed with HIP events."""
+def trace_system_timings(w, plan, prob, xd, K, l, eta, info, solve, stream, reps: int = 5, mv_reps: int = 50,
+                         cg_iters: int = 200):
+    """Condensation (A_K, b_K), gather assembly, complex CSR matvec, a fixed
+    number of CG iterations (no preconditioner), the trace scatter and the
+    reconstruction of the interior unknowns on the workload, timed with HIP
+    events."""
     import torch
     from paper_2609_03155_amd import dpg
     solve(dpg.DPG_FP64)
@@ -116,6 +119,29 @@ def trace_system_timings(w, plan, prob, xd, K, l, eta, info, solve, stream, reps
         fl += cnt * (4.0 / 3.0 * nu ** 3 + 4.0 * nu * nu * nt + 4.0 * nt * nt * nu)
         contrib += cnt * nt * nt
     mv_bytes = ts.nnz * (16 + 4) + (ts.n_dofs + 1) * 8 + 2 * ts.n_dofs * 16
+    # CG: cg_iters iterations from zero (tolerance 0, so all of them run)
+    t = torch.zeros(ts.n_dofs, dtype=torch.complex128, device="cuda")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    cg_it, cg_rr = ts.solve(vals, rhs, t, 0.0, cg_iters, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    cg_ms = e0.elapsed_time(e1) / max(cg_it, 1)
+    # per iteration: the matvec, x, p, r, q read and x, r written by the update, r, p read and p written
+    cg_bytes = mv_bytes + 9 * 16 * ts.n_dofs
+    tl = ts.scatter(t, stream=stream)
+    rec_out = {}
+
+    def do_rec():
+        rec_out["r"] = plan.reconstruct(K, l, tl, stream=stream)
+    rec_ms = timed_ms(do_rec, reps)
+    rinfo = rec_out["r"][1]
+    rfl = 0.0
+    for p in sorted(set(int(v) for v in w.degree)):
+        cnt = int(np.sum(w.degree == p))
+        nu, nt = 6 * (p + 1) ** 3, 24 * (p + 1) ** 2
+        rfl += cnt * (4.0 / 3.0 * nu ** 3 + 8.0 * nu * nt + 8.0 * nu * nu)
     out.update({
         "n_dofs": ts.n_dofs, "nnz": ts.nnz, "build_s": build_s,
         "condense_ms": cond_ms, "condense_tflops": fl / (cond_ms * 1e-3) / 1e12,
@@ -126,9 +152,15 @@ def trace_system_timings(w, plan, prob, xd, K, l, eta, info, solve, stream, reps
         "spmv_GBps": mv_bytes / (mv_ms * 1e-3) / 1e9,
         "spmv_frac_hbm": mv_bytes / (mv_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
         "spmv_bytes_note": "algorithmic: 16 B value + 4 B column per nonzero, row pointers, x and y once",
+        "cg_iterations": cg_it, "cg_relres": cg_rr, "cg_ms_per_iteration": cg_ms,
+        "cg_GBps": cg_bytes / (cg_ms * 1e-3) / 1e9,
+        "cg_frac_hbm": cg_bytes / (cg_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+        "cg_bytes_note": "per iteration: the matvec's algorithmic bytes plus 9 complex vectors of n (update, direction)",
+        "reconstruct_ms": rec_ms, "reconstruct_tflops": rfl / (rec_ms * 1e-3) / 1e12,
+        "reconstruct_failed_cells": int(np.sum(rinfo.cpu().numpy()[:w.n_cells] != 0)),
     })
     ts.close()
-    del A, b, vals, rhs
+    del A, b, vals, rhs, t, tl, rec_out
     return out
 
 

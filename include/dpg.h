@@ -317,6 +317,55 @@ dpg_status dpg_assemble(dpg_trace_system sys, const double* A, const double* b, 
 dpg_status dpg_csr_matvec(int64_t n_rows, const int64_t* row_ptr, const int32_t* col, const double* vals,
                           const double* x, double* y, void* stream);
 
+/* ---------------------------------------------------------------------
+ * Global solve (Sec. 2.3 and Algorithm 1: the condensed trace system is
+ * Hermitian positive definite and solved by CG without a preconditioner;
+ * the interior unknowns and the residual are then recovered cell by cell).
+ * --------------------------------------------------------------------- */
+
+/* Conjugate gradients for the complex Hermitian positive definite CSR system
+ * A x = b (n_rows unknowns; row_ptr [n_rows+1], col [nnz], vals [nnz]
+ * complex, b and x [n_rows] complex; all device pointers), without a
+ * preconditioner:
+ *   q = A p, alpha = r^H r / p^H q, x += alpha p, r -= alpha q,
+ *   beta = r_new^H r_new / r^H r, p = r + beta p,
+ * from the start x (in: initial guess, out: last iterate) until the
+ * recursively updated residual satisfies ||r||_2 <= tol ||b||_2, or
+ * max_iter iterations.  *iters receives the iterations done, *relres the
+ * final ||r||_2 / ||b||_2 (0 for b = 0, where x is left unchanged).  No
+ * iteration runs when the start already satisfies the test.  The scalars
+ * stay on the device and every reduction has a fixed order (bitwise
+ * reproducible); the host reads the convergence flag once per 16 iterations
+ * while the next 16 are queued.  Allocates and frees 3 n_rows complex
+ * vectors and O(n_rows / 256) partial sums on the current device; returns
+ * after synchronising `stream`.  DPG_ERR_ARG for null pointers, n_rows < 0,
+ * max_iter < 0 or tol < 0 (or NaN). */
+dpg_status dpg_cg_solve(int64_t n_rows, const int64_t* row_ptr, const int32_t* col, const double* vals,
+                        const double* b, double* x, double tol, int64_t max_iter, int64_t* iters,
+                        double* relres, void* stream);
+
+/* The cells' local trace coefficients t_K = P_K t from the global trace
+ * vector t (device, complex [n_dofs]): t_local (device, complex) is laid out
+ * like the condensed right-hand sides (dpg_plan_trace_offsets' b_off), zero
+ * where a local function is removed or constrained.  Stream-ordered. */
+dpg_status dpg_trace_system_scatter(dpg_trace_system sys, const double* t, double* t_local, void* stream);
+
+/* Interior unknowns of every cell from its traces (Sec. 2.3):
+ *   u_K = M1^{-1} (l_u - M2 t_K),  K_e = [[M1, M2], [M2^H, M3]], l_e = [l_u ; l_t],
+ * with K, l the outputs of a dpg_local_solve of the same plan (device, its
+ * layout) and t_local the traces in the b_off layout (dpg_trace_system_scatter).
+ * Writes x (device, complex, the v_off layout of the local solve's x and l:
+ * k = n_u + n_t per cell) = [u_K ; t_K], the whole coefficient vector of the
+ * cell, which a dpg_local_solve with this x turns into the residual
+ * indicator eta of the global solution.  On the GPU: a Jacobi-scaled blocked
+ * Cholesky of M1 with the row (D (l_u - M2 t_K))^H appended (the local
+ * solve's factorisation kernels), then a backward substitution.  info
+ * [n_cells]: 0, or the failing pivot column + 1 of M1.  Uses the plan's
+ * workspace (do not overlap with another call on the same plan).
+ * Stream-ordered. */
+dpg_status dpg_reconstruct(dpg_plan plan, const double* K, const double* l, const double* t_local, double* x,
+                           int32_t* info, void* stream);
+
 /* Kernel classes timed by the plan's optional profiler. */
 enum {
   DPG_K_SCALE = 0,      /* geometry check and Jacobi scaling            */

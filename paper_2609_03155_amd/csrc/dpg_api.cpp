@@ -41,6 +41,7 @@ struct DegreeGroup {
   hipStream_t stream = nullptr;       // branch stream of the concurrent schedule
   hipEvent_t done = nullptr;
   dpg::DevTables ct{};                // condensation: factorisation tables of the K_e-based matrix
+  dpg::DevTables rt{};                // reconstruction: the same with the single right-hand-side row
 };
 
 // Algorithmic flops of one cell (structure-aware counts: formation of the
@@ -86,6 +87,7 @@ struct dpg_trace_system_s {
   int64_t* contrib = nullptr;
   int64_t* rhs_ptr = nullptr;
   int64_t* rhs_contrib = nullptr;
+  int64_t* glob_dev = nullptr;        // device copy of glob (trace scatter)
 };
 
 struct dpg_graph_s {
@@ -413,6 +415,15 @@ dpg_status dpg_plan_create(int32_t device, const int8_t* degree_host, int64_t n_
         c.ldz = c.nrows + 4;
         c.zstride = c.ldz * c.nvp + 36;
         if (c.zstride > g.dt.zstride) throw std::bad_alloc();
+        // reconstruction matrix: the same columns, one row block below them
+        // whose first row is (D (l_u - M2 t_K))^H
+        dpg::DevTables& r = g.rt;
+        r = c;
+        r.k = 0;
+        r.kp = 64;
+        r.nrows = r.nvp + r.kp;
+        r.ldz = r.nrows + 4;
+        r.zstride = r.ldz * r.nvp + 36;
       }
       std::vector<void*> tmp;
       g.cells_dev = upload(tmp, g.cells);
@@ -781,6 +792,7 @@ dpg_status dpg_trace_system_create(dpg_plan plan, const int64_t* cells_host, con
     S->contrib = upload(own, contrib);
     S->rhs_ptr = upload(own, rptr);
     S->rhs_contrib = upload(own, rcontrib);
+    S->glob_dev = upload(own, S->glob);
     *out = S;
     return DPG_OK;
   } catch (const std::invalid_argument&) {
@@ -799,7 +811,7 @@ dpg_status dpg_trace_system_destroy(dpg_trace_system sys) {
   if (!sys) return DPG_ERR_ARG;
   (void)hipSetDevice(sys->device);
   for (void* p : {(void*)sys->row_ptr, (void*)sys->col, (void*)sys->contrib_ptr, (void*)sys->contrib,
-                  (void*)sys->rhs_ptr, (void*)sys->rhs_contrib})
+                  (void*)sys->rhs_ptr, (void*)sys->rhs_contrib, (void*)sys->glob_dev})
     if (p) (void)hipFree(p);
   delete sys;
   return DPG_OK;
@@ -850,6 +862,127 @@ dpg_status dpg_csr_matvec(int64_t n_rows, const int64_t* row_ptr, const int32_t*
                                               reinterpret_cast<hipStream_t>(stream));
   if (e != hipSuccess) {
     set_error("dpg_csr_matvec", e);
+    return DPG_ERR_HIP;
+  }
+  return DPG_OK;
+}
+
+dpg_status dpg_trace_system_scatter(dpg_trace_system sys, const double* t, double* t_local, void* stream) {
+  if (!sys || (!sys->glob.empty() && (!t_local || (sys->n_dofs > 0 && !t)))) return DPG_ERR_ARG;
+  if (hipSetDevice(sys->device) != hipSuccess) return DPG_ERR_HIP;
+  const hipError_t e = dpg::launch_scatter((int64_t)sys->glob.size(), sys->glob_dev, reinterpret_cast<const double2*>(t),
+                                           reinterpret_cast<double2*>(t_local), reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) {
+    set_error("dpg_trace_system_scatter", e);
+    return DPG_ERR_HIP;
+  }
+  return DPG_OK;
+}
+
+dpg_status dpg_cg_solve(int64_t n_rows, const int64_t* row_ptr, const int32_t* col, const double* vals, const double* b,
+                        double* x, double tol, int64_t max_iter, int64_t* iters, double* relres, void* stream) {
+  if (n_rows < 0 || max_iter < 0 || !(tol >= 0.0) || !iters || !relres) return DPG_ERR_ARG;
+  if (n_rows > 0 && (!row_ptr || !col || !vals || !b || !x)) return DPG_ERR_ARG;
+  *iters = 0;
+  *relres = 0.0;
+  if (n_rows == 0) return DPG_OK;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  std::vector<void*> own;
+  double* host = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  dpg_status rc = DPG_OK;
+  try {
+    dpg::CgArgs g{};
+    g.n = n_rows;
+    g.row_ptr = row_ptr;
+    g.col = col;
+    g.val = reinterpret_cast<const double2*>(vals);
+    g.b = reinterpret_cast<const double2*>(b);
+    g.x = reinterpret_cast<double2*>(x);
+    double2* vec = nullptr;
+    HIP_CHECK(hipMalloc(reinterpret_cast<void**>(&vec), sizeof(double2) * 3 * n_rows));
+    own.push_back(vec);
+    g.r = vec;
+    g.p = vec + n_rows;
+    g.q = vec + 2 * n_rows;
+    HIP_CHECK(hipMalloc(reinterpret_cast<void**>(&g.part), sizeof(double) * dpg::cg_part_len(n_rows)));
+    own.push_back(g.part);
+    HIP_CHECK(hipMalloc(reinterpret_cast<void**>(&g.sc), sizeof(double) * dpg::CG_NSC));
+    own.push_back(g.sc);
+    // pinned host slots: the start scalars, then two slots the scalars are
+    // copied back to after each batch of iterations
+    HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&host), sizeof(double) * 3 * dpg::CG_NSC, hipHostMallocDefault));
+    for (int k = 0; k < 3 * dpg::CG_NSC; ++k) host[k] = 0.0;
+    host[dpg::CG_TOL2] = tol * tol;
+    for (auto& e : ev) HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    HIP_CHECK(hipMemcpyAsync(g.sc, host, sizeof(double) * dpg::CG_NSC, hipMemcpyHostToDevice, st));
+    hip_check(dpg::launch_cg_start(g, st));
+    // Batches of iterations; the flag of batch k is read while batch k+1 runs
+    // (iterations past convergence return at once).
+    constexpr int64_t kBatch = 16;
+    int64_t launched = 0;
+    for (int64_t k = 0; launched < max_iter; ++k) {
+      const int64_t nb = std::min<int64_t>(kBatch, max_iter - launched);
+      hip_check(dpg::launch_cg_iterations(g, nb, st));
+      launched += nb;
+      double* slot = host + dpg::CG_NSC * (1 + (k & 1));
+      HIP_CHECK(hipMemcpyAsync(slot, g.sc, sizeof(double) * dpg::CG_NSC, hipMemcpyDeviceToHost, st));
+      HIP_CHECK(hipEventRecord(ev[k & 1], st));
+      if (k > 0) {
+        HIP_CHECK(hipEventSynchronize(ev[(k - 1) & 1]));
+        if (host[dpg::CG_NSC * (1 + ((k - 1) & 1)) + dpg::CG_DONE] != 0.0) break;
+      }
+    }
+    HIP_CHECK(hipMemcpyAsync(host + dpg::CG_NSC, g.sc, sizeof(double) * dpg::CG_NSC, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    const double* f = host + dpg::CG_NSC;
+    *iters = (int64_t)f[dpg::CG_ITERS];
+    *relres = f[dpg::CG_BN2] > 0.0 ? std::sqrt(f[dpg::CG_RR] / f[dpg::CG_BN2]) : 0.0;
+  } catch (const HipError&) {
+    rc = DPG_ERR_HIP;
+  }
+  if (rc != DPG_OK) (void)hipStreamSynchronize(st);
+  for (auto e : ev)
+    if (e) (void)hipEventDestroy(e);
+  if (host) (void)hipHostFree(host);
+  for (void* p : own) (void)hipFree(p);
+  return rc;
+}
+
+dpg_status dpg_reconstruct(dpg_plan plan, const double* K, const double* l, const double* t_local, double* x,
+                           int32_t* info, void* stream) {
+  if (!plan) return DPG_ERR_ARG;
+  if (plan->n_cells == 0) return DPG_OK;
+  if (!K || !l || !t_local || !x || !info) return DPG_ERR_ARG;
+  if (hipSetDevice(plan->device) != hipSuccess) return DPG_ERR_HIP;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = hipSuccess;
+  for (auto& g : plan->groups) {
+    const int64_t nc = (int64_t)g.cells.size();
+    for (int64_t s0 = 0; s0 < nc && e == hipSuccess; s0 += g.chunk) {
+      dpg::ChunkArgs ca{};
+      ca.cell_ids = g.cells_dev + s0;
+      ca.n = std::min<int64_t>(g.chunk, nc - s0);
+      ca.Z = g.Z;
+      ca.split = 0;
+      ca.info = info;
+      dpg::CondArgs cg{};
+      cg.Ke = reinterpret_cast<const double2*>(K);
+      cg.le = reinterpret_cast<const double2*>(l);
+      cg.Ke_off = plan->K_off_dev;
+      cg.le_off = plan->v_off_dev;
+      cg.nu = g.d.nu;
+      cg.kfull = g.d.k;
+      cg.tk = reinterpret_cast<const double2*>(t_local);
+      cg.tk_off = plan->b_off_dev;
+      cg.xout = reinterpret_cast<double2*>(x);
+      e = dpg::launch_recon_load(g.rt, ca, cg, st);
+      if (e == hipSuccess) e = dpg::launch_factor(g.rt, ca, st, nullptr);
+      if (e == hipSuccess) e = dpg::launch_recon_back(g.rt, ca, cg, st);
+    }
+  }
+  if (e != hipSuccess) {
+    set_error("dpg_reconstruct", e);
     return DPG_ERR_HIP;
   }
   return DPG_OK;

@@ -76,7 +76,27 @@ struct CondArgs {
   int64_t Ke_base, le_base;  // Ke_off[first], le_off[first] of the buffers' first cell
   int nu;                    // interior unknowns (first nu rows/columns of K_e)
   int kfull;                 // K_e dimension, nu + n_t
+  // reconstruction only: the cells' local trace coefficients t_K (n_t each,
+  // at tk_off[cell]) in, the whole coefficient vectors [u ; t_K] out (at
+  // le_off[cell], the layout of l_e)
+  const double2* tk;
+  const int64_t* tk_off;
+  double2* xout;
 };
+
+// Device data of one CG solve (CSR matrix, vectors, partial sums, scalars).
+struct CgArgs {
+  int64_t n;
+  const int64_t* row_ptr;
+  const int32_t* col;
+  const double2* val;
+  const double2* b;
+  double2* x;                // start in, iterate out
+  double2 *r, *p, *q;        // residual, direction, A p
+  double* part;              // [cg_part_len(n)] partial sums of the reductions
+  double* sc;                // [CG_NSC] iteration scalars
+};
+enum { CG_RR = 0, CG_ALPHA = 1, CG_BETA = 2, CG_BN2 = 3, CG_DONE = 4, CG_ITERS = 5, CG_TOL2 = 6, CG_NSC = 8 };
 
 // Optional per-kernel timing: when `on`, each launch is bracketed by two HIP
 // events recorded on the launch stream; `recs` keeps (class, begin, end).
@@ -126,6 +146,19 @@ hipError_t launch_gather(int64_t n, const int64_t* ptr, const int64_t* src, cons
 // y = A x for a complex CSR matrix
 hipError_t launch_csr_matvec(int64_t n_rows, const int64_t* row_ptr, const int32_t* col, const double2* val,
                              const double2* x, double2* y, hipStream_t st);
+// Reconstruction of the interior unknowns: load of D M1 D with the row
+// (D (l_u - M2 t_K))^H appended, and the backward substitution after the
+// factorisation (launch_factor on the reconstruction tables).
+hipError_t launch_recon_load(const DevTables& t, const ChunkArgs& ca, const CondArgs& a, hipStream_t st);
+hipError_t launch_recon_back(const DevTables& t, const ChunkArgs& ca, const CondArgs& a, hipStream_t st);
+// out[i] = t[glob[i]] (0 where glob[i] < 0)
+hipError_t launch_scatter(int64_t n, const int64_t* glob, const double2* t, double2* out, hipStream_t st);
+// CG: doubles of the partial-sum buffer for n unknowns; r = b - A x, p = r and
+// the start scalars (sc[CG_TOL2] and sc[CG_DONE] = 0 set by the caller); then
+// `count` iterations
+int64_t cg_part_len(int64_t n);
+hipError_t launch_cg_start(const CgArgs& g, hipStream_t st);
+hipError_t launch_cg_iterations(const CgArgs& g, int64_t count, hipStream_t st);
 // doubles of per-point metrics kept per cell (ChunkArgs::met)
 __host__ __device__ inline int64_t met_stride(const DevTables& t) { return 30 * (int64_t)t.nq + 36 * (int64_t)t.nfq; }
 // real copy of the factorised F block (the leading 64 floor(Np/64) rows and

@@ -25,7 +25,7 @@ EXPORTS = ("dpg_local_dims", "dpg_plan_create", "dpg_plan_destroy", "dpg_plan_of
            "dpg_plan_tuning", "dpg_graph_create", "dpg_graph_launch", "dpg_graph_destroy", "dpg_form_local",
            "dpg_plan_trace_offsets", "dpg_condense", "dpg_trace_numbering", "dpg_trace_system_create",
            "dpg_trace_system_destroy", "dpg_trace_system_info", "dpg_trace_system_numbering", "dpg_trace_system_csr",
-           "dpg_assemble", "dpg_csr_matvec",
+           "dpg_assemble", "dpg_csr_matvec", "dpg_cg_solve", "dpg_trace_system_scatter", "dpg_reconstruct",
            "dpg_plan_set_profiling", "dpg_plan_profile", "dpg_status_string", "dpg_last_error")
 KERNEL_CLASSES = ("scale", "form_SM", "form_IF", "form_pad", "form_B", "form_load", "resid", "chol_diag",
                   "chol_panel", "herk")
@@ -82,6 +82,9 @@ def lib():
         L.dpg_trace_system_csr.argtypes = [vp, C.POINTER(vp), C.POINTER(vp)]
         L.dpg_assemble.argtypes = [vp, vp, vp, vp, vp, vp]
         L.dpg_csr_matvec.argtypes = [i64, vp, vp, vp, vp, vp, vp]
+        L.dpg_cg_solve.argtypes = [i64, vp, vp, vp, vp, vp, dp_, i64, C.POINTER(i64), C.POINTER(dp_), vp]
+        L.dpg_trace_system_scatter.argtypes = [vp, vp, vp, vp]
+        L.dpg_reconstruct.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.dpg_plan_set_profiling.argtypes = [vp, i32]
         L.dpg_plan_profile.argtypes = [vp, vp, vp]
         L.dpg_status_string.argtypes = [i32]
@@ -273,6 +276,18 @@ class Plan:
                "dpg_condense")
         return A, b, info
 
+    def reconstruct(self, K, l, t_local, x=None, stream=None):
+        """dpg_reconstruct: (x, info) with x = [u_K ; t_K] per cell (the layout
+        of a solve's x) from a solve's K_e, l_e and the local traces."""
+        import torch
+        dev = K.device
+        if x is None:
+            x = torch.empty(max(int(self.v_off[-1]), 1), dtype=torch.complex128, device=dev)
+        info = torch.empty(max(self.n_cells, 1), dtype=torch.int32, device=dev)
+        _check(lib().dpg_reconstruct(self._h, _ptr(K), _ptr(l), _ptr(t_local), _ptr(x), _ptr(info), _stream(stream)),
+               "dpg_reconstruct")
+        return x, info
+
     def range_sizes(self, first: int, count: int):
         """(K elements, l/x elements) of the outputs of a range solve."""
         return (int(self.K_off[first + count] - self.K_off[first]), int(self.v_off[first + count] - self.v_off[first]))
@@ -306,6 +321,17 @@ def trace_numbering(cells, face_kind, degree):
     _check(lib().dpg_trace_numbering(cells.ctypes.data, fk.ctypes.data, deg.ctypes.data, int(deg.shape[0]),
                                      glob.ctypes.data, C.byref(n)), "dpg_trace_numbering")
     return glob[:total], n.value
+
+
+def cg_solve(n_rows: int, row_ptr, col, vals, b, x, tol: float, max_iter: int, stream=None):
+    """dpg_cg_solve on a device CSR system (row_ptr, col: tensors or raw device
+    addresses).  x: start in, last iterate out.  Returns (iterations, ||r|| / ||b||)."""
+    it, rr = C.c_int64(), C.c_double()
+    rp = row_ptr if isinstance(row_ptr, int) else _ptr(row_ptr)
+    cl = col if isinstance(col, int) else _ptr(col)
+    _check(lib().dpg_cg_solve(int(n_rows), rp, cl, _ptr(vals), _ptr(b), _ptr(x), float(tol), int(max_iter),
+                              C.byref(it), C.byref(rr), _stream(stream)), "dpg_cg_solve")
+    return it.value, rr.value
 
 
 class TraceSystem:
@@ -343,6 +369,21 @@ class TraceSystem:
     def matvec(self, vals, x, y, stream=None):
         _check(lib().dpg_csr_matvec(self.n_dofs, self.row_ptr_ptr, self.col_ptr, _ptr(vals), _ptr(x), _ptr(y),
                                     _stream(stream)), "dpg_csr_matvec")
+
+    def scatter(self, t, t_local=None, stream=None):
+        """dpg_trace_system_scatter: the cells' local traces (b_off layout) from the global vector t."""
+        import torch
+        if t_local is None:
+            total = int(self._plan.trace_offsets()[1][-1])
+            t_local = torch.empty(max(total, 1), dtype=torch.complex128, device=t.device)
+        _check(lib().dpg_trace_system_scatter(self._h, _ptr(t), _ptr(t_local), _stream(stream)),
+               "dpg_trace_system_scatter")
+        return t_local
+
+    def solve(self, vals, rhs, x, tol: float, max_iter: int, stream=None):
+        """CG on the assembled system (dpg_cg_solve); x: start in, solution out.
+        Returns (iterations, relative residual)."""
+        return cg_solve(self.n_dofs, self.row_ptr_ptr, self.col_ptr, vals, rhs, x, tol, max_iter, stream)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -1,0 +1,240 @@
+"""GPU parity of the global solve (§2.3, Algorithm 1): CG on the condensed
+trace system, the trace scatter and the reconstruction of the interior
+unknowns, through the C ABI, against the FP64 oracle.
+
+* CG on seeded synthetic sparse Hermitian positive definite systems
+  (Gershgorin-dominant, so the conditioning is known): the same iteration
+  count as the oracle's CG (+-1: the reductions round in another order), the
+  same iterate to 1e-10, the same residual history where capped, bitwise
+  reproducible; the edge cases b = 0, a start that already passes, n = 0.
+* Reconstruction on seeded synthetic cell matrices of every degree 1..4:
+  against the oracle per cell, bar max(1e-12, 4 kappa(D M1 D) u).
+* End to end on the 2x2x2 cube (p = 1) and a 2x2x2 piece of the WR340 guide
+  (p = 2): local solve, condensation, assembly, CG to 1e-12, scatter,
+  reconstruction and the residual indicator of the global solution, against
+  the oracle's own pipeline (its K_e, condensation, assembly and a dense
+  solve).  Two FP64 pipelines whose cell matrices agree to the local-solve
+  bar (1e-10 or the kappa u floor) give traces that agree to cond(A) times
+  that bar; the test takes 4 cond(A) (1e-10 + 1e-12) with cond(A) computed
+  from the oracle's matrix.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2609_03155_amd import workloads as W
+
+from _oracle_cases import oracle_cell, rel
+
+pytestmark = pytest.mark.gpu
+
+U64 = 2.0 ** -53
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _synthetic_hpd(n, per_row, dom, seed):
+    """Sparse complex Hermitian matrix, diagonal dom x (row sum of |off-diagonal|) + 1."""
+    import scipy.sparse as sps
+    rng = np.random.default_rng(seed)
+    rows = np.repeat(np.arange(n), per_row)
+    cols = rng.integers(0, n, n * per_row)
+    vals = rng.standard_normal(n * per_row) + 1j * rng.standard_normal(n * per_row)
+    S = sps.coo_matrix((vals, (rows, cols)), shape=(n, n)).tocsr()
+    H = (S + S.conj().T).tolil()
+    H.setdiag(0)
+    H = H.tocsr()
+    H.eliminate_zeros()
+    d = np.asarray(abs(H).sum(axis=1)).ravel()
+    A = (H + sps.diags(dom * d + 1.0)).tocsr()
+    A.sum_duplicates()
+    A.sort_indices()
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    return A, b
+
+
+def _device_csr(A):
+    torch = _torch()
+    rp = torch.from_numpy(A.indptr.astype(np.int64)).cuda()
+    cl = torch.from_numpy(A.indices.astype(np.int32)).cuda()
+    vv = torch.from_numpy(A.data.astype(np.complex128)).cuda()
+    return rp, cl, vv
+
+
+def _gpu_cg(A, b, tol, max_iter, x0=None):
+    torch = _torch()
+    from paper_2609_03155_amd import dpg
+    rp, cl, vv = _device_csr(A)
+    bd = torch.from_numpy(b).cuda()
+    xd = torch.zeros_like(bd) if x0 is None else torch.from_numpy(x0.copy()).cuda()
+    it, rr = dpg.cg_solve(A.shape[0], rp, cl, vv, bd, xd, tol, max_iter)
+    torch.cuda.synchronize()
+    return xd.cpu().numpy(), it, rr
+
+
+@pytest.mark.parametrize("n,per_row,dom", [(3000, 6, 1.05), (20000, 12, 1.005)])
+def test_cg_matches_oracle_on_synthetic_systems(n, per_row, dom):
+    from oracle import dpg_assembly as OA
+    _say(f"case: dpg_cg_solve synthetic n={n} per_row={per_row} dom={dom}")
+    A, b = _synthetic_hpd(n, per_row, dom, W.SEED_BASE + n)
+    xo, ito, hist = OA.cg(A, b, 1e-12, 5000)
+    xg, itg, rrg = _gpu_cg(A, b, 1e-12, 5000)
+    assert abs(itg - ito) <= 1, (itg, ito)
+    assert rrg <= 1e-12
+    assert rel(xg, xo) <= 1e-10, rel(xg, xo)
+    assert np.linalg.norm(A @ xg - b) <= 2e-12 * np.linalg.norm(b)
+    # bitwise reproducible
+    xg2, itg2, rrg2 = _gpu_cg(A, b, 1e-12, 5000)
+    assert itg2 == itg and rrg2 == rrg and np.array_equal(xg2, xg)
+    # capped: the same iterate and residual history entry as the oracle's
+    for cap in (1, 7):
+        xo_c, _, hist_c = OA.cg(A, b, 0.0, cap)
+        xg_c, itg_c, rrg_c = _gpu_cg(A, b, 0.0, cap)
+        assert itg_c == cap
+        assert abs(rrg_c - hist_c[-1]) <= 1e-10 * hist_c[-1]
+        assert rel(xg_c, xo_c) <= 1e-12
+
+
+def test_cg_edge_cases():
+    torch = _torch()
+    from paper_2609_03155_amd import dpg
+    _say("case: dpg_cg_solve edge cases (b = 0, converged start, n = 0, bad arguments)")
+    A, b = _synthetic_hpd(500, 5, 1.1, W.SEED_BASE + 500)
+    x0 = np.linalg.solve(A.toarray(), b)
+    # b = 0: nothing to do, x unchanged
+    xg, it, rr = _gpu_cg(A, np.zeros_like(b), 1e-10, 100, x0=x0)
+    assert it == 0 and rr == 0.0 and np.array_equal(xg, x0)
+    # a start that already passes the test
+    xg, it, rr = _gpu_cg(A, b, 1e-8, 100, x0=x0)
+    assert it == 0 and rr <= 1e-8 and np.array_equal(xg, x0)
+    # max_iter = 0
+    xg, it, rr = _gpu_cg(A, b, 1e-8, 0)
+    assert it == 0 and abs(rr - 1.0) <= 1e-15 and not np.any(xg)
+    # n = 0
+    it, rr = dpg.cg_solve(0, 0, 0, None, None, None, 1e-8, 10)
+    assert it == 0 and rr == 0.0
+    rp, cl, vv = _device_csr(A)
+    bd = torch.from_numpy(b).cuda()
+    xd = torch.zeros_like(bd)
+    for bad in (dict(tol=-1.0), dict(tol=float("nan")), dict(max_iter=-1)):
+        kw = dict(tol=1e-8, max_iter=10)
+        kw.update(bad)
+        with pytest.raises(dpg.DPGError):
+            dpg.cg_solve(A.shape[0], rp, cl, vv, bd, xd, kw["tol"], kw["max_iter"])
+
+
+def _kappa_tol(M, floor):
+    d = 1.0 / np.sqrt(np.real(np.diag(M)))
+    ev = np.linalg.eigvalsh(d[:, None] * M * d[None, :])
+    return max(floor, 4.0 * ev.max() / ev.min() * U64)
+
+
+def test_reconstruction_matches_oracle_on_synthetic_cells():
+    torch = _torch()
+    from oracle import dpg_assembly as OA
+    from paper_2609_03155_amd import dpg
+    degree = np.array([1, 2, 3, 4, 2, 1, 3], np.int8)
+    _say(f"case: dpg_reconstruct synthetic cells p={degree.tolist()}")
+    plan = dpg.Plan(degree, 1)
+    A_off, b_off = plan.trace_offsets()
+    rng = np.random.default_rng(W.SEED_BASE + 41)
+    Kh = np.zeros(int(plan.K_off[-1]), complex)
+    lh = np.zeros(int(plan.v_off[-1]), complex)
+    th = np.zeros(int(b_off[-1]), complex)
+    cells = []
+    for c, p in enumerate(degree):
+        nu, nt = 6 * (int(p) + 1) ** 3, 24 * (int(p) + 1) ** 2
+        k = nu + nt
+        X = rng.standard_normal((k, k)) + 1j * rng.standard_normal((k, k))
+        Kc = X @ X.conj().T / k + 0.05 * np.eye(k)
+        lc = rng.standard_normal(k) + 1j * rng.standard_normal(k)
+        tc = rng.standard_normal(nt) + 1j * rng.standard_normal(nt)
+        Kh[plan.K_off[c]:plan.K_off[c + 1]] = Kc.T.ravel()
+        lh[plan.v_off[c]:plan.v_off[c + 1]] = lc
+        th[b_off[c]:b_off[c + 1]] = tc
+        cells.append((Kc, lc, tc, nu))
+    K, l, t = (torch.from_numpy(a).cuda() for a in (Kh, lh, th))
+    x, info = plan.reconstruct(K, l, t)
+    torch.cuda.synchronize()
+    xh, ih = x.cpu().numpy(), info.cpu().numpy()
+    assert np.all(ih[:len(degree)] == 0)
+    for c, (Kc, lc, tc, nu) in enumerate(cells):
+        xo = OA.reconstruct(Kc, lc, nu, tc)
+        xg = xh[plan.v_off[c]:plan.v_off[c + 1]]
+        tol = _kappa_tol(Kc[:nu, :nu], 1e-12)
+        assert rel(xg[:nu], xo[:nu]) <= tol, (c, rel(xg[:nu], xo[:nu]), tol)
+        assert np.array_equal(xg[nu:], tc)
+    plan.close()
+
+
+def _oracle_pipeline(w):
+    from oracle import dpg_assembly as OA
+    from oracle import dpg_oracle as O
+    cells = []
+    for c in range(w.n_cells):
+        G, Bf, l, K, le, _ = oracle_cell(w, c)
+        cells.append((G, Bf, l, K, le, 6 * (int(w.degree[c]) + 1) ** 3))
+    cond = [OA.condense(K, le, nu) for (_, _, _, K, le, nu) in cells]
+    glob, n = OA.trace_numbering(w.cells, w.face_kind, w.degree)
+    Ao, bo = OA.assemble([a for a, _ in cond], [b for _, b in cond], glob, n)
+    Ad = Ao.toarray()
+    to = np.linalg.solve(Ad, bo)
+    ev = np.linalg.eigvalsh(Ad)
+    xs, etas = [], []
+    for (G, Bf, l, K, le, nu), g in zip(cells, glob):
+        x = OA.reconstruct(K, le, nu, OA.scatter(to, g))
+        xs.append(x)
+        etas.append(O.local_solve(G, Bf, l, x)[2])
+    return to, xs, np.array(etas), ev.max() / ev.min()
+
+
+@pytest.mark.parametrize("wname", ["config1", "config2_2x2x2"])
+def test_global_solve_end_to_end_matches_oracle(wname):
+    torch = _torch()
+    from paper_2609_03155_amd import dpg
+    w = W.config1() if wname == "config1" else W.config2(nx=2, ny=2, nz=2)
+    _say(f"case: global solve end to end on {w.name}")
+    plan = dpg.Plan(w.degree, w.dp)
+    prob = dpg.DeviceProblem.from_workload(w)
+    K, l, eta, info = plan.alloc_outputs()
+    plan.local_solve(prob, None, K, l, eta, info)
+    A, b, cinfo = plan.condense(K, l)
+    sys_ = dpg.TraceSystem(plan, w.cells, w.face_kind)
+    vals, rhs = sys_.assemble(A, b)
+    t = torch.zeros(sys_.n_dofs, dtype=torch.complex128, device="cuda")
+    it, rr = sys_.solve(vals, rhs, t, 1e-12, 100000)
+    _say(f"  CG: {it} iterations, relres {rr:.3e}")
+    tl = sys_.scatter(t)
+    x, rinfo = plan.reconstruct(K, l, tl)
+    K2, l2, eta2, info2 = plan.alloc_outputs()
+    plan.local_solve(prob, x, K2, l2, eta2, info2)
+    torch.cuda.synchronize()
+    assert rr <= 1e-12
+    assert np.all(cinfo.cpu().numpy()[:w.n_cells] == 0) and np.all(rinfo.cpu().numpy()[:w.n_cells] == 0)
+    to, xo, etao, cond = _oracle_pipeline(w)
+    tol = 4.0 * cond * (1e-10 + 1e-12)
+    tg = t.cpu().numpy()
+    _say(f"  cond(A) {cond:.3e}: traces rel {rel(tg, to):.3e}, bar {tol:.3e}")
+    assert rel(tg, to) <= tol
+    xh = x.cpu().numpy()
+    eg = eta2.cpu().numpy()
+    worst = 0.0
+    for c in range(w.n_cells):
+        xg = xh[plan.v_off[c]:plan.v_off[c + 1]]
+        worst = max(worst, rel(xg, xo[c]))
+        assert rel(xg, xo[c]) <= tol, (c, rel(xg, xo[c]))
+        assert abs(eg[c] - etao[c]) <= tol * max(etao[c], 1e-300), (c, eg[c], etao[c])
+    _say(f"  cell vectors worst rel {worst:.3e}; eta of the global solution {eg[:w.n_cells].min():.3e}..{eg[:w.n_cells].max():.3e}")
+    sys_.close()
+    plan.close()
