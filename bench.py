@@ -128,6 +128,10 @@ def trace_system_timings(w, plan, prob, xd, K, l, eta, info, solve, stream, reps
     e1.record(stream)
     torch.cuda.synchronize()
     cg_ms = e0.elapsed_time(e1) / max(cg_it, 1)
+    # the true residual of the last iterate, against the recursively updated one
+    ts.matvec(vals, t, y, stream=stream)
+    torch.cuda.synchronize()
+    cg_true = float(torch.linalg.vector_norm(rhs[:ts.n_dofs] - y[:ts.n_dofs]) / torch.linalg.vector_norm(rhs[:ts.n_dofs]))
     # per iteration: the matvec, x, p, r, q read and x, r written by the update, r, p read and p written
     cg_bytes = mv_bytes + 9 * 16 * ts.n_dofs
     tl = ts.scatter(t, stream=stream)
@@ -152,7 +156,7 @@ def trace_system_timings(w, plan, prob, xd, K, l, eta, info, solve, stream, reps
         "spmv_GBps": mv_bytes / (mv_ms * 1e-3) / 1e9,
         "spmv_frac_hbm": mv_bytes / (mv_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
         "spmv_bytes_note": "algorithmic: 16 B value + 4 B column per nonzero, row pointers, x and y once",
-        "cg_iterations": cg_it, "cg_relres": cg_rr, "cg_ms_per_iteration": cg_ms,
+        "cg_iterations": cg_it, "cg_relres": cg_rr, "cg_true_relres": cg_true, "cg_ms_per_iteration": cg_ms,
         "cg_GBps": cg_bytes / (cg_ms * 1e-3) / 1e9,
         "cg_frac_hbm": cg_bytes / (cg_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
         "cg_bytes_note": "per iteration: the matvec's algorithmic bytes plus 9 complex vectors of n (update, direction)",

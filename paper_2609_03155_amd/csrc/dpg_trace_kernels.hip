@@ -190,26 +190,39 @@ __global__ __launch_bounds__(NT) void k_cg_matvec_dot(int64_t n, const int64_t* 
   if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// Thread t's share of a fixed-order sum: part[t], part[t + RNT], ... added in
+// that order, the loads issued eight at a time (the partial sums of the
+// matvec are n / 4 doubles, which one workgroup reads).
+constexpr int RNT = 1024;
+__device__ __forceinline__ double strided_sum(const double* __restrict__ part, int64_t m) {
+  double v = 0.0;
+  int64_t i = threadIdx.x;
+  for (; i + 7 * (int64_t)RNT < m; i += 8 * (int64_t)RNT) {
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = part[i + (int64_t)u * RNT];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v += t[u];
+  }
+  for (; i < m; i += RNT) v += part[i];
+  return v;
+}
+
 // One workgroup: s = sum of part[0, m) in a fixed order, then
 //   MODE 0 (alpha):  alpha = rr / s  (0 if s <= 0: no further progress);
 //   MODE 1 (beta):   rr_new = s, beta = rr_new / rr, rr = rr_new, count the
 //                    iteration and set the flag once rr <= tol^2 ||b||^2;
 //   MODE 2 (start):  rr = s, ||b||^2 = part[m, 2m) summed likewise, flag set if
 //                    the start already satisfies the test.
-constexpr int RNT = 1024;
 template <int MODE>
 __global__ __launch_bounds__(RNT) void k_cg_scalar(const double* __restrict__ part, int64_t m, double* __restrict__ sc) {
   __shared__ double red[RNT];
   if (cg_done(sc)) return;
-  double v = 0.0;
-  for (int64_t i = threadIdx.x; i < m; i += RNT) v += part[i];
-  const double s = block_sum<RNT>(v, red);
+  const double s = block_sum<RNT>(strided_sum(part, m), red);
   double sb = 0.0;
   if (MODE == 2) {
     __syncthreads();
-    double w = 0.0;
-    for (int64_t i = threadIdx.x; i < m; i += RNT) w += part[m + i];
-    sb = block_sum<RNT>(w, red);
+    sb = block_sum<RNT>(strided_sum(part + m, m), red);
   }
   if (threadIdx.x != 0) return;
   if (MODE == 0) {
@@ -493,8 +506,10 @@ hipError_t launch_scatter(int64_t n, const int64_t* glob, const double2* t, doub
   return hipGetLastError();
 }
 
+int64_t cg_mv_blocks(int64_t n) { return (n + NT / 64 - 1) / (NT / 64); }
+
 int64_t cg_part_len(int64_t n) {
-  const int64_t nmv = (n + NT / 64 - 1) / (NT / 64), nv = (n + VCHUNK - 1) / VCHUNK;
+  const int64_t nmv = cg_mv_blocks(n), nv = (n + VCHUNK - 1) / VCHUNK;
   return std::max<int64_t>(nmv, 2 * nv) + 1;
 }
 
@@ -509,7 +524,7 @@ hipError_t launch_cg_start(const CgArgs& g, hipStream_t st) {
 
 hipError_t launch_cg_iterations(const CgArgs& g, int64_t count, hipStream_t st) {
   const int64_t n = g.n;
-  const unsigned nmv = (unsigned)((n + NT / 64 - 1) / (NT / 64)), nv = (unsigned)((n + VCHUNK - 1) / VCHUNK);
+  const unsigned nmv = (unsigned)cg_mv_blocks(n), nv = (unsigned)((n + VCHUNK - 1) / VCHUNK);
   for (int64_t it = 0; it < count; ++it) {
     hipLaunchKernelGGL(k_cg_matvec_dot, dim3(nmv), dim3(NT), 0, st, n, g.row_ptr, g.col, g.val, g.p, g.q, g.part, g.sc);
     hipLaunchKernelGGL(k_cg_scalar<0>, dim3(1), dim3(RNT), 0, st, g.part, (int64_t)nmv, g.sc);
