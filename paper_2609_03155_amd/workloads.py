@@ -110,6 +110,19 @@ def _robin_admittance(fk, y):
     return z
 
 
+def waveguide_te10(n: int, p: int, a: float = 0.25, b: float = 0.25, length: float = 1.0,
+                   freq_hz: float = 2.45e9) -> Workload:
+    """The §4.1 verification guide: a x b x length (0.25 x 0.25 x 1 m), vacuum,
+    n x n x 4n uniform hexes of degree p, dp = 1, PEC walls, TE10 port at
+    x3 = 0 and the matched impedance outlet at x3 = length."""
+    V, cells, fk, _ = box_mesh(n, n, 4 * n, a, b, length)
+    nc = cells.shape[0]
+    y = port_admittance(a, b, 1, 0, freq_hz)
+    return Workload(f"te10_{n}x{n}x{4 * n}_p{p}", V, cells, np.ones(nc, np.complex128), np.ones(nc, np.complex128),
+                    np.full(nc, p, np.int8), fk, _robin_admittance(fk, y), 1, freq_hz,
+                    dict(a=a, b=b, m=1, n=0, eps=1.0, mu=1.0), (n, n, 4 * n))
+
+
 def config1() -> Workload:
     """2x2x2 affine mesh of a 0.1 m cube, p=1, dp=1, 2.45 GHz; eps = 1 except
     the cell at the port corner, eps = 4 - 0.5i quoted => 4 + 0.5i here."""
