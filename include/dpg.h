@@ -366,6 +366,24 @@ dpg_status dpg_trace_system_scatter(dpg_trace_system sys, const double* t, doubl
 dpg_status dpg_reconstruct(dpg_plan plan, const double* K, const double* l, const double* t_local, double* x,
                            int32_t* info, void* stream);
 
+/* Dörfler marking for adaptive refinement (Sec. 4.2, the Fichera case, and
+ * its refinement table: fractions 0.30 and 0.05).  values [n] (device,
+ * finite, >= 0): one indicator per cell, e.g. the residual norm eta of a
+ * dpg_local_solve (or its square, for marking by eta^2).  Cells are ranked by
+ * decreasing value, equal values by increasing cell index; with T the sum of
+ * all values and S the sum of those ranked before a cell,
+ *   flags[i] = +1 (refine)  if S < refine_fraction T,
+ *            = -1 (coarsen) if not refined and T - S <= coarsen_fraction T,
+ *            =  0 otherwise
+ * (flags [n], device, int8): the shortest prefix of the ranking that carries
+ * refine_fraction of the total is refined, the longest run of the smallest
+ * values within coarsen_fraction of it is coarsened.  The sums run in a fixed
+ * order, so equal inputs give equal flags.  Allocates temporaries (about
+ * 40 n bytes) and returns after synchronising `stream`.  DPG_ERR_ARG for
+ * n < 0, null pointers or fractions outside [0, 1]. */
+dpg_status dpg_dorfler_mark(int64_t n, const double* values, double refine_fraction, double coarsen_fraction,
+                            int8_t* flags, void* stream);
+
 /* Kernel classes timed by the plan's optional profiler. */
 enum {
   DPG_K_SCALE = 0,      /* geometry check and Jacobi scaling            */

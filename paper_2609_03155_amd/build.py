@@ -12,8 +12,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdpgmi.so")
-SOURCES = ["csrc/dpg_kernels.hip", "csrc/dpg_trace_kernels.hip", "csrc/dpg_api.cpp", "csrc/dpg_tables.cpp",
-           "csrc/dpg_trace.cpp"]
+SOURCES = ["csrc/dpg_kernels.hip", "csrc/dpg_trace_kernels.hip", "csrc/dpg_marking.hip", "csrc/dpg_api.cpp",
+           "csrc/dpg_tables.cpp", "csrc/dpg_trace.cpp"]
 
 # Packed FP32 instructions are disabled for every device compilation.
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

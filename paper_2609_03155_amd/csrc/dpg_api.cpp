@@ -949,6 +949,22 @@ dpg_status dpg_cg_solve(int64_t n_rows, const int64_t* row_ptr, const int32_t* c
   return rc;
 }
 
+dpg_status dpg_dorfler_mark(int64_t n, const double* values, double refine_fraction, double coarsen_fraction,
+                            int8_t* flags, void* stream) {
+  if (n < 0 || !(refine_fraction >= 0.0 && refine_fraction <= 1.0) ||
+      !(coarsen_fraction >= 0.0 && coarsen_fraction <= 1.0))
+    return DPG_ERR_ARG;
+  if (n == 0) return DPG_OK;
+  if (!values || !flags) return DPG_ERR_ARG;
+  const hipError_t e =
+      dpg::dorfler_mark(n, values, refine_fraction, coarsen_fraction, flags, reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) {
+    set_error("dpg_dorfler_mark", e);
+    return DPG_ERR_HIP;
+  }
+  return DPG_OK;
+}
+
 dpg_status dpg_reconstruct(dpg_plan plan, const double* K, const double* l, const double* t_local, double* x,
                            int32_t* info, void* stream) {
   if (!plan) return DPG_ERR_ARG;

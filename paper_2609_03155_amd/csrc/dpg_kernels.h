@@ -159,6 +159,9 @@ hipError_t launch_scatter(int64_t n, const int64_t* glob, const double2* t, doub
 int64_t cg_part_len(int64_t n);
 hipError_t launch_cg_start(const CgArgs& g, hipStream_t st);
 hipError_t launch_cg_iterations(const CgArgs& g, int64_t count, hipStream_t st);
+// Dörfler marking: flags[i] = +1 (refine), -1 (coarsen) or 0 from values[i]
+// (n cells); allocates its temporaries and synchronises the stream.
+hipError_t dorfler_mark(int64_t n, const double* values, double fr, double fc, int8_t* flags, hipStream_t st);
 // doubles of per-point metrics kept per cell (ChunkArgs::met)
 __host__ __device__ inline int64_t met_stride(const DevTables& t) { return 30 * (int64_t)t.nq + 36 * (int64_t)t.nfq; }
 // real copy of the factorised F block (the leading 64 floor(Np/64) rows and

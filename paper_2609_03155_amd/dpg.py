@@ -26,6 +26,7 @@ EXPORTS = ("dpg_local_dims", "dpg_plan_create", "dpg_plan_destroy", "dpg_plan_of
            "dpg_plan_trace_offsets", "dpg_condense", "dpg_trace_numbering", "dpg_trace_system_create",
            "dpg_trace_system_destroy", "dpg_trace_system_info", "dpg_trace_system_numbering", "dpg_trace_system_csr",
            "dpg_assemble", "dpg_csr_matvec", "dpg_cg_solve", "dpg_trace_system_scatter", "dpg_reconstruct",
+           "dpg_dorfler_mark",
            "dpg_plan_set_profiling", "dpg_plan_profile", "dpg_status_string", "dpg_last_error")
 KERNEL_CLASSES = ("scale", "form_SM", "form_IF", "form_pad", "form_B", "form_load", "resid", "chol_diag",
                   "chol_panel", "herk")
@@ -85,6 +86,7 @@ def lib():
         L.dpg_cg_solve.argtypes = [i64, vp, vp, vp, vp, vp, dp_, i64, C.POINTER(i64), C.POINTER(dp_), vp]
         L.dpg_trace_system_scatter.argtypes = [vp, vp, vp, vp]
         L.dpg_reconstruct.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.dpg_dorfler_mark.argtypes = [i64, vp, dp_, dp_, vp, vp]
         L.dpg_plan_set_profiling.argtypes = [vp, i32]
         L.dpg_plan_profile.argtypes = [vp, vp, vp]
         L.dpg_status_string.argtypes = [i32]
@@ -332,6 +334,18 @@ def cg_solve(n_rows: int, row_ptr, col, vals, b, x, tol: float, max_iter: int, s
     _check(lib().dpg_cg_solve(int(n_rows), rp, cl, _ptr(vals), _ptr(b), _ptr(x), float(tol), int(max_iter),
                               C.byref(it), C.byref(rr), _stream(stream)), "dpg_cg_solve")
     return it.value, rr.value
+
+
+def dorfler_mark(values, refine_fraction: float = 0.30, coarsen_fraction: float = 0.05, flags=None, stream=None):
+    """dpg_dorfler_mark: int8 device flags (+1 refine, -1 coarsen, 0 keep) from
+    the float64 device tensor `values` (one indicator per cell)."""
+    import torch
+    n = int(values.numel())
+    if flags is None:
+        flags = torch.empty(max(n, 1), dtype=torch.int8, device=values.device)
+    _check(lib().dpg_dorfler_mark(n, _ptr(values), float(refine_fraction), float(coarsen_fraction), _ptr(flags),
+                                  _stream(stream)), "dpg_dorfler_mark")
+    return flags
 
 
 class TraceSystem:
