@@ -141,6 +141,14 @@ def trace_system_timings(w, plan, prob, xd, K, l, eta, info, solve, stream, reps
         rec_out["r"] = plan.reconstruct(K, l, tl, stream=stream)
     rec_ms = timed_ms(do_rec, reps)
     rinfo = rec_out["r"][1]
+    # Doerfler marking of the workload's eta (sort, scans, flags; synchronous, allocates)
+    ev = eta[:w.n_cells].contiguous()
+    dpg.dorfler_mark(ev, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dpg.dorfler_mark(ev, stream=stream)
+    mark_ms = (time.perf_counter() - t0) / reps * 1e3
     rfl = 0.0
     for p in sorted(set(int(v) for v in w.degree)):
         cnt = int(np.sum(w.degree == p))
@@ -162,6 +170,7 @@ def trace_system_timings(w, plan, prob, xd, K, l, eta, info, solve, stream, reps
         "cg_bytes_note": "per iteration: the matvec's algorithmic bytes plus 9 complex vectors of n (update, direction)",
         "reconstruct_ms": rec_ms, "reconstruct_tflops": rfl / (rec_ms * 1e-3) / 1e12,
         "reconstruct_failed_cells": int(np.sum(rinfo.cpu().numpy()[:w.n_cells] != 0)),
+        "dorfler_mark_ms": mark_ms,
     })
     ts.close()
     del A, b, vals, rhs, t, tl, rec_out
