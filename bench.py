@@ -141,6 +141,13 @@ def trace_system_timings(w, plan, prob, xd, K, l, eta, info, solve, stream, reps
         rec_out["r"] = plan.reconstruct(K, l, tl, stream=stream)
     rec_ms = timed_ms(do_rec, reps)
     rinfo = rec_out["r"][1]
+    # power dissipation of the reconstructed fields
+    xr = rec_out["r"][0]
+    pw = {}
+
+    def do_pw():
+        pw["r"] = plan.power_dissipation(prob, xr, stream=stream)
+    pw_ms = timed_ms(do_pw, reps)
     # Doerfler marking of the workload's eta (sort, scans, flags; synchronous, allocates)
     ev = eta[:w.n_cells].contiguous()
     dpg.dorfler_mark(ev, stream=stream)
@@ -171,9 +178,10 @@ def trace_system_timings(w, plan, prob, xd, K, l, eta, info, solve, stream, reps
         "reconstruct_ms": rec_ms, "reconstruct_tflops": rfl / (rec_ms * 1e-3) / 1e12,
         "reconstruct_failed_cells": int(np.sum(rinfo.cpu().numpy()[:w.n_cells] != 0)),
         "dorfler_mark_ms": mark_ms,
+        "power_dissipation_ms": pw_ms,
     })
     ts.close()
-    del A, b, vals, rhs, t, tl, rec_out
+    del A, b, vals, rhs, t, tl, rec_out, pw, xr
     return out
 
 

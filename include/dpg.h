@@ -366,6 +366,21 @@ dpg_status dpg_trace_system_scatter(dpg_trace_system sys, const double* t, doubl
 dpg_status dpg_reconstruct(dpg_plan plan, const double* K, const double* l, const double* t_local, double* x,
                            int32_t* info, void* stream);
 
+/* Electromagnetic power dissipated in every cell (Sec. 3.3: the heat source
+ * Q_em = sigma |E|^2/2 + omega eps0 eps_im |E|^2/2 + omega mu0 mu_im |H|^2/2,
+ * the time average of minus the divergence of the Poynting vector), from the
+ * cells' coefficient vectors x (device, complex, the v_off layout of a
+ * dpg_local_solve's x, e.g. dpg_reconstruct's output; only the interior
+ * part [E_x, E_y, E_z, H_x, H_y, H_z] is read).  In the non-dimensional
+ * variables (lengths in units of L, E in units of E0, H of E0/Z0,
+ * omega = 2 pi f L / c0, conductivity inside eps_im) the density is
+ * q = omega (eps_im |E|^2 + mu_im |H|^2) / 2 and Q_em = q E0^2 / (Z0 L).
+ * power [n_cells][3] (device): the cell integrals of q, |E|^2 and |H|^2, by
+ * the volume Gauss rule of the local solve (exact for them on trilinear
+ * cells).  Stream-ordered. */
+dpg_status dpg_power_dissipation(dpg_plan plan, const dpg_problem* prob, const double* x, double* power,
+                                 void* stream);
+
 /* Dörfler marking for adaptive refinement (Sec. 4.2, the Fichera case, and
  * its refinement table: fractions 0.30 and 0.05).  values [n] (device,
  * finite, >= 0): one indicator per cell, e.g. the residual norm eta of a

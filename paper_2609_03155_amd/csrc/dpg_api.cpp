@@ -949,6 +949,28 @@ dpg_status dpg_cg_solve(int64_t n_rows, const int64_t* row_ptr, const int32_t* c
   return rc;
 }
 
+dpg_status dpg_power_dissipation(dpg_plan plan, const dpg_problem* prob, const double* x, double* power,
+                                 void* stream) {
+  if (!plan) return DPG_ERR_ARG;
+  dpg::ProbArgs pa;
+  if (!make_prob_args(prob, pa) || prob->n_cells != plan->n_cells) return DPG_ERR_ARG;
+  if (plan->n_cells == 0) return DPG_OK;
+  if (!x || !power) return DPG_ERR_ARG;
+  if (hipSetDevice(plan->device) != hipSuccess) return DPG_ERR_HIP;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = hipSuccess;
+  for (auto& g : plan->groups) {
+    if (e != hipSuccess) break;
+    e = dpg::launch_power(g.dt, pa, g.cells_dev, (int64_t)g.cells.size(), reinterpret_cast<const double2*>(x),
+                          plan->v_off_dev, power, st);
+  }
+  if (e != hipSuccess) {
+    set_error("dpg_power_dissipation", e);
+    return DPG_ERR_HIP;
+  }
+  return DPG_OK;
+}
+
 dpg_status dpg_dorfler_mark(int64_t n, const double* values, double refine_fraction, double coarsen_fraction,
                             int8_t* flags, void* stream) {
   if (n < 0 || !(refine_fraction >= 0.0 && refine_fraction <= 1.0) ||

@@ -159,6 +159,11 @@ hipError_t launch_scatter(int64_t n, const int64_t* glob, const double2* t, doub
 int64_t cg_part_len(int64_t n);
 hipError_t launch_cg_start(const CgArgs& g, hipStream_t st);
 hipError_t launch_cg_iterations(const CgArgs& g, int64_t count, hipStream_t st);
+// Per-cell integrals {omega (eps_im |E|^2 + mu_im |H|^2) / 2, |E|^2, |H|^2} of
+// the DG fields of x (v_off layout) into out[3 gc + .] for the n cells of one
+// degree group (table t).
+hipError_t launch_power(const DevTables& t, const ProbArgs& pa, const int64_t* cell_ids, int64_t n, const double2* x,
+                        const int64_t* v_off, double* out, hipStream_t st);
 // Dörfler marking: flags[i] = +1 (refine), -1 (coarsen) or 0 from values[i]
 // (n cells); allocates its temporaries and synchronises the stream.
 hipError_t dorfler_mark(int64_t n, const double* values, double fr, double fc, int8_t* flags, hipStream_t st);

@@ -453,7 +453,100 @@ __global__ __launch_bounds__(NT) void k_recon_back(DevTables T, ChunkArgs C, Con
   }
 }
 
+// ---------------------------------------------------------------- power dissipation
+// Per cell of a degree group (one workgroup): with E, H the DG fields of the
+// cell's coefficients x = [E_x, E_y, E_z, H_x, H_y, H_z] (Lagrange-GLL
+// functions, the table's trial basis at the volume Gauss points), the
+// integrals over the cell of |E|^2 and |H|^2 and of the dissipated power
+// density omega (eps_im |E|^2 + mu_im |H|^2) / 2, in the non-dimensional
+// variables (lengths in units of L):  out[cell] = {power, |E|^2, |H|^2}.
+__global__ __launch_bounds__(NT) void k_power(DevTables T, ProbArgs P, const int64_t* __restrict__ cell_ids, int64_t n,
+                                              const double2* __restrict__ x, const int64_t* __restrict__ v_off,
+                                              double* __restrict__ out) {
+  extern __shared__ double2 xs[];   // [6 m1] the cell's field coefficients
+  __shared__ double red[2][NT];
+  const int64_t cell = blockIdx.x;
+  if (cell >= n) return;
+  const int64_t gc = cell_ids[cell];
+  const int m1 = T.m1;
+  const double2* xc = x + v_off[gc];
+  for (int i = threadIdx.x; i < 6 * m1; i += NT) xs[i] = xc[i];
+  double X[8][3];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    const int64_t id = P.cells[8 * gc + v];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) X[v][d] = P.vertices[3 * id + d] * P.inv_len;
+  }
+  __syncthreads();
+  double se = 0.0, sh = 0.0;
+  for (int q = threadIdx.x; q < T.nq; q += NT) {
+    const double* xi = T.vol_pts + 3 * q;
+    // J_ab = dx_a / dxi_b of the trilinear map (vertex v(i,j,k) at 4k + 2j + i)
+    double J[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      const int i = v & 1, j = (v >> 1) & 1, k = v >> 2;
+      const double fx = i ? xi[0] : 1.0 - xi[0], fy = j ? xi[1] : 1.0 - xi[1], fz = k ? xi[2] : 1.0 - xi[2];
+      const double gx = i ? 1.0 : -1.0, gy = j ? 1.0 : -1.0, gz = k ? 1.0 : -1.0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        J[a][0] += gx * fy * fz * X[v][a];
+        J[a][1] += fx * gy * fz * X[v][a];
+        J[a][2] += fx * fy * gz * X[v][a];
+      }
+    }
+    const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                       J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                       J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    const double wq = T.vol_w[q] * fabs(det);
+    double fr[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, fi[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const double* ph = T.vol_phi + (int64_t)q * m1;
+    for (int a = 0; a < m1; ++a) {
+      const double f = ph[a];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const double2 u = xs[c * m1 + a];
+        fr[c] = fma(f, u.x, fr[c]);
+        fi[c] = fma(f, u.y, fi[c]);
+      }
+    }
+    double e2 = 0.0, h2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      e2 += fr[c] * fr[c] + fi[c] * fi[c];
+      h2 += fr[3 + c] * fr[3 + c] + fi[3 + c] * fi[3 + c];
+    }
+    se = fma(wq, e2, se);
+    sh = fma(wq, h2, sh);
+  }
+  red[0][threadIdx.x] = se;
+  red[1][threadIdx.x] = sh;
+  __syncthreads();
+  for (int off = NT / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + off];
+      red[1][threadIdx.x] += red[1][threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double IE = red[0][0], IH = red[1][0];
+    out[3 * gc + 0] = 0.5 * P.omega * (P.eps[2 * gc + 1] * IE + P.mu[2 * gc + 1] * IH);
+    out[3 * gc + 1] = IE;
+    out[3 * gc + 2] = IH;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_power(const DevTables& t, const ProbArgs& pa, const int64_t* cell_ids, int64_t n, const double2* x,
+                        const int64_t* v_off, double* out, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_power, dim3((unsigned)n), dim3(NT), sizeof(double2) * 6 * t.m1, st, t, pa, cell_ids, n, x, v_off,
+                     out);
+  return hipGetLastError();
+}
 
 hipError_t launch_cond_load(const DevTables& t, const ChunkArgs& ca, const CondArgs& a, hipStream_t st) {
   if (ca.n <= 0) return hipSuccess;

@@ -26,7 +26,7 @@ EXPORTS = ("dpg_local_dims", "dpg_plan_create", "dpg_plan_destroy", "dpg_plan_of
            "dpg_plan_trace_offsets", "dpg_condense", "dpg_trace_numbering", "dpg_trace_system_create",
            "dpg_trace_system_destroy", "dpg_trace_system_info", "dpg_trace_system_numbering", "dpg_trace_system_csr",
            "dpg_assemble", "dpg_csr_matvec", "dpg_cg_solve", "dpg_trace_system_scatter", "dpg_reconstruct",
-           "dpg_dorfler_mark",
+           "dpg_dorfler_mark", "dpg_power_dissipation",
            "dpg_plan_set_profiling", "dpg_plan_profile", "dpg_status_string", "dpg_last_error")
 KERNEL_CLASSES = ("scale", "form_SM", "form_IF", "form_pad", "form_B", "form_load", "resid", "chol_diag",
                   "chol_panel", "herk")
@@ -87,6 +87,7 @@ def lib():
         L.dpg_trace_system_scatter.argtypes = [vp, vp, vp, vp]
         L.dpg_reconstruct.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.dpg_dorfler_mark.argtypes = [i64, vp, dp_, dp_, vp, vp]
+        L.dpg_power_dissipation.argtypes = [vp, C.POINTER(dpg_problem), vp, vp, vp]
         L.dpg_plan_set_profiling.argtypes = [vp, i32]
         L.dpg_plan_profile.argtypes = [vp, vp, vp]
         L.dpg_status_string.argtypes = [i32]
@@ -289,6 +290,17 @@ class Plan:
         _check(lib().dpg_reconstruct(self._h, _ptr(K), _ptr(l), _ptr(t_local), _ptr(x), _ptr(info), _stream(stream)),
                "dpg_reconstruct")
         return x, info
+
+    def power_dissipation(self, prob: DeviceProblem, x, out=None, stream=None):
+        """dpg_power_dissipation: [n_cells, 3] float64 device tensor of the cell
+        integrals of the dissipated power density, |E|^2 and |H|^2."""
+        import torch
+        if out is None:
+            out = torch.empty((max(self.n_cells, 1), 3), dtype=torch.float64, device=x.device)
+        s = prob.cstruct()
+        _check(lib().dpg_power_dissipation(self._h, C.byref(s), _ptr(x), _ptr(out), _stream(stream)),
+               "dpg_power_dissipation")
+        return out
 
     def range_sizes(self, first: int, count: int):
         """(K elements, l/x elements) of the outputs of a range solve."""
