@@ -9,8 +9,9 @@ unknowns, through the C ABI, against the FP64 oracle.
   reproducible; the edge cases b = 0, a start that already passes, n = 0.
 * Reconstruction on seeded synthetic cell matrices of every degree 1..4:
   against the oracle per cell, bar max(1e-12, 4 kappa(D M1 D) u).
-* End to end on the 2x2x2 cube (p = 1) and a 2x2x2 piece of the WR340 guide
-  (p = 2): local solve, condensation, assembly, CG to 1e-12, scatter,
+* End to end on the 2x2x2 cube (p = 1), a 2x2x2 piece of the WR340 guide
+  (p = 2) and a 2x2x2 mesh of mixed degrees 1..3 (minimum rule on shared
+  edges and faces): local solve, condensation, assembly, CG to 1e-12, scatter,
   reconstruction and the residual indicator of the global solution, against
   the oracle's own pipeline (its K_e, condensation, assembly and a dense
   solve).  Two FP64 pipelines whose cell matrices agree to the local-solve
@@ -202,11 +203,18 @@ def _oracle_pipeline(w):
     return to, xs, np.array(etas), ev.max() / ev.min()
 
 
-@pytest.mark.parametrize("wname", ["config1", "config2_2x2x2"])
+def _mixed_2x2x2():
+    w = W.config3(nx=2, ny=2, nz=2)
+    w.degree[:] = np.array([1, 2, 3, 1, 2, 1, 3, 2], np.int8)
+    return w
+
+
+@pytest.mark.parametrize("wname", ["config1", "config2_2x2x2", "mixed_p1to3_2x2x2"])
 def test_global_solve_end_to_end_matches_oracle(wname):
     torch = _torch()
     from paper_2609_03155_amd import dpg
-    w = W.config1() if wname == "config1" else W.config2(nx=2, ny=2, nz=2)
+    w = {"config1": W.config1, "config2_2x2x2": lambda: W.config2(nx=2, ny=2, nz=2),
+         "mixed_p1to3_2x2x2": _mixed_2x2x2}[wname]()
     _say(f"case: global solve end to end on {w.name}")
     plan = dpg.Plan(w.degree, w.dp)
     prob = dpg.DeviceProblem.from_workload(w)
