@@ -336,7 +336,9 @@ dpg_status dpg_csr_matvec(int64_t n_rows, const int64_t* row_ptr, const int32_t*
  * iteration runs when the start already satisfies the test.  The scalars
  * stay on the device and every reduction has a fixed order (bitwise
  * reproducible); the host reads the convergence flag once per 16 iterations
- * while the next 16 are queued.  Allocates and frees 3 n_rows complex
+ * while the next 16 are queued.  A must be Hermitian positive definite and
+ * every col entry in [0, n_rows) (not checked on the device).  Allocates and
+ * frees 3 n_rows complex
  * vectors and O(n_rows / 256) partial sums on the current device; returns
  * after synchronising `stream`.  DPG_ERR_ARG for null pointers, n_rows < 0,
  * max_iter < 0 or tol < 0 (or NaN). */
@@ -395,7 +397,7 @@ dpg_status dpg_power_dissipation(dpg_plan plan, const dpg_problem* prob, const d
  * values within coarsen_fraction of it is coarsened.  The sums run in a fixed
  * order, so equal inputs give equal flags.  Allocates temporaries (about
  * 40 n bytes) and returns after synchronising `stream`.  DPG_ERR_ARG for
- * n < 0, null pointers or fractions outside [0, 1]. */
+ * n < 0 or n > 2^31 - 1, null pointers or fractions outside [0, 1]. */
 dpg_status dpg_dorfler_mark(int64_t n, const double* values, double refine_fraction, double coarsen_fraction,
                             int8_t* flags, void* stream);
 

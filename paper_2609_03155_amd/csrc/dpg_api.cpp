@@ -973,7 +973,7 @@ dpg_status dpg_power_dissipation(dpg_plan plan, const dpg_problem* prob, const d
 
 dpg_status dpg_dorfler_mark(int64_t n, const double* values, double refine_fraction, double coarsen_fraction,
                             int8_t* flags, void* stream) {
-  if (n < 0 || !(refine_fraction >= 0.0 && refine_fraction <= 1.0) ||
+  if (n < 0 || n > INT32_MAX || !(refine_fraction >= 0.0 && refine_fraction <= 1.0) ||
       !(coarsen_fraction >= 0.0 && coarsen_fraction <= 1.0))
     return DPG_ERR_ARG;
   if (n == 0) return DPG_OK;
