@@ -266,3 +266,51 @@ def test_waveguide_te10_global_solve_converges():
         rate = math.log2(r4[key] / r8[key])
         assert rate >= 2.5 and r8[key] <= 0.1, (key, r4[key], r8[key], rate)
     assert r8["eta"] < 0.5 * r4["eta"]
+
+
+def test_global_pipeline_config2_full_size_properties():
+    """The WR340 workload at full size (5120 cells, p = 2) through the global
+    pipeline, checked by properties that hold at any size: after 30 CG
+    iterations the recursively updated residual equals the true one; the
+    reconstructed cells satisfy their interior equations M1 u + M2 t = l_u
+    (sampled cells, backward-error bar); the power dissipation is finite and
+    nonnegative everywhere."""
+    torch = _torch()
+    from paper_2609_03155_amd import dpg
+    w = W.config2()
+    _say(f"case: global pipeline properties on {w.name} (full size)")
+    plan = dpg.Plan(w.degree, w.dp)
+    prob = dpg.DeviceProblem.from_workload(w)
+    K, l, eta, info = plan.alloc_outputs()
+    plan.local_solve(prob, None, K, l, eta, info)
+    A, b, cinfo = plan.condense(K, l)
+    ts = dpg.TraceSystem(plan, w.cells, w.face_kind)
+    vals, rhs = ts.assemble(A, b)
+    del A, b
+    n = ts.n_dofs
+    t = torch.zeros(n, dtype=torch.complex128, device="cuda")
+    it, rr = ts.solve(vals, rhs, t, 0.0, 30)
+    y = torch.empty_like(t)
+    ts.matvec(vals, t, y)
+    torch.cuda.synchronize()
+    true_rr = float(torch.linalg.vector_norm(rhs[:n] - y) / torch.linalg.vector_norm(rhs[:n]))
+    _say(f"  30 CG iterations: recursive {rr:.6e}, true {true_rr:.6e}")
+    assert it == 30 and abs(rr - true_rr) <= 1e-8 * true_rr
+    x, rinfo = plan.reconstruct(K, l, ts.scatter(t))
+    pw = plan.power_dissipation(prob, x)
+    torch.cuda.synchronize()
+    assert np.all(rinfo.cpu().numpy()[:w.n_cells] == 0)
+    ph = pw.cpu().numpy()[:w.n_cells]
+    assert np.all(np.isfinite(ph)) and np.all(ph >= 0.0)
+    Kh, lh, xh = K.cpu().numpy(), l.cpu().numpy(), x.cpu().numpy()
+    rng = np.random.default_rng(W.SEED_BASE + 71)
+    nu = 6 * 3 ** 3
+    for c in sorted(set([0, w.n_cells - 1] + list(rng.choice(w.n_cells, 6, replace=False)))):
+        k = int(plan.v_off[c + 1] - plan.v_off[c])
+        Kc = Kh[plan.K_off[c]:plan.K_off[c + 1]].reshape(k, k).T
+        lc, xc = lh[plan.v_off[c]:plan.v_off[c + 1]], xh[plan.v_off[c]:plan.v_off[c + 1]]
+        res = Kc[:nu, :nu] @ xc[:nu] + Kc[:nu, nu:] @ xc[nu:] - lc[:nu]
+        scale = np.abs(Kc[:nu, :]).max() * np.abs(xc).max() * k
+        assert np.abs(res).max() <= 1e-12 * scale, (c, np.abs(res).max(), scale)
+    ts.close()
+    plan.close()
