@@ -44,3 +44,32 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(dpg, "_lib", None)
     with pytest.raises(dpg.DPGError):
         dpg.lib()
+
+
+@pytest.mark.skipif(not os.path.exists(dpg.LIB_PATH), reason="libdpgmi.so not built")
+def test_global_solve_entry_points_reject_bad_arguments_on_the_host():
+    """Argument errors of the global-solve entry points are returned
+    synchronously, before any device call (so they need no GPU); empty
+    inputs are no-ops."""
+    import ctypes as C
+    L = dpg.lib()
+    it, rr = C.c_int64(7), C.c_double(7.0)
+    cg = lambda n, tol, mi, iters=True: L.dpg_cg_solve(n, None, None, None, None, None, tol, mi,
+                                                      C.byref(it) if iters else None, C.byref(rr), None)
+    assert cg(-1, 1e-8, 10) == dpg.DPG_ERR_ARG
+    assert cg(5, 1e-8, 10) == dpg.DPG_ERR_ARG          # null device pointers
+    assert cg(0, -1.0, 10) == dpg.DPG_ERR_ARG
+    assert cg(0, float("nan"), 10) == dpg.DPG_ERR_ARG
+    assert cg(0, 1e-8, -1) == dpg.DPG_ERR_ARG
+    assert cg(0, 1e-8, 10, iters=False) == dpg.DPG_ERR_ARG
+    assert cg(0, 1e-8, 10) == dpg.DPG_OK and it.value == 0 and rr.value == 0.0
+    mark = lambda n, fr, fc: L.dpg_dorfler_mark(n, None, fr, fc, None, None)
+    assert mark(-1, 0.3, 0.05) == dpg.DPG_ERR_ARG
+    assert mark(2 ** 31, 0.3, 0.05) == dpg.DPG_ERR_ARG
+    assert mark(4, 0.3, 0.05) == dpg.DPG_ERR_ARG        # null device pointers
+    assert mark(0, 1.5, 0.05) == dpg.DPG_ERR_ARG
+    assert mark(0, 0.3, float("nan")) == dpg.DPG_ERR_ARG
+    assert mark(0, 0.3, 0.05) == dpg.DPG_OK
+    assert L.dpg_reconstruct(None, None, None, None, None, None, None) == dpg.DPG_ERR_ARG
+    assert L.dpg_power_dissipation(None, None, None, None, None) == dpg.DPG_ERR_ARG
+    assert L.dpg_trace_system_scatter(None, None, None, None) == dpg.DPG_ERR_ARG
