@@ -77,7 +77,7 @@ typedef enum {
   DPG_ERR_ARG = -1,          /* invalid argument (null pointer, bad degree, ...) */
   DPG_ERR_ALLOC = -2,        /* device or host allocation failed */
   DPG_ERR_HIP = -3,          /* a HIP runtime call or kernel launch failed */
-  DPG_ERR_UNSUPPORTED = -4   /* valid request this build does not support */
+  DPG_ERR_UNSUPPORTED = -4   /* valid request the library does not support */
 } dpg_status;
 
 typedef enum {
