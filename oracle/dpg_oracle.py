@@ -509,22 +509,121 @@ def cell_forms(cp: CellProblem):
     return G, Bf, l
 
 
+def cell_forms_blocks(cp: CellProblem):
+    """The same (G, B_f, l) as cell_forms by a second route: the real volume
+    matrices of the mapped test functions (psi, curl psi) and trial functions
+    (phi e_c),
+        M = (psi, psi), S = (curl psi, curl psi), C_ij = (curl psi_i, psi_j),
+        D_i,(c,a) = ((psi_i)_c, phi_a), R_i,(c,a) = ((curl psi_i)_c, phi_a),
+    per Robin face the tangential ones
+        Mt = (psi_t, psi_t), Rt_ij = (psi_i, n x psi_j), Dt_i,(c,a) = ((psi_i,t)_c, phi_a),
+    and the trace pairing T_ij = (psi_i, n x theta_j), combined with the
+    coefficients by expanding the forms of §2.2 on the basis (psi_i, 0),
+    (0, psi_i) (conjugation in the first argument):
+        G_FF = S + (w^2 |eps|^2 + alpha) M + sum_R |z|^2 Mt,
+        G_II = S + (w^2 |mu|^2 + alpha) M + sum_R Mt,
+        G_FI = i w conj(mu) C + i w eps C^T + sum_R z Rt,   G_IF = G_FI^H,
+        B_FE = i w eps D - sum_R z Dt,  B_FH = R,  B_IE = R,  B_IH = -i w mu D,
+        Bhat_IEhat = T (all faces),  Bhat_FHhat = T (non-Robin faces),
+        l_F = (psi, J) - sum_R (psi, g),  l_I = 0,
+    with z the face's Z^{-1}.  The arithmetic differs from the pointwise
+    route (real contractions first, coefficients after), so the exact solves
+    of the two FP64 systems differ by what FP64 formation roundoff moves
+    K_e, l_e and eta: the floor any independent FP64 implementation has."""
+    p, dp = cp.p, cp.dp
+    s, r = p + dp + 1, p + 1
+    n1 = p + dp + 2 + cp.quad_extra
+    N = 3 * s * (s + 1) ** 2
+    m1 = (p + 1) ** 3
+    om, eps, mu, alpha = cp.omega, complex(cp.eps), complex(cp.mu), cp.alpha
+
+    def rip(u, v, wt):
+        """sum_q wt_q u_i(q) . v_j(q) for real fields -> (nu, nv)"""
+        return u.reshape(u.shape[0], -1) @ (v * wt[None, :, None]).reshape(v.shape[0], -1).T
+
+    def dg(u, phi, wt):
+        """[i, c*m1 + a] = sum_q wt_q u_i,c(q) phi_a(q)"""
+        return np.einsum('iqc,aq,q->ica', u, phi, wt).reshape(u.shape[0], 3 * phi.shape[0])
+
+    pts, w = volume_rule(n1)
+    x, J = trilinear_map(cp.X, pts)
+    detJ = np.linalg.det(J)
+    if np.any(detJ <= 0.0):
+        raise ValueError("degenerate cell: det J <= 0")
+    Jinv = np.linalg.inv(J)
+    wd = w * detJ
+    val, curl = test_basis_ref(s, pts)
+    psi = np.einsum('qba,nqb->nqa', Jinv, val)
+    cpsi = np.einsum('qab,nqb->nqa', J, curl) / detJ[None, :, None]
+    phi = trial_basis_ref(p, pts)
+    M, S, C = rip(psi, psi, wd), rip(cpsi, cpsi, wd), rip(cpsi, psi, wd)
+    D, R = dg(psi, phi, wd), dg(cpsi, phi, wd)
+    cF = om * om * abs(eps) ** 2 + alpha
+    cI = om * om * abs(mu) ** 2 + alpha
+    GFF = S + cF * M + 0j
+    GII = S + cI * M + 0j
+    GFI = 1j * om * np.conj(mu) * C + 1j * om * eps * C.T
+    BFE = 1j * om * eps * D
+    nt = 12 * r * r
+    TI = np.zeros((N, nt))
+    TF = np.zeros((N, nt))
+    lF = np.zeros(N, dtype=complex)
+    if cp.J_src is not None:
+        Jx = np.asarray(cp.J_src(x), dtype=complex)
+        lF += np.einsum('iqa,qa,q->i', psi, Jx, wd)
+    for f in range(6):
+        kind = cp.face_kind[f]
+        fpts, fw = face_rule(n1, f)
+        xf, Jf, n, dS = face_geometry(cp.X, f, fpts)
+        wf = fw * dS
+        Jfinv = np.linalg.inv(Jf)
+        fval, _ = test_basis_ref(s, fpts)
+        fpsi = np.einsum('qba,nqb->nqa', Jfinv, fval)
+        th = np.einsum('qba,nqb->nqa', Jfinv, trace_basis_ref(r, fpts))
+        Tf = rip(fpsi, np.cross(n[None], th), wf)
+        TI += Tf
+        if not _robin(kind):
+            TF += Tf
+            continue
+        z = complex(cp.zinv[f])
+        pt = fpsi - np.einsum('nqa,qa->nq', fpsi, n)[:, :, None] * n[None]      # tangential part
+        GFF += abs(z) ** 2 * rip(pt, pt, wf)
+        GII += rip(pt, pt, wf)
+        GFI += z * rip(fpsi, np.cross(n[None], fpsi), wf)
+        BFE -= z * dg(pt, trial_basis_ref(p, fpts), wf)
+        g = None
+        if cp.g_src is not None:
+            g = cp.g_src(f, xf, n)
+        elif kind == FACE_PORT and cp.port is not None:
+            g = cp.port.robin_data(xf, n, z)
+        if g is not None:
+            lF -= np.einsum('iqa,qa,q->i', fpsi, np.asarray(g, dtype=complex), wf)
+    G = np.block([[GFF, GFI], [GFI.conj().T, GII]])
+    Z3 = np.zeros((N, nt))
+    B = np.block([[BFE, R + 0j, Z3, TF], [R + 0j, -1j * om * mu * D, TI, Z3]])
+    l = np.concatenate([lF, np.zeros(N, dtype=complex)])
+    return G, B, l
+
+
 # --------------------------------------------------------------------------
 # The local solve (§2.3): elimination of Psi, error representation
 # --------------------------------------------------------------------------
-def local_solve(G, Bf, l, x=None):
+def local_solve(G, Bf, l, x=None, r=None):
     """K_e = B_f^H G^{-1} B_f, l_e = B_f^H G^{-1} l and, if x is given,
-    eta = sqrt(r^H G^{-1} r) with r = B_f x - l.  Plain definition: the
-    G-solves are LU solves (numpy.linalg.solve)."""
+    eta = sqrt(r^H G^{-1} r) with r = B_f x - l (or with the residual r
+    itself, when it is given instead of x).  Plain definition: the G-solves
+    are LU solves (numpy.linalg.solve)."""
     k = Bf.shape[1]
     rhs = np.concatenate([Bf, l[:, None]], axis=1)
-    if x is not None:
-        rhs = np.concatenate([rhs, (Bf @ x - l)[:, None]], axis=1)
+    if r is None and x is not None:
+        r = Bf @ x - l
+    if r is not None:
+        rhs = np.concatenate([rhs, np.asarray(r)[:, None]], axis=1)
     X = np.linalg.solve(G, rhs)
     K = np.conj(Bf).T @ X[:, :k]
     le = np.conj(Bf).T @ X[:, k]
     eta = None
-    if x is not None:
+    if r is not None:
         rr = rhs[:, k + 1]
         eta = math.sqrt(max(0.0, float(np.real(np.conj(rr) @ X[:, k + 1]))))
     return K, le, eta
