@@ -85,7 +85,7 @@ typedef enum {
   DPG_SPLIT_FP32 = 1         /* split precision: formation, Cholesky and triangular solves in
                                 FP64; K_e = W^H W and l_e = W^H y from a three-term bf16 split of
                                 W (about 24 significant bits per operand, FP32 accumulation folded
-                                into FP64 every 64 terms) on bf16 MFMA; eta by an FP64 reduction */
+                                into FP64 every 32 terms) on bf16 MFMA; eta by an FP64 reduction */
 } dpg_precision;
 
 enum {
@@ -239,6 +239,23 @@ dpg_status dpg_graph_destroy(dpg_graph graph);
  * first + c at index c.  Synchronises `stream`. */
 dpg_status dpg_form_local(dpg_plan plan, const dpg_problem* prob, int64_t first, int64_t count,
                           double* G, double* Bf, double* lvec, int32_t* info, void* stream);
+
+/* Debug/parity entry: the Jacobi-scaled system of `count` consecutive cells
+ * first, ... (all of the plan's degree p) exactly as the factorisation of
+ * dpg_local_solve reads it, so that an independent solve of these FP64
+ * numbers measures the factorisation's own error (Sec. 2.3: K_e, l_e and
+ * eta are invariant under the scaling):
+ *   Gs = D G D (full Hermitian, built from the lower triangle the
+ *        factorisation reads), Bs = D B_f, ls = D l, rs = D (B_f x - l)
+ *        (zero when x is NULL), d = diag(G)^{-1/2} (real).
+ * Layouts as dpg_form_local (Gs [count][n_test][n_test], Bs [count][k][n_test],
+ * ls and rs [count][n_test], complex; d [count][n_test] doubles); x, if not
+ * NULL, holds the coefficients of the range (cell first + c at
+ * x + 2*(v_off[first + c] - v_off[first])).  All device pointers.
+ * Synchronises `stream`.  DPG_ERR_ARG as dpg_form_local, or for NULL rs or d. */
+dpg_status dpg_form_augmented(dpg_plan plan, const dpg_problem* prob, int64_t first, int64_t count,
+                              const double* x, double* Gs, double* Bs, double* ls, double* rs, double* d,
+                              int32_t* info, void* stream);
 
 /* ---------------------------------------------------------------------
  * Condensed trace system (Sec. 2.3: static condensation of the interior

@@ -331,6 +331,67 @@ dpg_status enqueue_solve(dpg_plan P, const dpg::ProbArgs& pa, int64_t first, int
   return DPG_OK;
 }
 
+// Formation of `count` consecutive cells of one degree and extraction of
+// their dense local matrices (the parity entries): unscaled G, B_f, l, or,
+// with rvec and dvec, the Jacobi-scaled system the factorisation reads.
+dpg_status form_cells(dpg_plan plan, const dpg_problem* prob, int64_t first, int64_t count, const double* x,
+                      double* G, double* Bf, double* lvec, double* rvec, double* dvec, int32_t* info, void* stream) {
+  if (!plan || !G || !Bf || !lvec || !info || first < 0 || count <= 0 || first + count > plan->n_cells)
+    return DPG_ERR_ARG;
+  dpg::ProbArgs pa;
+  if (!make_prob_args(prob, pa) || prob->n_cells != plan->n_cells) return DPG_ERR_ARG;
+  DegreeGroup* grp = nullptr;
+  for (auto& g : plan->groups) {
+    bool all = true;
+    for (int64_t c = first; c < first + count && all; ++c) {
+      auto it = std::lower_bound(g.cells.begin(), g.cells.end(), c);
+      all = (it != g.cells.end() && *it == c);
+    }
+    if (all) {
+      grp = &g;
+      break;
+    }
+  }
+  if (!grp) return DPG_ERR_ARG;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (hipSetDevice(plan->device) != hipSuccess) return DPG_ERR_HIP;
+  std::vector<int64_t> ids(count);
+  for (int64_t c = 0; c < count; ++c) ids[c] = first + c;
+  int64_t* ids_dev = nullptr;
+  if (hipMalloc(reinterpret_cast<void**>(&ids_dev), sizeof(int64_t) * count) != hipSuccess) return DPG_ERR_ALLOC;
+  dpg_status rc = DPG_OK;
+  if (hipMemcpyAsync(ids_dev, ids.data(), sizeof(int64_t) * count, hipMemcpyHostToDevice, st) != hipSuccess)
+    rc = DPG_ERR_HIP;
+  const dpg::Dims& d = grp->d;
+  const int64_t nv = 2 * d.N;
+  const bool scaled = rvec && dvec;
+  for (int64_t s0 = 0; s0 < count && rc == DPG_OK; s0 += grp->chunk) {
+    dpg::ChunkArgs ca{};
+    ca.cell_ids = ids_dev + s0;
+    ca.n = std::min<int64_t>(grp->chunk, count - s0);
+    ca.Z = grp->Z;
+    ca.dscale = grp->dscale;
+    ca.met = grp->met;
+    ca.K_off = plan->K_off_dev;
+    ca.v_off = plan->v_off_dev;
+    ca.cell_base = first;
+    ca.v_base = plan->v_off[first];
+    ca.x = reinterpret_cast<const double2*>(x);
+    ca.info = info;
+    if (dpg::launch_formation(grp->dt, pa, ca, st) != hipSuccess ||
+        dpg::launch_extract(grp->dt, ca, reinterpret_cast<double2*>(G) + s0 * nv * nv,
+                            reinterpret_cast<double2*>(Bf) + s0 * nv * d.k,
+                            reinterpret_cast<double2*>(lvec) + s0 * nv, st,
+                            scaled ? reinterpret_cast<double2*>(rvec) + s0 * nv : nullptr,
+                            scaled ? dvec + s0 * nv : nullptr) != hipSuccess)
+      rc = DPG_ERR_HIP;
+  }
+  // the id buffer must outlive the enqueued work
+  if (hipStreamSynchronize(st) != hipSuccess) rc = DPG_ERR_HIP;
+  (void)hipFree(ids_dev);
+  return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1055,56 +1116,14 @@ dpg_status dpg_plan_profile(dpg_plan plan, double* ms, int64_t* launches) {
 
 dpg_status dpg_form_local(dpg_plan plan, const dpg_problem* prob, int64_t first, int64_t count, double* G,
                           double* Bf, double* lvec, int32_t* info, void* stream) {
-  if (!plan || !G || !Bf || !lvec || !info || first < 0 || count <= 0 || first + count > plan->n_cells)
-    return DPG_ERR_ARG;
-  dpg::ProbArgs pa;
-  if (!make_prob_args(prob, pa) || prob->n_cells != plan->n_cells) return DPG_ERR_ARG;
-  DegreeGroup* grp = nullptr;
-  for (auto& g : plan->groups) {
-    bool all = true;
-    for (int64_t c = first; c < first + count && all; ++c) {
-      auto it = std::lower_bound(g.cells.begin(), g.cells.end(), c);
-      all = (it != g.cells.end() && *it == c);
-    }
-    if (all) {
-      grp = &g;
-      break;
-    }
-  }
-  if (!grp) return DPG_ERR_ARG;
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  if (hipSetDevice(plan->device) != hipSuccess) return DPG_ERR_HIP;
-  std::vector<int64_t> ids(count);
-  for (int64_t c = 0; c < count; ++c) ids[c] = first + c;
-  int64_t* ids_dev = nullptr;
-  if (hipMalloc(reinterpret_cast<void**>(&ids_dev), sizeof(int64_t) * count) != hipSuccess) return DPG_ERR_ALLOC;
-  dpg_status rc = DPG_OK;
-  if (hipMemcpyAsync(ids_dev, ids.data(), sizeof(int64_t) * count, hipMemcpyHostToDevice, st) != hipSuccess)
-    rc = DPG_ERR_HIP;
-  const dpg::Dims& d = grp->d;
-  const int64_t nv = 2 * d.N;
-  for (int64_t s0 = 0; s0 < count && rc == DPG_OK; s0 += grp->chunk) {
-    dpg::ChunkArgs ca{};
-    ca.cell_ids = ids_dev + s0;
-    ca.n = std::min<int64_t>(grp->chunk, count - s0);
-    ca.Z = grp->Z;
-    ca.dscale = grp->dscale;
-    ca.met = grp->met;
-    ca.K_off = plan->K_off_dev;
-    ca.v_off = plan->v_off_dev;
-    ca.cell_base = first;
-    ca.x = nullptr;
-    ca.info = info;
-    if (dpg::launch_formation(grp->dt, pa, ca, st) != hipSuccess ||
-        dpg::launch_extract(grp->dt, ca, reinterpret_cast<double2*>(G) + s0 * nv * nv,
-                            reinterpret_cast<double2*>(Bf) + s0 * nv * d.k,
-                            reinterpret_cast<double2*>(lvec) + s0 * nv, st) != hipSuccess)
-      rc = DPG_ERR_HIP;
-  }
-  // the id buffer must outlive the enqueued work
-  if (hipStreamSynchronize(st) != hipSuccess) rc = DPG_ERR_HIP;
-  (void)hipFree(ids_dev);
-  return rc;
+  return form_cells(plan, prob, first, count, nullptr, G, Bf, lvec, nullptr, nullptr, info, stream);
+}
+
+dpg_status dpg_form_augmented(dpg_plan plan, const dpg_problem* prob, int64_t first, int64_t count, const double* x,
+                              double* Gs, double* Bs, double* ls, double* rs, double* d, int32_t* info,
+                              void* stream) {
+  if (!rs || !d) return DPG_ERR_ARG;
+  return form_cells(plan, prob, first, count, x, Gs, Bs, ls, rs, d, info, stream);
 }
 
 }  // extern "C"

@@ -177,8 +177,9 @@ __host__ __device__ inline int64_t fr_stride(const DevTables& t) { return fr_ld(
 __host__ __device__ inline int64_t split_elems(const DevTables& t) { return 6 * (int64_t)t.kp * t.nvp; }
 // Raise the dynamic-LDS limit of the kernels that stage whole tiles (once per process).
 hipError_t configure_kernels();
-// Unscaled G, B_f, l of `n` cells into dense per-cell arrays (parity entry).
+// G, B_f, l of `n` cells into dense per-cell arrays (parity entries): unscaled,
+// or, when rvec and dvec are given, the Jacobi-scaled D G D, D B_f, D l, D r and d.
 hipError_t launch_extract(const DevTables& t, const ChunkArgs& ca, double2* G, double2* Bf, double2* lvec,
-                          hipStream_t st);
+                          hipStream_t st, double2* rvec = nullptr, double* dvec = nullptr);
 
 }  // namespace dpg

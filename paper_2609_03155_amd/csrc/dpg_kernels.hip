@@ -1041,8 +1041,13 @@ static_assert(kFactorSmem <= 80 * 1024, "two factorisation workgroups must fit o
 
 // 1/sqrt(d) for the pivots of the tile factorisation (d > 0 and finite, of
 // order one after the diagonal scaling): the hardware estimate refined by two
-// Newton steps y <- y + y (1 - d y^2) / 2, about one ulp, with a dependency
-// chain a quarter as long as an IEEE square root followed by a division.
+// Newton steps y <- y + y (1 - d y^2) / 2 (measured: at most 0.99 ulp), then
+// a third whose residual 1 - d y^2 is formed exactly (d y split into its
+// rounded value and remainder by an fma), which rounds correctly to within
+// half an ulp (measured: 0.5).  The pivot enters every column of the factor
+// and of the diagonal-block inverses, so its error sets much of the
+// factorisation's backward error.  The chain is still shorter than an IEEE
+// square root followed by a division.
 __device__ __forceinline__ double pivot_rsqrt(double d) {
   double y = __builtin_amdgcn_rsq(d);
 #pragma unroll
@@ -1050,34 +1055,46 @@ __device__ __forceinline__ double pivot_rsqrt(double d) {
     const double e = fma(-d * y, y, 1.0);
     y = fma(0.5 * y, e, y);
   }
-  return y;
+  const double h = d * y, hl = fma(d, y, -h);
+  const double e = fma(-hl, y, fma(-h, y, 1.0));
+  return fma(0.5 * y, e, y);
 }
 
-// Cholesky factor and inverse of the 64x64 Hermitian tile whose lower part
-// is in Cr/Ci[r*65+q]; writes L^{-1} (lower, zero upper) to the column-major
-// tile `out` and returns the first failing column + 1 (0 if none), the same
-// value in every thread.  Registers carry the work: thread (r, g) = (t & 63,
-// t >> 6) owns columns [16g, 16g + 16) of row r of both A (updated in place)
-// and X = L^{-1} (from the identity).  Step c broadcasts column c of A (its
-// owner wave; zero above the diagonal) and row c of X (lane c of every wave)
-// through a double-buffered LDS slot, one barrier per step, and every thread
-// applies
-//   A_rq -= L_rc conj(L_qc)   and   X_rq -= L_rc X_cq ,   L_rc = 0 for r <= c,
-// and row c of X is scaled by 1/L_cc (deferred to the end: the row is not
-// read again after step c, and the other rows use it before the scaling).
-// A wave skips the A update once all its columns are
-// done (16g + 15 < c) and the X update while X_cq = 0 for all its columns
-// (16g > c); entries of A left of column c or above the diagonal take
-// meaningless updates but are never read again.  Cr/Ci are reused as the
-// broadcast slots.  REAL: the tile is real (Ci is not read), and the
-// imaginary parts are dropped from the arithmetic and the broadcasts; L^{-1}
-// also goes to the real column-major tile rout (leading dimension ldr) if given.
+// Cholesky factorisation of the 64x64 Hermitian tile whose lower part is in
+// Cr/Ci[r*65+q], stored for the panel solves of the sweep: the tile L = chol
+// is cut into 16x16 blocks; the blocks below the block diagonal hold L itself
+// and the four diagonal blocks hold the inverses of L's diagonal blocks
+// (lower triangular; zeros above the diagonal of the tile).  A panel X is
+// then solved against L^H by block substitution over the four blocks with
+// those small inverses.  Multiplying by the inverse of the whole 64x64 factor
+// instead loses accuracy by the condition of that factor (measured: about
+// five times LAPACK's element-wise error on the trace block of K_e); with
+// 16x16 inverses the error is that of substitution.
+// Writes the column-major tile `out` and returns the first failing column + 1
+// (0 if none), the same value in every thread.  Registers carry the work:
+// thread (r, g) = (t & 63, t >> 6) owns columns [16g, 16g + 16) of row r of
+// A (updated in place) and of X (from the identity; for the rows of block g
+// the inverse of that diagonal block).  Step c (block kb = c / 16) broadcasts
+// column c of A (its owner wave kb; zero above the diagonal) and row c of X
+// (lane c of wave kb) through a double-buffered LDS slot, one barrier per
+// step; with L_rc = A_rc / sqrt(A_cc):
+//   wave kb stores L_rc for the rows r below block kb,
+//   waves g >= kb:  A_rq -= L_rc conj(L_qc) for their columns q (entries left
+//                   of column c or above the diagonal take meaningless updates
+//                   but are never read again),
+//   wave kb:        X_rq -= (L_rc / L_cc) X_cq  (q in block kb),
+// and row r of X is scaled by 1/L_rr at the end (deferred: row c of X is
+// read unscaled by the later rows of its block).  REAL: the tile is real (Ci
+// is not read) and the imaginary parts are dropped from the arithmetic and
+// the broadcasts; the stored tile also goes to the real column-major tile
+// rout (leading dimension ldr) if given.
 template <bool REAL>
 __device__ __forceinline__ int chol_inv_tile(double* Cr, const double* Ci, double2* __restrict__ out, int64_t ld,
                                              double* __restrict__ rout = nullptr, int64_t ldr = 0) {
   int r = threadIdx.x & 63;
   __asm__ volatile("" : "+v"(r));   // not hoisted out of a caller's loop (as in wave_tile)
   const int g = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
+  const bool rowblk = (r >> 4) == g;   // row r lies in this wave's diagonal block
   double ar[16], ai[16], xr[16], xi[16];
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
@@ -1103,12 +1120,12 @@ __device__ __forceinline__ int chol_inv_tile(double* Cr, const double* Ci, doubl
       if (g == kb) {
         if (REAL) cbr[par + r] = r >= c ? ar[uc] : 0.0;
         else cb[par + r] = r >= c ? make_double2(ar[uc], ai[uc]) : make_double2(0.0, 0.0);
-      }
-      if (r == c) {
+        if (r == c) {
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-          if (REAL) rbr[par + 16 * g + u] = xr[u];
-          else rb[par + 16 * g + u] = make_double2(xr[u], xi[u]);
+          for (int u = 0; u < 16; ++u) {
+            if (REAL) rbr[par + u] = xr[u];
+            else rb[par + u] = make_double2(xr[u], xi[u]);
+          }
         }
       }
       __syncthreads();
@@ -1129,6 +1146,12 @@ __device__ __forceinline__ int chol_inv_tile(double* Cr, const double* Ci, doubl
       const double inv = pivot_rsqrt(d);
       const double inv2 = inv * inv;
       const double lr = r > c ? ownr * inv2 : 0.0, li = r > c ? owni * inv2 : 0.0;   // L_rc / L_cc
+      if (g == kb && (r >> 4) > kb) {
+        // column c of L below the block diagonal, stored at its step (the
+        // registers of column c take meaningless updates from here on)
+        out[(int64_t)c * ld + r] = make_double2(ownr * inv, REAL ? 0.0 : owni * inv);
+        if (REAL && rout) rout[(int64_t)c * ldr + r] = ownr * inv;
+      }
       if (g >= kb) {
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
@@ -1143,13 +1166,14 @@ __device__ __forceinline__ int chol_inv_tile(double* Cr, const double* Ci, doubl
           }
         }
       }
-      if (g <= kb) {
+      if (g == kb) {
+        // rows outside block kb take meaningless X updates (never stored)
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
           if (REAL) {
-            xr[u] = fma(-lr, rbr[par + 16 * g + u], xr[u]);
+            xr[u] = fma(-lr, rbr[par + u], xr[u]);
           } else {
-            const double2 y = rb[par + 16 * g + u];   // X_cq before scaling (broadcast)
+            const double2 y = rb[par + u];   // X_cq before scaling (broadcast)
             xr[u] = fma(-lr, y.x, xr[u]);
             xr[u] = fma(li, y.y, xr[u]);
             xi[u] = fma(-lr, y.y, xi[u]);
@@ -1162,19 +1186,21 @@ __device__ __forceinline__ int chol_inv_tile(double* Cr, const double* Ci, doubl
   }
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
-    xr[u] *= pinv;
-    if (!REAL) xi[u] *= pinv;
-  }
-#pragma unroll
-  for (int u = 0; u < 16; ++u) {
     const int q = 16 * g + u;
-    out[(int64_t)q * ld + r] = q <= r ? make_double2(xr[u], REAL ? 0.0 : xi[u]) : make_double2(0.0, 0.0);
-    if (REAL && rout) rout[(int64_t)q * ldr + r] = q <= r ? xr[u] : 0.0;
+    if ((r >> 4) > g) continue;   // L below the block diagonal: stored at its step
+    double vr = 0.0, vi = 0.0;
+    if (rowblk && q <= r) {
+      // diagonal block: the inverse of L's diagonal block (lower triangular)
+      vr = xr[u] * pinv;
+      vi = REAL ? 0.0 : xi[u] * pinv;
+    }
+    out[(int64_t)q * ld + r] = make_double2(vr, vi);
+    if (REAL && rout) rout[(int64_t)q * ldr + r] = vr;
   }
   return fail;
 }
 
-// Step 0 diagonal block: A_00 = L L^H, store L^{-1}.
+// Step 0 diagonal block: A_00 = L L^H, stored for the panel solves (chol_inv_tile).
 __global__ __launch_bounds__(NT) void k_chol_diag0(DevTables T, ChunkArgs C) {
   const int64_t cell = blockIdx.x;
   if (cell >= C.n) return;
@@ -1197,10 +1223,10 @@ __global__ __launch_bounds__(NT) void k_chol_diag0(DevTables T, ChunkArgs C) {
   if (threadIdx.x == 0 && fail && C.info[gc - C.cell_base] == 0) C.info[gc - C.cell_base] = fail;
 }
 
-// ---------------------------------------------------------------- one wave, half a tile
-// Register-direct tile product for one wave, which owns the 32 rows
-// [32h, 32h + 32) of a 64x64 output tile: Q -= conj(B_j) A_i^T with B_j the
-// 64-row panel of the tile's columns and A_i the wave's 32 rows, over columns
+// ---------------------------------------------------------------- one wave, part of a tile
+// Register-direct tile product for one wave, which owns the 16 NV rows
+// [16 NV h, 16 NV (h + 1)) of a 64x64 output tile: Q -= conj(B_j) A_i^T with B_j the
+// 64-row panel of the tile's columns and A_i the wave's rows, over columns
 // [0, K) of the panels.  No LDS and no barriers: every operand goes from
 // memory to the MFMA source registers.  Block (u, v) of Q (u: rows from panel
 // j, v: rows from the wave's half of panel i) is one 16x16 f64 MFMA
@@ -1230,10 +1256,11 @@ struct WOpsT {
 // Register buffers of the k-step pipeline (prefetch distance NB - 1): the
 // fewer MFMAs a k-step has, the deeper the prefetch; sized to what the
 // register file holds next to the accumulators without spilling.
-template <int MODE, int NV = 2>
+template <int MODE, int NV = 2, bool TWO = false>
 struct WPipe {
-  // a wave of 16 rows (NV = 1) has half the accumulators, so room for twice the buffers
-  static constexpr int NB = NV == 2 ? (MODE == MM_RR ? 4 : 2) : (MODE == MM_RR ? 8 : 4);
+  // a wave of 16 rows (NV = 1) has half the accumulators, so room for twice the
+  // buffers, unless the two-level summation takes that room for its run sums
+  static constexpr int NB = (NV == 2 || TWO) ? (MODE == MM_RR ? 4 : 2) : (MODE == MM_RR ? 8 : 4);
   // k-steps per buffer (more than one lets a mode with few MFMAs per k-step
   // keep more work in flight; two for the complex x real mode spilled, so one)
   static constexpr int KS = 1;
@@ -1293,13 +1320,41 @@ __device__ __forceinline__ void wave_step(const WOpsT<NV>& o, WAccT<NV>& q) {
 // end re-read the last k-step), so the wait before each k-step leaves the
 // younger prefetches in flight; the last nks % NB k-steps, already loaded,
 // follow the loop.
-template <int MODE, bool FRB = false, int NV = 2>
+// TWO: two-level summation.  The products of each run of 16 k-steps (64
+// columns) are summed in accumulators of their own, started at zero, and each
+// run's sum is then added to q; the rounding errors of a long sum (up to
+// thousands of terms at p = 4) then grow with the runs' partial sums instead
+// of the running total (measured in an emulation of the sweep: K_e and eta
+// three to twenty times closer to the exact solve at p = 4, dp = 2).
+template <int MODE, bool FRB = false, int NV = 2, bool TWO = false>
 __device__ __forceinline__ void wave_gemm_t(const double2* __restrict__ Ai, int64_t lda, const void* __restrict__ Bj,
                                             int64_t ldb, int K, WAccT<NV>& q) {
-  constexpr int NB = WPipe<MODE, NV>::NB, KS = WPipe<MODE, NV>::KS;
+  constexpr int NB = WPipe<MODE, NV, TWO>::NB, KS = WPipe<MODE, NV, TWO>::KS;
+  static_assert(!TWO || 16 % NB == 0, "a run of 16 k-steps spans whole pipeline rounds");
   const int nks = K / (4 * KS);   // buffers' worth of k-steps (K is a multiple of 64)
   if (nks <= 0) return;
   const int nfull = nks - nks % NB;
+  WAccT<NV> qb;                   // the current run's sum (TWO)
+  auto zero_run = [&]() {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        qb.re[u][v] = d4{0, 0, 0, 0};
+        qb.im[u][v] = d4{0, 0, 0, 0};
+      }
+  };
+  auto fold_run = [&]() {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        q.re[u][v] += qb.re[u][v];
+        if (MODE != MM_RR) q.im[u][v] += qb.im[u][v];
+      }
+  };
+  if (TWO) zero_run();
+  WAccT<NV>& acc = TWO ? qb : q;
   WOpsT<NV> o[NB][KS];
 #pragma unroll
   for (int s = 0; s < NB - 1; ++s)
@@ -1313,16 +1368,21 @@ __device__ __forceinline__ void wave_gemm_t(const double2* __restrict__ Ai, int6
         wave_load<MODE, FRB, NV>(Ai, lda, Bj, ldb, min(k0 + s + NB - 1, nks - 1) * KS + u, o[(s + NB - 1) % NB][u]);
       __builtin_amdgcn_sched_barrier(0);   // keep each prefetch in its slot (bounded live ranges)
 #pragma unroll
-      for (int u = 0; u < KS; ++u) wave_step<MODE, NV>(o[s][u], q);
+      for (int u = 0; u < KS; ++u) wave_step<MODE, NV>(o[s][u], acc);
       __builtin_amdgcn_sched_barrier(0);
+    }
+    if (TWO && ((k0 + NB) & 15) == 0) {
+      fold_run();
+      zero_run();
     }
   }
 #pragma unroll
   for (int s = 0; s < NB - 1; ++s)
     if (s < nks - nfull) {
 #pragma unroll
-      for (int u = 0; u < KS; ++u) wave_step<MODE, NV>(o[s][u], q);
+      for (int u = 0; u < KS; ++u) wave_step<MODE, NV>(o[s][u], acc);
     }
+  if (TWO && (nks & 15) != 0) fold_run();
 }
 
 // Structure of the augmented rows [r0, r0 + nr) in the F columns: the
@@ -1348,26 +1408,28 @@ __device__ inline int herk_k0(const DevTables& T, int a, int b) {
   return zero_f(a) || zero_f(b) ? (T.Np / TB) * TB : 0;
 }
 
-// Rows [32h, 32h + 32) of the regular tile (i, j) of step j, one wave:
-// X = A_ij - L_i,<j L_j,<j^H, then L_ij = X Linv_jj^H (the sum over columns
-// from k0, the caller's bound below which the rows are zero), computed transposed as
-// L_ij^T = conj(Linv_jj) X^T with the lower-triangular Linv_jj (16x16 blocks
-// above its diagonal skipped).  Row halves are independent: row r of L_ij
-// needs row r of X only.
-// Regular tiles of the sweep run on waves of 16 RNV rows, 64 / (16 RNV) waves
-// per tile and 4 / that tiles per workgroup.  Waves of 16 rows (one tile per
-// workgroup, a deeper prefetch in the registers the smaller accumulators
-// free) were measured on the WR340 workload: no faster than 32-row waves.
-constexpr int RNV = 2;                    // 16-row blocks per wave of a regular tile
+// Rows [16 NV h, 16 NV (h + 1)) of the tile (i, j) of step j, one wave:
+// X = A_ij - L_i,<j L_j,<j^H (the sum over columns from k0, the caller's bound
+// below which the rows are zero), then L_ij = X L_jj^{-H} by block
+// substitution over the four 16x16 blocks of the diagonal tile (chol_inv_tile's
+// storage), computed transposed.  The waves of a tile are independent: row r
+// of L_ij needs row r of X only.
+// The tiles of the sweep run on waves of 16 RNV rows, 64 / (16 RNV) waves per
+// tile and 4 / that tiles per workgroup.  Waves of 16 rows leave room for the
+// run sums of the two-level summation next to the accumulators (with 32-row
+// waves the accumulators alone fill half the registers); without it, 16- and
+// 32-row waves were measured equally fast on the WR340 workload.
+constexpr int RNV = 1;                    // 16-row blocks per wave of a regular tile
 constexpr int RWPT = TB / (16 * RNV);   // waves per regular tile
 static_assert(RWPT * 16 * RNV == TB, "the waves of a regular tile cover its rows");
 constexpr int RTPW = 4 / RWPT;            // regular tiles per workgroup
 
 // Use of the compact real copy of the F block by a tile: none, its operands
-// (panel j and Linv_jj) from it, or the tile's real output written to it too.
+// (panel j and the stored diagonal tile j) from it, or the tile's real output
+// written to it too.
 enum { FR_NONE = 0, FR_READ = 1, FR_WRITE = 2 };
 
-template <int MODE, int FR = FR_NONE, int NV = 2>
+template <int MODE, int FR = FR_NONE, int NV = 2, bool TWO = false>
 __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __restrict__ Z, int64_t cell, int i, int j,
                           int h, unsigned char* slab, int k0 = 0) {
   constexpr int RW = 16 * NV;   // rows of the wave: [RW h, RW h + RW) of the tile
@@ -1393,26 +1455,55 @@ __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __res
         q.im[u][v][t] = MODE == MM_RR ? 0.0 : a.y;
       }
   __builtin_amdgcn_sched_barrier(0);
-  // panel j and Linv_jj: from Z, or from the real copy of the F block
+  // panel j and the diagonal tile j: from Z, or from the real copy of the F block
   constexpr bool FRB = FR == FR_READ;
   const int64_t ldf = fr_ld(T);
   double* Fr = FR != FR_NONE ? C.fr + cell * fr_stride(T) : nullptr;
   if (FRB)
-    wave_gemm_t<MODE, true, NV>(Z + (int64_t)k0 * ld + i * TB + RW * h, ld, Fr + (int64_t)k0 * ldf + j * TB, ldf,
-                            j * TB - k0, q);
+    wave_gemm_t<MODE, true, NV, TWO>(Z + (int64_t)k0 * ld + i * TB + RW * h, ld, Fr + (int64_t)k0 * ldf + j * TB,
+                                     ldf, j * TB - k0, q);
   else
-    wave_gemm_t<MODE, false, NV>(Z + (int64_t)k0 * ld + i * TB + RW * h, ld, Z + (int64_t)k0 * ld + j * TB, ld,
-                              j * TB - k0, q);
+    wave_gemm_t<MODE, false, NV, TWO>(Z + (int64_t)k0 * ld + i * TB + RW * h, ld, Z + (int64_t)k0 * ld + j * TB, ld,
+                                      j * TB - k0, q);
   __builtin_amdgcn_sched_barrier(0);
-  const double2* tL = Z + (int64_t)(j * TB) * ld + j * TB;   // Linv_jj, lower
+  const double2* tL = Z + (int64_t)(j * TB) * ld + j * TB;   // diagonal tile j (chol_inv_tile's storage)
   const double* tLr = FRB ? Fr + (int64_t)(j * TB) * ldf + j * TB : nullptr;
   const int nvb = T.nvp / TB;
   const bool wsplit = C.split && i >= nvb;
   const bool last_w = j + 1 == nvb;
   uint16_t* wp = wsplit ? C.wsplit + cell * split_elems(T) : nullptr;
   const int nkc = T.nvp / 32;
+  // Block forward substitution conj(L_jj) Y = Q over the four 16-row blocks
+  // (Y = L_ij^T, Q = X^T; chol_inv_tile's storage: L_jj below the block
+  // diagonal, the inverses Dinv of its diagonal blocks on it):
+  //   Q[mb] -= sum_{kb < mb} conj(L_jj[mb][kb]) Y[kb],  Y[mb] = conj(Dinv[mb]) Q[mb],
+  // where Y[mb] replaces Q[mb] in the accumulators (it is the B operand of the
+  // later updates, item t of lane l being row 16 mb + 4 t + (l >> 4)).
+  // A operand of block (m, k) at k-step t: element [16 m + (l & 15)][16 k + 4 t + (l >> 4)].
+#define DPG_DIAG_OP(m, k, t)                                                                              \
+  (FRB ? make_double2(tLr[(int64_t)(16 * (k) + 4 * (t) + (lane >> 4)) * ldf + 16 * (m) + (lane & 15)], 0.0)  \
+       : tL[(int64_t)(16 * (k) + 4 * (t) + (lane >> 4)) * ld + 16 * (m) + (lane & 15)])
 #pragma unroll
-  for (int mb = 3; mb >= 0; --mb) {
+  for (int mb = 0; mb < 4; ++mb) {
+    __builtin_amdgcn_sched_barrier(0);   // one block at a time (bounded live ranges)
+    // Q[mb] -= sum_{kb < mb} conj(L_jj[mb][kb]) Y[kb]
+#pragma unroll
+    for (int kb = 0; kb < mb; ++kb)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const double2 L = DPG_DIAG_OP(mb, kb, t);
+#pragma unroll
+        for (int nb = 0; nb < NV; ++nb) {
+          q.re[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-L.x, q.re[kb][nb][t], q.re[mb][nb], 0, 0, 0);
+          if (MODE != MM_RR)
+            q.im[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-L.x, q.im[kb][nb][t], q.im[mb][nb], 0, 0, 0);
+          if (MODE == MM_CC) {
+            q.re[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-L.y, q.im[kb][nb][t], q.re[mb][nb], 0, 0, 0);
+            q.im[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(L.y, q.re[kb][nb][t], q.im[mb][nb], 0, 0, 0);
+          }
+        }
+      }
+    // Y[mb] = conj(Dinv[mb]) Q[mb]
     d4 yr[NV], yi[NV];
 #pragma unroll
     for (int nb = 0; nb < NV; ++nb) {
@@ -1420,23 +1511,18 @@ __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __res
       yi[nb] = d4{0, 0, 0, 0};
     }
 #pragma unroll
-    for (int kb = 0; kb <= mb; ++kb)
+    for (int t = 0; t < 4; ++t) {
+      const double2 L = DPG_DIAG_OP(mb, mb, t);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        // A operand conj(Linv)[16 mb + (l & 15)][16 kb + 4 t + (l >> 4)]
-        double2 L;
-        if (FRB) L = make_double2(tLr[(int64_t)(16 * kb + 4 * t + (lane >> 4)) * ldf + 16 * mb + (lane & 15)], 0.0);
-        else L = tL[(int64_t)(16 * kb + 4 * t + (lane >> 4)) * ld + 16 * mb + (lane & 15)];
-#pragma unroll
-        for (int nb = 0; nb < NV; ++nb) {
-          yr[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(L.x, q.re[kb][nb][t], yr[nb], 0, 0, 0);
-          if (MODE != MM_RR) yi[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(L.x, q.im[kb][nb][t], yi[nb], 0, 0, 0);
-          if (MODE == MM_CC) {
-            yr[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(L.y, q.im[kb][nb][t], yr[nb], 0, 0, 0);
-            yi[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-L.y, q.re[kb][nb][t], yi[nb], 0, 0, 0);
-          }
+      for (int nb = 0; nb < NV; ++nb) {
+        yr[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(L.x, q.re[mb][nb][t], yr[nb], 0, 0, 0);
+        if (MODE != MM_RR) yi[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(L.x, q.im[mb][nb][t], yi[nb], 0, 0, 0);
+        if (MODE == MM_CC) {
+          yr[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(L.y, q.im[mb][nb][t], yr[nb], 0, 0, 0);
+          yi[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-L.y, q.re[mb][nb][t], yi[nb], 0, 0, 0);
         }
       }
+    }
     // item t of block (mb, nb): L_ij[row RW h + 16 nb + (l & 15)][column 16 mb + 4 t + (l >> 4)]
 #pragma unroll
     for (int nb = 0; nb < NV; ++nb)
@@ -1484,28 +1570,36 @@ __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __res
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+    // Y[mb] replaces Q[mb]: the B operand of the later blocks' updates
+#pragma unroll
+    for (int nb = 0; nb < NV; ++nb) {
+      q.re[mb][nb] = yr[nb];
+      if (MODE != MM_RR) q.im[mb][nb] = yi[nb];
+    }
   }
 }
 
-// Rows [32h, 32h + 32) of a diagonal block update, one wave:
-//   S = S0 - P_h P^H ,  P the 64-row panel (columns [0, K) at P), P_h its rows [32h, 32h + 32),
+// Rows [RW h, RW h + RW) (RW = 16 NV) of a diagonal block update, one wave:
+//   S = S0 - P_h P^H ,  P the 64-row panel (columns [0, K) at P), P_h its rows [RW h, RW h + RW),
 // with S0 the column-major tile S0g (FROM_TILE) or the LDS block
-// Sr/Si[r*65 + c] itself; the whole 32 x 64 result is written to
-// Sr/Si[r*65 + c] (only its lower part is meaningful).
-template <int MODE, bool FROM_TILE>
+// Sr/Si[r*65 + c] itself; the whole RW x 64 result is written to
+// Sr/Si[r*65 + c] (only its lower part is meaningful).  TWO: two-level
+// summation (wave_gemm_t).
+template <int MODE, bool FROM_TILE, int NV = 2, bool TWO = false>
 __device__ __forceinline__ void diag_update(const double2* __restrict__ S0g, const double2* __restrict__ P, int64_t ld,
                                             int K, int h, double* Sr, double* Si) {
+  constexpr int RW = 16 * NV;
   int lane = threadIdx.x & 63;
   __asm__ volatile("" : "+v"(lane));   // not hoisted out of a caller's loop (as in wave_tile)
   __asm__ volatile("" : "+s"(ld));
-  WAcc q;
+  WAccT<NV> q;
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int v = 0; v < 2; ++v)
+    for (int v = 0; v < NV; ++v)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const int r = 32 * h + 16 * v + (lane & 15), c = 16 * u + 4 * t + (lane >> 4);
+        const int r = RW * h + 16 * v + (lane & 15), c = 16 * u + 4 * t + (lane >> 4);
         if (FROM_TILE) {
           const double2 a = S0g[(int64_t)c * ld + r];
           q.re[u][v][t] = a.x;
@@ -1515,32 +1609,32 @@ __device__ __forceinline__ void diag_update(const double2* __restrict__ S0g, con
           q.im[u][v][t] = MODE == MM_RR ? 0.0 : Si[r * 65 + c];
         }
       }
-  wave_gemm_t<MODE>(P + 32 * h, ld, P, ld, K, q);
-  // item t of block (u, v): S[row 32h + 16v + (l & 15)][column 16u + 4t + (l >> 4)]
+  wave_gemm_t<MODE, false, NV, TWO>(P + RW * h, ld, P, ld, K, q);
+  // item t of block (u, v): S[row RW h + 16v + (l & 15)][column 16u + 4t + (l >> 4)]
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int v = 0; v < 2; ++v)
+    for (int v = 0; v < NV; ++v)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const int r = 32 * h + 16 * v + (lane & 15), c = 16 * u + 4 * t + (lane >> 4);
+        const int r = RW * h + 16 * v + (lane & 15), c = 16 * u + 4 * t + (lane >> 4);
         Sr[r * 65 + c] = q.re[u][v][t];
         if (MODE != MM_RR) Si[r * 65 + c] = q.im[u][v][t];   // a real block has no Si
       }
 }
 
 // Step j of the left-looking factorisation over the row tiles i > j:
-//   L_ij = (A_ij - sum_{m<j} L_im L_jm^H) Linv_jj^H ,
+//   L_ij = (A_ij - sum_{m<j} L_im L_jm^H) L_jj^{-H} ,
 // for the columns after the real F block (all of them when there is none),
 // where every tile is complex.  Tile i = j+1 (while it is a test tile) is
 // the lookahead tile: its workgroup also forms A_ii - sum_{m<=j} L_im L_im^H
-// and factorises it (Cholesky + inverse), storing Linv_ii for step j+1, so
-// no separate launch factors diagonal blocks.  Every other tile is two waves
-// (wave_tile, one row half each), two tiles per workgroup.
+// and factorises it (chol_inv_tile) for step j+1, so no separate launch
+// factors diagonal blocks.  Every tile is four 16-row waves (wave_tile), one
+// tile per workgroup; every long sum is two-level.
 __global__ __launch_bounds__(NT, 2) void k_chol_step(DevTables T, ChunkArgs C, int j) {
   const int nrb = T.nrows / TB, nvb = T.nvp / TB;
   const bool la = j + 1 < nvb;
-  const int nreg = nrb - j - 1 - (la ? 1 : 0);   // tiles done by wave pairs
+  const int nreg = nrb - j - 1 - (la ? 1 : 0);   // regular tiles
   // Workgroup ids [0, n8) carry the lookahead tile of every cell and are
   // dispatched first, spread over all CUs (cell c on XCD c % 8).  The regular
   // tiles follow: per XCD x the (cell, tile) pairs of its cells c = 8 m + x
@@ -1562,14 +1656,13 @@ __global__ __launch_bounds__(NT, 2) void k_chol_step(DevTables T, ChunkArgs C, i
     // rows that are zero in the F columns stay zero there (k_chol_fpanel leaves them), so their sum starts after
     const int r0 = i * TB + 16 * RNV * h;
     const int k0 = frows_class(T, r0, 16 * RNV) == FROWS_ZERO ? (T.Np / TB) * TB : 0;
-    wave_tile<MM_CC, FR_NONE, RNV>(T, C, Z, cell, i, j, h, slab, k0);
+    wave_tile<MM_CC, FR_NONE, RNV, true>(T, C, Z, cell, i, j, h, slab, k0);
     return;
   }
-  // ---- lookahead workgroup: tile (i, j), i = j + 1, on waves 0 and 1 (one
-  // row half each); meanwhile waves 2 and 3 form the two row halves of
-  // A_ii - sum_{m<j} L_im L_im^H in LDS, add the new term -L_ij L_ij^H once
-  // L_ij is stored, and all four waves factorise the result (Cholesky +
-  // inverse).
+  // ---- lookahead workgroup: tile (i, j), i = j + 1, on the four waves (16
+  // rows each); then the four waves form A_ii - sum_{m<=j} L_im L_im^H in LDS
+  // (16 rows each) and factorise it (Cholesky + diagonal-block inverses).
+  // Both long sums are two-level.
   const int64_t cell = blockIdx.x;
   if (cell >= C.n) return;
   const int i = j + 1;
@@ -1580,13 +1673,9 @@ __global__ __launch_bounds__(NT, 2) void k_chol_step(DevTables T, ChunkArgs C, i
   double* Cr = smem;
   double* Ci = Cr + 64 * 65;
   double2* tileD = Z + (int64_t)(i * TB) * ld + i * TB;
-  if (wave < 2) wave_tile<MM_CC>(T, C, Z, cell, i, j, wave, nullptr);
-  else diag_update<MM_CC, true>(tileD, Z + i * TB, ld, j * TB, wave - 2, Cr, Ci);
-  __syncthreads();   // L_ij stored (workgroup scope); partial diagonal block in LDS
-  if (wave >= 2) {
-    const double2* Lij = Z + (int64_t)(j * TB) * ld + i * TB;   // column block j of panel i
-    diag_update<MM_CC, false>(nullptr, Lij, ld, TB, wave - 2, Cr, Ci);
-  }
+  wave_tile<MM_CC, FR_NONE, 1, true>(T, C, Z, cell, i, j, wave, nullptr);
+  __syncthreads();   // L_ij stored (workgroup scope)
+  diag_update<MM_CC, true, 1, true>(tileD, Z + i * TB, ld, (j + 1) * TB, wave, Cr, Ci);
   __syncthreads();
   const int fail = chol_inv_tile<false>(Cr, Ci, tileD, ld);
   const int64_t gc = C.cell_ids[cell];
@@ -1595,10 +1684,11 @@ __global__ __launch_bounds__(NT, 2) void k_chol_step(DevTables T, ChunkArgs C, i
 
 // Factorisation of the real F block (row and column tiles < nF) of every
 // cell in one launch, one workgroup per cell:
-//   Linv_00 = chol(A_00)^{-1};  for j = 0 .. nF-2:
-//     L_ij = (A_ij - sum_{m<j} L_im L_jm^T) Linv_jj^T   for j < i < nF
-//            (two tiles at a time, one per wave pair),
-//     Linv_{j+1,j+1} = chol(A_{j+1,j+1} - sum_{m<=j} L_{j+1,m} L_{j+1,m}^T)^{-1} .
+//   L_00 = chol(A_00);  for j = 0 .. nF-2:
+//     L_ij = (A_ij - sum_{m<j} L_im L_jm^T) L_jj^{-T}   for j < i < nF
+//            (one tile at a time on the four 16-row waves),
+//     L_{j+1,j+1} = chol(A_{j+1,j+1} - sum_{m<=j} L_{j+1,m} L_{j+1,m}^T)
+// (diagonal tiles in chol_inv_tile's storage; two-level sums).
 // The block is small, so its cost is the latency of the chain, which one
 // workgroup walks without a launch (and a pass over all cells) per step.
 __global__ __launch_bounds__(NT, 3) void k_chol_fblock(DevTables T, ChunkArgs C, int nF) {
@@ -1612,7 +1702,7 @@ __global__ __launch_bounds__(NT, 3) void k_chol_fblock(DevTables T, ChunkArgs C,
   double* Cr = smem;
   double* Ci = Cr + 64 * 65;
   // the factorised block is also kept as a compact real copy (L_ij below the
-  // diagonal, Linv_jj on it), the real operands of the F-column launch
+  // diagonal, the diagonal tiles as stored), the real operands of the F-column launch
   double* fr = C.fr + cell * fr_stride(T);
   const int64_t ldf = fr_ld(T);
   int fail = 0;
@@ -1624,16 +1714,15 @@ __global__ __launch_bounds__(NT, 3) void k_chol_fblock(DevTables T, ChunkArgs C,
         const int q = e >> 6, r = e & 63;
         if (q <= r) Cr[r * 65 + q] = tileD[(int64_t)q * ld + r].x;
       }
-    } else if (wave < 2) {
-      diag_update<MM_RR, true>(tileD, Z + j * TB, ld, j * TB, wave, Cr, Ci);
+    } else {
+      diag_update<MM_RR, true, 1, true>(tileD, Z + j * TB, ld, j * TB, wave, Cr, Ci);
     }
     __syncthreads();
     const int f = chol_inv_tile<true>(Cr, Ci, tileD, ld, fr + (int64_t)(j * TB) * ldf + j * TB, ldf);
     if (f && !fail) fail = j * TB + f;
     if (j + 1 == nF) break;
-    __syncthreads();   // Linv_jj stored (workgroup scope); LDS free
-    for (int i = j + 1 + (wave >> 1); i < nF; i += 2)
-      wave_tile<MM_RR, FR_WRITE>(T, C, Z, cell, i, j, wave & 1, nullptr);
+    __syncthreads();   // diagonal tile j stored (workgroup scope); LDS free
+    for (int i = j + 1; i < nF; ++i) wave_tile<MM_RR, FR_WRITE, 1, true>(T, C, Z, cell, i, j, wave, nullptr);
     __syncthreads();   // column block j stored
   }
 
@@ -1642,15 +1731,14 @@ __global__ __launch_bounds__(NT, 3) void k_chol_fblock(DevTables T, ChunkArgs C,
 
 // The real F columns of all remaining rows in one launch.  Once the F block
 // (row and column tiles < nF, all real) is factorised, the rows i >= nF need
-// nothing else for their F columns: a wave pair walks its row tile through
+// nothing else for their F columns: each 16-row wave walks its rows through
 // j = 0 .. nF-1,
-//   L_ij = (A_ij - sum_{m<j} L_im L_jm^T) Linv_jj^T ,
+//   L_ij = (A_ij - sum_{m<j} L_im L_jm^T) L_jj^{-T} ,
 // and reads back the row panel L_i,<j it has just written, which is still
 // in the caches, instead of every step re-reading it from HBM in a launch of
-// its own.  Row tile nF is taken by the first workgroups (one per cell):
-// waves 0 and 1 walk it while waves 2 and 3 subtract each finished
-// L_{nF,j} L_{nF,j}^H from the diagonal block in LDS, and all four
-// factorise the result, storing Linv_{nF,nF} for the step nF.
+// its own.  Row tile nF is taken by the first workgroups (one per cell): the
+// four waves walk it, then form A_ii - sum_{m<nF} L_im L_im^H in LDS and
+// factorise it for the step nF.  Every sum is two-level.
 __global__ __launch_bounds__(NT, 2) void k_chol_fpanel(DevTables T, ChunkArgs C, int nF) {
   const int nrb = T.nrows / TB;
   const int nreg = nrb - nF - 1;   // row tiles after nF, RTPW per workgroup
@@ -1689,8 +1777,8 @@ __global__ __launch_bounds__(NT, 2) void k_chol_fpanel(DevTables T, ChunkArgs C,
       return;
     }
     for (int j = 0; j < nF; ++j) {
-      if (cls == FROWS_REAL) wave_tile<MM_RR, FR_READ, RNV>(T, C, Z, cell, i, j, h, slab);
-      else wave_tile<MM_CR, FR_READ, RNV>(T, C, Z, cell, i, j, h, slab);
+      if (cls == FROWS_REAL) wave_tile<MM_RR, FR_READ, RNV, true>(T, C, Z, cell, i, j, h, slab);
+      else wave_tile<MM_CR, FR_READ, RNV, true>(T, C, Z, cell, i, j, h, slab);
       // L_ij (stored by all lanes) feeds the loads of step j + 1
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
       __builtin_amdgcn_wave_barrier();
@@ -1706,12 +1794,15 @@ __global__ __launch_bounds__(NT, 2) void k_chol_fpanel(DevTables T, ChunkArgs C,
   double* Cr = smem;
   double* Ci = Cr + 64 * 65;
   double2* tileD = Z + (int64_t)(i * TB) * ld + i * TB;
-  if (wave >= 2) diag_update<MM_CC, true>(tileD, Z + i * TB, ld, 0, wave - 2, Cr, Ci);   // A_ii into LDS
   for (int j = 0; j < nF; ++j) {
-    if (wave < 2) wave_tile<MM_CR, FR_READ>(T, C, Z, cell, i, j, wave, nullptr);
-    __syncthreads();   // L_ij stored (workgroup scope)
-    if (wave >= 2) diag_update<MM_CC, false>(nullptr, Z + (int64_t)(j * TB) * ld + i * TB, ld, TB, wave - 2, Cr, Ci);
+    wave_tile<MM_CR, FR_READ, 1, true>(T, C, Z, cell, i, j, wave, nullptr);
+    // L_ij (the wave's own rows) feeds the loads of step j + 1
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   }
+  __syncthreads();   // row tile nF stored (workgroup scope)
+  diag_update<MM_CC, true, 1, true>(tileD, Z + i * TB, ld, nF * TB, wave, Cr, Ci);
   __syncthreads();
   const int fail = chol_inv_tile<false>(Cr, Ci, tileD, ld);
   const int64_t gc = C.cell_ids[cell];
@@ -1759,8 +1850,8 @@ __global__ __launch_bounds__(NT, 2) void k_herk(DevTables T, ChunkArgs C) {
 // K_aug = W^H W from the three-term bf16 splits of W^H on bf16 MFMA
 // (v_mfma_f32_16x16x32_bf16): for each real product X Y^T the terms
 // X_s Y_t with s + t <= 2 are kept (six products, ~24-bit operands); the
-// FP32 accumulators are folded into FP64 every 64 columns.  eta is not taken
-// from here (FP64 reduction in k_eta).
+// FP32 accumulators are folded into FP64 after every 32 columns.  eta is not
+// taken from here (FP64 reduction in k_eta).
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 constexpr int SKC = 32;              // k per stage
@@ -1886,24 +1977,28 @@ __global__ __launch_bounds__(NT, 2) void k_herk_split(DevTables T, ChunkArgs C) 
         Ai[t] = lds_frag(ss->A[3 + t], arow, kq);
         nAr[t] = neg_frag(Ar[t]);
       }
-      // re += Ar Br^T + Ai Bi^T ; im += Ai Br^T - Ar Bi^T   (terms with s + t <= 2)
+      // re += Ar Br^T + Ai Bi^T ; im += Ai Br^T - Ar Bi^T   (terms with s + t <= 2).
+      // The accumulators start each stage at zero and take the small terms
+      // first and the two leading (s = t = 0) products last, so that only
+      // those two roundings happen at the size of the stage's sum.
 #pragma unroll
-      for (int s2 = 0; s2 < 3; ++s2)
+      for (int o = 0; o < 6; ++o) {
+        // (s, t) = (2,0) (1,1) (0,2) (1,0) (0,1) (0,0)
+        const int s2 = o < 3 ? 2 - o : (o < 5 ? 4 - o : 0);
+        const int t2 = o < 3 ? o : (o < 5 ? o - 3 : 0);
 #pragma unroll
-        for (int t2 = 0; t2 + s2 < 3; ++t2) {
-#pragma unroll
-          for (int v = 0; v < 2; ++v) {
-            fr[u][v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ar[s2], Br[v][t2], fr[u][v], 0, 0, 0);
-            fi[u][v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ai[s2], Br[v][t2], fi[u][v], 0, 0, 0);
-          }
-#pragma unroll
-          for (int v = 0; v < 2; ++v) {
-            fr[u][v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ai[s2], Bi[v][t2], fr[u][v], 0, 0, 0);
-            fi[u][v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nAr[s2], Bi[v][t2], fi[u][v], 0, 0, 0);
-          }
+        for (int v = 0; v < 2; ++v) {
+          fr[u][v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ar[s2], Br[v][t2], fr[u][v], 0, 0, 0);
+          fi[u][v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ai[s2], Br[v][t2], fi[u][v], 0, 0, 0);
         }
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+          fr[u][v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ai[s2], Bi[v][t2], fr[u][v], 0, 0, 0);
+          fi[u][v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nAr[s2], Bi[v][t2], fi[u][v], 0, 0, 0);
+        }
+      }
     }
-    if ((sidx & 1) || sidx + 1 == nst) {
+    {
 #pragma unroll
       for (int u = 0; u < 2; ++u)
 #pragma unroll
@@ -1990,9 +2085,14 @@ __global__ __launch_bounds__(NT) void k_eta(DevTables T, ChunkArgs C) {
 }
 
 // ================================================================ parity extraction
-// Unscaled G (full Hermitian), B_f and l of each chunk cell from the workspace
-// (before factorisation).
-__global__ __launch_bounds__(NT) void k_extract(DevTables T, ChunkArgs C, double2* G, double2* Bf, double2* lv) {
+// G (full Hermitian, from the lower triangle), B_f and l of each chunk cell
+// from the workspace (before factorisation).  SCALED = false: the unscaled
+// forms (each entry divided by its Jacobi factors).  SCALED = true: the
+// Jacobi-scaled system exactly as the factorisation reads it, D G D, D B_f,
+// D l and D r (r = B_f x - l, zero without x), plus d = diag(G)^{-1/2}.
+template <bool SCALED>
+__global__ __launch_bounds__(NT) void k_extract(DevTables T, ChunkArgs C, double2* G, double2* Bf, double2* lv,
+                                                double2* rv, double* dv) {
   const int64_t cell = blockIdx.y;
   if (cell >= C.n) return;
   const int nv = 2 * T.N;
@@ -2006,19 +2106,23 @@ __global__ __launch_bounds__(NT) void k_extract(DevTables T, ChunkArgs C, double
     const int i = (int)(e % nv), jj = (int)(e / nv);
     const int zi = zrow(i), zj = zrow(jj);
     double2 v = (zi >= zj) ? Z[(int64_t)zj * ld + zi] : cconj(Z[(int64_t)zi * ld + zj]);
-    const double s = 1.0 / (d[zi] * d[zj]);
+    const double s = SCALED ? 1.0 : 1.0 / (d[zi] * d[zj]);
     G[cell * nG + e] = make_double2(v.x * s, v.y * s);
   } else if (e < nG + nB) {
     const int64_t f = e - nG;
     const int i = (int)(f % nv), a = (int)(f / nv);
     const int zi = zrow(i);
     const double2 v = cconj(Z[(int64_t)zi * ld + T.nvp + a]);
-    Bf[cell * nB + f] = make_double2(v.x / d[zi], v.y / d[zi]);
+    Bf[cell * nB + f] = SCALED ? v : make_double2(v.x / d[zi], v.y / d[zi]);
   } else if (e < nG + nB + nv) {
     const int i = (int)(e - nG - nB);
     const int zi = zrow(i);
     const double2 v = cconj(Z[(int64_t)zi * ld + T.nvp + T.k]);
-    lv[cell * nv + i] = make_double2(v.x / d[zi], v.y / d[zi]);
+    lv[cell * nv + i] = SCALED ? v : make_double2(v.x / d[zi], v.y / d[zi]);
+    if (SCALED) {
+      rv[cell * nv + i] = cconj(Z[(int64_t)zi * ld + T.nvp + T.k + 1]);
+      dv[cell * nv + i] = d[zi];
+    }
   }
 }
 
@@ -2097,12 +2201,15 @@ hipError_t launch_herk(const DevTables& t, const ChunkArgs& ca, hipStream_t st, 
 }
 
 hipError_t launch_extract(const DevTables& t, const ChunkArgs& ca, double2* G, double2* Bf, double2* lvec,
-                          hipStream_t st) {
+                          hipStream_t st, double2* rvec, double* dvec) {
   if (ca.n <= 0) return hipSuccess;
   const int64_t nv = 2 * t.N;
   const int64_t tot = nv * nv + nv * t.k + nv;
-  hipLaunchKernelGGL(k_extract, dim3((unsigned)((tot + NT - 1) / NT), (unsigned)ca.n), dim3(NT), 0, st, t, ca, G, Bf,
-                     lvec);
+  const dim3 grid((unsigned)((tot + NT - 1) / NT), (unsigned)ca.n);
+  if (rvec && dvec)
+    hipLaunchKernelGGL(k_extract<true>, grid, dim3(NT), 0, st, t, ca, G, Bf, lvec, rvec, dvec);
+  else
+    hipLaunchKernelGGL(k_extract<false>, grid, dim3(NT), 0, st, t, ca, G, Bf, lvec, rvec, dvec);
   return hipGetLastError();
 }
 

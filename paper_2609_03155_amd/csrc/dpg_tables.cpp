@@ -10,8 +10,10 @@
 // n dS = det J J^{-T} n_hat dS_hat, so the metric cancels pointwise).
 #include "dpg_tables.h"
 
+#include <algorithm>
 #include <cmath>
 #include <stdexcept>
+#include <thread>
 
 namespace dpg {
 
@@ -258,46 +260,75 @@ RefTables build_tables(int p, int dp) {
       }
   }
 
-  // geometry-free reference matrices
-  T.Cref.assign((size_t)d.N * d.N, 0.0);
-  for (int q = 0; q < d.nq; ++q) {
-    double w = T.vol_w[q];
-    for (int i = 0; i < d.N; ++i) {
-      const double* ci = &T.vol_c[((size_t)q * d.Np + i) * 3];
-      for (int j = 0; j < d.N; ++j)
-        T.Cref[(size_t)i * d.N + j] += w * ci[tf[j].comp] * T.vol_v[(size_t)q * d.Np + j];
-    }
-  }
-  T.Rt.assign((size_t)6 * d.N * d.N, 0.0);
-  T.T.assign((size_t)6 * d.N * d.nt1, 0.0);
+  // geometry-free reference matrices; the quadrature sums run in long double
+  // (a 64-bit significand), so that each entry is the correctly rounded FP64
+  // value of the rule's sum of the FP64 basis values (up to thousands of
+  // terms at p = 4, where FP64 accumulation would carry several ulps).  Rows
+  // are independent: host threads take interleaved rows.
+  std::vector<double> fpsi((size_t)6 * d.nfq * d.N * 3, 0.0), fnpsi(fpsi.size()), fnth((size_t)6 * d.nfq * d.nt1 * 3);
   for (int f = 0; f < 6; ++f) {
-    int nax = f / 2, side = f % 2;
     double nh[3] = {0, 0, 0};
-    nh[nax] = side ? 1.0 : -1.0;
+    nh[f / 2] = (f % 2) ? 1.0 : -1.0;
     for (int fq = 0; fq < d.nfq; ++fq) {
-      double w = T.face_w[f * d.nfq + fq];
-      const double* X = &T.face_pts[(f * d.nfq + fq) * 3];
-      std::vector<double> psi((size_t)d.N * 3, 0.0), npsi((size_t)d.N * 3), th((size_t)d.nt1 * 3), nth((size_t)d.nt1 * 3);
+      const size_t o = (size_t)f * d.nfq + fq;
+      const double* X = &T.face_pts[o * 3];
       for (int i = 0; i < d.N; ++i) {
-        psi[3 * i + tf[i].comp] = T.face_v[((size_t)f * d.nfq + fq) * d.Np + i];
-        cross(nh, &psi[3 * i], &npsi[3 * i]);
+        double* ps = &fpsi[(o * d.N + i) * 3];
+        ps[tf[i].comp] = T.face_v[o * d.Np + i];
+        cross(nh, ps, &fnpsi[(o * d.N + i) * 3]);
       }
       for (int j = 0; j < d.nt1; ++j) {
-        eval_trace(trf[j], d.r, X, &th[3 * j]);
-        cross(nh, &th[3 * j], &nth[3 * j]);
-      }
-      for (int i = 0; i < d.N; ++i) {
-        for (int j = 0; j < d.N; ++j) {
-          double s = npsi[3 * i] * psi[3 * j] + npsi[3 * i + 1] * psi[3 * j + 1] + npsi[3 * i + 2] * psi[3 * j + 2];
-          T.Rt[((size_t)f * d.N + i) * d.N + j] += w * s;
-        }
-        for (int j = 0; j < d.nt1; ++j) {
-          double s = psi[3 * i] * nth[3 * j] + psi[3 * i + 1] * nth[3 * j + 1] + psi[3 * i + 2] * nth[3 * j + 2];
-          T.T[((size_t)f * d.N + i) * d.nt1 + j] += w * s;
-        }
+        double th[3];
+        eval_trace(trf[j], d.r, X, th);
+        cross(nh, th, &fnth[(o * d.nt1 + j) * 3]);
       }
     }
   }
+  T.Cref.assign((size_t)d.N * d.N, 0.0);
+  T.Rt.assign((size_t)6 * d.N * d.N, 0.0);
+  T.T.assign((size_t)6 * d.N * d.nt1, 0.0);
+  auto rows = [&](int i0, int step) {
+    std::vector<long double> acc((size_t)std::max(d.N, d.nt1));
+    for (int i = i0; i < d.N; i += step) {
+      std::fill(acc.begin(), acc.end(), 0.0L);
+      for (int q = 0; q < d.nq; ++q) {
+        const long double wc = (long double)T.vol_w[q];
+        const double* ci = &T.vol_c[((size_t)q * d.Np + i) * 3];
+        const double* vq = &T.vol_v[(size_t)q * d.Np];
+        for (int j = 0; j < d.N; ++j) acc[j] += wc * (long double)ci[tf[j].comp] * (long double)vq[j];
+      }
+      for (int j = 0; j < d.N; ++j) T.Cref[(size_t)i * d.N + j] = (double)acc[j];
+      for (int f = 0; f < 6; ++f) {
+        std::fill(acc.begin(), acc.end(), 0.0L);
+        for (int fq = 0; fq < d.nfq; ++fq) {
+          const size_t o = (size_t)f * d.nfq + fq;
+          const long double w = (long double)T.face_w[o];
+          const double* ni = &fnpsi[(o * d.N + i) * 3];
+          for (int j = 0; j < d.N; ++j) {
+            const double* pj = &fpsi[(o * d.N + j) * 3];
+            acc[j] += w * ((long double)ni[0] * pj[0] + (long double)ni[1] * pj[1] + (long double)ni[2] * pj[2]);
+          }
+        }
+        for (int j = 0; j < d.N; ++j) T.Rt[((size_t)f * d.N + i) * d.N + j] = (double)acc[j];
+        std::fill(acc.begin(), acc.end(), 0.0L);
+        for (int fq = 0; fq < d.nfq; ++fq) {
+          const size_t o = (size_t)f * d.nfq + fq;
+          const long double w = (long double)T.face_w[o];
+          const double* pi = &fpsi[(o * d.N + i) * 3];
+          for (int j = 0; j < d.nt1; ++j) {
+            const double* nj = &fnth[(o * d.nt1 + j) * 3];
+            acc[j] += w * ((long double)pi[0] * nj[0] + (long double)pi[1] * nj[1] + (long double)pi[2] * nj[2]);
+          }
+        }
+        for (int j = 0; j < d.nt1; ++j) T.T[((size_t)f * d.N + i) * d.nt1 + j] = (double)acc[j];
+      }
+    }
+  };
+  const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nth; ++t) pool.emplace_back(rows, t, nth);
+  rows(0, nth);
+  for (auto& th : pool) th.join();
   return T;
 }
 

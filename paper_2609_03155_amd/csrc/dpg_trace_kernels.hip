@@ -387,14 +387,16 @@ __global__ __launch_bounds__(NT) void k_recon_load(DevTables T, ChunkArgs C, Con
 }
 
 // Backward substitution per cell (one workgroup): z = L^{-H} y with y the
-// conjugate of row nvp and L stored as Linv_jj on the diagonal tiles and
-// L_ij below them; for column blocks J = nvb-1 .. 0
-//   s_J = y_J - sum_{I > J} L_IJ^H z_I,   z_J = Linv_JJ^H s_J ;
-// then x_e = [D z (first nu) ; t_K].  Each wave takes 16 columns of block J,
-// its lanes run down a column (contiguous), and one butterfly per column
-// sums the lanes (fixed order).
+// conjugate of row nvp and L stored by the factorisation (L_ij below the
+// diagonal tiles; on them L_jj below the 16x16 block diagonal and the
+// inverses of its diagonal blocks); for column blocks J = nvb-1 .. 0
+//   s_J = y_J - sum_{I > J} L_IJ^H z_I,   L_JJ^H z_J = s_J ;
+// then x_e = [D z (first nu) ; t_K].  For s_J each wave takes 16 columns of
+// block J, its lanes run down a column (contiguous), and one butterfly per
+// column sums the lanes (fixed order); the tile's own substitution is small
+// and runs on one wave.
 __global__ __launch_bounds__(NT) void k_recon_back(DevTables T, ChunkArgs C, CondArgs A) {
-  extern __shared__ double2 zs[];   // [nvp] z, then [64] s of the current block
+  extern __shared__ double2 zs[];   // [nvp] z, then [64] s and [64] t of the current block
   const int64_t cell = blockIdx.x;
   if (cell >= C.n) return;
   const int64_t gc = C.cell_ids[cell];
@@ -424,17 +426,41 @@ __global__ __launch_bounds__(NT) void k_recon_back(DevTables T, ChunkArgs C, Con
       }
     }
     __syncthreads();
-    for (int cc = 0; cc < 16; ++cc) {
-      const int c = wave * 16 + cc;
-      const double2 l = Z[(int64_t)(J * TB + c) * ld + J * TB + lane];   // Linv_JJ[lane, c] (0 above the diagonal)
-      const double2 s = sb[lane];
-      double re = l.x * s.x + l.y * s.y, im = l.x * s.y - l.y * s.x;
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        re += __shfl_xor(re, off, 64);
-        im += __shfl_xor(im, off, 64);
+    // L_JJ^H z_J = s_J by backward substitution over the tile's four 16-row
+    // blocks m (the factorisation stores L_JJ below the block diagonal and the
+    // inverses Dinv of its diagonal blocks on it):
+    //   t = s[m] - sum_{m2 > m} L_JJ[m2][m]^H z[m2],  z[m] = Dinv[m]^H t.
+    if (wave == 0) {
+      const double2* tile = Z + (int64_t)(J * TB) * ld + J * TB;   // column c at tile + c ld
+      double2* tb = sb + TB;                                        // [64] t of the current block
+      for (int m = 3; m >= 0; --m) {
+        if (lane < 16) {
+          const int c = 16 * m + lane;
+          double re = sb[c].x, im = sb[c].y;
+          for (int r = 16 * (m + 1); r < TB; ++r) {
+            const double2 l = tile[(int64_t)c * ld + r], z = zs[J * TB + r];
+            re -= l.x * z.x + l.y * z.y;   // conj(l) z
+            im -= l.x * z.y - l.y * z.x;
+          }
+          tb[c] = make_double2(re, im);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (lane < 16) {
+          const int c = 16 * m + lane;
+          double re = 0.0, im = 0.0;
+          for (int r = c; r < 16 * (m + 1); ++r) {
+            const double2 l = tile[(int64_t)c * ld + r], t = tb[r];
+            re += l.x * t.x + l.y * t.y;
+            im += l.x * t.y - l.y * t.x;
+          }
+          zs[J * TB + c] = make_double2(re, im);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
       }
-      if (lane == 0) zs[J * TB + c] = make_double2(re, im);
     }
     __syncthreads();
   }
@@ -588,7 +614,7 @@ hipError_t launch_recon_load(const DevTables& t, const ChunkArgs& ca, const Cond
 
 hipError_t launch_recon_back(const DevTables& t, const ChunkArgs& ca, const CondArgs& a, hipStream_t st) {
   if (ca.n <= 0) return hipSuccess;
-  const size_t smem = sizeof(double2) * ((size_t)t.nvp + TB);
+  const size_t smem = sizeof(double2) * ((size_t)t.nvp + 2 * TB);
   hipLaunchKernelGGL(k_recon_back, dim3((unsigned)ca.n), dim3(NT), smem, st, t, ca, a);
   return hipGetLastError();
 }

@@ -23,6 +23,7 @@ FACE_INTERIOR, FACE_PEC, FACE_PORT, FACE_ROBIN0 = 0, 1, 2, 3
 EXPORTS = ("dpg_local_dims", "dpg_plan_create", "dpg_plan_destroy", "dpg_plan_offsets", "dpg_plan_layout",
            "dpg_local_solve", "dpg_local_solve_range", "dpg_plan_set_concurrency", "dpg_plan_autotune",
            "dpg_plan_tuning", "dpg_graph_create", "dpg_graph_launch", "dpg_graph_destroy", "dpg_form_local",
+           "dpg_form_augmented",
            "dpg_plan_trace_offsets", "dpg_condense", "dpg_trace_numbering", "dpg_trace_system_create",
            "dpg_trace_system_destroy", "dpg_trace_system_info", "dpg_trace_system_numbering", "dpg_trace_system_csr",
            "dpg_assemble", "dpg_csr_matvec", "dpg_cg_solve", "dpg_trace_system_scatter", "dpg_reconstruct",
@@ -73,6 +74,7 @@ def lib():
         L.dpg_graph_launch.argtypes = [vp, vp]
         L.dpg_graph_destroy.argtypes = [vp]
         L.dpg_form_local.argtypes = [vp, C.POINTER(dpg_problem), i64, i64, vp, vp, vp, vp, vp]
+        L.dpg_form_augmented.argtypes = [vp, C.POINTER(dpg_problem), i64, i64, vp, vp, vp, vp, vp, vp, vp, vp]
         L.dpg_plan_trace_offsets.argtypes = [vp, vp, vp]
         L.dpg_condense.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.dpg_trace_numbering.argtypes = [vp, vp, vp, i64, vp, C.POINTER(i64)]
@@ -322,6 +324,27 @@ class Plan:
                                     _ptr(info), _stream(stream)), "dpg_form_local")
         # column-major per cell: G[c][col][row] -> transpose to [row][col]
         return G.transpose(1, 2), Bf.transpose(1, 2), lv, info
+
+    def form_augmented(self, prob: DeviceProblem, first: int, count: int, x=None, stream=None):
+        """dpg_form_augmented: the Jacobi-scaled D G D, D B_f, D l, D r and d of
+        cells first..first+count-1 (same degree); x holds the range's
+        coefficients (or None: r = 0)."""
+        import torch
+        p = int(self.degree[first])
+        nt, nu, ntr = dpg_local_dims(p, self.dp)
+        k = nu + ntr
+        dev = prob.vertices.device
+        G = torch.empty((count, nt, nt), dtype=torch.complex128, device=dev)
+        Bf = torch.empty((count, k, nt), dtype=torch.complex128, device=dev)
+        lv = torch.empty((count, nt), dtype=torch.complex128, device=dev)
+        rv = torch.empty((count, nt), dtype=torch.complex128, device=dev)
+        d = torch.empty((count, nt), dtype=torch.float64, device=dev)
+        info = torch.zeros(count, dtype=torch.int32, device=dev)
+        s = prob.cstruct()
+        _check(lib().dpg_form_augmented(self._h, C.byref(s), int(first), int(count), _ptr(x), _ptr(G), _ptr(Bf),
+                                        _ptr(lv), _ptr(rv), _ptr(d), _ptr(info), _stream(stream)),
+               "dpg_form_augmented")
+        return G.transpose(1, 2), Bf.transpose(1, 2), lv, rv, d, info
 
 
 def trace_numbering(cells, face_kind, degree):
