@@ -1,16 +1,25 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
 
-Tolerances (FP64 path).  The oracle solves with LU, the GPU with a
-Jacobi-scaled blocked Cholesky; both are backward stable, so each carries a
-forward error of order kappa(D G D) * u.  The bar per cell is
-    tol = max(1e-10, 4 kappa(D G D) u),   u = 2^-53,
-i.e. 1e-10 wherever FP64 can deliver it and the FP64 floor where the Gram
-matrix is worse conditioned (kappa ~ 1e6-1e7 for the lossy eps ~ 10 cells of
-the WR340 workload, where the oracle's own LU result is ~1.5e-10 from an
-extended-precision solve).  Measured on
-  K_e : ||K_gpu - K_or||_F / ||K_or||_F
-  l_e : ||.||_2 relative
-  eta : |d eta| / eta_or
+Every entry is compared on its own scale.  K_e = W^H W is Hermitian
+positive semidefinite, so |K_ab| <= sqrt(K_aa K_bb) and |l_e,a| <=
+sqrt(K_aa) ||y||; the errors are
+    max_ab |dK_ab| / sqrt(K_aa K_bb),   max_a |dl_a| / (sqrt(K_aa) ||y||),
+    |d eta| / eta,
+so the interior block M1 (which the condensation inverts) counts as much as
+the trace block, whose entries are up to 1e5 larger.  The H-hat rows of
+functions that live only on Robin faces must be exactly zero.
+
+Bars (see _oracle_cases.OracleRef; every reference is computed by oracle/
+alone):
+  FP64 path   max(1e-10, 2 (e_or + s_form)) per output, with e_or the
+              larger FP64 solve error of the oracle's two solve routes (LU;
+              Jacobi-scaled Cholesky), against an extended-precision solve
+              of the oracle's FP64 system, and s_form the distance
+              between the exact solves of the oracle's two formation routes
+              (pointwise, and by App. A's real block matrices: the floor
+              formation roundoff sets for any FP64 implementation;
+              kappa(D G D) ~ 1e6-3e7 here);
+  split path  1e-6 element-wise on K_e and l_e (plus the FP64 bar), eta FP64.
 The local matrices G, B_f, l (before the solve) agree to 1e-12 of their
 largest entry.
 """
@@ -22,7 +31,7 @@ import pytest
 
 from paper_2609_03155_amd import workloads as W
 
-from _oracle_cases import fp64_tol, oracle_cell, rel
+from _oracle_cases import OracleRef, check_fp64, check_split, oracle_cell, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -57,6 +66,13 @@ def _cell_out(plan, K, l, c):
     k = int(plan.v_off[c + 1] - plan.v_off[c])
     Kc = K[plan.K_off[c]:plan.K_off[c + 1]].reshape(k, k).T
     return Kc, l[plan.v_off[c]:plan.v_off[c + 1]]
+
+
+def _report(tag, ref, e):
+    """One line per checked cell (the per-block errors quoted in the design notes)."""
+    import json
+    row = dict(tag=tag, **ref.summary(), err={k: v for k, v in e.items() if k != "blocks"}, blocks=e["blocks"])
+    _say("ACC " + json.dumps(row))
 
 
 def test_form_local_matches_oracle_config1():
@@ -102,12 +118,9 @@ def test_local_solve_config1_all_cells():
     assert np.all(info == 0)
     assert np.array_equal(plan.v_off, off)
     for c in range(w.n_cells):
-        Go, _, _, Ko, lo, eo = oracle_cell(w, c, x[off[c]:off[c + 1]])
-        tol = fp64_tol(Go)
+        ref = OracleRef(w, c, x[off[c]:off[c + 1]])
         Kg, lg = _cell_out(plan, K, l, c)
-        assert rel(Kg, Ko) < tol, (c, rel(Kg, Ko), tol)
-        assert rel(lg, lo) < tol, (c, rel(lg, lo), tol)
-        assert abs(eta[c] - eo) < tol * eo, (c, abs(eta[c] - eo) / eo, tol)
+        _report("c1 fp64", ref, check_fp64(ref, Kg, lg, eta[c], f"c1 cell {c}"))
 
 
 def test_local_solve_without_coefficients_gives_zero_eta():
@@ -127,19 +140,24 @@ def c2_full():
     return w, x, off, plan, K, l, eta, info
 
 
+# WR340 cells: port face with two PEC walls (corners 0 and 15), outlet
+# corner 4992, the last cell, and seeded interior cells
+C2_CELLS = (0, 15, 4992, 5119)
+
+
+def _c2_sample(w):
+    rng = np.random.default_rng(W.SEED_BASE + 22)
+    return sorted(set(C2_CELLS + tuple(int(c) for c in rng.choice(w.n_cells, 2, replace=False))))
+
+
 def test_local_solve_config2_sampled(c2_full):
     w, x, off, plan, K, l, eta, info = c2_full
     assert np.all(info == 0)
     assert np.all(np.isfinite(eta))
-    rng = np.random.default_rng(W.SEED_BASE + 22)
-    sample = sorted(set([0, w.n_cells - 1] + list(rng.choice(w.n_cells, 4, replace=False))))
-    for c in sample:
-        Go, _, _, Ko, lo, eo = oracle_cell(w, c, x[off[c]:off[c + 1]])
-        tol = fp64_tol(Go)
+    for c in _c2_sample(w):
+        ref = OracleRef(w, c, x[off[c]:off[c + 1]])
         Kg, lg = _cell_out(plan, K, l, c)
-        assert rel(Kg, Ko) < tol, (c, rel(Kg, Ko), tol)
-        assert rel(lg, lo) < tol, (c, rel(lg, lo), tol)
-        assert abs(eta[c] - eo) < tol * eo, (c, abs(eta[c] - eo) / eo, tol)
+        _report("c2 fp64", ref, check_fp64(ref, Kg, lg, eta[c], f"c2 cell {c}"))
 
 
 def test_local_solve_config2_properties_all_cells(c2_full):
@@ -160,12 +178,9 @@ def test_mixed_degrees_and_enrichment():
     plan, K, l, eta, info = _run(w, x)
     assert np.all(info == 0)
     for c in (0, 1, 2, 3, 17, 35):
-        Go, _, _, Ko, lo, eo = oracle_cell(w, c, x[off[c]:off[c + 1]])
-        tol = fp64_tol(Go)
+        ref = OracleRef(w, c, x[off[c]:off[c + 1]])
         Kg, lg = _cell_out(plan, K, l, c)
-        assert rel(Kg, Ko) < tol, (c, w.degree[c], rel(Kg, Ko), tol)
-        assert rel(lg, lo) < tol, (c, w.degree[c], rel(lg, lo), tol)
-        assert abs(eta[c] - eo) < tol * eo, (c, w.degree[c])
+        _report("mixed fp64", ref, check_fp64(ref, Kg, lg, eta[c], f"mixed cell {c} p={w.degree[c]}"))
 
 
 def test_high_order_p4_dp2():
@@ -175,12 +190,9 @@ def test_high_order_p4_dp2():
     plan, K, l, eta, info = _run(w, x)
     assert np.all(info == 0)
     for c in (0, 7):
-        Go, _, _, Ko, lo, eo = oracle_cell(w, c, x[off[c]:off[c + 1]])
-        tol = fp64_tol(Go)
+        ref = OracleRef(w, c, x[off[c]:off[c + 1]])
         Kg, lg = _cell_out(plan, K, l, c)
-        assert rel(Kg, Ko) < tol, (c, rel(Kg, Ko), tol)
-        assert rel(lg, lo) < tol, (c, rel(lg, lo), tol)
-        assert abs(eta[c] - eo) < tol * eo, (c, abs(eta[c] - eo) / eo, tol)
+        _report("p4dp2 fp64", ref, check_fp64(ref, Kg, lg, eta[c], f"p4dp2 cell {c}"))
 
 
 def test_chunked_workspace_matches_single_chunk():
@@ -264,9 +276,9 @@ def test_degenerate_cell_reports_info_and_others_unaffected():
     plan, K, l, eta, info = _run(w2, x)
     assert info[3] == -1
     assert np.all(np.delete(info, 3) == 0)
-    Go, _, _, Ko, lo, eo = oracle_cell(w2, 0, x[off[0]:off[1]])
+    ref = OracleRef(w2, 0, x[off[0]:off[1]])
     Kg, lg = _cell_out(plan, K, l, 0)
-    assert rel(Kg, Ko) < fp64_tol(Go)
+    check_fp64(ref, Kg, lg, eta[0], "cell 0 next to a degenerate cell")
 
 
 def test_argument_errors_are_synchronous():
@@ -303,17 +315,11 @@ def test_empty_batch():
 
 
 # ------------------------------------------------------------ split precision
-SPLIT_TOL = 1e-6     # required bar of the split path for K_e and l_e; eta stays FP64
-
-
-def _check_split(w, cells, plan, K, l, eta, x, off):
+def _check_split(w, cells, plan, K, l, eta, x, off, tag):
     for c in cells:
-        Go, _, _, Ko, lo, eo = oracle_cell(w, c, x[off[c]:off[c + 1]])
+        ref = OracleRef(w, c, x[off[c]:off[c + 1]])
         Kg, lg = _cell_out(plan, K, l, c)
-        assert rel(Kg, Ko) < SPLIT_TOL, (c, rel(Kg, Ko))
-        if np.linalg.norm(lo) > 0:
-            assert rel(lg, lo) < SPLIT_TOL, (c, rel(lg, lo))
-        assert abs(eta[c] - eo) < fp64_tol(Go) * eo, (c, abs(eta[c] - eo) / eo)
+        _report(tag, ref, check_split(ref, Kg, lg, eta[c], f"{tag} cell {c}"))
 
 
 def test_split_precision_config1():
@@ -322,7 +328,7 @@ def test_split_precision_config1():
     _say("case: dpg_local_solve split precision config1")
     plan, K, l, eta, info = _run(w, x, precision=1)
     assert np.all(info == 0)
-    _check_split(w, range(w.n_cells), plan, K, l, eta, x, off)
+    _check_split(w, range(w.n_cells), plan, K, l, eta, x, off, "c1 split")
 
 
 def test_split_precision_config2_sampled():
@@ -331,9 +337,7 @@ def test_split_precision_config2_sampled():
     _say("case: dpg_local_solve split precision config2 full (5120 cells)")
     plan, K, l, eta, info = _run(w, x, precision=1)
     assert np.all(info == 0)
-    rng = np.random.default_rng(W.SEED_BASE + 23)
-    _check_split(w, sorted(set([0, w.n_cells - 1] + list(rng.choice(w.n_cells, 4, replace=False)))), plan, K, l,
-                 eta, x, off)
+    _check_split(w, _c2_sample(w), plan, K, l, eta, x, off, "c2 split")
 
 
 def test_split_precision_mixed_degrees():
@@ -343,7 +347,16 @@ def test_split_precision_mixed_degrees():
     _say("case: dpg_local_solve split precision mixed p 1..4")
     plan, K, l, eta, info = _run(w, x, precision=1)
     assert np.all(info == 0)
-    _check_split(w, (0, 1, 2, 3), plan, K, l, eta, x, off)
+    _check_split(w, (0, 1, 2, 3, 17, 35), plan, K, l, eta, x, off, "mixed split")
+
+
+def test_split_precision_p4_dp2():
+    w = W.config4(n=2)
+    x, off = W.random_coefficients(w)
+    _say("case: dpg_local_solve split precision p=4 dp=2 (8 cells)")
+    plan, K, l, eta, info = _run(w, x, precision=1)
+    assert np.all(info == 0)
+    _check_split(w, range(w.n_cells), plan, K, l, eta, x, off, "p4dp2 split")
 
 
 # ------------------------------------------------------------ batching, graphs, autotuner
@@ -535,78 +548,82 @@ def test_assembly_and_matvec_match_oracle():
 
 
 # ------------------------------------------------------------ full-size workloads (sampled)
-def _sampled_full(w, cells):
+def _full_outputs(w, cells, first=0, count=None):
+    """Solves cells [first, first + count) of the full workload in both
+    precisions (range-relative outputs, as the streamed workload needs) and
+    returns {precision: {cell: (K_e, l_e, eta)}} for the sampled cells; every
+    cell's info is 0 and every eta finite and nonnegative."""
     torch = _torch()
     from paper_2609_03155_amd import dpg
     torch.cuda.empty_cache()
+    count = w.n_cells - first if count is None else count
     x, off = W.random_coefficients(w)
     plan = dpg.Plan(w.degree, w.dp)
     prob = dpg.DeviceProblem.from_workload(w)
-    K, l, eta, info = plan.alloc_outputs()
-    xd = torch.from_numpy(x).cuda()
-    plan.local_solve(prob, xd, K, l, eta, info)
-    torch.cuda.synchronize()
-    ih = info.cpu().numpy()
-    assert np.all(ih == 0)
-    eh = eta.cpu().numpy()
-    assert np.all(np.isfinite(eh)) and np.all(eh >= 0)
+    nK, nv = plan.range_sizes(first, count)
+    xr = torch.from_numpy(x[off[first]:off[first + count]].copy()).cuda()
+    out = {}
+    for name, prec in (("fp64", dpg.DPG_FP64), ("split", dpg.DPG_SPLIT_FP32)):
+        K = torch.empty(nK, dtype=torch.complex128, device="cuda")
+        l = torch.empty(nv, dtype=torch.complex128, device="cuda")
+        eta = torch.empty(count, dtype=torch.float64, device="cuda")
+        info = torch.empty(count, dtype=torch.int32, device="cuda")
+        plan.local_solve_range(prob, first, count, xr, K, l, eta, info, prec)
+        torch.cuda.synchronize()
+        assert np.all(info.cpu().numpy() == 0), name
+        eh = eta.cpu().numpy()
+        assert np.all(np.isfinite(eh)) and np.all(eh >= 0), name
+        out[name] = {}
+        for c in cells:
+            k = int(off[c + 1] - off[c])
+            a = int(plan.K_off[c] - plan.K_off[first])
+            b = int(off[c] - off[first])
+            out[name][c] = (K[a:a + k * k].cpu().numpy().reshape(k, k).T, l[b:b + k].cpu().numpy(), float(eh[c - first]))
+        del K, l, eta, info
+    plan.close()
+    return x, off, out
+
+
+def _check_full(w, cells, tag, first=0, count=None):
+    x, off, out = _full_outputs(w, cells, first, count)
     for c in cells:
-        Go, _, _, Ko, lo, eo = oracle_cell(w, c, x[off[c]:off[c + 1]])
-        tol = fp64_tol(Go)
-        k = int(off[c + 1] - off[c])
-        Kg = K[int(plan.K_off[c]):int(plan.K_off[c + 1])].cpu().numpy().reshape(k, k).T
-        lg = l[int(off[c]):int(off[c + 1])].cpu().numpy()
-        assert rel(Kg, Ko) < tol, (c, rel(Kg, Ko), tol)
-        if np.linalg.norm(lo) > 0:
-            assert rel(lg, lo) < tol, (c, rel(lg, lo), tol)
-        assert abs(eh[c] - eo) < tol * eo, (c, abs(eh[c] - eo) / eo, tol)
-    del K, l
+        ref = OracleRef(w, c, x[off[c]:off[c + 1]])
+        _report(f"{tag} fp64", ref, check_fp64(ref, *out["fp64"][c], f"{tag} fp64 cell {c}"))
+        _report(f"{tag} split", ref, check_split(ref, *out["split"][c], f"{tag} split cell {c}"))
 
 
 def test_config3_full_size_sampled():
+    """Mixed degrees at full size: one cell of each degree, a seeded one, the ends."""
     w = W.config3()
     rng = np.random.default_rng(W.SEED_BASE + 33)
-    cells = sorted(set([0, w.n_cells - 1] + [int(c) for c in rng.choice(w.n_cells, 3, replace=False)]
-                       + [int(np.nonzero(w.degree == 4)[0][0])]))
-    _say(f"case: config3 full size (20000 cells, p 1..4), oracle on cells {cells}")
-    _sampled_full(w, cells)
+    cells = sorted(set([0, w.n_cells - 1] + [int(rng.integers(w.n_cells))]
+                       + [int(np.nonzero(w.degree == p)[0][0]) for p in (1, 2, 3, 4)]))
+    _say(f"case: config3 full size (20000 cells, p 1..4), both precisions, oracle on cells {cells}")
+    _check_full(w, cells, "c3")
 
 
 def test_config4_full_size_sampled():
+    """p = 4, dp = 2 at full size: the port/PEC corner cell 0, the first
+    hot-spot cell (tan d = 1) on the port, a hot spot inside the box."""
     w = W.config4()
-    rng = np.random.default_rng(W.SEED_BASE + 34)
-    cells = sorted(set([w.n_cells - 1] + [int(c) for c in rng.choice(w.n_cells, 1, replace=False)]))
-    _say(f"case: config4 full size (4096 cells, p=4 dp=2), oracle on cells {cells}")
-    _sampled_full(w, cells)
+    td = np.imag(w.eps) / np.real(w.eps)
+    hot = [int(c) for c in np.nonzero(np.isclose(td, 1.0))[0]]
+    fk = w.face_kind
+    assert (fk[0] == 2).any() and (fk[0] == 1).sum() == 2            # port + two PEC walls
+    hot_port = [c for c in hot if (fk[c] == 2).any()][0]
+    hot_in = [c for c in hot if (fk[c] == 0).all()][0]
+    cells = sorted({0, hot_port, hot_in})
+    _say(f"case: config4 full size (4096 cells, p=4 dp=2), both precisions, oracle on cells {cells}")
+    _check_full(w, cells, "c4")
 
 
 def test_config5_streamed_range_sampled():
     """The 262144-cell curved workload is solved in ranges (its K_e do not
-    fit); one 8192-cell range at the end of the mesh, sampled against the oracle."""
-    torch = _torch()
-    from paper_2609_03155_amd import dpg
+    fit); one 8192-cell range at the end of the mesh (outlet cells), both
+    precisions, sampled against the oracle."""
     w = W.config5()
-    x, off = W.random_coefficients(w)
-    torch.cuda.empty_cache()
-    plan = dpg.Plan(w.degree, w.dp)
-    prob = dpg.DeviceProblem.from_workload(w)
     first, count = w.n_cells - 8192, 8192
-    nK, nv = plan.range_sizes(first, count)
-    K = torch.empty(nK, dtype=torch.complex128, device="cuda")
-    l = torch.empty(nv, dtype=torch.complex128, device="cuda")
-    eta = torch.empty(count, dtype=torch.float64, device="cuda")
-    info = torch.empty(count, dtype=torch.int32, device="cuda")
-    xr = torch.from_numpy(x[off[first]:off[first + count]].copy()).cuda()
-    _say("case: config5 range solve of the last 8192 cells (p 2/3, curved)")
-    plan.local_solve_range(prob, first, count, xr, K, l, eta, info)
-    torch.cuda.synchronize()
-    assert np.all(info.cpu().numpy() == 0)
     rng = np.random.default_rng(W.SEED_BASE + 35)
-    for c in sorted(set([w.n_cells - 1] + [first + int(q) for q in rng.choice(count, 1, replace=False)])):
-        Go, _, _, Ko, lo, eo = oracle_cell(w, c, x[off[c]:off[c + 1]])
-        tol = fp64_tol(Go)
-        k = int(off[c + 1] - off[c])
-        a = int(plan.K_off[c] - plan.K_off[first])
-        Kg = K[a:a + k * k].cpu().numpy().reshape(k, k).T
-        assert rel(Kg, Ko) < tol, (c, rel(Kg, Ko), tol)
-        assert abs(float(eta[c - first]) - eo) < tol * eo
+    cells = sorted(set([w.n_cells - 1, first] + [first + int(q) for q in rng.choice(count, 1, replace=False)]))
+    _say(f"case: config5 range solve of the last 8192 cells (p 2/3, curved), both precisions, oracle on {cells}")
+    _check_full(w, cells, "c5", first, count)
