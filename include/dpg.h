@@ -418,6 +418,21 @@ dpg_status dpg_power_dissipation(dpg_plan plan, const dpg_problem* prob, const d
 dpg_status dpg_dorfler_mark(int64_t n, const double* values, double refine_fraction, double coarsen_fraction,
                             int8_t* flags, void* stream);
 
+/* Dörfler marking without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same flags as dpg_dorfler_mark
+ * (bit for bit) with the same arguments, but its temporaries (sort keys and
+ * cell ids, chunk sums, the sort's own temporaries) live in a static device
+ * array of 64 MiB on every GPU the library runs on, held until the process
+ * ends; its device address is looked up once per device on the first call.
+ * n <= 1048576 (2^20) cells; larger n, or temporaries beyond the array,
+ * return DPG_ERR_UNSUPPORTED before anything is enqueued.  Stream-ordered:
+ * returns without synchronising.  Every call on one GPU uses that GPU's one
+ * array, so calls that overlap in time on the same GPU race (order them on
+ * one stream).  Other errors as dpg_dorfler_mark. */
+dpg_status dpg_dorfler_mark_noalloc(int64_t n, const double* values, double refine_fraction,
+                                    double coarsen_fraction, int8_t* flags, void* stream);
+
 /* Kernel classes timed by the plan's optional profiler. */
 enum {
   DPG_K_SCALE = 0,      /* geometry check and Jacobi scaling            */

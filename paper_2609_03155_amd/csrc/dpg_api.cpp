@@ -1048,6 +1048,35 @@ dpg_status dpg_dorfler_mark(int64_t n, const double* values, double refine_fract
   return DPG_OK;
 }
 
+dpg_status dpg_dorfler_mark_noalloc(int64_t n, const double* values, double refine_fraction,
+                                    double coarsen_fraction, int8_t* flags, void* stream) {
+  if (n < 0 || n > INT32_MAX || !(refine_fraction >= 0.0 && refine_fraction <= 1.0) ||
+      !(coarsen_fraction >= 0.0 && coarsen_fraction <= 1.0))
+    return DPG_ERR_ARG;
+  if (n == 0) return DPG_OK;
+  if (!values || !flags) return DPG_ERR_ARG;
+  if (n > dpg::kMarkMaxCells) {
+    std::snprintf(g_last_error, sizeof(g_last_error),
+                  "dpg_dorfler_mark_noalloc: %lld cells exceed the static scratch limit of %lld",
+                  (long long)n, (long long)dpg::kMarkMaxCells);
+    return DPG_ERR_UNSUPPORTED;
+  }
+  bool too_large = false;
+  const hipError_t e = dpg::dorfler_mark_noalloc(n, values, refine_fraction, coarsen_fraction, flags,
+                                                 reinterpret_cast<hipStream_t>(stream), &too_large);
+  if (e != hipSuccess) {
+    set_error("dpg_dorfler_mark_noalloc", e);
+    return DPG_ERR_HIP;
+  }
+  if (too_large) {
+    std::snprintf(g_last_error, sizeof(g_last_error),
+                  "dpg_dorfler_mark_noalloc: the temporaries of %lld cells exceed the static scratch of %zu bytes",
+                  (long long)n, dpg::kMarkScratchBytes);
+    return DPG_ERR_UNSUPPORTED;
+  }
+  return DPG_OK;
+}
+
 dpg_status dpg_reconstruct(dpg_plan plan, const double* K, const double* l, const double* t_local, double* x,
                            int32_t* info, void* stream) {
   if (!plan) return DPG_ERR_ARG;

@@ -167,6 +167,14 @@ hipError_t launch_power(const DevTables& t, const ProbArgs& pa, const int64_t* c
 // Dörfler marking: flags[i] = +1 (refine), -1 (coarsen) or 0 from values[i]
 // (n cells); allocates its temporaries and synchronises the stream.
 hipError_t dorfler_mark(int64_t n, const double* values, double fr, double fc, int8_t* flags, hipStream_t st);
+// The same marking with its temporaries in a static device array of
+// kMarkScratchBytes per GPU (no allocation, no synchronisation); n up to
+// kMarkMaxCells.  *too_large is set (and nothing runs) when n or the
+// temporaries exceed the array.  Calls that overlap on one GPU race.
+constexpr size_t kMarkScratchBytes = (size_t)64 << 20;
+constexpr int64_t kMarkMaxCells = (int64_t)1 << 20;
+hipError_t dorfler_mark_noalloc(int64_t n, const double* values, double fr, double fc, int8_t* flags,
+                                hipStream_t st, bool* too_large);
 // doubles of per-point metrics kept per cell (ChunkArgs::met)
 __host__ __device__ inline int64_t met_stride(const DevTables& t) { return 30 * (int64_t)t.nq + 36 * (int64_t)t.nfq; }
 // real copy of the factorised F block (the leading 64 floor(Np/64) rows and

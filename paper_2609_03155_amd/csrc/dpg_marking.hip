@@ -12,6 +12,9 @@
 // Every step is deterministic: the same values give the same flags.
 #include <hipcub/hipcub.hpp>
 
+#include <mutex>
+#include <unordered_map>
+
 #include "dpg_kernels.h"
 
 namespace dpg {
@@ -98,23 +101,27 @@ __global__ __launch_bounds__(MT) void k_mark_flags(int64_t n, const double* __re
   }
 }
 
-}  // namespace
-
-hipError_t dorfler_mark(int64_t n, const double* values, double fr, double fc, int8_t* flags, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
+// Bytes of the marking's temporaries for n cells (keys and ids in and out,
+// chunk sums, the sort's temporaries); *sort_bytes receives the last.
+hipError_t mark_scratch_bytes(int64_t n, size_t* total, size_t* sort_bytes, hipStream_t st) {
   const int64_t nc = (n + MCH - 1) / MCH;
-  // workspace: keys in/out, ids in/out, chunk sums, sort temporaries
-  size_t sort_bytes = 0;
-  hipError_t e = hipcub::DeviceRadixSort::SortPairsDescending(nullptr, sort_bytes, (const double*)nullptr,
-                                                               (double*)nullptr, (const int64_t*)nullptr,
-                                                               (int64_t*)nullptr, (int)n, 0, 64, st);
+  *sort_bytes = 0;
+  const hipError_t e = hipcub::DeviceRadixSort::SortPairsDescending(
+      nullptr, *sort_bytes, (const double*)nullptr, (double*)nullptr, (const int64_t*)nullptr, (int64_t*)nullptr,
+      (int)n, 0, 64, st);
   if (e != hipSuccess) return e;
-  const size_t al = 256;
-  auto up = [&](size_t b) { return (b + al - 1) / al * al; };
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  *total = 2 * up(sizeof(double) * n) + 2 * up(sizeof(int64_t) * n) + up(sizeof(double) * (nc + 1)) + up(*sort_bytes);
+  return hipSuccess;
+}
+
+// The marking of n > 0 cells with its temporaries in ws (at least
+// mark_scratch_bytes, 256-byte aligned).  Stream-ordered.
+hipError_t dorfler_mark_ws(int64_t n, const double* values, double fr, double fc, int8_t* flags, char* ws,
+                           size_t sort_bytes, hipStream_t st) {
+  const int64_t nc = (n + MCH - 1) / MCH;
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
   const size_t kb = up(sizeof(double) * n), ib = up(sizeof(int64_t) * n), cb = up(sizeof(double) * (nc + 1));
-  char* ws = nullptr;
-  e = hipMalloc(reinterpret_cast<void**>(&ws), 2 * kb + 2 * ib + cb + up(sort_bytes));
-  if (e != hipSuccess) return e;
   double* k_in = reinterpret_cast<double*>(ws);
   double* k_out = reinterpret_cast<double*>(ws + kb);
   int64_t* i_in = reinterpret_cast<int64_t*>(ws + 2 * kb);
@@ -122,7 +129,7 @@ hipError_t dorfler_mark(int64_t n, const double* values, double fr, double fc, i
   double* csum = reinterpret_cast<double*>(ws + 2 * kb + 2 * ib);
   void* tmp = ws + 2 * kb + 2 * ib + cb;
   hipLaunchKernelGGL(k_mark_init, dim3((unsigned)((n + MT - 1) / MT)), dim3(MT), 0, st, n, values, k_in, i_in);
-  e = hipGetLastError();
+  hipError_t e = hipGetLastError();
   if (e == hipSuccess)
     e = hipcub::DeviceRadixSort::SortPairsDescending(tmp, sort_bytes, k_in, k_out, i_in, i_out, (int)n, 0, 64, st);
   if (e == hipSuccess) {
@@ -131,9 +138,73 @@ hipError_t dorfler_mark(int64_t n, const double* values, double fr, double fc, i
     hipLaunchKernelGGL(k_mark_flags, dim3((unsigned)nc), dim3(MT), 0, st, n, k_out, i_out, csum, nc, fr, fc, flags);
     e = hipGetLastError();
   }
+  return e;
+}
+
+// Temporaries of the allocation-free marking: one copy of this array on
+// every GPU the library runs on, held until the process ends.  Host code
+// never uses its name as an address: the device address of each GPU's copy
+// comes from hipGetSymbolAddress (mark_scratch_ptr).
+static __device__ __align__(256) unsigned char scratch[kMarkScratchBytes];
+
+std::mutex g_scratch_mu;
+std::unordered_map<int, char*> g_scratch_ptr;   // device -> address of its copy of `scratch`
+
+}  // namespace
+
+hipError_t dorfler_mark(int64_t n, const double* values, double fr, double fc, int8_t* flags, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  size_t total = 0, sort_bytes = 0;
+  hipError_t e = mark_scratch_bytes(n, &total, &sort_bytes, st);
+  if (e != hipSuccess) return e;
+  char* ws = nullptr;
+  e = hipMalloc(reinterpret_cast<void**>(&ws), total);
+  if (e != hipSuccess) return e;
+  e = dorfler_mark_ws(n, values, fr, fc, flags, ws, sort_bytes, st);
   const hipError_t es = hipStreamSynchronize(st);
   const hipError_t ef = hipFree(ws);
   return e != hipSuccess ? e : (es != hipSuccess ? es : ef);
+}
+
+// Device address of this GPU's copy of `scratch`, looked up once per device
+// (with that device current) and kept.
+static hipError_t mark_scratch_ptr(char** ptr) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) {
+    *ptr = it->second;
+    return hipSuccess;
+  }
+  void* p = nullptr;
+  e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[dev] = static_cast<char*>(p);
+  *ptr = static_cast<char*>(p);
+  return hipSuccess;
+}
+
+hipError_t dorfler_mark_noalloc(int64_t n, const double* values, double fr, double fc, int8_t* flags,
+                                hipStream_t st, bool* too_large) {
+  *too_large = false;
+  if (n <= 0) return hipSuccess;
+  if (n > kMarkMaxCells) {
+    *too_large = true;
+    return hipSuccess;
+  }
+  size_t total = 0, sort_bytes = 0;
+  hipError_t e = mark_scratch_bytes(n, &total, &sort_bytes, st);
+  if (e != hipSuccess) return e;
+  if (total > kMarkScratchBytes) {
+    *too_large = true;
+    return hipSuccess;
+  }
+  char* ws = nullptr;
+  e = mark_scratch_ptr(&ws);
+  if (e != hipSuccess) return e;
+  return dorfler_mark_ws(n, values, fr, fc, flags, ws, sort_bytes, st);
 }
 
 }  // namespace dpg

@@ -27,7 +27,7 @@ EXPORTS = ("dpg_local_dims", "dpg_plan_create", "dpg_plan_destroy", "dpg_plan_of
            "dpg_plan_trace_offsets", "dpg_condense", "dpg_trace_numbering", "dpg_trace_system_create",
            "dpg_trace_system_destroy", "dpg_trace_system_info", "dpg_trace_system_numbering", "dpg_trace_system_csr",
            "dpg_assemble", "dpg_csr_matvec", "dpg_cg_solve", "dpg_trace_system_scatter", "dpg_reconstruct",
-           "dpg_dorfler_mark", "dpg_power_dissipation",
+           "dpg_dorfler_mark", "dpg_dorfler_mark_noalloc", "dpg_power_dissipation",
            "dpg_plan_set_profiling", "dpg_plan_profile", "dpg_status_string", "dpg_last_error")
 KERNEL_CLASSES = ("scale", "form_SM", "form_IF", "form_pad", "form_B", "form_load", "resid", "chol_diag",
                   "chol_panel", "herk")
@@ -89,6 +89,7 @@ def lib():
         L.dpg_trace_system_scatter.argtypes = [vp, vp, vp, vp]
         L.dpg_reconstruct.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.dpg_dorfler_mark.argtypes = [i64, vp, dp_, dp_, vp, vp]
+        L.dpg_dorfler_mark_noalloc.argtypes = [i64, vp, dp_, dp_, vp, vp]
         L.dpg_power_dissipation.argtypes = [vp, C.POINTER(dpg_problem), vp, vp, vp]
         L.dpg_plan_set_profiling.argtypes = [vp, i32]
         L.dpg_plan_profile.argtypes = [vp, vp, vp]
@@ -380,6 +381,20 @@ def dorfler_mark(values, refine_fraction: float = 0.30, coarsen_fraction: float 
         flags = torch.empty(max(n, 1), dtype=torch.int8, device=values.device)
     _check(lib().dpg_dorfler_mark(n, _ptr(values), float(refine_fraction), float(coarsen_fraction), _ptr(flags),
                                   _stream(stream)), "dpg_dorfler_mark")
+    return flags
+
+
+def dorfler_mark_noalloc(values, refine_fraction: float = 0.30, coarsen_fraction: float = 0.05, flags=None,
+                        stream=None):
+    """dpg_dorfler_mark_noalloc: the flags of dorfler_mark, with the library's
+    static device scratch instead of an allocation (n <= 2^20); `flags`
+    (int8, device, at least n entries) must be given to allocate nothing."""
+    import torch
+    n = int(values.numel())
+    if flags is None:
+        flags = torch.empty(max(n, 1), dtype=torch.int8, device=values.device)
+    _check(lib().dpg_dorfler_mark_noalloc(n, _ptr(values), float(refine_fraction), float(coarsen_fraction),
+                                          _ptr(flags), _stream(stream)), "dpg_dorfler_mark_noalloc")
     return flags
 
 
