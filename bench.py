@@ -47,6 +47,43 @@ def algorithmic_flops(p: int, dp: int) -> dict:
                 vec=32 * nv * k)
 
 
+PEAK_BF16_TFLOPS = 2500.0    # MI355X dense bf16 matrix peak
+BF16_FLOPS_PER_TILE_STAGE = 4 * 96 * 2 * 16 * 16 * 32   # k_herk_split: 4 waves x 96 MFMA 16x16x32 per 32-column stage
+
+
+def split_herk_executed_flops(p: int, dp: int) -> float:
+    """bf16 MFMA flops k_herk_split executes per cell: 6.3 MF per 64x64 output
+    tile and 32-column stage, over the tiles of the lower triangle of
+    K_aug; a tile whose row block of W^H is zero in the F test columns skips
+    their stages (the kernel's herk_k0)."""
+    s, r = p + dp + 1, p + 1
+    N = 3 * s * (s + 1) ** 2
+    Np = (N + 31) // 32 * 32
+    nvp = 2 * Np
+    m1 = (p + 1) ** 3
+    nu, nt1 = 6 * m1, 12 * r * r
+    k = nu + 2 * nt1
+    kp = (k + 2 + 63) // 64 * 64
+
+    def zero_rows(r0, nr=32):
+        eh0, hh0, lr0 = nvp + nu, nvp + nu + nt1, nvp + k
+        pad0, r1 = lr0 + 2, r0 + nr
+        if r0 < eh0 or (r0 < pad0 and r1 > lr0):
+            return False                        # complex rows
+        return not (r0 < lr0 and r1 > hh0)      # zero unless real (H-hat) rows
+
+    def zero_f(blk):
+        r0 = nvp + 64 * blk
+        return zero_rows(r0) and zero_rows(r0 + 32)
+    kb = kp // 64
+    stages = 0
+    for a in range(kb):
+        for b in range(a + 1):
+            k0 = (Np // 64) * 64 if (zero_f(a) or zero_f(b)) else 0
+            stages += (nvp - k0) // 32
+    return float(stages) * BF16_FLOPS_PER_TILE_STAGE
+
+
 def measured_traffic(workload: str, precision: str, kernel: str):
     """HBM bytes per launch of the dominant kernel class from the committed
     rocprofv3 counter summaries (profiles/*.md), or None when none matches or
@@ -185,37 +222,191 @@ def trace_system_timings(w, plan, prob, xd, K, l, eta, info, solve, stream, reps
     return out
 
 
-def cpu_baseline(w, budget_s: float = 20.0):
-    """The oracle, as it stands, on a bounded seeded sample of the workload's
-    cells; returns (record, per-cell oracle outputs)."""
+def _oracle_cells(args):
+    """Worker of the CPU baseline: forms and solves the given cells with the
+    oracle, one thread (returns the number of cells done)."""
+    wname, cells = args
+    import threadpoolctl
     from oracle import dpg_oracle as O
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
-    except Exception:
-        cores = os.cpu_count() or 1
+    w = W.CONFIGS[int(wname[1])]()
     om = O.omega_dimensionless(w.freq_hz)
     pt = w.port
     pm = O.PortMode(pt["a"], pt["b"], pt["m"], pt["n"], om, pt["eps"], pt["mu"])
     x, off = W.random_coefficients(w)
+    with threadpoolctl.threadpool_limits(1):
+        for c in cells:
+            cp = O.CellProblem(X=w.cell_vertices(c), p=int(w.degree[c]), dp=w.dp, eps=complex(w.eps[c]),
+                               mu=complex(w.mu[c]), omega=om, face_kind=tuple(int(k) for k in w.face_kind[c]),
+                               zinv=tuple(complex(z) for z in w.zinv[c]), port=pm)
+            G, Bf, l = O.cell_forms(cp)
+            O.local_solve(G, Bf, l, x[off[c]:off[c + 1]])
+    return len(cells)
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wname: str, budget_s: float = 20.0):
+    """The oracle, as it stands (numpy forms + LAPACK LU per cell, FP64), on
+    the GPU machine's host: a seeded sample of the workload's cells solved by a
+    pool of single-threaded worker processes (the cell loop parallelised, one
+    process per core used), then by one process on one core; each leg runs
+    for about budget_s / 2 seconds.  Returns the cpu_baseline record."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    w = W.CONFIGS[int(wname[1])]()
     rng = np.random.default_rng(W.SEED_BASE + 77)
-    order = rng.permutation(w.n_cells)
-    outs = {}
+    order = [int(c) for c in rng.permutation(w.n_cells)]
+    ncores = min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1))
+    half = budget_s / 2.0
+    # all cores: chunks of 2 cells handed to the pool until the time is up
+    ctx = mp.get_context("spawn")
+    with cf.ProcessPoolExecutor(max_workers=ncores, mp_context=ctx) as ex:
+        list(ex.map(_oracle_cells, [(wname, order[:1])] * ncores))   # start-up and imports, not timed
+        t0 = time.perf_counter()
+        pending, done, pos = set(), 0, 0
+        while True:
+            while len(pending) < 2 * ncores and time.perf_counter() - t0 < half:
+                pending.add(ex.submit(_oracle_cells, (wname, order[pos:pos + 2])))
+                pos += 2
+            if not pending:
+                break
+            fin, pending = cf.wait(pending, return_when=cf.FIRST_COMPLETED)
+            done += sum(f.result() for f in fin)
+        t_par = time.perf_counter() - t0
+    # one core
     t0 = time.perf_counter()
-    for c in order:
-        c = int(c)
-        cp = O.CellProblem(X=w.cell_vertices(c), p=int(w.degree[c]), dp=w.dp, eps=complex(w.eps[c]),
-                           mu=complex(w.mu[c]), omega=om, face_kind=tuple(int(k) for k in w.face_kind[c]),
-                           zinv=tuple(complex(z) for z in w.zinv[c]), port=pm)
-        G, Bf, l = O.cell_forms(cp)
-        K, le, eta = O.local_solve(G, Bf, l, x[off[c]:off[c + 1]])
-        outs[c] = (K, le, eta)
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
-    rec = {"value": len(outs) / dt, "unit": "elements/s", "cores": int(cores), "kind": "oracle",
-           "sample": f"{len(outs)} seeded cells of {w.name} ({dt:.1f} s, numpy/LAPACK FP64, LU solves)"}
-    return rec, outs
+    n1 = 0
+    while time.perf_counter() - t0 < half:
+        n1 += _oracle_cells((wname, order[n1:n1 + 1]))
+    t_one = time.perf_counter() - t0
+    return {"value": done / t_par, "unit": "elements/s", "cores": ncores, "kind": "oracle",
+            "one_core_value": n1 / t_one, "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "sample": (f"seeded cells of {w.name}: {done} cells on {ncores} single-threaded worker processes "
+                       f"in {t_par:.1f} s, {n1} cells on one core in {t_one:.1f} s (numpy forms, LAPACK LU, FP64)")}
+
+
+def accuracy_report(w, cells, outputs):
+    """Element-wise errors of the GPU outputs of the sampled cells against the
+    oracle (tests/_oracle_cases.OracleRef: scale sqrt(K_aa K_bb), the oracle's
+    own FP64 floor e_or and formation floor s_form).  outputs: {precision:
+    {cell: (K_e, l_e, eta)}}."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from _oracle_cases import OracleRef
+    x, off = W.random_coefficients(w)
+    rows = {name: [] for name in outputs}
+    floors = []
+    for c in cells:
+        ref = OracleRef(w, c, x[off[c]:off[c + 1]])
+        floors.append(ref)
+        for name, out in outputs.items():
+            rows[name].append(ref.errors(*out[c]))
+    rec = {"cells": [int(c) for c in cells], "metric": "max_ab |dK_ab| / sqrt(K_aa K_bb); max_a |dl_a| / "
+           "(sqrt(K_aa) ||y||); |d eta| / eta; against the oracle's FP64 LU solve",
+           "oracle_floor": {q: float(max(r.e_or[q] for r in floors)) for q in ("K", "l", "eta")},
+           "formation_floor": {q: float(max(r.s_form[q] for r in floors)) for q in ("K", "l", "eta")},
+           "fp64_bar_min": {q: float(min(r.fp64_bar(q) for r in floors)) for q in ("K", "l", "eta")}}
+    for name, es in rows.items():
+        d = {}
+        for q in ("K", "l", "eta", "K_x", "K_frob"):
+            v = [e[q] for e in es if q in e]
+            d[q + "_max"] = float(max(v))
+            d[q + "_median"] = float(np.median(v))
+        d["blocks_max"] = {b: float(max(e["blocks"][b] for e in es)) for b in es[0]["blocks"]}
+        d["within_bars"] = bool(all(e["K"] <= r.fp64_bar("K") + (1e-6 if name == "split" else 0) and
+                                    e["l"] <= r.fp64_bar("l") + (1e-6 if name == "split" else 0) and
+                                    e.get("eta", 0) <= r.fp64_bar("eta") for e, r in zip(es, floors)))
+        d["robin_null_rows_exact"] = bool(all(e["null_exact"] for e in es))
+        rec[name] = d
+    return rec
+
+
+FORM_KEYS = ("scale", "form_SM", "form_IF", "form_pad", "form_B", "form_load")
+
+
+def sub_record(wname: str, steps: int = 2, warmup: int = 1, err_cells=None):
+    """A smaller measurement of another workload for the same JSON line: both
+    precisions, default batching (concurrent degree branches, whole chunks;
+    not autotuned), one profiled eager solve on the sequential schedule for
+    the kernel-class times, then `steps` timed graph replays after `warmup`;
+    element-wise errors of `err_cells(w)` against the oracle if given."""
+    import torch
+    from paper_2609_03155_amd import dpg
+    torch.cuda.empty_cache()
+    w = W.CONFIGS[int(wname[1])]()
+    x, off = W.random_coefficients(w)
+    plan = dpg.Plan(w.degree, w.dp)
+    prob = dpg.DeviceProblem.from_workload(w)
+    xd = torch.from_numpy(x).cuda()
+    K, l, eta, info = plan.alloc_outputs()
+    stream = torch.cuda.current_stream()
+    degs = sorted(set(int(v) for v in w.degree))
+    rec = {"workload": w.name, "cells": w.n_cells, "degrees": degs, "dp": w.dp,
+           "batching": "concurrent degree branches, whole chunks (default plan, not autotuned)",
+           "cells_per_launch": {str(p): plan.tuning(p)[0] for p in degs}}
+    cells = err_cells(w) if err_cells else []
+    outs = {}
+    for name, code in (("fp64", dpg.DPG_FP64), ("split", dpg.DPG_SPLIT_FP32)):
+        plan.local_solve(prob, xd, K, l, eta, info, precision=code, stream=stream)   # first touch
+        torch.cuda.synchronize()
+        plan.profile()
+        plan.set_concurrency(False)
+        plan.set_profiling(True)
+        plan.local_solve(prob, xd, K, l, eta, info, precision=code, stream=stream)
+        torch.cuda.synchronize()
+        plan.set_profiling(False)
+        plan.set_concurrency(True)
+        prof = plan.profile()
+        if cells:
+            outs[name] = {}
+            for c in cells:
+                k = int(off[c + 1] - off[c])
+                outs[name][c] = (K[int(plan.K_off[c]):int(plan.K_off[c + 1])].cpu().numpy().reshape(k, k).T,
+                                 l[int(off[c]):int(off[c + 1])].cpu().numpy(), float(eta[c]))
+        g = plan.graph(prob, xd, K, l, eta, info, code)
+        for _ in range(warmup):
+            g.launch(stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            g.launch(stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        g.close()
+        ms = e0.elapsed_time(e1) / steps
+        assert int((info != 0).sum()) == 0
+        rec[name] = {"value": w.n_cells / (ms * 1e-3), "unit": "elements/s", "ms_per_step": ms,
+                     "formation_ms": sum(prof[k][0] for k in FORM_KEYS),
+                     "sweep_ms": prof["chol_diag"][0] + prof["chol_panel"][0], "herk_ms": prof["herk"][0],
+                     "eager_sequential_ms": sum(v[0] for v in prof.values())}
+        print(f"[bench] {w.name} {name}: {rec[name]['value']:.0f} elements/s", file=sys.stderr, flush=True)
+    rec["speedup_split_vs_fp64"] = rec["fp64"]["ms_per_step"] / rec["split"]["ms_per_step"]
+    del K, l, eta, info, xd
+    plan.close()
+    torch.cuda.empty_cache()
+    if cells:
+        rec["rel_err_vs_oracle"] = accuracy_report(w, cells, outs)
+    return rec
+
+
+def _c2_cells(w):
+    """WR340 cells: port face with two PEC walls (0, 15), the outlet corner,
+    the last cell and two seeded interior ones."""
+    rng = np.random.default_rng(W.SEED_BASE + 22)
+    return sorted(set([0, 15, 4992, w.n_cells - 1] + [int(c) for c in rng.choice(w.n_cells, 2, replace=False)]))
+
+
+def _c3_cells(w):
+    """One cell of each degree of the mixed workload."""
+    return [int(np.nonzero(w.degree == p)[0][0]) for p in sorted(set(int(v) for v in w.degree))]
 
 
 def main():
@@ -234,6 +425,8 @@ def main():
     ap.add_argument("--sequential", action="store_true", help="degree groups one after the other (no branches)")
     ap.add_argument("--no-trace-system", action="store_true",
                     help="skip the condensation / assembly / CSR matvec measurement")
+    ap.add_argument("--no-sub", action="store_true",
+                    help="skip the mixed-degree (c3) and high-order (c4) sub-records of the default workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (requested --gpus {args.gpus}); the per-cell local solve needs no "
@@ -412,25 +605,41 @@ def main():
         rec["speedup_split_vs_fp64"] = runs["fp64"][0] / runs["split"][0]
     if not args.no_trace_system and not streaming:
         rec["trace_system"] = trace_system_timings(w, plan, prob, xd, K, l, eta, info, solve, stream)
+    if "split" in runs:
+        # the split HERK against its own (bf16) MFMA peak, and its FP64-equivalent work
+        ms_h, n_h = runs["split"][1]["herk"]
+        ex = sum(int(np.sum(w.degree == p)) * split_herk_executed_flops(p, w.dp)
+                 for p in sorted(set(int(v) for v in w.degree))) * args.steps
+        alg = (fl["herk"] + fl["vec"]) * args.steps
+        rec["roofline_split_herk"] = {
+            "kernel": "k_herk_split (K_aug = W^H W from bf16x3 splits on v_mfma_f32_16x16x32_bf16)",
+            "bound": "mfma", "achieved": ex / (ms_h * 1e-3) / 1e12, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+            "frac": ex / (ms_h * 1e-3) / 1e12 / PEAK_BF16_TFLOPS,
+            "fp64_equivalent_achieved": alg / (ms_h * 1e-3) / 1e12,
+            "fp64_equivalent_frac": alg / (ms_h * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+            "avg_launch_ms": ms_h / max(1, n_h), "launches_per_step": n_h / args.steps,
+            "note": "executed: 6 bf16 products per real product, 64x64 tiles of the lower triangle of K_aug "
+                    "incl. padding; FP64-equivalent: 4 k^2 n_v + 32 n_v k per cell"}
     if not args.no_cpu_baseline:
-        base, outs = cpu_baseline(w, args.cpu_budget)
-        rec["cpu_baseline"] = base
-        errs = {}
+        if not streaming and w.name.startswith("c2"):
+            cells = _c2_cells(w)
+        else:
+            rng = np.random.default_rng(W.SEED_BASE + 77)
+            cells = sorted(int(c) for c in rng.choice(w.n_cells, 2, replace=False))
+        outs = {}
         for name, (_, _, code, _) in runs.items():
-            eK, el, ee = [], [], []
             if not streaming:
                 solve(code)                  # outputs of this precision
                 torch.cuda.synchronize()
-            for c, (Ko, lo, eo) in outs.items():
-                Kg, lg, eg = cell_outputs(code, c)
-                eK.append(np.linalg.norm(Kg - Ko) / np.linalg.norm(Ko))
-                if np.linalg.norm(lo) > 0:
-                    el.append(np.linalg.norm(lg - lo) / np.linalg.norm(lo))
-                ee.append(abs(eg - eo) / eo)
-            errs[name] = {"cells": len(outs), "K_e_max": float(np.max(eK)), "K_e_median": float(np.median(eK)),
-                          "l_e_max": float(np.max(el)) if el else None, "l_e_cells": len(el),
-                          "eta_max": float(np.max(ee))}
-        rec["rel_err_vs_oracle"] = errs
+            outs[name] = {c: cell_outputs(code, c) for c in cells}
+        rec["rel_err_vs_oracle"] = accuracy_report(w, cells, outs)
+        rec["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_budget)
+    if not args.no_sub and args.workload == "c2":
+        del K, l, eta, info
+        plan.close()
+        torch.cuda.empty_cache()
+        rec["sub_records"] = {"c3_mixed_degrees": sub_record("c3", err_cells=_c3_cells),
+                              "c4_p4_dp2": sub_record("c4", steps=1, warmup=1)}
     print(json.dumps(rec), flush=True)
 
 
