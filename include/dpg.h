@@ -385,7 +385,7 @@ dpg_status dpg_trace_system_scatter(dpg_trace_system sys, const double* t, doubl
 dpg_status dpg_reconstruct(dpg_plan plan, const double* K, const double* l, const double* t_local, double* x,
                            int32_t* info, void* stream);
 
-/* Electromagnetic power dissipated in every cell (Sec. 3.3: the heat source
+/* Electromagnetic power dissipated in every cell (Sec. 3.2: the heat source
  * Q_em = sigma |E|^2/2 + omega eps0 eps_im |E|^2/2 + omega mu0 mu_im |H|^2/2,
  * the time average of minus the divergence of the Poynting vector), from the
  * cells' coefficient vectors x (device, complex, the v_off layout of a

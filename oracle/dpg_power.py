@@ -1,5 +1,5 @@
 """Plain CPU oracle of the electromagnetic power dissipated in each cell
-(§3.3, the heat source of the enthalpy equation: Q_em = sigma |E|^2 / 2 +
+(§3.2, the heat source of the enthalpy equation: Q_em = sigma |E|^2 / 2 +
 omega eps0 eps_im |E|^2 / 2 + omega mu0 mu_im |H|^2 / 2, the time average of
 minus the divergence of the Poynting vector).
 

@@ -1,4 +1,4 @@
-"""GPU parity of the per-cell power dissipation (dpg_power_dissipation, §3.3
+"""GPU parity of the per-cell power dissipation (dpg_power_dissipation, §3.2
 heat source) against the oracle (oracle/dpg_power.py), through the C ABI, on
 seeded random coefficient vectors: the cube (p = 1, one lossy cell), a
 perturbed lossy piece of the WR340 guide (p = 2), mixed degrees 1..4, p = 4
