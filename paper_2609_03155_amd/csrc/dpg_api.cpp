@@ -145,14 +145,7 @@ void build_group(DegreeGroup& g, int dp) {
     for (int i = 0; i < d.N; ++i)
       for (int j = 0; j < d.N; ++j)
         RtT[((size_t)f * d.N + j) * d.N + i] = rt.Rt[((size_t)f * d.N + i) * d.N + j];
-  // S/M formation tiles: component pairs (a >= b) x 64-blocks (lower for a == b)
-  const int nc = d.N / 3, ncb = (nc + 63) / 64;
-  std::vector<int4> tiles;
-  for (int a = 0; a < 3; ++a)
-    for (int b = 0; b <= a; ++b)
-      for (int I = 0; I < ncb; ++I)
-        for (int J = 0; J < ncb; ++J)
-          if (a > b || J <= I) tiles.push_back(make_int4(a, b, I, J));
+  const int nc = d.N / 3;
   dpg::DevTables& t = g.dt;
   t.p = d.p;
   t.dp = d.dp;
@@ -198,8 +191,8 @@ void build_group(DegreeGroup& g, int dp) {
       for (size_t e = 0; e < ts.size(); ++e) ts[e] += rt.T[(size_t)f * ts.size() + e];
     t.Tsum = upload(g.bufs, ts);
   }
-  t.sm_tiles = upload(g.bufs, tiles);
-  t.n_sm_tiles = (int)tiles.size();
+  t.sf_tab = upload(g.bufs, rt.sf_tab);
+  t.sf_side = upload(g.bufs, rt.sf_side);
 }
 
 void free_plan(dpg_plan_s* p) {

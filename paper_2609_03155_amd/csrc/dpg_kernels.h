@@ -27,8 +27,8 @@ struct DevTables {
   const double* RtT;       // [6][N][N]  RtT[f][j][i] = Rt_f[i][j]
   const double* T;         // [6][N][nt1]
   const double* Tsum;      // [N][nt1] sum of T over the faces
-  const int4* sm_tiles;    // formation tiles (a, b, I, J) of the S/M kernel
-  int n_sm_tiles;
+  const double* sf_tab;    // [2][n1][n1] q_k(x_q) then q_k'(x_q), [k][q]: 1D factors of the test basis
+  const double* sf_side;   // [2][n1] q_k(0), q_k(1)
 };
 
 // Per-call problem data (device pointers) plus derived scalars.

@@ -2,7 +2,8 @@
 //
 // Per degree group and chunk of cells the pipeline is
 //   k_cell_scale  geometry check and Jacobi scaling d_i = G_ii^{-1/2}
-//   k_form_SM     G_FF, G_II from S, M (volume) and the Robin face mass
+//   k_form_SM     G_FF, G_II from S, M (volume) and the Robin face mass, by
+//                 sum factorisation over the tensor-product test basis
 //   k_form_IF     G_IF from the geometry-free C and Rt (Sec. 2.2 test norm)
 //   k_form_pad    identity/zero padding of the test space
 //   k_form_B      rows of B_f^H, l^H and r^H = (B_f x - l)^H (Sec. 2.2 forms,
@@ -839,196 +840,330 @@ __device__ inline void acc_for_each(const Acc& c, F&& f) {
 }
 
 // ================================================================ G_FF, G_II
-// One workgroup per (cell, 64x64 tile of the N x N test index space restricted
-// to a component pair (a, b)): rows share reference component a, columns b.
-// With v the nonzero component and chat the curl of the reference functions,
-//   M_ij = sum_q v_i(q) Gm_ab(q) v_j(q),
-//   S_ij = sum_q sum_{u != a} chat_iu(q) (sum_{w != b} Gc_uw(q) chat_jw(q)),
-// two real GEMMs over quadrature points on f64 MFMA (the metric is folded into
-// the column operand); Robin faces add Mt_ij = sum v_i Q_ab v_j.
-constexpr int SQC = 16;   // quadrature points per staged chunk
-
-struct RAcc {
-  d4 b[2][2];
+// Sum factorisation.  The test functions of component a are tensor products
+//   psi_hat_i = q_{i0}(xi_0) q_{i1}(xi_1) q_{i2}(xi_2) e_a
+// of orthonormal shifted Legendre polynomials, degree i_d < n_ad (n_ad = s
+// along a, s + 1 across it), numbered i0 fastest; the volume rule is the
+// tensor Gauss rule with n1 points per direction, numbered q0 fastest.  With
+// curl(f e_a) = grad f x e_a, component a+1 of chat_i is d_{a+2} f and
+// component a+2 is -d_{a+1} f (indices mod 3), so for a pair of components
+// (a, b) every entry is a sum of terms
+//   sum_q X0(i0,j0,q0) X1(i1,j1,q1) X2(i2,j2,q2) W(q),
+//   Xd(i,j,q) = f_i(x_q) g_j(x_q),  f, g in {q_k, q_k'},
+// one for M (weight Gm_ab, values only) and four for S (weights
+// s_u s_v Gc_uv, u = a+1, a+2, v = b+1, b+2; the derivative taken along the
+// direction that the curl component differentiates).  W is the point metric
+// of the trilinear map: any pointwise weight factors this way, so curved
+// and perturbed cells take the same path as affine ones.  The directions
+// are contracted one at a time,
+//   T1(q0,q1; i2,j2)       = sum_q2 X2 W,
+//   T2(q0; i1,j1,i2,j2)    = sum_q1 X1 T1,
+//   G(i0,j0; i1,j1,i2,j2) += sum_q0 X0 T2,
+// which costs O(N^2 n1) per pair instead of the O(N^2 n1^3) of a sum over all
+// points.  The last contraction is a real GEMM with rows (i0, j0), K = (term,
+// q0) and columns (i1, j1, i2, j2), run on f64 MFMA; its row operand X0 does
+// not depend on the cell and stays in registers.  A Robin face f adds
+// sum_fq v_i v_j Q_ab to both blocks, weighted |z|^2 in G_FF: the same
+// three contractions with one point (the face's side) in its normal
+// direction.
+//
+// One workgroup per (cell, pair a >= b); the columns (i2, j2 blocks, j2 <= i2
+// for a == b) go in chunks of CC = 16 ctiles columns, and the 16-row tiles x
+// 16-column tiles of a chunk are dealt to the four waves (tile tau = w + 4k).
+template <int Q1>
+struct SfShape {
+  static constexpr int S = Q1 - 1;                // test degree index s: degrees 0..s-1 along a, 0..s across
+  static constexpr int NQ = Q1 * Q1 * Q1;
+  static constexpr int KSS = Q1;                  // k-steps of the four curl-curl terms (rows t Q1 + q0)
+  static constexpr int KSM = (Q1 + 3) / 4;        // k-steps of the mass term (rows 4 Q1 + q0, zero padded)
+  static constexpr int KS = KSS + KSM;
+  static constexpr int KR = 4 * KS;               // staged T2 rows
+  __host__ __device__ static constexpr int n(int comp, int dir) { return comp == dir ? S : Q1; }
+  __host__ __device__ static constexpr int rtiles(int a, int b) { return (n(a, 0) * n(b, 0) + 15) / 16; }
+  __host__ __device__ static constexpr int ctiles(int a, int b) { return 16 / rtiles(a, b) < 8 ? 16 / rtiles(a, b) : 8; }
+  __host__ __device__ static constexpr int cc(int a, int b) { return 16 * ctiles(a, b); }
+  __host__ __device__ static constexpr int nbc(int a, int b) { return cc(a, b) / (n(a, 1) * n(b, 1)); }
+  __host__ __device__ static constexpr int ccmax() {
+    int m = 0;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b <= a; ++b) m = cc(a, b) > m ? cc(a, b) : m;
+    return m;
+  }
+  __host__ __device__ static constexpr int nbmax() {
+    int m = 0;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b <= a; ++b) m = nbc(a, b) > m ? nbc(a, b) : m;
+    return m;
+  }
+  static constexpr int CCP = ccmax();             // T2 row pitch
+  // LDS offsets (doubles): 1D tables q_k(x_q), q_k'(x_q) [k][q], q_k(0), q_k(1);
+  // volume weights [5][NQ]; Robin face weights [6][Q1^2]; T1 [5][nbmax][Q1^2]; T2 [KR][CCP]
+  // row operands X0 [rtiles][KS][64 lanes], of a Robin face [rtiles][KSM][64]
+  static constexpr int oV = 0, oD = Q1 * Q1, oSide = 2 * Q1 * Q1, oW = oSide + 2 * Q1, oWf = oW + 5 * NQ,
+                       oT1 = oWf + 6 * Q1 * Q1, oT2 = oT1 + 5 * nbmax() * Q1 * Q1, oA = oT2 + KR * CCP,
+                       oAf = oA + 4 * KS * 64, total = oAf + 4 * KSM * 64;
+  static_assert(total * 8 <= 80 * 1024, "two workgroups per CU");
 };
 
-__device__ inline void racc_zero(RAcc& c) {
-  for (int u = 0; u < 2; ++u)
-    for (int v = 0; v < 2; ++v) c.b[u][v] = d4{0, 0, 0, 0};
-}
-
-template <class F>
-__device__ inline void racc_for_each(const RAcc& c, F&& f) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wr = w & 1, wc = w >> 1;
-#pragma unroll
-  for (int u = 0; u < 2; ++u)
-#pragma unroll
-    for (int v = 0; v < 2; ++v)
-#pragma unroll
-      for (int it = 0; it < 4; ++it)
-        f(wr * 32 + u * 16 + (lane >> 4) + 4 * it, wc * 32 + v * 16 + (lane & 15), c.b[u][v][it]);
-}
-
-// acc += A^T B over a staged chunk: A, B as [k][row] planes of pitch LDP.
-__device__ inline void lds_atb(const double* A, const double* B, int K, RAcc& c) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wr = w & 1, wc = w >> 1;
-#pragma unroll
-  for (int ks = 0; ks < K / 4; ++ks) {
-    const int kk = ks * 4 + (lane >> 4);
-    double a[2], b[2];
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      a[u] = A[kk * LDP + wr * 32 + u * 16 + (lane & 15)];
-      b[u] = B[kk * LDP + wc * 32 + u * 16 + (lane & 15)];
-    }
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-      for (int v = 0; v < 2; ++v) c.b[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[v], c.b[u][v], 0, 0, 0);
+// (i2, j2) of block g: all n_a2 x n_b2 (i2 fastest), or j2 <= i2 row by row when tri
+__device__ __forceinline__ void sf_block(int g, bool tri, int na2, int& i2, int& j2) {
+  if (!tri) {
+    i2 = g % na2;
+    j2 = g / na2;
+    return;
   }
+  int r = 0;
+  while ((r + 1) * (r + 2) / 2 <= g) ++r;
+  i2 = r;
+  j2 = g - r * (r + 1) / 2;
 }
 
-__global__ __launch_bounds__(NT, 3) void k_form_SM(DevTables T, ProbArgs P, ChunkArgs C) {
-  int64_t cell;
-  int tile;
-  if (!decode_cell_tile(C.n, T.n_sm_tiles, cell, tile)) return;
+// 1D factors of volume term t (0..3: curl-curl (u, v) = (a+1+(t>>1), b+1+(t&1)), 4: mass) in direction d
+__device__ __forceinline__ void sf_tabs(int t, int a, int b, int d, const double* sV, const double* sD,
+                                        const double*& fi, const double*& fj) {
+  const bool di = t < 4 && d == (a + 2 - (t >> 1)) % 3;
+  const bool dj = t < 4 && d == (b + 2 - (t & 1)) % 3;
+  fi = di ? sD : sV;
+  fj = dj ? sD : sV;
+}
+
+// The (a, b) block of one cell; a and b are compile-time, so that the tile
+// counts, the chunk shape and the index splits are constants.
+template <int Q1, int a, int b>
+__device__ __forceinline__ void sf_pair_block(const DevTables& T, const ProbArgs& P, const ChunkArgs& C, int64_t cell,
+                                              double* smem) {
+  using SH = SfShape<Q1>;
+  constexpr int NQ = SH::NQ, KSS = SH::KSS, KS = SH::KS, CCP = SH::CCP, NBM = SH::nbmax();
   const int64_t gc = C.cell_ids[cell];
-  __shared__ double sMet[SQC][12];          // Gc (6) | Gm (6) of the chunk's points
-  __shared__ double Av[SQC * LDP], Ac1[SQC * LDP], Ac2[SQC * LDP];
-  __shared__ double Bv[SQC * LDP], By1[SQC * LDP], By2[SQC * LDP];
-  int8_t fk[6];
-  for (int f = 0; f < 6; ++f) fk[f] = P.face_kind[gc * 6 + f];
-  const int4 tl = T.sm_tiles[tile];
-  const int a = tl.x, b = tl.y;
-  const int a1 = (a == 0) ? 1 : 0, a2 = (a == 2) ? 1 : 2;
-  const int b1 = (b == 0) ? 1 : 0, b2 = (b == 2) ? 1 : 2;
-  const int sab = sym3(a, b);
-  const int s11 = sym3(a1, b1), s12 = sym3(a1, b2), s21 = sym3(a2, b1), s22 = sym3(a2, b2);
-  // S and M over the volume points; then S + cF M and S + cI M, to which the
-  // Robin-face masses add (two accumulators live at a time: three workgroups
-  // fit a CU)
-  RAcc S, M;
-  racc_zero(S);
-  racc_zero(M);
-  __syncthreads();
+  double* sV = smem + SH::oV;
+  double* sD = smem + SH::oD;
+  double* sSide = smem + SH::oSide;
+  double* sW = smem + SH::oW;
+  double* sWf = smem + SH::oWf;
+  double* sT1 = smem + SH::oT1;
+  double* sT2 = smem + SH::oT2;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  int rmask = 0;   // bit f: face f is a Robin face
+  for (int f = 0; f < 6; ++f) rmask |= is_robin(P.face_kind[gc * 6 + f]) ? 1 << f : 0;
   const double* gmet = C.met + cell * met_stride(T);
-  // ---- volume points, in chunks of SQC; the table values and metrics of
-  // the next chunk are fetched into registers while the current one is
-  // multiplied, so the load latency hides behind the MFMAs
-  constexpr int PER = SQC * 64 / NT;   // staged elements per thread and chunk
-  double pv[PER], pc1[PER], pc2[PER], qv[PER], qc1[PER], qc2[PER];
-  double pm = 0.0;
-  auto fetch = [&](int q0) {
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      const int e = threadIdx.x + k * NT;
-      const int qq = e >> 6, il = e & 63;
-      const int q = min(q0 + qq, T.nq - 1);
-      const int i = a * T.nc + min(tl.z * 64 + il, T.nc - 1);
-      const int jj = b * T.nc + min(tl.w * 64 + il, T.nc - 1);
-      const double* ci = &T.vol_c[((size_t)q * T.Np + i) * 3];
-      const double* cj = &T.vol_c[((size_t)q * T.Np + jj) * 3];
-      pv[k] = T.vol_v[(size_t)q * T.Np + i];
-      pc1[k] = ci[a1];
-      pc2[k] = ci[a2];
-      qv[k] = T.vol_v[(size_t)q * T.Np + jj];
-      qc1[k] = cj[b1];
-      qc2[k] = cj[b2];
-    }
-    if (threadIdx.x < SQC * 12) {
-      const int qq = threadIdx.x / 12, e = threadIdx.x % 12, q = q0 + qq;
-      // gmet layout: Gc[nq][6] then Gm[nq][6]
-      pm = (q < T.nq) ? gmet[(e < 6 ? 0 : 6 * T.nq) + 6 * q + (e % 6)] : 0.0;
-    }
-  };
-  fetch(0);
-  for (int q0 = 0; q0 < T.nq; q0 += SQC) {
-    if (threadIdx.x < SQC * 12) sMet[threadIdx.x / 12][threadIdx.x % 12] = pm;
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      const int e = threadIdx.x + k * NT;
-      const int qq = e >> 6, il = e & 63;
-      const double* m = sMet[qq];
-      Av[qq * LDP + il] = pv[k];
-      Ac1[qq * LDP + il] = pc1[k];
-      Ac2[qq * LDP + il] = pc2[k];
-      Bv[qq * LDP + il] = m[6 + sab] * qv[k];
-      By1[qq * LDP + il] = m[s11] * qc1[k] + m[s12] * qc2[k];
-      By2[qq * LDP + il] = m[s21] * qc1[k] + m[s22] * qc2[k];
-    }
-    __syncthreads();
-    if (q0 + SQC < T.nq) fetch(q0 + SQC);
-    lds_atb(Av, Bv, SQC, M);
-    lds_atb(Ac1, By1, SQC, S);
-    lds_atb(Ac2, By2, SQC, S);
-    __syncthreads();
+  for (int e = tid; e < 2 * Q1 * Q1; e += NT) smem[SH::oV + e] = T.sf_tab[e];   // values then derivatives
+  for (int e = tid; e < 2 * Q1; e += NT) sSide[e] = T.sf_side[e];
+  // weights: s_u s_v Gc_uv of the four curl-curl terms, Gm_ab
+  for (int e = tid; e < 4 * NQ; e += NT) {
+    const int t = e / NQ, q = e - t * NQ;
+    const int u = (a + 1 + (t >> 1)) % 3, v = (b + 1 + (t & 1)) % 3;
+    const double sg = ((t >> 1) ^ (t & 1)) ? -1.0 : 1.0;
+    sW[e] = sg * gmet[6 * q + sym3(u, v)];
+  }
+  for (int q = tid; q < NQ; q += NT) sW[4 * NQ + q] = gmet[6 * NQ + 6 * q + sym3(a, b)];
+  if (rmask)
+    for (int e = tid; e < 6 * Q1 * Q1; e += NT)
+      sWf[e] = ((rmask >> (e / (Q1 * Q1))) & 1) ? gmet[12 * NQ + 6 * e + sym3(a, b)] : 0.0;
+  // mass-term padding rows of T2 (never written by the chunks)
+  for (int e = tid; e < (4 * KS - 5 * Q1) * CCP; e += NT) sT2[5 * Q1 * CCP + e] = 0.0;
+  __syncthreads();
+
+  constexpr int na0 = SH::n(a, 0), nb0 = SH::n(b, 0), na1 = SH::n(a, 1), nb1 = SH::n(b, 1), na2 = SH::n(a, 2);
+  constexpr int R = na0 * nb0, Rt = SH::rtiles(a, b), ctl = SH::ctiles(a, b), CC = 16 * ctl, Tn = Rt * ctl;
+  constexpr int ncb = na1 * nb1, nbc = CC / ncb;
+  constexpr bool tri = a == b;
+  constexpr int nblk = tri ? na2 * (na2 + 1) / 2 : na2 * SH::n(b, 2);
+  // row operands X0 of the tiles, in MFMA lane order: row (i0, j0) = rt 16 + (lane & 15),
+  // k = 4 ks + (lane >> 4) (the cell-independent products of the q0 factors)
+  double* sA = smem + SH::oA;
+  for (int e = tid; e < Rt * KS * 64; e += NT) {
+    const int ln = e & 63, ks = (e >> 6) % KS, rt = e / (64 * KS);
+    const int row = rt * 16 + (ln & 15), kk = 4 * ks + (ln >> 4);
+    const int t = ks < KSS ? kk / Q1 : 4;
+    const int q0 = ks < KSS ? kk - t * Q1 : kk - 4 * Q1;
+    const int i0 = row % na0, j0 = row / na0;
+    const double *fi, *fj;
+    sf_tabs(t, a, b, 0, sV, sD, fi, fj);
+    sA[e] = row < R && q0 < Q1 ? fi[i0 * Q1 + q0] * fj[j0 * Q1 + q0] : 0.0;
   }
   const double2 eps = make_double2(P.eps[2 * gc], P.eps[2 * gc + 1]);
   const double2 mu = make_double2(P.mu[2 * gc], P.mu[2 * gc + 1]);
   const double om2 = P.omega * P.omega;
   const double cF = om2 * (eps.x * eps.x + eps.y * eps.y) + P.alpha;
   const double cI = om2 * (mu.x * mu.x + mu.y * mu.y) + P.alpha;
-  // S <- S + cF M (G_FF),  M <- S + cI M (G_II)
-#pragma unroll
-  for (int u = 0; u < 2; ++u)
-#pragma unroll
-    for (int v = 0; v < 2; ++v)
-#pragma unroll
-      for (int it = 0; it < 4; ++it) {
-        const double sv = S.b[u][v][it], mv = M.b[u][v][it];
-        S.b[u][v][it] = sv + cF * mv;
-        M.b[u][v][it] = sv + cI * mv;
-      }
-  // ---- Robin faces
-  for (int f = 0; f < 6; ++f) {
-    if (!is_robin(fk[f])) continue;
-    const double zr = P.zinv[(gc * 6 + f) * 2], zi = P.zinv[(gc * 6 + f) * 2 + 1];
-    const double z2 = zr * zr + zi * zi;
-    for (int q0 = 0; q0 < T.nfq; q0 += SQC) {
-      if (threadIdx.x < SQC) {
-        const int fq = q0 + threadIdx.x;
-        sMet[threadIdx.x][0] = (fq < T.nfq) ? gmet[12 * T.nq + (f * T.nfq + fq) * 6 + sab] : 0.0;
-      }
-      __syncthreads();
-      for (int e = threadIdx.x; e < SQC * 64; e += NT) {
-        const int qq = e >> 6, il = e & 63;
-        const int fq = min(q0 + qq, T.nfq - 1);
-        const int i = a * T.nc + min(tl.z * 64 + il, T.nc - 1);
-        const int jj = b * T.nc + min(tl.w * 64 + il, T.nc - 1);
-        const double* vv = T.face_v + ((size_t)f * T.nfq + fq) * T.Np;
-        const double bq = sMet[qq][0] * vv[jj];
-        Av[qq * LDP + il] = vv[i];
-        Bv[qq * LDP + il] = bq;
-        By1[qq * LDP + il] = z2 * bq;
-      }
-      __syncthreads();
-      lds_atb(Av, Bv, SQC, M);    // G_II part
-      lds_atb(Av, By1, SQC, S);   // G_FF part
-      __syncthreads();
-    }
-  }
-  const double* d = C.dscale + cell * (int64_t)T.nvp;
+  const double* dsc = C.dscale + cell * (int64_t)T.nvp;
   double2* Z = C.Z + cell * T.zstride;
   const int64_t ld = T.ldz;
-  // combine per item (same lane mapping for all four accumulators)
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wr = w & 1, wc = w >> 1;
-  for (int u = 0; u < 2; ++u)
-    for (int v = 0; v < 2; ++v)
-      for (int it = 0; it < 4; ++it) {
-        const int li = tl.z * 64 + wr * 32 + u * 16 + (lane >> 4) + 4 * it;
-        const int lj = tl.w * 64 + wc * 32 + v * 16 + (lane & 15);
-        if (li >= T.nc || lj >= T.nc) continue;
-        const int i = a * T.nc + li, j = b * T.nc + lj;
-        if (a == b && j > i) continue;
-        const double gff = S.b[u][v][it], gii = M.b[u][v][it];
-        Z[(int64_t)j * ld + i] = make_double2(d[i] * d[j] * gff, 0.0);
-        Z[(int64_t)(T.Np + j) * ld + T.Np + i] = make_double2(d[T.Np + i] * d[T.Np + j] * gii, 0.0);
+
+  for (int g0 = 0; g0 < nblk; g0 += nbc) {
+    const int nb = min(nbc, nblk - g0);
+    // ---- T1(t, blk; q0, q1) = sum_q2 X2 W_t
+    for (int e = tid; e < 5 * nb * Q1 * Q1; e += NT) {
+      const int q0 = e % Q1, q1 = (e / Q1) % Q1, r = e / (Q1 * Q1);
+      const int blk = r % nb, t = r / nb;
+      int i2, j2;
+      sf_block(g0 + blk, tri, na2, i2, j2);
+      const double *fi, *fj;
+      sf_tabs(t, a, b, 2, sV, sD, fi, fj);
+      const double* wv = sW + t * NQ + q0 + Q1 * q1;
+      double acc = 0.0;
+#pragma unroll
+      for (int q2 = 0; q2 < Q1; ++q2) acc = fma(fi[i2 * Q1 + q2] * fj[j2 * Q1 + q2], wv[Q1 * Q1 * q2], acc);
+      sT1[(t * NBM + blk) * Q1 * Q1 + q1 * Q1 + q0] = acc;
+    }
+    __syncthreads();
+    // ---- T2(t q0; c) = sum_q1 X1 T1, column c = (i1, j1, blk), i1 fastest
+    for (int e = tid; e < 5 * CC; e += NT) {
+      const int t = e / CC, c = e - t * CC;
+      const int blk = c / ncb, cc = c - blk * ncb;
+      double out[Q1];
+#pragma unroll
+      for (int q0 = 0; q0 < Q1; ++q0) out[q0] = 0.0;
+      if (blk < nb) {
+        const int i1 = cc % na1, j1 = cc / na1;
+        const double *fi, *fj;
+        sf_tabs(t, a, b, 1, sV, sD, fi, fj);
+        const double* t1 = sT1 + (t * NBM + blk) * Q1 * Q1;
+#pragma unroll 2
+        for (int q1 = 0; q1 < Q1; ++q1) {
+          const double x = fi[i1 * Q1 + q1] * fj[j1 * Q1 + q1];
+#pragma unroll
+          for (int q0 = 0; q0 < Q1; ++q0) out[q0] = fma(x, t1[q1 * Q1 + q0], out[q0]);
+        }
       }
+      const int row0 = t < 4 ? t * Q1 : 4 * Q1;
+#pragma unroll
+      for (int q0 = 0; q0 < Q1; ++q0) sT2[(row0 + q0) * CCP + c] = out[q0];
+    }
+    __syncthreads();
+    // ---- G(i0 j0; c) = sum_(t, q0) X0 T2: S (curl-curl rows) and M (mass rows)
+    d4 acS[4], acM[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acS[k] = acM[k] = d4{0, 0, 0, 0};
+    auto kstep = [&](int ks, d4* acc) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int tau = w + 4 * k;
+        if (tau < Tn) {
+          const double av = sA[((tau % Rt) * KS + ks) * 64 + lane];
+          const double bv = sT2[(4 * ks + (lane >> 4)) * CCP + (tau / Rt) * 16 + (lane & 15)];
+          acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[k], 0, 0, 0);
+        }
+      }
+    };
+#pragma unroll 2
+    for (int ks = 0; ks < KSS; ++ks) kstep(ks, acS);
+#pragma unroll
+    for (int ks = KSS; ks < KS; ++ks) kstep(ks, acM);
+    // G_FF = S + cF M (in acS), G_II = S + cI M (in acM)
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int it = 0; it < 4; ++it) {
+        const double sv = acS[k][it], mv = acM[k][it];
+        acS[k][it] = fma(cF, mv, sv);
+        acM[k][it] = fma(cI, mv, sv);
+      }
+    // ---- Robin faces: one point (the face's side) in the normal direction
+#pragma unroll 1
+    for (int f = 0; f < 6; ++f) {
+      if (!((rmask >> f) & 1)) continue;
+      const int nax = f >> 1;
+      const double* side = sSide + (f & 1) * Q1;
+      const double z2 = P.zinv[(gc * 6 + f) * 2] * P.zinv[(gc * 6 + f) * 2] +
+                        P.zinv[(gc * 6 + f) * 2 + 1] * P.zinv[(gc * 6 + f) * 2 + 1];
+      // points and 1D factors per direction (ld: stride of k in the table)
+      const int nq0 = nax == 0 ? 1 : Q1, nq1 = nax == 1 ? 1 : Q1, nq2 = nax == 2 ? 1 : Q1;
+      const double* f0 = nax == 0 ? side : sV;
+      const double* f1 = nax == 1 ? side : sV;
+      const double* f2 = nax == 2 ? side : sV;
+      const int l0 = nax == 0 ? 1 : Q1, l1 = nax == 1 ? 1 : Q1, l2 = nax == 2 ? 1 : Q1;
+      const double* wf = sWf + f * Q1 * Q1;   // face points: tangential axes in increasing order, first fastest
+      __syncthreads();   // T1, T2 free
+#pragma unroll 1
+      for (int e = tid; e < nb * nq0 * nq1; e += NT) {
+        const int q0 = e % nq0, q1 = (e / nq0) % nq1, blk = e / (nq0 * nq1);
+        int i2, j2;
+        sf_block(g0 + blk, tri, na2, i2, j2);
+        double acc = 0.0;
+#pragma unroll 1
+        for (int q2 = 0; q2 < nq2; ++q2)
+          acc = fma(f2[i2 * l2 + q2] * f2[j2 * l2 + q2], wf[q0 + nq0 * (q1 + nq1 * q2)], acc);
+        sT1[blk * Q1 * Q1 + q1 * nq0 + q0] = acc;
+      }
+      __syncthreads();
+      // (rows nq0 .. 4 KSM of T2 are zero)
+#pragma unroll 1
+      for (int e = tid; e < 4 * SH::KSM * CC; e += NT) {
+        const int q0 = e / CC, c = e - q0 * CC;
+        const int blk = c / ncb, cc = c - blk * ncb;
+        double acc = 0.0;
+        if (blk < nb && q0 < nq0) {
+          const int i1 = cc % na1, j1 = cc / na1;
+          const double* t1 = sT1 + blk * Q1 * Q1 + q0;
+#pragma unroll 1
+          for (int q1 = 0; q1 < nq1; ++q1) acc = fma(f1[i1 * l1 + q1] * f1[j1 * l1 + q1], t1[q1 * nq0], acc);
+        }
+        sT2[q0 * CCP + c] = acc;
+      }
+      double* sAf = smem + SH::oAf;
+#pragma unroll 1
+      for (int e = tid; e < Rt * SH::KSM * 64; e += NT) {
+        const int ln = e & 63, ks = (e >> 6) % SH::KSM, rt = e / (64 * SH::KSM);
+        const int row = rt * 16 + (ln & 15), kk = 4 * ks + (ln >> 4);
+        const int i0 = row % na0, j0 = row / na0;
+        sAf[e] = row < R && kk < nq0 ? f0[i0 * l0 + kk] * f0[j0 * l0 + kk] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int ks = 0; ks < SH::KSM; ++ks) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int tau = w + 4 * k;
+          if (tau < Tn) {
+            const double av = sAf[((tau % Rt) * SH::KSM + ks) * 64 + lane];
+            const double bv = sT2[(4 * ks + (lane >> 4)) * CCP + (tau / Rt) * 16 + (lane & 15)];
+            acS[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(z2 * av, bv, acS[k], 0, 0, 0);
+            acM[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acM[k], 0, 0, 0);
+          }
+        }
+      }
+    }
+    // ---- scaled lower triangles of the (a, b) blocks of D G_FF D and D G_II D
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int tau = w + 4 * k;
+      if (tau >= Tn) continue;
+      const int col = (tau / Rt) * 16 + (lane & 15);
+      const int blk = col / ncb, cc = col - blk * ncb;
+      if (blk >= nb) continue;
+      int i2, j2;
+      sf_block(g0 + blk, tri, na2, i2, j2);
+      const int ic = a * T.nc + na0 * ((cc % na1) + na1 * i2), jc = b * T.nc + nb0 * ((cc / na1) + nb1 * j2);
+#pragma unroll
+      for (int it = 0; it < 4; ++it) {
+        const int row = (tau % Rt) * 16 + (lane >> 4) + 4 * it;
+        if (row >= R) continue;
+        const int i = ic + row % na0, j = jc + row / na0;
+        if (tri && j > i) continue;
+        Z[(int64_t)j * ld + i] = make_double2(dsc[i] * dsc[j] * acS[k][it], 0.0);
+        Z[(int64_t)(T.Np + j) * ld + T.Np + i] = make_double2(dsc[T.Np + i] * dsc[T.Np + j] * acM[k][it], 0.0);
+      }
+    }
+  }
 }
+
+template <int Q1>
+__global__ __launch_bounds__(NT, 2) void k_form_SM(DevTables T, ProbArgs P, ChunkArgs C) {
+  int64_t cell;
+  int pr;
+  if (!decode_cell_tile(C.n, 6, cell, pr)) return;
+  extern __shared__ double smem[];
+  switch (pr) {
+    case 0: sf_pair_block<Q1, 0, 0>(T, P, C, cell, smem); break;
+    case 1: sf_pair_block<Q1, 1, 0>(T, P, C, cell, smem); break;
+    case 2: sf_pair_block<Q1, 1, 1>(T, P, C, cell, smem); break;
+    case 3: sf_pair_block<Q1, 2, 0>(T, P, C, cell, smem); break;
+    case 4: sf_pair_block<Q1, 2, 1>(T, P, C, cell, smem); break;
+    default: sf_pair_block<Q1, 2, 2>(T, P, C, cell, smem); break;
+  }
+}
+
 
 // ================================================================ Cholesky
 // LDS of the factorisation kernels (aliased phases, two workgroups per CU):
@@ -2147,8 +2282,22 @@ hipError_t launch_formation(const DevTables& t, const ProbArgs& pa, const ChunkA
   if (ca.n <= 0) return hipSuccess;
   const size_t sm = scale_smem(t);
   DPG_LAUNCH(KC_SCALE, prof, st, k_cell_scale, dim3((unsigned)ca.n), dim3(NT), sm, st, t, pa, ca);
-  DPG_LAUNCH(KC_FORM_SM, prof, st, k_form_SM, dim3(grid_cells_tiles(ca.n, t.n_sm_tiles)), dim3(NT), 0, st, t, pa,
-             ca);
+  const dim3 gsm(grid_cells_tiles(ca.n, 6));
+  switch (t.n1) {
+#define DPG_SM_CASE(Q)                                                                                          \
+  case Q:                                                                                                       \
+    DPG_LAUNCH(KC_FORM_SM, prof, st, k_form_SM<Q>, gsm, dim3(NT), sizeof(double) * SfShape<Q>::total, st, t, pa, \
+               ca);                                                                                             \
+    break;
+    DPG_SM_CASE(4)
+    DPG_SM_CASE(5)
+    DPG_SM_CASE(6)
+    DPG_SM_CASE(7)
+    DPG_SM_CASE(8)
+#undef DPG_SM_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
   const int nt = (t.Np + 63) / 64;
   DPG_LAUNCH(KC_FORM_IF, prof, st, k_form_IF, dim3(grid_cells_tiles(ca.n, nt * nt)), dim3(NT), 0, st, t, pa, ca);
   DPG_LAUNCH(KC_FORM_PAD, prof, st, k_form_pad, dim3((unsigned)ca.n), dim3(NT), 0, st, t, ca);

@@ -225,6 +225,22 @@ RefTables build_tables(int p, int dp) {
       T.vol_v[(size_t)q * d.Np + i] = v;
       for (int u = 0; u < 3; ++u) T.vol_c[((size_t)q * d.Np + i) * 3 + u] = c[u];
     }
+  // 1D factors of the test basis for the sum-factorised formation
+  T.sf_tab.assign((size_t)2 * (d.s + 1) * d.n1, 0.0);
+  T.sf_side.assign((size_t)2 * (d.s + 1), 0.0);
+  for (int q = 0; q < d.n1; ++q) {
+    std::vector<double> v, dv;
+    onb(d.s, gx[q], v, dv);
+    for (int k = 0; k <= d.s; ++k) {
+      T.sf_tab[(size_t)k * d.n1 + q] = v[k];
+      T.sf_tab[(size_t)(d.s + 1 + k) * d.n1 + q] = dv[k];
+    }
+  }
+  for (int side = 0; side < 2; ++side) {
+    std::vector<double> v, dv;
+    onb(d.s, (double)side, v, dv);
+    for (int k = 0; k <= d.s; ++k) T.sf_side[(size_t)side * (d.s + 1) + k] = v[k];
+  }
   auto phi_at = [&](const double* xi, double* out) {
     int n = p + 1;
     for (int kk = 0; kk < n; ++kk)

@@ -110,6 +110,40 @@ def test_form_local_matches_oracle_perturbed_p2():
         assert np.abs(lv[c] - lo).max() <= 1e-12 * max(np.abs(lo).max(), 1e-300), c
 
 
+@pytest.mark.parametrize("p,dp", [(1, 2), (2, 2), (3, 1), (3, 2), (4, 1), (4, 2)])
+def test_form_local_matches_oracle_all_degrees(p, dp):
+    """Every (p, dp) shape of the sum-factorised formation (n1 = 4..8 points
+    per direction), on perturbed trilinear cells whose walls are all Robin
+    faces (impedance walls on x and y, the port and the outlet on z): every
+    cell has a Robin face normal to each of the three directions."""
+    import dataclasses
+    torch = _torch()
+    from paper_2609_03155_amd import dpg
+    w0 = W.config2(nx=2, ny=2, nz=2)
+    fk = w0.face_kind.copy()
+    zinv = w0.zinv.copy()
+    walls = fk == W.FACE_PEC
+    fk[walls] = W.FACE_ROBIN0
+    zinv[walls] = 0.7 - 0.3j
+    w = dataclasses.replace(w0, name=f"c2_2x2x2_p{p}dp{dp}", degree=np.full(w0.n_cells, p, np.int8), dp=dp,
+                            face_kind=fk, zinv=zinv)
+    _say(f"case: dpg_form_local 2x2x2 perturbed p={p} dp={dp}")
+    plan = dpg.Plan(w.degree, w.dp)
+    prob = dpg.DeviceProblem.from_workload(w)
+    G, Bf, lv, info = plan.form_local(prob, 0, w.n_cells)
+    torch.cuda.synchronize()
+    G, Bf, lv = G.cpu().numpy(), Bf.cpu().numpy(), lv.cpu().numpy()
+    assert np.all(info.cpu().numpy() == 0)
+    for c in (0, 7):    # the port corner and the outlet corner
+        Go, Bo, lo, *_ = oracle_cell(w, c)
+        eg = np.abs(G[c] - Go).max() / np.abs(Go).max()
+        eb = np.abs(Bf[c] - Bo).max() / np.abs(Bo).max()
+        _say(f"  cell {c}: G {eg:.2e}  B_f {eb:.2e}")
+        assert eg < 1e-12, c
+        assert eb < 1e-12, c
+        assert np.abs(lv[c] - lo).max() <= 1e-12 * max(np.abs(lo).max(), 1e-300), c
+
+
 def test_local_solve_config1_all_cells():
     w = W.config1()
     x, off = W.random_coefficients(w)
