@@ -193,6 +193,8 @@ void build_group(DegreeGroup& g, int dp) {
   }
   t.sf_tab = upload(g.bufs, rt.sf_tab);
   t.sf_side = upload(g.bufs, rt.sf_side);
+  t.sf_phi = upload(g.bufs, rt.sf_phi);
+  t.sf_phis = upload(g.bufs, rt.sf_phis);
 }
 
 void free_plan(dpg_plan_s* p) {

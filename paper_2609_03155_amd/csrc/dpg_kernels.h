@@ -29,6 +29,8 @@ struct DevTables {
   const double* Tsum;      // [N][nt1] sum of T over the faces
   const double* sf_tab;    // [2][n1][n1] q_k(x_q) then q_k'(x_q), [k][q]: 1D factors of the test basis
   const double* sf_side;   // [2][n1] q_k(0), q_k(1)
+  const double* sf_phi;    // [p+1][n1] 1D Lagrange factors of the DG basis at the Gauss points
+  const double* sf_phis;   // [2][p+1] the same at 0 and 1
 };
 
 // Per-call problem data (device pointers) plus derived scalars.

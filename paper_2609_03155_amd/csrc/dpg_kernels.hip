@@ -119,7 +119,8 @@ __device__ inline void face_normal(const Geo& g, int f, double n[3], double& s) 
   const int ax = f >> 1;
   const double sg = (f & 1) ? 1.0 : -1.0;
   double v[3];
-  for (int a = 0; a < 3; ++a) v[a] = sg * g.det * g.Ji[ax][a];
+  // (row ax of J^{-1} by selects: a runtime index would put g in scratch memory)
+  for (int a = 0; a < 3; ++a) v[a] = sg * g.det * (ax == 0 ? g.Ji[0][a] : (ax == 1 ? g.Ji[1][a] : g.Ji[2][a]));
   s = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
   for (int a = 0; a < 3; ++a) n[a] = v[a] / s;
 }
@@ -347,281 +348,598 @@ __global__ __launch_bounds__(NT) void k_form_pad(DevTables T, ChunkArgs C) {
   }
 }
 
-// ================================================================ B_f^H, l^H
-// One workgroup per (cell, 64 test functions i).  For the volume terms
-//   D_c(i,m) = sum_q w det (J^{-T} psi_hat_i)_c phi_m,   R_c(i,m) = sum_q w (J chat_i)_c phi_m
-// and on Robin faces Dt_c(i,m) = sum w s (psi_i - (psi_i.n) n)_c phi_m; then
-//   B(F_i, E_cm) = i w eps D - sum_R z Dt,  B(F_i, H_cm) = R_c,
-//   B(I_i, E_cm) = R_c,                     B(I_i, H_cm) = -i w mu D,
-//   B(F_i, Hhat_j) = sum_{f not Robin} T_f(i,j),  B(I_i, Ehat_j) = sum_f T_f(i,j),
-//   l(F_i) = - sum_port int psi_i . g dS.
-constexpr int BQC = 16;   // quadrature points per staged chunk
+// ================================================================ B_f^H by sum factorisation
+// The DG trial functions are tensor products of 1D Lagrange factors at the
+// Gauss-Lobatto nodes, phi_m = l_{m0}(xi_0) l_{m1}(xi_1) l_{m2}(xi_2), m0
+// fastest.  For the test functions of component a and the trial component c,
+//   D_c(i,m) = sum_q w det (J^{-1})_{ac} v_i phi_m,
+//   R_c(i,m) = sum_q w (J chat_i)_c phi_m
+//            = sum_q w [J_{c,a+1} d_{a+2} f_i - J_{c,a+2} d_{a+1} f_i] phi_m
+// are three sum-factorisable terms with the weights w det J^{-1}_{ac},
+// w J_{c,a+1} and -w J_{c,a+2}.  As for G: T1 over q2 (blocks (i2, m2)), T2
+// over q1 (columns (m1, i1)), then an f64 MFMA GEMM with rows (m0, i0) and
+// K = (term, q0), whose row operand does not depend on the cell.  Every B
+// entry fills four places of (D B_f)^H:
+//   column F_i:  row E_cm  conj(dF (i w eps D)),   row H_cm  dF R,
+//   column I_i:  row E_cm  dI R,                   row H_cm  conj(dI (-i w mu D)).
+// The Robin-face part of B(F, E) (k_form_Bt), the trace rows, the padding
+// and the residual row (k_form_T, k_form_resid) are written by other kernels.
+// One workgroup per (cell, a, c); a is a compile-time parameter.
+template <int Q1, int P1>
+struct SfbShape {
+  static constexpr int S = Q1 - 1;
+  static constexpr int NQ = Q1 * Q1 * Q1;
+  static constexpr int KD = (Q1 + 3) / 4;         // k-steps of D (rows q0, zero padded)
+  static constexpr int KR = (2 * Q1 + 3) / 4;     // k-steps of the two R terms (rows 4 KD + t' Q1 + q0)
+  static constexpr int KS = KD + KR;
+  __host__ __device__ static constexpr int n(int comp, int dir) { return comp == dir ? S : Q1; }
+  __host__ __device__ static constexpr int rows(int a) { return n(a, 0) * P1; }
+  __host__ __device__ static constexpr int rtiles(int a) { return (rows(a) + 15) / 16; }
+  __host__ __device__ static constexpr int ncb(int a) { return n(a, 1) * P1; }
+  __host__ __device__ static constexpr int ctiles(int a) {
+    return (ncb(a) + 15) / 16 > (16 / rtiles(a) < 8 ? 16 / rtiles(a) : 8) ? (ncb(a) + 15) / 16
+                                                                       : (16 / rtiles(a) < 8 ? 16 / rtiles(a) : 8);
+  }
+  __host__ __device__ static constexpr int cc(int a) { return 16 * ctiles(a); }
+  __host__ __device__ static constexpr int nbc(int a) { return cc(a) / ncb(a); }
+  __host__ __device__ static constexpr int ccmax() {
+    int m = 0;
+    for (int a = 0; a < 3; ++a) m = cc(a) > m ? cc(a) : m;
+    return m;
+  }
+  __host__ __device__ static constexpr int nbmax() {
+    int m = 0;
+    for (int a = 0; a < 3; ++a) m = nbc(a) > m ? nbc(a) : m;
+    return m;
+  }
+  static constexpr int CCP = ccmax();
+  // LDS (doubles): q_k, q_k' at the points [k][q]; l_m [m][q]; weights [3][NQ];
+  // T1 [3][nbmax][Q1^2]; T2 [4 KS][CCP]; row operands [rtiles][KS][64]
+  static constexpr int oV = 0, oD = Q1 * Q1, oP = 2 * Q1 * Q1, oW = oP + P1 * Q1, oT1 = oW + 3 * NQ,
+                       oT2 = oT1 + 3 * nbmax() * Q1 * Q1, oA = oT2 + 4 * KS * CCP, total = oA + 4 * KS * 64;
+  static_assert(total * 8 <= 80 * 1024, "two workgroups per CU");
+};
+
+// test-side 1D factor of B term t (0: D, values; 1: d/dxi_{a+2}; 2: d/dxi_{a+1}) in direction d
+__device__ __forceinline__ const double* sfb_tab(int t, int a, int d, const double* sV, const double* sD) {
+  const bool der = (t == 1 && d == (a + 2) % 3) || (t == 2 && d == (a + 1) % 3);
+  return der ? sD : sV;
+}
+
+template <int Q1, int P1, int a>
+__device__ __forceinline__ void sfb_block(const DevTables& T, const ProbArgs& P, const ChunkArgs& C, int64_t cell,
+                                          int c, double* smem) {
+  using SH = SfbShape<Q1, P1>;
+  constexpr int NQ = SH::NQ, KD = SH::KD, KS = SH::KS, CCP = SH::CCP, NBM = SH::nbmax();
+  constexpr int na0 = SH::n(a, 0), na1 = SH::n(a, 1), na2 = SH::n(a, 2);
+  constexpr int R = SH::rows(a), Rt = SH::rtiles(a), ctl = SH::ctiles(a), CC = 16 * ctl, Tn = Rt * ctl;
+  constexpr int ncb = SH::ncb(a), nbc = SH::nbc(a), nblk = na2 * P1;
+  const int64_t gc = C.cell_ids[cell];
+  double* sV = smem + SH::oV;
+  double* sD = smem + SH::oD;
+  double* sP = smem + SH::oP;
+  double* sW = smem + SH::oW;
+  double* sT1 = smem + SH::oT1;
+  double* sT2 = smem + SH::oT2;
+  double* sA = smem + SH::oA;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const double* gmet = C.met + cell * met_stride(T);
+  const double* wdj = gmet + 12 * NQ + 36 * T.nfq;   // [q][9] w det J^{-1}
+  const double* wj = wdj + 9 * NQ;                   // [q][9] w J
+  for (int e = tid; e < 2 * Q1 * Q1; e += NT) smem[SH::oV + e] = T.sf_tab[e];
+  for (int e = tid; e < P1 * Q1; e += NT) sP[e] = T.sf_phi[e];
+  constexpr int u1 = (a + 1) % 3, u2 = (a + 2) % 3;
+  for (int q = tid; q < NQ; q += NT) {
+    sW[q] = wdj[9 * q + 3 * a + c];
+    sW[NQ + q] = wj[9 * q + 3 * c + u1];
+    sW[2 * NQ + q] = -wj[9 * q + 3 * c + u2];
+  }
+  // zero rows of T2: D rows Q1 .. 4 KD, R rows 4 KD + 2 Q1 .. 4 KS
+  for (int e = tid; e < (4 * KD - Q1) * CCP; e += NT) sT2[Q1 * CCP + e] = 0.0;
+  for (int e = tid; e < (4 * KS - 4 * KD - 2 * Q1) * CCP; e += NT) sT2[(4 * KD + 2 * Q1) * CCP + e] = 0.0;
+  __syncthreads();
+  // row operands: row (m0, i0) = rt 16 + (lane & 15), m0 fastest; k = 4 ks + (lane >> 4)
+  for (int e = tid; e < Rt * KS * 64; e += NT) {
+    const int ln = e & 63, ks = (e >> 6) % KS, rt = e / (64 * KS);
+    const int row = rt * 16 + (ln & 15), kk = 4 * ks + (ln >> 4);
+    int t, q0;
+    if (ks < KD) {
+      t = 0;
+      q0 = kk;
+    } else {
+      const int r = kk - 4 * KD;
+      t = 1 + r / Q1;
+      q0 = r - (t - 1) * Q1;
+    }
+    const int m0 = row % P1, i0 = row / P1;
+    const double* ft = sfb_tab(t < 3 ? t : 0, a, 0, sV, sD);
+    sA[e] = row < R && t < 3 && q0 < Q1 ? ft[i0 * Q1 + q0] * sP[m0 * Q1 + q0] : 0.0;
+  }
+  const double2 eps = make_double2(P.eps[2 * gc], P.eps[2 * gc + 1]);
+  const double2 mu = make_double2(P.mu[2 * gc], P.mu[2 * gc + 1]);
+  const double om = P.omega;
+  const double* dsc = C.dscale + cell * (int64_t)T.nvp;
+  double2* Z = C.Z + cell * T.zstride;
+  const int64_t ld = T.ldz;
+  const int m1t = T.m1;
+  const int64_t rowE = T.nvp + (int64_t)c * m1t, rowH = T.nvp + (int64_t)(3 + c) * m1t;
+
+  for (int g0 = 0; g0 < nblk; g0 += nbc) {
+    const int nb = min(nbc, nblk - g0);
+    // ---- T1(t, blk; q0, q1) = sum_q2 X2 W_t, block (m2, i2) = (g % P1, g / P1)
+    for (int e = tid; e < 3 * nb * Q1 * Q1; e += NT) {
+      const int q0 = e % Q1, q1 = (e / Q1) % Q1, r = e / (Q1 * Q1);
+      const int blk = r % nb, t = r / nb;
+      const int g = g0 + blk, m2 = g % P1, i2 = g / P1;
+      const double* ft = sfb_tab(t, a, 2, sV, sD);
+      const double* wv = sW + t * NQ + q0 + Q1 * q1;
+      double acc = 0.0;
+#pragma unroll
+      for (int q2 = 0; q2 < Q1; ++q2) acc = fma(ft[i2 * Q1 + q2] * sP[m2 * Q1 + q2], wv[Q1 * Q1 * q2], acc);
+      sT1[(t * NBM + blk) * Q1 * Q1 + q1 * Q1 + q0] = acc;
+    }
+    __syncthreads();
+    // ---- T2(t q0; col) = sum_q1 X1 T1, column (m1, i1, blk), m1 fastest
+    for (int e = tid; e < 3 * CC; e += NT) {
+      const int t = e / CC, col = e - t * CC;
+      const int blk = col / ncb, cc = col - blk * ncb;
+      double out[Q1];
+#pragma unroll
+      for (int q0 = 0; q0 < Q1; ++q0) out[q0] = 0.0;
+      if (blk < nb) {
+        const int m1 = cc % P1, i1 = cc / P1;
+        const double* ft = sfb_tab(t, a, 1, sV, sD);
+        const double* t1 = sT1 + (t * NBM + blk) * Q1 * Q1;
+#pragma unroll 2
+        for (int q1 = 0; q1 < Q1; ++q1) {
+          const double x = ft[i1 * Q1 + q1] * sP[m1 * Q1 + q1];
+#pragma unroll
+          for (int q0 = 0; q0 < Q1; ++q0) out[q0] = fma(x, t1[q1 * Q1 + q0], out[q0]);
+        }
+      }
+      const int row0 = t == 0 ? 0 : 4 * KD + (t - 1) * Q1;
+#pragma unroll
+      for (int q0 = 0; q0 < Q1; ++q0) sT2[(row0 + q0) * CCP + col] = out[q0];
+    }
+    __syncthreads();
+    // ---- D (rows of term 0) and R (terms 1, 2)
+    d4 acD[4], acR[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acD[k] = acR[k] = d4{0, 0, 0, 0};
+    auto kstep = [&](int ks, d4* acc) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int tau = w + 4 * k;
+        if (tau < Tn) {
+          const double av = sA[((tau % Rt) * KS + ks) * 64 + lane];
+          const double bv = sT2[(4 * ks + (lane >> 4)) * CCP + (tau / Rt) * 16 + (lane & 15)];
+          acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[k], 0, 0, 0);
+        }
+      }
+    };
+#pragma unroll
+    for (int ks = 0; ks < KD; ++ks) kstep(ks, acD);
+#pragma unroll 2
+    for (int ks = KD; ks < KS; ++ks) kstep(ks, acR);
+    // ---- the four entries of every (i, m)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int tau = w + 4 * k;
+      if (tau >= Tn) continue;
+      const int col = (tau / Rt) * 16 + (lane & 15);
+      const int blk = col / ncb, cc = col - blk * ncb;
+      if (blk >= nb) continue;
+      const int g = g0 + blk, m2 = g % P1, i2 = g / P1;
+      const int ib = a * T.nc + na0 * ((cc / P1) + na1 * i2), mb = P1 * ((cc % P1) + P1 * m2);
+#pragma unroll
+      for (int it = 0; it < 4; ++it) {
+        const int row = (tau % Rt) * 16 + (lane >> 4) + 4 * it;
+        if (row >= R) continue;
+        const int i = ib + row / P1, m = mb + row % P1;
+        const double D = acD[k][it], Rv = acR[k][it];
+        const double dF = dsc[i], dI = dsc[T.Np + i];
+        double2* zf = Z + (int64_t)i * ld;
+        double2* zi = Z + (int64_t)(T.Np + i) * ld;
+        zf[rowE + m] = make_double2(-dF * om * eps.y * D, -dF * om * eps.x * D);
+        zf[rowH + m] = make_double2(dF * Rv, 0.0);
+        zi[rowE + m] = make_double2(dI * Rv, 0.0);
+        zi[rowH + m] = make_double2(dI * om * mu.y * D, dI * om * mu.x * D);
+      }
+    }
+  }
+}
+
+template <int Q1, int P1>
+__global__ __launch_bounds__(NT, 2) void k_form_Bsf(DevTables T, ProbArgs P, ChunkArgs C) {
+  int64_t cell;
+  int ac;
+  if (!decode_cell_tile(C.n, 9, cell, ac)) return;
+  extern __shared__ double smem[];
+  const int c = ac % 3;
+  switch (ac / 3) {
+    case 0: sfb_block<Q1, P1, 0>(T, P, C, cell, c, smem); break;
+    case 1: sfb_block<Q1, P1, 1>(T, P, C, cell, c, smem); break;
+    default: sfb_block<Q1, P1, 2>(T, P, C, cell, c, smem); break;
+  }
+}
+
+// ================================================================ residual row
+// The volume part of D B_f x for every test function, without forming B:
+// the trial coefficients are interpolated to the points (three 1D passes
+// over the DG factors), combined pointwise with the metric into the fields
+// that the test functions of component a meet,
+//   F rows:  g0 = i w eps sum_c w det J^{-1}_{ac} E_c,  g1 = sum_c w J_{c,a+1} H_c,  g2 = -sum_c w J_{c,a+2} H_c,
+//   I rows:  g0 = -i w mu sum_c w det J^{-1}_{ac} H_c,  g1 = sum_c w J_{c,a+1} E_c,  g2 = -sum_c w J_{c,a+2} E_c,
+// (E_c, H_c the interpolated trial fields), and integrated against them with
+// three 1D passes over the test factors (g1 meets d_{a+2} f_i, g2 meets
+// d_{a+1} f_i).  Writes d (B_f x)_i, unconjugated, to the residual row of
+// columns i < N; k_form_Bt adds the Robin-face part and k_form_T the trace
+// part and takes the conjugate.  One workgroup per cell; fixed summation order.
+template <int Q1, int P1>
+struct SfrShape {
+  static constexpr int NQ = Q1 * Q1 * Q1, M1 = P1 * P1 * P1;
+  // interpolation: 12 real fields (E_c, H_c; re, im)
+  static constexpr int nA = 12 * P1 * P1 * Q1, nB = 12 * P1 * Q1 * Q1;
+  // test integration of one (a, side): fields [3][2][NQ], T1 [3][2][Q1][Q1^2], T2 [3][2][Q1^2][Q1]
+  static constexpr int nG = 6 * NQ, nT1 = 6 * Q1 * Q1 * Q1;
+  static constexpr int nR1 = nA + nB > nG + nT1 ? nA + nB : nG + nT1;
+  static constexpr int oV = 0, oD = Q1 * Q1, oP = 2 * Q1 * Q1, oX = oP + P1 * Q1, oU = oX + 12 * M1,
+                       oR1 = oU + 12 * NQ, total = oR1 + nR1;
+  static_assert(total * 8 <= 160 * 1024, "fits the LDS of a CU");
+};
+
+template <int Q1, int P1>
+__global__ __launch_bounds__(NT) void k_form_resid(DevTables T, ProbArgs P, ChunkArgs C) {
+  using SH = SfrShape<Q1, P1>;
+  constexpr int NQ = SH::NQ, M1 = SH::M1, S = Q1 - 1;
+  const int64_t cell = blockIdx.x;
+  if (cell >= C.n) return;
+  const int64_t gc = C.cell_ids[cell];
+  extern __shared__ double smem[];
+  double* sV = smem + SH::oV;
+  double* sD = smem + SH::oD;
+  double* sP = smem + SH::oP;
+  double* sX = smem + SH::oX;     // [12][M1], field f = 2 (3 h + c) + reim
+  double* sU = smem + SH::oU;     // [12][NQ]
+  double* sA = smem + SH::oR1;    // [12][P1 P1][Q1]
+  double* sB = sA + SH::nA;       // [12][P1][Q1 Q1]
+  double* sG = smem + SH::oR1;    // [3][2][NQ] (after the interpolation)
+  double* sT1 = sG + SH::nG;      // [3][2][Q1][Q1 Q1]
+  double* sT2 = sG;               // [3][2][Q1 Q1][Q1] (after T1)
+  const int tid = threadIdx.x;
+  const double2* xc = C.x + (C.v_off[gc] - C.v_base);
+  for (int e = tid; e < 2 * Q1 * Q1; e += NT) smem[SH::oV + e] = T.sf_tab[e];
+  for (int e = tid; e < P1 * Q1; e += NT) sP[e] = T.sf_phi[e];
+  for (int e = tid; e < 6 * M1; e += NT) {
+    const double2 v = xc[e];   // x[(3 h + c) m1 + m]
+    const int f = e / M1, m = e - f * M1;
+    sX[(2 * f) * M1 + m] = v.x;
+    sX[(2 * f + 1) * M1 + m] = v.y;
+  }
+  __syncthreads();
+  // ---- interpolation to the points: m0 -> q0, m1 -> q1, m2 -> q2
+  for (int e = tid; e < 12 * P1 * P1 * Q1; e += NT) {
+    const int q0 = e % Q1, r = e / Q1, mm = r % (P1 * P1), f = r / (P1 * P1);
+    double acc = 0.0;
+#pragma unroll
+    for (int m0 = 0; m0 < P1; ++m0) acc = fma(sP[m0 * Q1 + q0], sX[f * M1 + m0 + P1 * mm], acc);
+    sA[(f * P1 * P1 + mm) * Q1 + q0] = acc;
+  }
+  __syncthreads();
+  for (int e = tid; e < 12 * P1 * Q1 * Q1; e += NT) {
+    const int q0 = e % Q1, q1 = (e / Q1) % Q1, r = e / (Q1 * Q1), m2 = r % P1, f = r / P1;
+    double acc = 0.0;
+#pragma unroll
+    for (int m1 = 0; m1 < P1; ++m1) acc = fma(sP[m1 * Q1 + q1], sA[(f * P1 * P1 + m1 + P1 * m2) * Q1 + q0], acc);
+    sB[((f * P1 + m2) * Q1 + q1) * Q1 + q0] = acc;
+  }
+  __syncthreads();
+  for (int e = tid; e < 12 * NQ; e += NT) {
+    const int qq = e % (Q1 * Q1), q2 = (e / (Q1 * Q1)) % Q1, f = e / NQ;
+    double acc = 0.0;
+#pragma unroll
+    for (int m2 = 0; m2 < P1; ++m2) acc = fma(sP[m2 * Q1 + q2], sB[(f * P1 + m2) * Q1 * Q1 + qq], acc);
+    sU[e] = acc;
+  }
+  const double2 eps = make_double2(P.eps[2 * gc], P.eps[2 * gc + 1]);
+  const double2 mu = make_double2(P.mu[2 * gc], P.mu[2 * gc + 1]);
+  const double om = P.omega;
+  // i w eps = w (-eps.y, eps.x);  -i w mu = w (mu.y, -mu.x)
+  const double2 cE = make_double2(-om * eps.y, om * eps.x), cH = make_double2(om * mu.y, -om * mu.x);
+  const double* gmet = C.met + cell * met_stride(T);
+  const double* wdj = gmet + 12 * NQ + 36 * T.nfq;
+  const double* wj = wdj + 9 * NQ;
+  const double* dsc = C.dscale + cell * (int64_t)T.nvp;
+  double2* Z = C.Z + cell * T.zstride;
+  const int64_t ld = T.ldz, rrow = T.nvp + T.k + 1;
+  for (int pass = 0; pass < 6; ++pass) {
+    const int a = pass >> 1, side = pass & 1;   // side 0: F rows (E through D, H through R); 1: I rows
+    const int na0 = a == 0 ? S : Q1, na1 = a == 1 ? S : Q1, na2 = a == 2 ? S : Q1;
+    const int u1 = (a + 1) % 3, u2 = (a + 2) % 3;
+    const int fd = side == 0 ? 0 : 6, fr = side == 0 ? 6 : 0;   // fields met by D, by R
+    const double2 cd = side == 0 ? cE : cH;
+    __syncthreads();   // U complete; G, T1 free
+    for (int q = tid; q < NQ; q += NT) {
+      double dr = 0.0, di = 0.0, r1r = 0.0, r1i = 0.0, r2r = 0.0, r2i = 0.0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double wd = wdj[9 * q + 3 * a + c], j1 = wj[9 * q + 3 * c + u1], j2 = wj[9 * q + 3 * c + u2];
+        const double udr = sU[(fd + 2 * c) * NQ + q], udi = sU[(fd + 2 * c + 1) * NQ + q];
+        const double urr = sU[(fr + 2 * c) * NQ + q], uri = sU[(fr + 2 * c + 1) * NQ + q];
+        dr = fma(wd, udr, dr);
+        di = fma(wd, udi, di);
+        r1r = fma(j1, urr, r1r);
+        r1i = fma(j1, uri, r1i);
+        r2r = fma(-j2, urr, r2r);
+        r2i = fma(-j2, uri, r2i);
+      }
+      sG[0 * NQ + q] = cd.x * dr - cd.y * di;
+      sG[1 * NQ + q] = cd.x * di + cd.y * dr;
+      sG[2 * NQ + q] = r1r;
+      sG[3 * NQ + q] = r1i;
+      sG[4 * NQ + q] = r2r;
+      sG[5 * NQ + q] = r2i;
+    }
+    __syncthreads();
+    // T1[t][ri][i2][q1 q0] = sum_q2 f_t,2(i2, q2) g_t
+    for (int e = tid; e < 6 * na2 * Q1 * Q1; e += NT) {
+      const int qq = e % (Q1 * Q1), r = e / (Q1 * Q1), i2 = r % na2, tr = r / na2, t = tr >> 1;
+      const double* ft = sfb_tab(t, a, 2, sV, sD);
+      double acc = 0.0;
+#pragma unroll
+      for (int q2 = 0; q2 < Q1; ++q2) acc = fma(ft[i2 * Q1 + q2], sG[tr * NQ + q2 * Q1 * Q1 + qq], acc);
+      sT1[(tr * Q1 + i2) * Q1 * Q1 + qq] = acc;
+    }
+    __syncthreads();
+    // T2[t][ri][i1 + na1 i2][q0] = sum_q1 f_t,1(i1, q1) T1
+    for (int e = tid; e < 6 * na1 * na2 * Q1; e += NT) {
+      const int q0 = e % Q1, r = e / Q1, ii = r % (na1 * na2), tr = r / (na1 * na2), t = tr >> 1;
+      const int i1 = ii % na1, i2 = ii / na1;
+      const double* ft = sfb_tab(t, a, 1, sV, sD);
+      double acc = 0.0;
+#pragma unroll
+      for (int q1 = 0; q1 < Q1; ++q1) acc = fma(ft[i1 * Q1 + q1], sT1[(tr * Q1 + i2) * Q1 * Q1 + q1 * Q1 + q0], acc);
+      sT2[(tr * Q1 * Q1 + ii) * Q1 + q0] = acc;
+    }
+    __syncthreads();
+    // (B x)_i = sum_t sum_q0 f_t,0(i0, q0) T2
+    for (int il = tid; il < na0 * na1 * na2; il += NT) {
+      const int i0 = il % na0, ii = il / na0;
+      double sr = 0.0, si = 0.0;
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        const double* ft = sfb_tab(t, a, 0, sV, sD);
+#pragma unroll
+        for (int q0 = 0; q0 < Q1; ++q0) {
+          const double fv = ft[i0 * Q1 + q0];
+          sr = fma(fv, sT2[((2 * t) * Q1 * Q1 + ii) * Q1 + q0], sr);
+          si = fma(fv, sT2[((2 * t + 1) * Q1 * Q1 + ii) * Q1 + q0], si);
+        }
+      }
+      const int i = a * T.nc + il, col = side * T.Np + i;
+      Z[(int64_t)col * ld + rrow] = make_double2(dsc[col] * sr, dsc[col] * si);
+    }
+  }
+}
+
+// ================================================================ Robin part of B(F, E)
+// On Robin faces B(F_i, E_cm) also holds -sum_R z Dt_c(i,m),
+//   Dt_c(i,m) = sum_fq w s (psi_i - (psi_i . n) n)_c phi_m,
+// a sum over the face points only.  Added to the rows that k_form_Bsf wrote,
+// and its part of D B_f x to the residual row (after k_form_resid).  One
+// workgroup per (cell, 64 test functions); cells without a Robin face return
+// at once.  Thread t owns test row il = t/4 and the DG functions m = t%4,
+// t%4 + 4, ...; the four shares of a row's residual are added in a fixed
+// order.
+constexpr int BQC = 16;   // face points per staged chunk
 constexpr int BIT = 4;    // DG functions per thread and batch
-// Thread t owns test row il = t/4 of the tile and the DG functions / trace
-// functions m = t%4, t%4 + 4, ...; its share of (D B_f x) for its row is
-// accumulated in a fixed order and the four shares of a row are added in a
-// fixed order, so the residual row is bitwise reproducible.
-__global__ __launch_bounds__(NT, 2) void k_form_B(DevTables T, ProbArgs P, ChunkArgs C) {
+__global__ __launch_bounds__(NT, 2) void k_form_Bt(DevTables T, ProbArgs P, ChunkArgs C) {
+  const int nrt = (T.Np + 63) / 64;
+  int64_t cell;
+  int tile;
+  if (!decode_cell_tile(C.n, nrt, cell, tile)) return;
+  const int64_t gc = C.cell_ids[cell];
+  int rmask = 0;   // bit f: face f is a Robin face
+  for (int f = 0; f < 6; ++f) rmask |= is_robin(P.face_kind[gc * 6 + f]) ? 1 << f : 0;
+  if (!rmask) return;
+  const int i0 = tile * 64;
+  __shared__ double sX[8][3];
+  __shared__ double sGeo[BQC][9];          // tangential maps w s (r_a - (r_a . n) n)
+  __shared__ double sPt[BQC][64][3];       // w s (psi_hat_i tangential)_c
+  __shared__ double2 sRes[64][4];
+  extern __shared__ double smem[];
+  double* sPhi = smem;                      // [BQC][m1]
+  load_cell_vertices(P, gc, sX);
+  const double2* xc = C.x ? C.x + (C.v_off[gc] - C.v_base) : nullptr;
+  const double* d = C.dscale + cell * (int64_t)T.nvp;
+  double2* Z = C.Z + cell * T.zstride;
+  const int64_t ld = T.ldz;
+  const int m1 = T.m1;
+  const int il = threadIdx.x >> 2, sub = threadIdx.x & 3;
+  const int i = i0 + il;
+  const bool ok = i < T.N;
+  const double dF = ok ? d[i] : 0.0;
+  double2 rF = make_double2(0.0, 0.0);
+  __syncthreads();
+  for (int ib = 0; ib < m1; ib += 4 * BIT) {
+    double Dtr[BIT][3], Dti[BIT][3];
+#pragma unroll
+    for (int u = 0; u < BIT; ++u)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) Dtr[u][c] = Dti[u][c] = 0.0;
+    for (int f = 0; f < 6; ++f) {
+      if (!((rmask >> f) & 1)) continue;
+      const double2 zf = make_double2(P.zinv[(gc * 6 + f) * 2], P.zinv[(gc * 6 + f) * 2 + 1]);
+      for (int q0 = 0; q0 < T.nfq; q0 += BQC) {
+        const int nqc = min(BQC, T.nfq - q0);
+        __syncthreads();
+        for (int qq = threadIdx.x; qq < nqc; qq += NT) {
+          const int fq = q0 + qq;
+          const double* xi = &T.face_pts[(f * T.nfq + fq) * 3];
+          Geo g;
+          trilinear(sX, xi[0], xi[1], xi[2], g);
+          double n[3], sa;
+          face_normal(g, f, n, sa);
+          const double ws = T.face_w[f * T.nfq + fq] * sa;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            const double rn = g.Ji[a][0] * n[0] + g.Ji[a][1] * n[1] + g.Ji[a][2] * n[2];
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) sGeo[qq][a * 3 + cc] = ws * (g.Ji[a][cc] - rn * n[cc]);
+          }
+        }
+        for (int e = threadIdx.x; e < nqc * m1; e += NT)
+          sPhi[e] = T.face_phi[((size_t)f * T.nfq + q0 + e / m1) * m1 + e % m1];
+        __syncthreads();
+        for (int e = threadIdx.x; e < nqc * 64; e += NT) {
+          const int qq = e / 64, jl = e % 64;
+          const int ii = min(i0 + jl, T.N - 1);
+          const int a = T.comp[ii];
+          const double v = T.face_v[((size_t)f * T.nfq + q0 + qq) * T.Np + ii];
+          for (int cc = 0; cc < 3; ++cc) sPt[qq][jl][cc] = v * sGeo[qq][a * 3 + cc];
+        }
+        __syncthreads();
+        for (int qq = 0; qq < nqc; ++qq) {
+          const double p0 = sPt[qq][il][0], p1 = sPt[qq][il][1], p2 = sPt[qq][il][2];
+#pragma unroll
+          for (int u = 0; u < BIT; ++u) {
+            const int m = ib + sub + 4 * u;
+            const double ph = (m < m1) ? sPhi[qq * m1 + m] : 0.0;
+            Dtr[u][0] += zf.x * p0 * ph;
+            Dtr[u][1] += zf.x * p1 * ph;
+            Dtr[u][2] += zf.x * p2 * ph;
+            Dti[u][0] += zf.y * p0 * ph;
+            Dti[u][1] += zf.y * p1 * ph;
+            Dti[u][2] += zf.y * p2 * ph;
+          }
+        }
+      }
+    }
+    // stored conj(dF (-z Dt)) = (-dF Re(z Dt), dF Im(z Dt)), added to the volume part
+    if (ok) {
+#pragma unroll
+      for (int u = 0; u < BIT; ++u) {
+        const int m = ib + sub + 4 * u;
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+          if (m >= m1) break;
+          double2* z = Z + (int64_t)i * ld + T.nvp + cc * m1 + m;
+          const double2 dl = make_double2(-dF * Dtr[u][cc], dF * Dti[u][cc]);
+          const double2 v = *z;
+          *z = make_double2(v.x + dl.x, v.y + dl.y);
+          if (xc) {
+            // (d B x) += conj(stored) x
+            const double2 xe = xc[cc * m1 + m];
+            rF.x += dl.x * xe.x + dl.y * xe.y;
+            rF.y += dl.x * xe.y - dl.y * xe.x;
+          }
+        }
+      }
+    }
+  }
+  if (!xc) return;
+  sRes[il][sub] = rF;
+  __syncthreads();
+  if (sub == 0 && ok) {
+    double2 s = sRes[il][0];
+    for (int q = 1; q < 4; ++q) s = make_double2(s.x + sRes[il][q].x, s.y + sRes[il][q].y);
+    double2* z = Z + (int64_t)i * ld + T.nvp + T.k + 1;
+    const double2 v = *z;
+    *z = make_double2(v.x + s.x, v.y + s.y);
+  }
+}
+
+// ================================================================ trace rows, padding, residual
+// Per (cell, 64 test functions):
+//   B(F_i, Hhat_j) = sum_{f not Robin} T_f(i,j),  B(I_i, Ehat_j) = sum_f T_f(i,j)
+// (real, geometry free: the pairing summed over all faces is a table and
+// Robin faces are taken off it for the F rows), the zero rows of the
+// padding test functions, the zero load row (k_form_load writes the load on
+// port cells) and the residual row conj(D B_f x), whose volume and Robin
+// parts k_form_resid and k_form_Bt left in the row.  One wave per column, its
+// lanes along the trace rows in chunks of 64 (coalesced stores); each lane
+// sums its rows' part of D B_f x over the chunks and the wave reduces the
+// column's sum once, in a fixed order.
+__global__ __launch_bounds__(NT) void k_form_T(DevTables T, ProbArgs P, ChunkArgs C) {
   const int nrt = (T.Np + 63) / 64;
   int64_t cell;
   int tile;
   if (!decode_cell_tile(C.n, nrt, cell, tile)) return;
   const int64_t gc = C.cell_ids[cell];
   const int i0 = tile * 64;
-  __shared__ double sX[8][3];
-  __shared__ double sGeo[BQC][21];          // w J (9), w det J^{-T} (9) | Robin: tangential maps
-  // sP = sPQ[0]: w det (J^{-T} psi_hat_i)_c;  sQ = sPQ[1]: w (J chat_i)_c.  One
-  // array, so that the write-out staging below may span both.
-  __shared__ double sPQ[2][BQC][64][3];
-  auto& sP = sPQ[0];
-  auto& sQ = sPQ[1];
-  __shared__ double2 sRes[64][4][2];        // per-thread shares of (D B_f x): [row][share][F/I]
-  extern __shared__ double smem[];
-  double* sPhi = smem;                      // [BQC][m1]
-  load_cell_vertices(P, gc, sX);
   const double2* xc = C.x ? C.x + (C.v_off[gc] - C.v_base) : nullptr;
-  int rmask = 0;   // bit f: face f is a Robin face (a mask, not a per-face array: no scratch)
+  int rmask = 0;
   for (int f = 0; f < 6; ++f) rmask |= is_robin(P.face_kind[gc * 6 + f]) ? 1 << f : 0;
   const int nrobin = __builtin_popcount(rmask);
-  __syncthreads();
-  const double2 eps = make_double2(P.eps[2 * gc], P.eps[2 * gc + 1]);
-  const double2 mu = make_double2(P.mu[2 * gc], P.mu[2 * gc + 1]);
-  const double om = P.omega;
   const double* d = C.dscale + cell * (int64_t)T.nvp;
   double2* Z = C.Z + cell * T.zstride;
-  const double* gmet = C.met + cell * met_stride(T);
   const int64_t ld = T.ldz;
   const int nvp = T.nvp;
-  const int m1 = T.m1;
-  const int il = threadIdx.x >> 2, sub = threadIdx.x & 3;
-  const int i = i0 + il;
-  const bool inrange = i < T.Np, ok = i < T.N;
-  const double dF = inrange ? d[i] : 0.0, dI = inrange ? d[T.Np + i] : 0.0;
-  double2 rF = make_double2(0.0, 0.0), rI = rF;
-  for (int ib = 0; ib < m1; ib += 4 * BIT) {
-    double D[BIT][3], R[BIT][3], Dtr[BIT][3], Dti[BIT][3];
-#pragma unroll
-    for (int u = 0; u < BIT; ++u)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) D[u][c] = R[u][c] = Dtr[u][c] = Dti[u][c] = 0.0;
-    // ---- volume quadrature
-    for (int q0 = 0; q0 < T.nq; q0 += BQC) {
-      const int nqc = min(BQC, T.nq - q0);
-      __syncthreads();
-      for (int e = threadIdx.x; e < nqc * 18; e += NT) {
-        const int qq = e / 18, k = e % 18;
-        // [0, 9): w J ; [9, 18): w det J^{-T} (row a of J^{-1} at 9 + 3a)
-        sGeo[qq][k] = k < 9 ? gmet[21 * T.nq + 36 * T.nfq + 9 * (q0 + qq) + k]
-                            : gmet[12 * T.nq + 36 * T.nfq + 9 * (q0 + qq) + (k - 9)];
-      }
-      for (int e = threadIdx.x; e < nqc * m1; e += NT) sPhi[e] = T.vol_phi[(size_t)(q0 + e / m1) * m1 + e % m1];
-      __syncthreads();
-      for (int e = threadIdx.x; e < nqc * 64; e += NT) {
-        const int qq = e / 64, jl = e % 64;
-        const int ii = min(i0 + jl, T.N - 1);
-        const int q = q0 + qq;
-        const int a = T.comp[ii];
-        const double v = T.vol_v[(size_t)q * T.Np + ii];
-        const double* c = &T.vol_c[((size_t)q * T.Np + ii) * 3];
-        const double* G = sGeo[qq];
-        for (int cc = 0; cc < 3; ++cc) {
-          sP[qq][jl][cc] = G[9 + a * 3 + cc] * v;                             // w det (J^{-T})_{c a}
-          sQ[qq][jl][cc] = G[cc * 3] * c[0] + G[cc * 3 + 1] * c[1] + G[cc * 3 + 2] * c[2];   // w (J chat)_c
-        }
-      }
-      __syncthreads();
-      for (int qq = 0; qq < nqc; ++qq) {
-        const double p0 = sP[qq][il][0], p1 = sP[qq][il][1], p2 = sP[qq][il][2];
-        const double q0v = sQ[qq][il][0], q1v = sQ[qq][il][1], q2v = sQ[qq][il][2];
-#pragma unroll
-        for (int u = 0; u < BIT; ++u) {
-          const int m = ib + sub + 4 * u;
-          const double ph = (m < m1) ? sPhi[qq * m1 + m] : 0.0;
-          D[u][0] += p0 * ph;
-          D[u][1] += p1 * ph;
-          D[u][2] += p2 * ph;
-          R[u][0] += q0v * ph;
-          R[u][1] += q1v * ph;
-          R[u][2] += q2v * ph;
-        }
-      }
-    }
-    // ---- Robin faces: Dt weighted by z (complex)
-    if (nrobin) {
-      for (int f = 0; f < 6; ++f) {
-        if (!((rmask >> f) & 1)) continue;
-        const double2 zf = make_double2(P.zinv[(gc * 6 + f) * 2], P.zinv[(gc * 6 + f) * 2 + 1]);
-        for (int q0 = 0; q0 < T.nfq; q0 += BQC) {
-          const int nqc = min(BQC, T.nfq - q0);
-          __syncthreads();
-          for (int qq = threadIdx.x; qq < nqc; qq += NT) {
-            const int fq = q0 + qq;
-            const double* xi = &T.face_pts[(f * T.nfq + fq) * 3];
-            Geo g;
-            trilinear(sX, xi[0], xi[1], xi[2], g);
-            double n[3], sa;
-            face_normal(g, f, n, sa);
-            const double ws = T.face_w[f * T.nfq + fq] * sa;
-            // tangential part of the rows of J^{-1}: t_a = r_a - (r_a . n) n
-            for (int a = 0; a < 3; ++a) {
-              const double rn = g.Ji[a][0] * n[0] + g.Ji[a][1] * n[1] + g.Ji[a][2] * n[2];
-              for (int cc = 0; cc < 3; ++cc) sGeo[qq][a * 3 + cc] = ws * (g.Ji[a][cc] - rn * n[cc]);
-            }
-          }
-          for (int e = threadIdx.x; e < nqc * m1; e += NT)
-            sPhi[e] = T.face_phi[((size_t)f * T.nfq + q0 + e / m1) * m1 + e % m1];
-          __syncthreads();
-          for (int e = threadIdx.x; e < nqc * 64; e += NT) {
-            const int qq = e / 64, jl = e % 64;
-            const int ii = min(i0 + jl, T.N - 1);
-            const int a = T.comp[ii];
-            const double v = T.face_v[((size_t)f * T.nfq + q0 + qq) * T.Np + ii];
-            for (int cc = 0; cc < 3; ++cc) sP[qq][jl][cc] = v * sGeo[qq][a * 3 + cc];
-          }
-          __syncthreads();
-          for (int qq = 0; qq < nqc; ++qq) {
-            const double p0 = sP[qq][il][0], p1 = sP[qq][il][1], p2 = sP[qq][il][2];
-#pragma unroll
-            for (int u = 0; u < BIT; ++u) {
-              const int m = ib + sub + 4 * u;
-              const double ph = (m < m1) ? sPhi[qq * m1 + m] : 0.0;
-              Dtr[u][0] += zf.x * p0 * ph;
-              Dtr[u][1] += zf.x * p1 * ph;
-              Dtr[u][2] += zf.x * p2 * ph;
-              Dti[u][0] += zf.y * p0 * ph;
-              Dti[u][1] += zf.y * p1 * ph;
-              Dti[u][2] += zf.y * p2 * ph;
-            }
-          }
-        }
-      }
-    }
-    // ---- interior-unknown rows of (D B_f)^H: accumulate D B_f x, then write
-    // through LDS (sP/sQ are free until the next batch) so that every store
-    // instruction covers runs of 16 consecutive rows of one column
-    const int nm = min(4 * BIT, m1 - ib);   // DG functions of this batch
-    // [2 rows E/H][16 m][SBP columns]; the pitch of SBP = 66 16-byte slots puts the
-    // eight lanes of one 128-bit access (two columns x four m) in distinct banks
-    constexpr int SBP = 66;
-    static_assert(2 * 16 * SBP * sizeof(double2) <= sizeof(double) * 2 * BQC * 64 * 3, "staging fits sP and sQ");
-    double2* sb = reinterpret_cast<double2*>(&sPQ[0][0][0][0]);
-#pragma unroll
-    for (int cc = 0; cc < 3; ++cc)
-#pragma unroll
-      for (int side = 0; side < 2; ++side) {
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < BIT; ++u) {
-          const int m = ib + sub + 4 * u;
-          double2 bE = make_double2(0, 0), bH = bE;
-          if (inrange && ok && m < m1) {
-            if (side == 0) {
-              // B(F,E) = i w eps D - z Dt -> stored conj(dF B);  B(F,H) = R
-              const double2 fe =
-                  make_double2(-om * eps.y * D[u][cc] - Dtr[u][cc], om * eps.x * D[u][cc] - Dti[u][cc]);
-              bE = make_double2(dF * fe.x, -dF * fe.y);
-              bH = make_double2(dF * R[u][cc], 0.0);
-            } else {
-              // B(I,E) = R;  B(I,H) = -i w mu D -> conj = w (mu.y, mu.x) D
-              bE = make_double2(dI * R[u][cc], 0.0);
-              bH = make_double2(dI * om * mu.y * D[u][cc], dI * om * mu.x * D[u][cc]);
-            }
-            if (xc) {
-              // (d B x) += conj(stored) x
-              const double2 xe = xc[cc * m1 + m], xh = xc[(3 + cc) * m1 + m];
-              const double px = bE.x * xe.x + bE.y * xe.y + bH.x * xh.x + bH.y * xh.y;
-              const double py = bE.x * xe.y - bE.y * xe.x + bH.x * xh.y - bH.y * xh.x;
-              if (side == 0) {
-                rF.x += px;
-                rF.y += py;
-              } else {
-                rI.x += px;
-                rI.y += py;
-              }
-            }
-          }
-          sb[(0 * 16 + sub + 4 * u) * SBP + il] = bE;
-          sb[(1 * 16 + sub + 4 * u) * SBP + il] = bH;
-        }
-        __syncthreads();
-        // column i0 + e / 32 of this side, rows (E or H, cc, m) for m < nm
-        for (int e = threadIdx.x; e < 64 * 32; e += NT) {
-          const int jl = e >> 5, hr = (e >> 4) & 1, ml = e & 15;
-          const int ii = i0 + jl;
-          if (ml >= nm || ii >= T.Np) continue;
-          const int row = nvp + (3 * hr + cc) * m1 + ib + ml;
-          Z[(int64_t)(side * T.Np + ii) * ld + row] = sb[(hr * 16 + ml) * SBP + jl];
-        }
-      }
-  }
-  sRes[il][sub][0] = rF;
-  sRes[il][sub][1] = rI;
-  // ---- trace unknowns (real, geometry free): one wave per column, its lanes
-  // along the trace rows in chunks of 64 (coalesced stores); each lane sums
-  // its rows' part of D B_f x over the chunks, and the wave reduces the
-  // column's sum once, in a fixed order.  The pairing summed over all faces
-  // is a table; Robin faces are taken off it for the F rows.
   __shared__ double2 sTr[64][2];
-  {
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int ncol = min(64, T.Np - i0);   // columns of this tile
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ncol = min(64, T.Np - i0);   // columns of this tile
+  // interior rows of the padding test functions: zero
+  for (int jl = wv; jl < ncol; jl += NT / 64) {
+    const int ii = i0 + jl;
+    if (ii < T.N) continue;
+    for (int r = lane; r < T.nu; r += 64) {
+      Z[(int64_t)ii * ld + nvp + r] = make_double2(0.0, 0.0);
+      Z[(int64_t)(T.Np + ii) * ld + nvp + r] = make_double2(0.0, 0.0);
+    }
+  }
 #pragma unroll 2
-    for (int jl = wv; jl < ncol; jl += NT / 64) {
-      const int ii = i0 + jl;
-      const double dF = d[ii], dI = d[T.Np + ii];
-      double2 aF = make_double2(0.0, 0.0), aI = aF;
-      for (int c0 = 0; c0 < T.nt1; c0 += 64) {
-        const int jt = c0 + lane;
-        const bool okt = jt < T.nt1, okc = ii < T.N && okt;
-        double tI = okc ? T.Tsum[(size_t)ii * T.nt1 + jt] : 0.0, tF = tI;
-        if (nrobin && okc) {
-          for (int f = 0; f < 6; ++f)
-            if ((rmask >> f) & 1) tF -= T.T[((size_t)f * T.N + ii) * T.nt1 + jt];
-        }
-        const double tf = dF * tF, ti = dI * tI;
-        if (okt) {
-          const int rowEh = nvp + T.nu + jt, rowHh = nvp + T.nu + T.nt1 + jt;
-          Z[(int64_t)ii * ld + rowEh] = make_double2(0.0, 0.0);
-          Z[(int64_t)ii * ld + rowHh] = make_double2(tf, 0.0);
-          Z[(int64_t)(T.Np + ii) * ld + rowEh] = make_double2(ti, 0.0);
-          Z[(int64_t)(T.Np + ii) * ld + rowHh] = make_double2(0.0, 0.0);
-          if (xc) {
-            const double2 xe = xc[T.nu + jt], xh = xc[T.nu + T.nt1 + jt];
-            aF.x += tf * xh.x;
-            aF.y += tf * xh.y;
-            aI.x += ti * xe.x;
-            aI.y += ti * xe.y;
-          }
+  for (int jl = wv; jl < ncol; jl += NT / 64) {
+    const int ii = i0 + jl;
+    const double dF = d[ii], dI = d[T.Np + ii];
+    double2 aF = make_double2(0.0, 0.0), aI = aF;
+    for (int c0 = 0; c0 < T.nt1; c0 += 64) {
+      const int jt = c0 + lane;
+      const bool okt = jt < T.nt1, okc = ii < T.N && okt;
+      double tI = okc ? T.Tsum[(size_t)ii * T.nt1 + jt] : 0.0, tF = tI;
+      if (nrobin && okc) {
+        for (int f = 0; f < 6; ++f)
+          if ((rmask >> f) & 1) tF -= T.T[((size_t)f * T.N + ii) * T.nt1 + jt];
+      }
+      const double tf = dF * tF, ti = dI * tI;
+      if (okt) {
+        const int rowEh = nvp + T.nu + jt, rowHh = nvp + T.nu + T.nt1 + jt;
+        Z[(int64_t)ii * ld + rowEh] = make_double2(0.0, 0.0);
+        Z[(int64_t)ii * ld + rowHh] = make_double2(tf, 0.0);
+        Z[(int64_t)(T.Np + ii) * ld + rowEh] = make_double2(ti, 0.0);
+        Z[(int64_t)(T.Np + ii) * ld + rowHh] = make_double2(0.0, 0.0);
+        if (xc) {
+          const double2 xe = xc[T.nu + jt], xh = xc[T.nu + T.nt1 + jt];
+          aF.x += tf * xh.x;
+          aF.y += tf * xh.y;
+          aI.x += ti * xe.x;
+          aI.y += ti * xe.y;
         }
       }
+    }
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        aF.x += __shfl_xor(aF.x, off, 64);
-        aF.y += __shfl_xor(aF.y, off, 64);
-        aI.x += __shfl_xor(aI.x, off, 64);
-        aI.y += __shfl_xor(aI.y, off, 64);
-      }
-      if (lane == 0) {
-        sTr[jl][0] = aF;
-        sTr[jl][1] = aI;
-      }
+    for (int off = 32; off > 0; off >>= 1) {
+      aF.x += __shfl_xor(aF.x, off, 64);
+      aF.y += __shfl_xor(aF.y, off, 64);
+      aI.x += __shfl_xor(aI.x, off, 64);
+      aI.y += __shfl_xor(aI.y, off, 64);
+    }
+    if (lane == 0) {
+      sTr[jl][0] = aF;
+      sTr[jl][1] = aI;
     }
   }
   __syncthreads();
-  // ---- padding rows of the RHS block, zero load row, residual row conj(D B_f x)
-  // (k_form_load subtracts the load on port cells)
+  // padding rows of the RHS block, zero load row, residual row
   for (int e = threadIdx.x; e < 64 * (T.kp - T.k); e += NT) {
     const int jl = e % 64, rr = e / 64;
     const int ii = i0 + jl;
     if (ii >= T.Np) continue;
     const int row = nvp + T.k + rr;
     double2 vF = make_double2(0.0, 0.0), vI = vF;
-    if (rr == 1) {
-      for (int q = 0; q < 4; ++q) {
-        vF.x += sRes[jl][q][0].x;
-        vF.y += sRes[jl][q][0].y;
-        vI.x += sRes[jl][q][1].x;
-        vI.y += sRes[jl][q][1].y;
+    if (rr == 1 && xc) {
+      if (ii < T.N) {
+        vF = Z[(int64_t)ii * ld + row];
+        vI = Z[(int64_t)(T.Np + ii) * ld + row];
       }
       vF.x += sTr[jl][0].x;
       vF.y += sTr[jl][0].y;
@@ -672,8 +990,10 @@ __global__ __launch_bounds__(NT) void k_form_load(DevTables T, ProbArgs P, Chunk
       double2 E[3], H[3];
       te_fields(P, P.omega, g.x, E, H);
       double2 En = make_double2(0, 0);
+#pragma unroll
       for (int a = 0; a < 3; ++a) En = make_double2(En.x + E[a].x * n[a], En.y + E[a].y * n[a]);
       double2 gv[3];
+#pragma unroll
       for (int a = 0; a < 3; ++a) {
         const int b = (a + 1) % 3, c = (a + 2) % 3;
         const double2 nxh = make_double2(n[b] * H[c].x - n[c] * H[b].x, n[b] * H[c].y - n[c] * H[b].y);
@@ -682,8 +1002,10 @@ __global__ __launch_bounds__(NT) void k_form_load(DevTables T, ProbArgs P, Chunk
         gv[a] = make_double2(nxh.x + zet.x, nxh.y + zet.y);
       }
       const double ws = T.face_w[f * T.nfq + fq] * s;
+#pragma unroll
       for (int a = 0; a < 3; ++a) {
         double2 rg = make_double2(0, 0);
+#pragma unroll
         for (int cc = 0; cc < 3; ++cc) {
           rg.x += g.Ji[a][cc] * gv[cc].x;
           rg.y += g.Ji[a][cc] * gv[cc].y;
@@ -2301,8 +2623,33 @@ hipError_t launch_formation(const DevTables& t, const ProbArgs& pa, const ChunkA
   const int nt = (t.Np + 63) / 64;
   DPG_LAUNCH(KC_FORM_IF, prof, st, k_form_IF, dim3(grid_cells_tiles(ca.n, nt * nt)), dim3(NT), 0, st, t, pa, ca);
   DPG_LAUNCH(KC_FORM_PAD, prof, st, k_form_pad, dim3((unsigned)ca.n), dim3(NT), 0, st, t, ca);
-  DPG_LAUNCH(KC_FORM_B, prof, st, k_form_B, dim3(grid_cells_tiles(ca.n, nt)), dim3(NT), sizeof(double) * BQC * t.m1,
+  // B_f^H: volume D and R (sum factorised), the volume part of the residual
+  // row (matrix free), the Robin-face part, then the trace rows and padding
+  const dim3 gb(grid_cells_tiles(ca.n, 9));
+  switch (t.n1 * 16 + t.p + 1) {
+#define DPG_B_CASE(Q, PP)                                                                                            \
+  case Q * 16 + PP:                                                                                                  \
+    DPG_LAUNCH(KC_FORM_B, prof, st, (k_form_Bsf<Q, PP>), gb, dim3(NT), (sizeof(double) * SfbShape<Q, PP>::total), st,  \
+               t, pa, ca);                                                                                           \
+    if (ca.x)                                                                                                        \
+      DPG_LAUNCH(KC_FORM_B, prof, st, (k_form_resid<Q, PP>), dim3((unsigned)ca.n), dim3(NT),                         \
+                 (sizeof(double) * SfrShape<Q, PP>::total), st, t, pa, ca);                                          \
+    break;
+    DPG_B_CASE(4, 2)
+    DPG_B_CASE(5, 2)
+    DPG_B_CASE(5, 3)
+    DPG_B_CASE(6, 3)
+    DPG_B_CASE(6, 4)
+    DPG_B_CASE(7, 4)
+    DPG_B_CASE(7, 5)
+    DPG_B_CASE(8, 5)
+#undef DPG_B_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  DPG_LAUNCH(KC_FORM_B, prof, st, k_form_Bt, dim3(grid_cells_tiles(ca.n, nt)), dim3(NT), sizeof(double) * BQC * t.m1,
              st, t, pa, ca);
+  DPG_LAUNCH(KC_FORM_B, prof, st, k_form_T, dim3(grid_cells_tiles(ca.n, nt)), dim3(NT), 0, st, t, pa, ca);
   DPG_LAUNCH(KC_FORM_LOAD, prof, st, k_form_load, dim3(grid_cells_tiles(ca.n, nt)), dim3(NT),
              sizeof(double2) * 3 * t.nfq, st, t, pa, ca);
   return hipGetLastError();
@@ -2373,8 +2720,16 @@ hipError_t configure_kernels() {
   const void* fns[] = {reinterpret_cast<const void*>(&k_chol_diag0), reinterpret_cast<const void*>(&k_chol_step),
                        reinterpret_cast<const void*>(&k_chol_fpanel), reinterpret_cast<const void*>(&k_chol_fblock),
                        reinterpret_cast<const void*>(&k_cell_scale),
-                       reinterpret_cast<const void*>(&k_form_B), reinterpret_cast<const void*>(&k_herk),
-                       reinterpret_cast<const void*>(&k_herk_split)};
+                       reinterpret_cast<const void*>(&k_form_Bt), reinterpret_cast<const void*>(&k_herk),
+                       reinterpret_cast<const void*>(&k_herk_split),
+#define DPG_FORM_FNS(Q, PP)                                                                                      \
+  reinterpret_cast<const void*>(&k_form_Bsf<Q, PP>), reinterpret_cast<const void*>(&k_form_resid<Q, PP>),
+                       DPG_FORM_FNS(4, 2) DPG_FORM_FNS(5, 2) DPG_FORM_FNS(5, 3) DPG_FORM_FNS(6, 3) DPG_FORM_FNS(6, 4)
+                       DPG_FORM_FNS(7, 4) DPG_FORM_FNS(7, 5) DPG_FORM_FNS(8, 5)
+#undef DPG_FORM_FNS
+                       reinterpret_cast<const void*>(&k_form_SM<4>), reinterpret_cast<const void*>(&k_form_SM<5>),
+                       reinterpret_cast<const void*>(&k_form_SM<6>), reinterpret_cast<const void*>(&k_form_SM<7>),
+                       reinterpret_cast<const void*>(&k_form_SM<8>)};
   for (const void* f : fns) {
     hipFuncAttributes fa;
     e = hipFuncGetAttributes(&fa, f);

@@ -241,6 +241,12 @@ RefTables build_tables(int p, int dp) {
     onb(d.s, (double)side, v, dv);
     for (int k = 0; k <= d.s; ++k) T.sf_side[(size_t)side * (d.s + 1) + k] = v[k];
   }
+  T.sf_phi.assign((size_t)(p + 1) * d.n1, 0.0);
+  T.sf_phis.assign((size_t)2 * (p + 1), 0.0);
+  for (int k = 0; k <= p; ++k) {
+    for (int q = 0; q < d.n1; ++q) T.sf_phi[(size_t)k * d.n1 + q] = lagrange(zl, k, gx[q]);
+    for (int side = 0; side < 2; ++side) T.sf_phis[(size_t)side * (p + 1) + k] = lagrange(zl, k, (double)side);
+  }
   auto phi_at = [&](const double* xi, double* out) {
     int n = p + 1;
     for (int kk = 0; kk < n; ++kk)

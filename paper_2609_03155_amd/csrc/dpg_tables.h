@@ -30,6 +30,8 @@ struct RefTables {
   std::vector<double> face_v;             // [6][nfq][Np]
   std::vector<double> sf_tab;             // [2][s+1][n1]: orthonormal shifted Legendre q_k and q_k' at the Gauss points
   std::vector<double> sf_side;            // [2][s+1]: q_k(0), q_k(1) (the normal factor on the faces)
+  std::vector<double> sf_phi;             // [p+1][n1]: 1D Lagrange factors of the DG basis at the Gauss points
+  std::vector<double> sf_phis;            // [2][p+1]: the same at 0 and 1
   std::vector<double> face_phi;           // [6][nfq][m1]
   std::vector<double> Cref;               // [N][N]  int curl psi_hat_i . psi_hat_j
   std::vector<double> Rt;                 // [6][N][N] int_f (n_hat x psi_hat_i) . psi_hat_j
