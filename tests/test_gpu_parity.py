@@ -509,39 +509,60 @@ def _kappa_tol(M):
 
 
 def _condense_case(w):
+    """dpg_condense on the oracle's K_e, l_e of every cell (uploaded in the
+    plan's output layout) against the oracle's condensation of the same
+    matrices.  Returns the plan, the oracle's A_K, b_K uploaded in the
+    condensation's output layout, and the oracle's per-cell A_K, b_K."""
     torch = _torch()
     from oracle import dpg_assembly as OA
     from paper_2609_03155_amd import dpg
     plan = dpg.Plan(w.degree, w.dp)
-    prob = dpg.DeviceProblem.from_workload(w)
-    K, l, eta, info = plan.alloc_outputs()
-    plan.local_solve(prob, None, K, l, eta, info)
+    K, l, _, _ = plan.alloc_outputs()
+    Kh = np.zeros(K.shape[0], np.complex128)
+    lh = np.zeros(l.shape[0], np.complex128)
+    cells = []
+    for c in range(w.n_cells):
+        *_, Ko, lo, _ = oracle_cell(w, c)
+        Kh[plan.K_off[c]:plan.K_off[c + 1]] = Ko.T.ravel()     # column-major
+        lh[plan.v_off[c]:plan.v_off[c + 1]] = lo
+        cells.append((Ko, lo))
+    K.copy_(torch.from_numpy(Kh))
+    l.copy_(torch.from_numpy(lh))
     A, b, cinfo = plan.condense(K, l)
     torch.cuda.synchronize()
-    Kh, lh, Ah, bh = K.cpu().numpy(), l.cpu().numpy(), A.cpu().numpy(), b.cpu().numpy()
+    Ah, bh = A.cpu().numpy(), b.cpu().numpy()
     A_off, b_off = plan.trace_offsets()
     assert np.all(cinfo.cpu().numpy()[:w.n_cells] == 0)
+    Ao_all = np.zeros_like(Ah)
+    bo_all = np.zeros_like(bh)
     cellsA, cellsb = [], []
     for c in range(w.n_cells):
         p = int(w.degree[c])
         nu, nt = 6 * (p + 1) ** 3, 24 * (p + 1) ** 2
-        k = nu + nt
-        Kc = Kh[plan.K_off[c]:plan.K_off[c + 1]].reshape(k, k).T
-        lc = lh[plan.v_off[c]:plan.v_off[c + 1]]
-        Ao, bo = OA.condense(Kc, lc, nu)
+        Ko, lo = cells[c]
+        Ao, bo = OA.condense(Ko, lo, nu)
         Ag = Ah[A_off[c]:A_off[c + 1]].reshape(nt, nt).T
         bg = bh[b_off[c]:b_off[c + 1]]
-        tol = _kappa_tol(Kc[:nu, :nu])
+        tol = _kappa_tol(Ko[:nu, :nu])
         assert rel(Ag, Ao) < tol, (c, p, rel(Ag, Ao), tol)
-        assert np.linalg.norm(bg - bo) <= tol * max(np.linalg.norm(bo), 1e-300), (c, p)
-        cellsA.append(Ag)
-        cellsb.append(bg)
-    return plan, A, b, cellsA, cellsb
+        # b_K = l_t - M2^H M1^{-1} l_u is a difference: its rounding error is
+        # relative to the size of the two terms, not of the (possibly much
+        # smaller) result
+        bscale = np.linalg.norm(lo[nu:]) + np.linalg.norm(Ko[:nu, nu:].conj().T @ np.linalg.solve(Ko[:nu, :nu], lo[:nu]))
+        assert np.linalg.norm(bg - bo) <= tol * max(bscale, 1e-300), (c, p, np.linalg.norm(bg - bo), bscale)
+        Ao_all[A_off[c]:A_off[c + 1]] = Ao.T.ravel()
+        bo_all[b_off[c]:b_off[c + 1]] = bo
+        cellsA.append(Ao)
+        cellsb.append(bo)
+    Ad = torch.from_numpy(Ao_all).cuda()
+    bd = torch.from_numpy(bo_all).cuda()
+    return plan, Ad, bd, cellsA, cellsb
 
 
 def test_condensation_matches_oracle_on_gpu_local_matrices():
-    """A_K, b_K from the GPU's K_e, l_e against the oracle's condensation of
-    the same K_e, l_e (per cell, bar max(1e-10, 4 kappa(D M1 D) u)); mixed degrees."""
+    """A_K, b_K of dpg_condense on the oracle's K_e, l_e against the oracle's
+    condensation of the same matrices (per cell, bar max(1e-10, 4 kappa(D M1
+    D) u)); mixed degrees."""
     _say("case: dpg_condense config1 and mixed p 1..4")
     _condense_case(W.config1())
     w = W.config3(nx=3, ny=2, nz=2)
