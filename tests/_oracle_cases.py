@@ -224,3 +224,28 @@ def check_split(ref, Kg, lg, eg, what=""):
     if "eta" in e:
         assert e["eta"] <= ref.fp64_bar("eta"), info
     return e
+
+
+def oracle_global_solve(w):
+    """The oracle's whole global solve of workload w (every cell's K_e, its
+    condensation, the assembled trace system solved densely, reconstruction,
+    and the residual indicator of the reconstructed cell vectors).  Returns
+    (traces, cell vectors, eta per cell, cond(A))."""
+    from oracle import dpg_assembly as OA
+    from oracle import dpg_oracle as O
+    cells = []
+    for c in range(w.n_cells):
+        G, Bf, l, K, le, _ = oracle_cell(w, c)
+        cells.append((G, Bf, l, K, le, 6 * (int(w.degree[c]) + 1) ** 3))
+    cond = [OA.condense(K, le, nu) for (_, _, _, K, le, nu) in cells]
+    glob, n = OA.trace_numbering(w.cells, w.face_kind, w.degree)
+    Ao, bo = OA.assemble([a for a, _ in cond], [b for _, b in cond], glob, n)
+    Ad = Ao.toarray()
+    to = np.linalg.solve(Ad, bo)
+    ev = np.linalg.eigvalsh(Ad)
+    xs, etas = [], []
+    for (G, Bf, l, K, le, nu), g in zip(cells, glob):
+        x = OA.reconstruct(K, le, nu, OA.scatter(to, g))
+        xs.append(x)
+        etas.append(O.local_solve(G, Bf, l, x)[2])
+    return to, xs, np.array(etas), ev.max() / ev.min()

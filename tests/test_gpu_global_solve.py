@@ -29,7 +29,7 @@ import pytest
 
 from paper_2609_03155_amd import workloads as W
 
-from _oracle_cases import oracle_cell, rel
+from _oracle_cases import oracle_cell, oracle_global_solve as _oracle_pipeline, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -180,27 +180,6 @@ def test_reconstruction_matches_oracle_on_synthetic_cells():
         assert rel(xg[:nu], xo[:nu]) <= tol, (c, rel(xg[:nu], xo[:nu]), tol)
         assert np.array_equal(xg[nu:], tc)
     plan.close()
-
-
-def _oracle_pipeline(w):
-    from oracle import dpg_assembly as OA
-    from oracle import dpg_oracle as O
-    cells = []
-    for c in range(w.n_cells):
-        G, Bf, l, K, le, _ = oracle_cell(w, c)
-        cells.append((G, Bf, l, K, le, 6 * (int(w.degree[c]) + 1) ** 3))
-    cond = [OA.condense(K, le, nu) for (_, _, _, K, le, nu) in cells]
-    glob, n = OA.trace_numbering(w.cells, w.face_kind, w.degree)
-    Ao, bo = OA.assemble([a for a, _ in cond], [b for _, b in cond], glob, n)
-    Ad = Ao.toarray()
-    to = np.linalg.solve(Ad, bo)
-    ev = np.linalg.eigvalsh(Ad)
-    xs, etas = [], []
-    for (G, Bf, l, K, le, nu), g in zip(cells, glob):
-        x = OA.reconstruct(K, le, nu, OA.scatter(to, g))
-        xs.append(x)
-        etas.append(O.local_solve(G, Bf, l, x)[2])
-    return to, xs, np.array(etas), ev.max() / ev.min()
 
 
 def _mixed_2x2x2():
