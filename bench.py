@@ -331,12 +331,14 @@ def accuracy_report(w, cells, outputs):
 FORM_KEYS = ("scale", "form_SM", "form_IF", "form_pad", "form_B", "form_load")
 
 
-def sub_record(wname: str, steps: int = 2, warmup: int = 1, err_cells=None):
+def sub_record(wname: str, steps: int = 2, warmup: int = 1, err_cells=None, tune: bool = False):
     """A smaller measurement of another workload for the same JSON line: both
-    precisions, default batching (concurrent degree branches, whole chunks;
-    not autotuned), one profiled eager solve on the sequential schedule for
-    the kernel-class times, then `steps` timed graph replays after `warmup`;
-    element-wise errors of `err_cells(w)` against the oracle if given."""
+    precisions, default batching (concurrent degree branches, whole chunks)
+    or, with `tune`, the autotuner's choice (chunking, formation tile shape
+    and schedule per degree, tuned once on the split path); one profiled
+    eager solve on the sequential schedule for the kernel-class times, then
+    `steps` timed graph replays after `warmup`; element-wise errors of
+    `err_cells(w)` against the oracle if given."""
     import torch
     from paper_2609_03155_amd import dpg
     torch.cuda.empty_cache()
@@ -348,9 +350,15 @@ def sub_record(wname: str, steps: int = 2, warmup: int = 1, err_cells=None):
     K, l, eta, info = plan.alloc_outputs()
     stream = torch.cuda.current_stream()
     degs = sorted(set(int(v) for v in w.degree))
+    if tune:
+        plan.autotune(prob, xd, K, l, eta, info, precision=dpg.DPG_SPLIT_FP32, stream=stream)
+        torch.cuda.synchronize()
     rec = {"workload": w.name, "cells": w.n_cells, "degrees": degs, "dp": w.dp,
-           "batching": "concurrent degree branches, whole chunks (default plan, not autotuned)",
-           "cells_per_launch": {str(p): plan.tuning(p)[0] for p in degs}}
+           "batching": ("autotuned (split path): cells per launch sequence, formation tile shape, schedule"
+                        if tune else "concurrent degree branches, whole chunks (default plan, not autotuned)"),
+           "concurrent_degree_branches": plan.tuning(degs[0])[1],
+           "cells_per_launch": {str(p): plan.tuning(p)[0] for p in degs},
+           "formation_col_tiles": {str(p): plan.tiles(p) for p in degs}}
     cells = err_cells(w) if err_cells else []
     outs = {}
     for name, code in (("fp64", dpg.DPG_FP64), ("split", dpg.DPG_SPLIT_FP32)):
@@ -362,7 +370,7 @@ def sub_record(wname: str, steps: int = 2, warmup: int = 1, err_cells=None):
         plan.local_solve(prob, xd, K, l, eta, info, precision=code, stream=stream)
         torch.cuda.synchronize()
         plan.set_profiling(False)
-        plan.set_concurrency(True)
+        plan.set_concurrency(rec["concurrent_degree_branches"])
         prof = plan.profile()
         if cells:
             outs[name] = {}
@@ -600,7 +608,8 @@ def main():
     degs = sorted(set(int(v) for v in w.degree))
     rec["batching"] = {"timed": "eager" if args.no_graph else "hip-graph replays",
                        "concurrent_degree_branches": plan.tuning(degs[0])[1],
-                       "cells_per_launch": {str(p): plan.tuning(p)[0] for p in degs}}
+                       "cells_per_launch": {str(p): plan.tuning(p)[0] for p in degs},
+                       "formation_col_tiles": {str(p): plan.tiles(p) for p in degs}}
     if "split" in runs and "fp64" in runs:
         rec["speedup_split_vs_fp64"] = runs["fp64"][0] / runs["split"][0]
     if not args.no_trace_system and not streaming:
@@ -638,7 +647,7 @@ def main():
         del K, l, eta, info
         plan.close()
         torch.cuda.empty_cache()
-        rec["sub_records"] = {"c3_mixed_degrees": sub_record("c3", err_cells=_c3_cells),
+        rec["sub_records"] = {"c3_mixed_degrees": sub_record("c3", err_cells=_c3_cells, tune=True),
                               "c4_p4_dp2": sub_record("c4", steps=1, warmup=1)}
     print(json.dumps(rec), flush=True)
 

@@ -195,11 +195,14 @@ dpg_status dpg_local_solve_range(dpg_plan plan, const dpg_problem* prob, int64_t
  * same bit for bit either way.  Host only; affects later solves and graphs. */
 dpg_status dpg_plan_set_concurrency(dpg_plan plan, int32_t enable);
 
-/* Autotuner of the batching: after one warm-up solve, for each degree group
- * (queue order) it times whole solves of all n_cells cells with 1, 1/2 and
- * 1/4 of the group's chunk per launch sequence and keeps the fastest, then
- * times the concurrent schedule against the sequential one and keeps the
- * faster.
+/* Autotuner of the batching and tile shapes: after one warm-up solve, for
+ * each degree group (queue order) it times whole solves of all n_cells cells
+ * with 1, 1/2 and 1/4 of the group's chunk per launch sequence and keeps the
+ * fastest; then, for each group, the tile shape of the sum-factorised
+ * formation (8 or 4 column tiles of 16 per chunk, see dpg_plan_tiles) and
+ * keeps the faster; then times the concurrent schedule against the
+ * sequential one and keeps the faster.  Results do not depend on any of
+ * these choices (bit for bit).
  * Arguments as dpg_local_solve (all cells); the outputs hold a complete
  * solve with the chosen settings on return.  *best_ms (may be NULL)
  * receives the time of that last solve.  Synchronises `stream`. */
@@ -209,6 +212,16 @@ dpg_status dpg_plan_autotune(dpg_plan plan, const dpg_problem* prob, const doubl
 /* Current batching of degree p: cells per launch sequence and whether the
  * concurrent schedule is on.  Host only. */
 dpg_status dpg_plan_tuning(dpg_plan plan, int32_t p, int64_t* run_chunk, int32_t* concurrent);
+
+/* Tile shape of degree p's sum-factorised formation (the contractions of the
+ * test-norm and trial-to-test forms, Sec. 2.2): the number of 16-column MFMA
+ * tiles per chunk of the last contraction, 8 (the default) or 4 (less LDS
+ * per workgroup, more workgroups per CU); wider blocks are never split.
+ * dpg_plan_set_tiles sets it (DPG_ERR_ARG for other values or a degree the
+ * plan does not hold); dpg_plan_autotune picks it.  Results are the same bit
+ * for bit with either.  Host only; affects later solves and graphs. */
+dpg_status dpg_plan_tiles(dpg_plan plan, int32_t p, int32_t* form_col_tiles);
+dpg_status dpg_plan_set_tiles(dpg_plan plan, int32_t p, int32_t form_col_tiles);
 
 /* Captures dpg_local_solve_range(plan, prob, first, count, x, K, l, eta,
  * info, precision) into a HIP graph (degree groups as parallel branches when

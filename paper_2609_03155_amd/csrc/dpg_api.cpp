@@ -195,6 +195,7 @@ void build_group(DegreeGroup& g, int dp) {
   t.sf_side = upload(g.bufs, rt.sf_side);
   t.sf_phi = upload(g.bufs, rt.sf_phi);
   t.sf_phis = upload(g.bufs, rt.sf_phis);
+  t.sf_cap = 8;
 }
 
 void free_plan(dpg_plan_s* p) {
@@ -670,7 +671,26 @@ dpg_status dpg_plan_autotune(dpg_plan plan, const dpg_problem* prob, const doubl
     g.run_chunk = pick;
     best = pick_ms;
   }
-  // 2. concurrent degree branches or one stream
+  // 2. tile shape of the sum-factorised formation of each group: column
+  // tiles per chunk (8, or 4: less LDS, more workgroups per CU)
+  for (auto& g : plan->groups) {
+    if (rc != DPG_OK) break;
+    const int cand[2] = {8, 4};
+    int pick = g.dt.sf_cap;
+    float pick_ms = 0.f;
+    for (int c = 0; c < 2 && rc == DPG_OK; ++c) {
+      g.dt.sf_cap = cand[c];
+      float ms = 0.f;
+      rc = timed(ms);
+      if (rc == DPG_OK && (c == 0 || ms < pick_ms)) {
+        pick_ms = ms;
+        pick = cand[c];
+      }
+    }
+    g.dt.sf_cap = pick;
+    best = pick_ms;
+  }
+  // 3. concurrent degree branches or one stream
   if (rc == DPG_OK && plan->groups.size() > 1) {
     plan->concurrent = true;
     float ms = 0.f;
@@ -688,6 +708,26 @@ dpg_status dpg_plan_autotune(dpg_plan plan, const dpg_problem* prob, const doubl
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
   return rc;
+}
+
+dpg_status dpg_plan_tiles(dpg_plan plan, int32_t p, int32_t* form_col_tiles) {
+  if (!plan || !form_col_tiles) return DPG_ERR_ARG;
+  for (auto& g : plan->groups)
+    if (g.p == p) {
+      *form_col_tiles = g.dt.sf_cap;
+      return DPG_OK;
+    }
+  return DPG_ERR_ARG;
+}
+
+dpg_status dpg_plan_set_tiles(dpg_plan plan, int32_t p, int32_t form_col_tiles) {
+  if (!plan || (form_col_tiles != 4 && form_col_tiles != 8)) return DPG_ERR_ARG;
+  for (auto& g : plan->groups)
+    if (g.p == p) {
+      g.dt.sf_cap = form_col_tiles;
+      return DPG_OK;
+    }
+  return DPG_ERR_ARG;
 }
 
 dpg_status dpg_plan_tuning(dpg_plan plan, int32_t p, int64_t* run_chunk, int32_t* concurrent) {

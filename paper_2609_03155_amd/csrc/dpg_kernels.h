@@ -31,6 +31,7 @@ struct DevTables {
   const double* sf_side;   // [2][n1] q_k(0), q_k(1)
   const double* sf_phi;    // [p+1][n1] 1D Lagrange factors of the DG basis at the Gauss points
   const double* sf_phis;   // [2][p+1] the same at 0 and 1
+  int sf_cap;              // column tiles per chunk of the sum-factorised formation (4 or 8; autotuned)
 };
 
 // Per-call problem data (device pointers) plus derived scalars.

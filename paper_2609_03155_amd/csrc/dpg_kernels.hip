@@ -365,7 +365,7 @@ __global__ __launch_bounds__(NT) void k_form_pad(DevTables T, ChunkArgs C) {
 // The Robin-face part of B(F, E) (k_form_Bt), the trace rows, the padding
 // and the residual row (k_form_T, k_form_resid) are written by other kernels.
 // One workgroup per (cell, a, c); a is a compile-time parameter.
-template <int Q1, int P1>
+template <int Q1, int P1, int CAP>
 struct SfbShape {
   static constexpr int S = Q1 - 1;
   static constexpr int NQ = Q1 * Q1 * Q1;
@@ -376,9 +376,12 @@ struct SfbShape {
   __host__ __device__ static constexpr int rows(int a) { return n(a, 0) * P1; }
   __host__ __device__ static constexpr int rtiles(int a) { return (rows(a) + 15) / 16; }
   __host__ __device__ static constexpr int ncb(int a) { return n(a, 1) * P1; }
+  // column tiles per chunk: at most 16 tiles in all and at most CAP columns
+  // tiles (the tile shape the autotuner picks), but at least one (i2, m2) block
   __host__ __device__ static constexpr int ctiles(int a) {
-    return (ncb(a) + 15) / 16 > (16 / rtiles(a) < 8 ? 16 / rtiles(a) : 8) ? (ncb(a) + 15) / 16
-                                                                       : (16 / rtiles(a) < 8 ? 16 / rtiles(a) : 8);
+    return (ncb(a) + 15) / 16 > (16 / rtiles(a) < CAP ? 16 / rtiles(a) : CAP)
+               ? (ncb(a) + 15) / 16
+               : (16 / rtiles(a) < CAP ? 16 / rtiles(a) : CAP);
   }
   __host__ __device__ static constexpr int cc(int a) { return 16 * ctiles(a); }
   __host__ __device__ static constexpr int nbc(int a) { return cc(a) / ncb(a); }
@@ -406,10 +409,10 @@ __device__ __forceinline__ const double* sfb_tab(int t, int a, int d, const doub
   return der ? sD : sV;
 }
 
-template <int Q1, int P1, int a>
+template <int Q1, int P1, int CAP, int a>
 __device__ __forceinline__ void sfb_block(const DevTables& T, const ProbArgs& P, const ChunkArgs& C, int64_t cell,
                                           int c, double* smem) {
-  using SH = SfbShape<Q1, P1>;
+  using SH = SfbShape<Q1, P1, CAP>;
   constexpr int NQ = SH::NQ, KD = SH::KD, KS = SH::KS, CCP = SH::CCP, NBM = SH::nbmax();
   constexpr int na0 = SH::n(a, 0), na1 = SH::n(a, 1), na2 = SH::n(a, 2);
   constexpr int R = SH::rows(a), Rt = SH::rtiles(a), ctl = SH::ctiles(a), CC = 16 * ctl, Tn = Rt * ctl;
@@ -549,7 +552,7 @@ __device__ __forceinline__ void sfb_block(const DevTables& T, const ProbArgs& P,
   }
 }
 
-template <int Q1, int P1>
+template <int Q1, int P1, int CAP>
 __global__ __launch_bounds__(NT, 2) void k_form_Bsf(DevTables T, ProbArgs P, ChunkArgs C) {
   int64_t cell;
   int ac;
@@ -557,9 +560,9 @@ __global__ __launch_bounds__(NT, 2) void k_form_Bsf(DevTables T, ProbArgs P, Chu
   extern __shared__ double smem[];
   const int c = ac % 3;
   switch (ac / 3) {
-    case 0: sfb_block<Q1, P1, 0>(T, P, C, cell, c, smem); break;
-    case 1: sfb_block<Q1, P1, 1>(T, P, C, cell, c, smem); break;
-    default: sfb_block<Q1, P1, 2>(T, P, C, cell, c, smem); break;
+    case 0: sfb_block<Q1, P1, CAP, 0>(T, P, C, cell, c, smem); break;
+    case 1: sfb_block<Q1, P1, CAP, 1>(T, P, C, cell, c, smem); break;
+    default: sfb_block<Q1, P1, CAP, 2>(T, P, C, cell, c, smem); break;
   }
 }
 
@@ -1192,7 +1195,7 @@ __device__ inline void acc_for_each(const Acc& c, F&& f) {
 // One workgroup per (cell, pair a >= b); the columns (i2, j2 blocks, j2 <= i2
 // for a == b) go in chunks of CC = 16 ctiles columns, and the 16-row tiles x
 // 16-column tiles of a chunk are dealt to the four waves (tile tau = w + 4k).
-template <int Q1>
+template <int Q1, int CAP>
 struct SfShape {
   static constexpr int S = Q1 - 1;                // test degree index s: degrees 0..s-1 along a, 0..s across
   static constexpr int NQ = Q1 * Q1 * Q1;
@@ -1202,7 +1205,11 @@ struct SfShape {
   static constexpr int KR = 4 * KS;               // staged T2 rows
   __host__ __device__ static constexpr int n(int comp, int dir) { return comp == dir ? S : Q1; }
   __host__ __device__ static constexpr int rtiles(int a, int b) { return (n(a, 0) * n(b, 0) + 15) / 16; }
-  __host__ __device__ static constexpr int ctiles(int a, int b) { return 16 / rtiles(a, b) < 8 ? 16 / rtiles(a, b) : 8; }
+  // column tiles per chunk: at most 16 tiles in all and at most CAP column
+  // tiles (the tile shape the autotuner picks)
+  __host__ __device__ static constexpr int ctiles(int a, int b) {
+    return 16 / rtiles(a, b) < CAP ? 16 / rtiles(a, b) : CAP;
+  }
   __host__ __device__ static constexpr int cc(int a, int b) { return 16 * ctiles(a, b); }
   __host__ __device__ static constexpr int nbc(int a, int b) { return cc(a, b) / (n(a, 1) * n(b, 1)); }
   __host__ __device__ static constexpr int ccmax() {
@@ -1251,10 +1258,10 @@ __device__ __forceinline__ void sf_tabs(int t, int a, int b, int d, const double
 
 // The (a, b) block of one cell; a and b are compile-time, so that the tile
 // counts, the chunk shape and the index splits are constants.
-template <int Q1, int a, int b>
+template <int Q1, int CAP, int a, int b>
 __device__ __forceinline__ void sf_pair_block(const DevTables& T, const ProbArgs& P, const ChunkArgs& C, int64_t cell,
                                               double* smem) {
-  using SH = SfShape<Q1>;
+  using SH = SfShape<Q1, CAP>;
   constexpr int NQ = SH::NQ, KSS = SH::KSS, KS = SH::KS, CCP = SH::CCP, NBM = SH::nbmax();
   const int64_t gc = C.cell_ids[cell];
   double* sV = smem + SH::oV;
@@ -1470,19 +1477,19 @@ __device__ __forceinline__ void sf_pair_block(const DevTables& T, const ProbArgs
   }
 }
 
-template <int Q1>
+template <int Q1, int CAP>
 __global__ __launch_bounds__(NT, 2) void k_form_SM(DevTables T, ProbArgs P, ChunkArgs C) {
   int64_t cell;
   int pr;
   if (!decode_cell_tile(C.n, 6, cell, pr)) return;
   extern __shared__ double smem[];
   switch (pr) {
-    case 0: sf_pair_block<Q1, 0, 0>(T, P, C, cell, smem); break;
-    case 1: sf_pair_block<Q1, 1, 0>(T, P, C, cell, smem); break;
-    case 2: sf_pair_block<Q1, 1, 1>(T, P, C, cell, smem); break;
-    case 3: sf_pair_block<Q1, 2, 0>(T, P, C, cell, smem); break;
-    case 4: sf_pair_block<Q1, 2, 1>(T, P, C, cell, smem); break;
-    default: sf_pair_block<Q1, 2, 2>(T, P, C, cell, smem); break;
+    case 0: sf_pair_block<Q1, CAP, 0, 0>(T, P, C, cell, smem); break;
+    case 1: sf_pair_block<Q1, CAP, 1, 0>(T, P, C, cell, smem); break;
+    case 2: sf_pair_block<Q1, CAP, 1, 1>(T, P, C, cell, smem); break;
+    case 3: sf_pair_block<Q1, CAP, 2, 0>(T, P, C, cell, smem); break;
+    case 4: sf_pair_block<Q1, CAP, 2, 1>(T, P, C, cell, smem); break;
+    default: sf_pair_block<Q1, CAP, 2, 2>(T, P, C, cell, smem); break;
   }
 }
 
@@ -2605,17 +2612,23 @@ hipError_t launch_formation(const DevTables& t, const ProbArgs& pa, const ChunkA
   const size_t sm = scale_smem(t);
   DPG_LAUNCH(KC_SCALE, prof, st, k_cell_scale, dim3((unsigned)ca.n), dim3(NT), sm, st, t, pa, ca);
   const dim3 gsm(grid_cells_tiles(ca.n, 6));
-  switch (t.n1) {
-#define DPG_SM_CASE(Q)                                                                                          \
-  case Q:                                                                                                       \
-    DPG_LAUNCH(KC_FORM_SM, prof, st, k_form_SM<Q>, gsm, dim3(NT), sizeof(double) * SfShape<Q>::total, st, t, pa, \
-               ca);                                                                                             \
+  if (t.sf_cap != 4 && t.sf_cap != 8) return hipErrorInvalidValue;
+  switch (t.n1 * 16 + t.sf_cap) {
+#define DPG_SM_CASE(Q, CP)                                                                                    \
+  case Q * 16 + CP:                                                                                           \
+    DPG_LAUNCH(KC_FORM_SM, prof, st, (k_form_SM<Q, CP>), gsm, dim3(NT), (sizeof(double) * SfShape<Q, CP>::total), \
+               st, t, pa, ca);                                                                                \
     break;
-    DPG_SM_CASE(4)
-    DPG_SM_CASE(5)
-    DPG_SM_CASE(6)
-    DPG_SM_CASE(7)
-    DPG_SM_CASE(8)
+    DPG_SM_CASE(4, 4)
+    DPG_SM_CASE(4, 8)
+    DPG_SM_CASE(5, 4)
+    DPG_SM_CASE(5, 8)
+    DPG_SM_CASE(6, 4)
+    DPG_SM_CASE(6, 8)
+    DPG_SM_CASE(7, 4)
+    DPG_SM_CASE(7, 8)
+    DPG_SM_CASE(8, 4)
+    DPG_SM_CASE(8, 8)
 #undef DPG_SM_CASE
     default:
       return hipErrorInvalidValue;
@@ -2626,11 +2639,18 @@ hipError_t launch_formation(const DevTables& t, const ProbArgs& pa, const ChunkA
   // B_f^H: volume D and R (sum factorised), the volume part of the residual
   // row (matrix free), the Robin-face part, then the trace rows and padding
   const dim3 gb(grid_cells_tiles(ca.n, 9));
-  switch (t.n1 * 16 + t.p + 1) {
-#define DPG_B_CASE(Q, PP)                                                                                            \
-  case Q * 16 + PP:                                                                                                  \
-    DPG_LAUNCH(KC_FORM_B, prof, st, (k_form_Bsf<Q, PP>), gb, dim3(NT), (sizeof(double) * SfbShape<Q, PP>::total), st,  \
-               t, pa, ca);                                                                                           \
+  switch ((t.n1 * 16 + t.p + 1) * 16 + t.sf_cap) {
+#define DPG_B_CASE(Q, PP)                                                                                          \
+  case (Q * 16 + PP) * 16 + 4:                                                                                     \
+    DPG_LAUNCH(KC_FORM_B, prof, st, (k_form_Bsf<Q, PP, 4>), gb, dim3(NT), (sizeof(double) * SfbShape<Q, PP, 4>::total), \
+               st, t, pa, ca);                                                                                     \
+    if (ca.x)                                                                                                      \
+      DPG_LAUNCH(KC_FORM_B, prof, st, (k_form_resid<Q, PP>), dim3((unsigned)ca.n), dim3(NT),                       \
+                 (sizeof(double) * SfrShape<Q, PP>::total), st, t, pa, ca);                                        \
+    break;                                                                                                         \
+  case (Q * 16 + PP) * 16 + 8:                                                                                     \
+    DPG_LAUNCH(KC_FORM_B, prof, st, (k_form_Bsf<Q, PP, 8>), gb, dim3(NT), (sizeof(double) * SfbShape<Q, PP, 8>::total), \
+               st, t, pa, ca);                                                                                     \
     if (ca.x)                                                                                                        \
       DPG_LAUNCH(KC_FORM_B, prof, st, (k_form_resid<Q, PP>), dim3((unsigned)ca.n), dim3(NT),                         \
                  (sizeof(double) * SfrShape<Q, PP>::total), st, t, pa, ca);                                          \
@@ -2723,14 +2743,17 @@ hipError_t configure_kernels() {
                        reinterpret_cast<const void*>(&k_form_Bt), reinterpret_cast<const void*>(&k_herk),
                        reinterpret_cast<const void*>(&k_herk_split),
 #define DPG_FORM_FNS(Q, PP)                                                                                      \
-  reinterpret_cast<const void*>(&k_form_Bsf<Q, PP>), reinterpret_cast<const void*>(&k_form_resid<Q, PP>),
+  reinterpret_cast<const void*>(&k_form_Bsf<Q, PP, 4>), reinterpret_cast<const void*>(&k_form_Bsf<Q, PP, 8>),     \
+      reinterpret_cast<const void*>(&k_form_resid<Q, PP>),
                        DPG_FORM_FNS(4, 2) DPG_FORM_FNS(5, 2) DPG_FORM_FNS(5, 3) DPG_FORM_FNS(6, 3) DPG_FORM_FNS(6, 4)
                        DPG_FORM_FNS(7, 4) DPG_FORM_FNS(7, 5) DPG_FORM_FNS(8, 5)
 #undef DPG_FORM_FNS
-                       reinterpret_cast<const void*>(&k_form_SM<4>), reinterpret_cast<const void*>(&k_form_SM<5>),
-                       reinterpret_cast<const void*>(&k_form_SM<6>), reinterpret_cast<const void*>(&k_form_SM<7>),
-                       reinterpret_cast<const void*>(&k_form_SM<8>)};
+#define DPG_SM_FNS(Q) reinterpret_cast<const void*>(&k_form_SM<Q, 4>), reinterpret_cast<const void*>(&k_form_SM<Q, 8>),
+                       DPG_SM_FNS(4) DPG_SM_FNS(5) DPG_SM_FNS(6) DPG_SM_FNS(7) DPG_SM_FNS(8)
+#undef DPG_SM_FNS
+                       nullptr};
   for (const void* f : fns) {
+    if (!f) continue;
     hipFuncAttributes fa;
     e = hipFuncGetAttributes(&fa, f);
     if (e != hipSuccess) return e;

@@ -22,7 +22,7 @@ FACE_INTERIOR, FACE_PEC, FACE_PORT, FACE_ROBIN0 = 0, 1, 2, 3
 
 EXPORTS = ("dpg_local_dims", "dpg_plan_create", "dpg_plan_destroy", "dpg_plan_offsets", "dpg_plan_layout",
            "dpg_local_solve", "dpg_local_solve_range", "dpg_plan_set_concurrency", "dpg_plan_autotune",
-           "dpg_plan_tuning", "dpg_graph_create", "dpg_graph_launch", "dpg_graph_destroy", "dpg_form_local",
+           "dpg_plan_tuning", "dpg_plan_tiles", "dpg_plan_set_tiles", "dpg_graph_create", "dpg_graph_launch", "dpg_graph_destroy", "dpg_form_local",
            "dpg_form_augmented",
            "dpg_plan_trace_offsets", "dpg_condense", "dpg_trace_numbering", "dpg_trace_system_create",
            "dpg_trace_system_destroy", "dpg_trace_system_info", "dpg_trace_system_numbering", "dpg_trace_system_csr",
@@ -70,6 +70,8 @@ def lib():
         L.dpg_plan_set_concurrency.argtypes = [vp, i32]
         L.dpg_plan_autotune.argtypes = [vp, C.POINTER(dpg_problem), vp, vp, vp, vp, vp, i32, vp, C.POINTER(dp_)]
         L.dpg_plan_tuning.argtypes = [vp, i32, C.POINTER(i64), C.POINTER(i32)]
+        L.dpg_plan_tiles.argtypes = [vp, i32, C.POINTER(i32)]
+        L.dpg_plan_set_tiles.argtypes = [vp, i32, i32]
         L.dpg_graph_create.argtypes = [vp, C.POINTER(dpg_problem), i64, i64, vp, vp, vp, vp, vp, i32, C.POINTER(vp)]
         L.dpg_graph_launch.argtypes = [vp, vp]
         L.dpg_graph_destroy.argtypes = [vp]
@@ -251,6 +253,16 @@ class Plan:
         a, b = C.c_int64(), C.c_int32()
         _check(lib().dpg_plan_tuning(self._h, int(p), C.byref(a), C.byref(b)), "dpg_plan_tuning")
         return a.value, bool(b.value)
+
+    def tiles(self, p: int) -> int:
+        """dpg_plan_tiles: column tiles per chunk of degree p's sum-factorised formation."""
+        a = C.c_int32()
+        _check(lib().dpg_plan_tiles(self._h, int(p), C.byref(a)), "dpg_plan_tiles")
+        return a.value
+
+    def set_tiles(self, p: int, form_col_tiles: int):
+        """dpg_plan_set_tiles."""
+        _check(lib().dpg_plan_set_tiles(self._h, int(p), int(form_col_tiles)), "dpg_plan_set_tiles")
 
     def graph(self, prob: DeviceProblem, x, K, l, eta, info, precision: int = DPG_FP64, first: int = 0,
               count: int = None) -> "Graph":

@@ -499,6 +499,41 @@ def test_autotune_keeps_results_and_reports_choice():
         run, conc = plan.tuning(p)
         cap = plan.layout(p)[2]
         assert 1 <= run <= cap
+        assert plan.tiles(p) in (4, 8)
+        _say(f"  p={p}: {run} cells per launch sequence, formation tiles {plan.tiles(p)}, concurrent {conc}")
+
+
+@pytest.mark.parametrize("dp", [1, 2])
+def test_formation_tile_shapes_agree_bitwise(dp):
+    """Both tile shapes of the sum-factorised formation give the same K_e,
+    l_e, eta bit for bit (every entry's sum runs in the same order), for
+    every degree; other shapes are rejected."""
+    torch = _torch()
+    from paper_2609_03155_amd import dpg
+    w = _mixed36()
+    w.dp = dp
+    x, off = W.random_coefficients(w)
+    _say(f"case: formation tile shapes 8 and 4, mixed p 1..4, dp={dp}")
+    plan = dpg.Plan(w.degree, w.dp)
+    prob = dpg.DeviceProblem.from_workload(w)
+    xd = torch.from_numpy(x).cuda()
+    outs = []
+    for t in (8, 4):
+        for p in (1, 2, 3, 4):
+            plan.set_tiles(p, t)
+            assert plan.tiles(p) == t
+        for prec in (dpg.DPG_FP64, dpg.DPG_SPLIT_FP32):
+            K, l, eta, info = plan.alloc_outputs()
+            plan.local_solve(prob, xd, K, l, eta, info, prec)
+            torch.cuda.synchronize()
+            outs.append(_host(K, l, eta, info))
+    for a, b in zip(outs[0] + outs[1], outs[2] + outs[3]):
+        assert np.array_equal(a, b)
+    with pytest.raises(dpg.DPGError):
+        plan.set_tiles(2, 6)
+    with pytest.raises(dpg.DPGError):
+        plan.set_tiles(7, 8)
+    plan.close()
 
 
 # ------------------------------------------------------------ condensed trace system
