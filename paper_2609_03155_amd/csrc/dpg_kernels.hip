@@ -1534,132 +1534,165 @@ __device__ __forceinline__ double pivot_rsqrt(double d) {
 // instead loses accuracy by the condition of that factor (measured: about
 // five times LAPACK's element-wise error on the trace block of K_e); with
 // 16x16 inverses the error is that of substitution.
-// Writes the column-major tile `out` and returns the first failing column + 1
-// (0 if none), the same value in every thread.  Registers carry the work:
-// thread (r, g) = (t & 63, t >> 6) owns columns [16g, 16g + 16) of row r of
-// A (updated in place) and of X (from the identity; for the rows of block g
-// the inverse of that diagonal block).  Step c (block kb = c / 16) broadcasts
-// column c of A (its owner wave kb; zero above the diagonal) and row c of X
-// (lane c of wave kb) through a double-buffered LDS slot, one barrier per
-// step; with L_rc = A_rc / sqrt(A_cc):
-//   wave kb stores L_rc for the rows r below block kb,
-//   waves g >= kb:  A_rq -= L_rc conj(L_qc) for their columns q (entries left
-//                   of column c or above the diagonal take meaningless updates
-//                   but are never read again),
-//   wave kb:        X_rq -= (L_rc / L_cc) X_cq  (q in block kb),
-// and row r of X is scaled by 1/L_rr at the end (deferred: row c of X is
-// read unscaled by the later rows of its block).  REAL: the tile is real (Ci
-// is not read) and the imaginary parts are dropped from the arithmetic and
-// the broadcasts; the stored tile also goes to the real column-major tile
-// rout (leading dimension ldr) if given.
+// Blocked, right-looking over the four 16-column blocks kb, two barriers per
+// block:
+//   A. every wave factorises the diagonal block D = A[kb][kb] in its own
+//      registers by column elimination (the same arithmetic in each wave, so
+//      no barrier and no broadcast through LDS; values move between lanes by
+//      shuffles) and forms its inverse X = L_kk^{-1}: lane (i, g) = (l & 15,
+//      l >> 4) holds row i, columns 4e + g (e = 0..3), of D and of X; column
+//      c's step takes L_ic / L_cc = D_ic / d_cc, subtracts it times conj(D_qc)
+//      from D_iq and times X_cq from X_iq, and the rows of X are scaled by
+//      1 / L_ii at the end.  1/sqrt(d_cc) is pivot_rsqrt;
+//   B. wave ib > kb forms the panel block L[ib][kb] = A[ib][kb] X^H on f64
+//      MFMA (X's registers are already its B operand) and puts it in LDS;
+//   C. wave ib subtracts L[ib][kb] L[jb][kb]^H from A[ib][jb], kb < jb <= ib
+//      (f64 MFMA, accumulators started from the LDS block).
+// Wave kb writes X into the LDS diagonal block after the first barrier; the
+// tile then leaves LDS for `out` (and, REAL, for the real column-major tile
+// rout of leading dimension ldr if given) in one coalesced pass.  Returns the
+// first failing column + 1 (0 if none), the same value in every thread.
+// REAL: the tile is real, Ci is never accessed (it need not exist).
 template <bool REAL>
-__device__ __forceinline__ int chol_inv_tile(double* Cr, const double* Ci, double2* __restrict__ out, int64_t ld,
+__device__ __forceinline__ int chol_inv_tile(double* Cr, double* Ci, double2* __restrict__ out, int64_t ld,
                                              double* __restrict__ rout = nullptr, int64_t ldr = 0) {
-  int r = threadIdx.x & 63;
-  __asm__ volatile("" : "+v"(r));   // not hoisted out of a caller's loop (as in wave_tile)
-  const int g = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
-  const bool rowblk = (r >> 4) == g;   // row r lies in this wave's diagonal block
-  double ar[16], ai[16], xr[16], xi[16];
-#pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int q = 16 * g + u;
-    ar[u] = q <= r ? Cr[r * 65 + q] : 0.0;
-    ai[u] = !REAL && q <= r ? Ci[r * 65 + q] : 0.0;
-    xr[u] = q == r ? 1.0 : 0.0;
-    xi[u] = 0.0;
-  }
-  __syncthreads();
-  // broadcast slots [2][64] of column c of A and of row c of X (before its scaling)
-  double2* cb = reinterpret_cast<double2*>(Cr);
-  double2* rb = cb + 128;
-  double* cbr = Cr;
-  double* rbr = Cr + 128;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
+  const int i = lane & 15, g4 = lane >> 4;
   int fail = 0;
-  double pinv = 1.0;   // 1 / L_rr of this thread's row
   for (int kb = 0; kb < 4; ++kb) {
+    const int o = 16 * kb;
+    // ---- A: D = L_kk L_kk^H and X = L_kk^{-1}, in every wave
+    double dr[4], di[4], xr[4], xi[4];
 #pragma unroll
-    for (int uc = 0; uc < 16; ++uc) {
-      const int c = 16 * kb + uc;
-      const int par = (uc & 1) * 64;
-      if (g == kb) {
-        if (REAL) cbr[par + r] = r >= c ? ar[uc] : 0.0;
-        else cb[par + r] = r >= c ? make_double2(ar[uc], ai[uc]) : make_double2(0.0, 0.0);
-        if (r == c) {
+    for (int e = 0; e < 4; ++e) {
+      const int q = 4 * e + g4;
+      dr[e] = q <= i ? Cr[(o + i) * 65 + o + q] : 0.0;
+      di[e] = (!REAL && q <= i) ? Ci[(o + i) * 65 + o + q] : 0.0;
+      xr[e] = q == i ? 1.0 : 0.0;
+      xi[e] = 0.0;
+    }
+    double pinv = 1.0;
 #pragma unroll
-          for (int u = 0; u < 16; ++u) {
-            if (REAL) rbr[par + u] = xr[u];
-            else rb[par + u] = make_double2(xr[u], xi[u]);
-          }
-        }
+    for (int c = 0; c < 16; ++c) {
+      const int ce = c >> 2, cg = c & 3;   // column c: element ce of the lanes with g4 == cg
+      double dcc = __shfl(dr[ce], c + 16 * cg, 64);
+      if (!(dcc > 0.0) || !isfinite(dcc)) {
+        if (!fail) fail = o + c + 1;
+        dcc = 1.0;
       }
-      __syncthreads();
-      double ownr, owni = 0.0, d;
-      if (REAL) {
-        ownr = cbr[par + r];
-        d = cbr[par + c];
-      } else {
-        const double2 own = cb[par + r];
-        ownr = own.x;
-        owni = own.y;
-        d = cb[par + c].x;
-      }
-      if (!(d > 0.0) || !isfinite(d)) {
-        if (!fail) fail = c + 1;
-        d = 1.0;
-      }
-      const double inv = pivot_rsqrt(d);
+      const double inv = pivot_rsqrt(dcc);
       const double inv2 = inv * inv;
-      const double lr = r > c ? ownr * inv2 : 0.0, li = r > c ? owni * inv2 : 0.0;   // L_rc / L_cc
-      if (g == kb && (r >> 4) > kb) {
-        // column c of L below the block diagonal, stored at its step (the
-        // registers of column c take meaningless updates from here on)
-        out[(int64_t)c * ld + r] = make_double2(ownr * inv, REAL ? 0.0 : owni * inv);
-        if (REAL && rout) rout[(int64_t)c * ldr + r] = ownr * inv;
-      }
-      if (g >= kb) {
+      const double cr = __shfl(dr[ce], i + 16 * cg, 64);
+      const double ci = REAL ? 0.0 : __shfl(di[ce], i + 16 * cg, 64);
+      const double lr = i > c ? cr * inv2 : 0.0, li = i > c ? ci * inv2 : 0.0;   // L_ic / L_cc
+      // every read of this step before any of its updates (column c sits in
+      // element ce, which the updates below change)
+      double qr[4], qi[4], yr[4], yi[4];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-          if (REAL) {
-            ar[u] = fma(-lr, cbr[par + 16 * g + u], ar[u]);
-          } else {
-            const double2 m = cb[par + 16 * g + u];   // A_qc (broadcast)
-            ar[u] = fma(-lr, m.x, ar[u]);
-            ar[u] = fma(-li, m.y, ar[u]);
-            ai[u] = fma(-li, m.x, ai[u]);
-            ai[u] = fma(lr, m.y, ai[u]);
-          }
+      for (int e = 0; e < 4; ++e) {
+        const int q = 4 * e + g4;
+        qr[e] = __shfl(dr[ce], q + 16 * cg, 64);            // D_qc
+        qi[e] = REAL ? 0.0 : __shfl(di[ce], q + 16 * cg, 64);
+        yr[e] = __shfl(xr[e], c + 16 * g4, 64);             // X_cq (before its scaling)
+        yi[e] = REAL ? 0.0 : __shfl(xi[e], c + 16 * g4, 64);
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        dr[e] = fma(-lr, qr[e], dr[e]);
+        xr[e] = fma(-lr, yr[e], xr[e]);
+        if (!REAL) {
+          dr[e] = fma(-li, qi[e], dr[e]);
+          di[e] = fma(-li, qr[e], di[e]);
+          di[e] = fma(lr, qi[e], di[e]);
+          xr[e] = fma(li, yi[e], xr[e]);
+          xi[e] = fma(-lr, yi[e], xi[e]);
+          xi[e] = fma(-li, yr[e], xi[e]);
         }
       }
-      if (g == kb) {
-        // rows outside block kb take meaningless X updates (never stored)
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-          if (REAL) {
-            xr[u] = fma(-lr, rbr[par + u], xr[u]);
-          } else {
-            const double2 y = rb[par + u];   // X_cq before scaling (broadcast)
-            xr[u] = fma(-lr, y.x, xr[u]);
-            xr[u] = fma(li, y.y, xr[u]);
-            xi[u] = fma(-lr, y.y, xi[u]);
-            xi[u] = fma(-li, y.x, xi[u]);
-          }
-        }
-      }
-      if (r == c) pinv = inv;
+      if (i == c) pinv = inv;
     }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      xr[e] *= pinv;
+      xi[e] *= pinv;
+    }
+    // ---- B: L[w][kb] = A[w][kb] X^H  (re = Ar Xr^T + Ai Xi^T, im = Ai Xr^T - Ar Xi^T)
+    if (w > kb) {
+      d4 cre = d4{0, 0, 0, 0}, cim = d4{0, 0, 0, 0};
+      const int ar0 = (16 * w + (lane & 15)) * 65 + o + (lane >> 4);
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const double a_r = Cr[ar0 + 4 * ks];
+        cre = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r, xr[ks], cre, 0, 0, 0);
+        if (!REAL) {
+          const double a_i = Ci[ar0 + 4 * ks];
+          cre = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i, xi[ks], cre, 0, 0, 0);
+          cim = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i, xr[ks], cim, 0, 0, 0);
+          cim = __builtin_amdgcn_mfma_f64_16x16x4f64(-a_r, xi[ks], cim, 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int it = 0; it < 4; ++it) {
+        const int idx = (16 * w + (lane >> 4) + 4 * it) * 65 + o + (lane & 15);
+        Cr[idx] = cre[it];
+        if (!REAL) Ci[idx] = cim[it];
+      }
+    }
+    __syncthreads();   // panel blocks of column block kb in LDS; diagonal block kb read by every wave
+    if (w == kb) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int idx = (o + i) * 65 + o + 4 * e + g4;
+        Cr[idx] = xr[e];
+        if (!REAL) Ci[idx] = xi[e];
+      }
+    }
+    // ---- C: A[w][jb] -= L[w][kb] L[jb][kb]^H for kb < jb <= w
+    //      (re -= Lr_w Lr_j^T + Li_w Li_j^T, im -= Li_w Lr_j^T - Lr_w Li_j^T)
+    if (w > kb) {
+      const int aw = (16 * w + (lane & 15)) * 65 + o + (lane >> 4);
+      for (int jb = kb + 1; jb <= w; ++jb) {
+        const int bj = (16 * jb + (lane & 15)) * 65 + o + (lane >> 4);
+        d4 cre, cim = d4{0, 0, 0, 0};
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+          const int idx = (16 * w + (lane >> 4) + 4 * it) * 65 + 16 * jb + (lane & 15);
+          cre[it] = Cr[idx];
+          if (!REAL) cim[it] = Ci[idx];
+        }
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          const double wr = Cr[aw + 4 * ks], jr = Cr[bj + 4 * ks];
+          cre = __builtin_amdgcn_mfma_f64_16x16x4f64(-wr, jr, cre, 0, 0, 0);
+          if (!REAL) {
+            const double wi = Ci[aw + 4 * ks], ji = Ci[bj + 4 * ks];
+            cre = __builtin_amdgcn_mfma_f64_16x16x4f64(-wi, ji, cre, 0, 0, 0);
+            cim = __builtin_amdgcn_mfma_f64_16x16x4f64(-wi, jr, cim, 0, 0, 0);
+            cim = __builtin_amdgcn_mfma_f64_16x16x4f64(wr, ji, cim, 0, 0, 0);
+          }
+        }
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+          const int idx = (16 * w + (lane >> 4) + 4 * it) * 65 + 16 * jb + (lane & 15);
+          Cr[idx] = cre[it];
+          if (!REAL) Ci[idx] = cim[it];
+        }
+      }
+    }
+    __syncthreads();   // trailing blocks updated
   }
-#pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int q = 16 * g + u;
-    if ((r >> 4) > g) continue;   // L below the block diagonal: stored at its step
-    double vr = 0.0, vi = 0.0;
-    if (rowblk && q <= r) {
-      // diagonal block: the inverse of L's diagonal block (lower triangular)
-      vr = xr[u] * pinv;
-      vi = REAL ? 0.0 : xi[u] * pinv;
+  // ---- the tile: L below the block diagonal, the inverses on it, zeros above
+  for (int e = threadIdx.x; e < 64 * 64; e += NT) {
+    const int c = e >> 6, r = e & 63;
+    const bool keep = (r >> 4) >= (c >> 4);
+    const double vr = keep ? Cr[r * 65 + c] : 0.0;
+    if (REAL) {
+      out[(int64_t)c * ld + r] = make_double2(vr, 0.0);
+      if (rout) rout[(int64_t)c * ldr + r] = vr;
+    } else {
+      out[(int64_t)c * ld + r] = make_double2(vr, keep ? Ci[r * 65 + c] : 0.0);
     }
-    out[(int64_t)q * ld + r] = make_double2(vr, vi);
-    if (REAL && rout) rout[(int64_t)q * ldr + r] = vr;
   }
   return fail;
 }
