@@ -1688,7 +1688,7 @@ __device__ __forceinline__ int chol_inv_tile(double* Cr, double* Ci, double2* __
     const bool keep = (r >> 4) >= (c >> 4);
     const double vr = keep ? Cr[r * 65 + c] : 0.0;
     if (REAL) {
-      out[(int64_t)c * ld + r] = make_double2(vr, 0.0);
+      if (out) out[(int64_t)c * ld + r] = make_double2(vr, 0.0);
       if (rout) rout[(int64_t)c * ldr + r] = vr;
     } else {
       out[(int64_t)c * ld + r] = make_double2(vr, keep ? Ci[r * 65 + c] : 0.0);
@@ -1764,17 +1764,20 @@ struct WPipe {
 };
 
 // Operands of one k-step: A from the complex panel Ai (leading dimension
-// lda), B from the complex panel Bj or, when FRB, from a real matrix (the
-// compact copy of the factorised F block, leading dimension ldb).
-template <int MODE, bool FRB, int NV>
-__device__ __forceinline__ void wave_load(const double2* __restrict__ Ai, int64_t lda, const void* __restrict__ Bj,
+// lda) or, when FRA, from a real matrix, B from the complex panel Bj or, when
+// FRB, from a real matrix (the compact copy of the factorised F block,
+// leading dimension ldb).
+template <int MODE, bool FRB, int NV, bool FRA = false>
+__device__ __forceinline__ void wave_load(const void* __restrict__ Ai, int64_t lda, const void* __restrict__ Bj,
                                           int64_t ldb, int ks, WOpsT<NV>& o) {
   const int lane = threadIdx.x & 63;
   const int64_t offa = (int64_t)(4 * ks + (lane >> 4)) * lda + (lane & 15);
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
-    if (MODE == MM_RR) o.a[v].x = reinterpret_cast<const double*>(Ai + offa + 16 * v)[0];
-    else o.a[v] = Ai[offa + 16 * v];
+    if (FRA) o.a[v].x = reinterpret_cast<const double*>(Ai)[offa + 16 * v];
+    else if (MODE == MM_RR)
+      o.a[v].x = reinterpret_cast<const double*>(reinterpret_cast<const double2*>(Ai) + offa + 16 * v)[0];
+    else o.a[v] = reinterpret_cast<const double2*>(Ai)[offa + 16 * v];
   }
   const int64_t offb = (int64_t)(4 * ks + (lane >> 4)) * ldb + (lane & 15);
 #pragma unroll
@@ -1823,8 +1826,8 @@ __device__ __forceinline__ void wave_step(const WOpsT<NV>& o, WAccT<NV>& q) {
 // thousands of terms at p = 4) then grow with the runs' partial sums instead
 // of the running total (measured in an emulation of the sweep: K_e and eta
 // three to twenty times closer to the exact solve at p = 4, dp = 2).
-template <int MODE, bool FRB = false, int NV = 2, bool TWO = false>
-__device__ __forceinline__ void wave_gemm_t(const double2* __restrict__ Ai, int64_t lda, const void* __restrict__ Bj,
+template <int MODE, bool FRB = false, int NV = 2, bool TWO = false, bool FRA = false>
+__device__ __forceinline__ void wave_gemm_t(const void* __restrict__ Ai, int64_t lda, const void* __restrict__ Bj,
                                             int64_t ldb, int K, WAccT<NV>& q) {
   constexpr int NB = WPipe<MODE, NV, TWO>::NB, KS = WPipe<MODE, NV, TWO>::KS;
   static_assert(!TWO || 16 % NB == 0, "a run of 16 k-steps spans whole pipeline rounds");
@@ -1856,13 +1859,14 @@ __device__ __forceinline__ void wave_gemm_t(const double2* __restrict__ Ai, int6
 #pragma unroll
   for (int s = 0; s < NB - 1; ++s)
 #pragma unroll
-    for (int u = 0; u < KS; ++u) wave_load<MODE, FRB, NV>(Ai, lda, Bj, ldb, min(s, nks - 1) * KS + u, o[s][u]);
+    for (int u = 0; u < KS; ++u) wave_load<MODE, FRB, NV, FRA>(Ai, lda, Bj, ldb, min(s, nks - 1) * KS + u, o[s][u]);
   for (int k0 = 0; k0 < nfull; k0 += NB) {
 #pragma unroll
     for (int s = 0; s < NB; ++s) {
 #pragma unroll
       for (int u = 0; u < KS; ++u)
-        wave_load<MODE, FRB, NV>(Ai, lda, Bj, ldb, min(k0 + s + NB - 1, nks - 1) * KS + u, o[(s + NB - 1) % NB][u]);
+        wave_load<MODE, FRB, NV, FRA>(Ai, lda, Bj, ldb, min(k0 + s + NB - 1, nks - 1) * KS + u,
+                                      o[(s + NB - 1) % NB][u]);
       __builtin_amdgcn_sched_barrier(0);   // keep each prefetch in its slot (bounded live ranges)
 #pragma unroll
       for (int u = 0; u < KS; ++u) wave_step<MODE, NV>(o[s][u], acc);
@@ -1922,9 +1926,10 @@ static_assert(RWPT * 16 * RNV == TB, "the waves of a regular tile cover its rows
 constexpr int RTPW = 4 / RWPT;            // regular tiles per workgroup
 
 // Use of the compact real copy of the F block by a tile: none, its operands
-// (panel j and the stored diagonal tile j) from it, or the tile's real output
-// written to it too.
-enum { FR_NONE = 0, FR_READ = 1, FR_WRITE = 2 };
+// (panel j and the stored diagonal tile j) from it, the tile's real output
+// written to it too, or (a tile of the F block itself) every operand from it
+// and the output to it only.
+enum { FR_NONE = 0, FR_READ = 1, FR_WRITE = 2, FR_FB = 3 };
 
 template <int MODE, int FR = FR_NONE, int NV = 2, bool TWO = false>
 __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __restrict__ Z, int64_t cell, int i, int j,
@@ -1953,10 +1958,13 @@ __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __res
       }
   __builtin_amdgcn_sched_barrier(0);
   // panel j and the diagonal tile j: from Z, or from the real copy of the F block
-  constexpr bool FRB = FR == FR_READ;
+  constexpr bool FRB = FR == FR_READ || FR == FR_FB;
   const int64_t ldf = fr_ld(T);
   double* Fr = FR != FR_NONE ? C.fr + cell * fr_stride(T) : nullptr;
-  if (FRB)
+  if (FR == FR_FB)
+    wave_gemm_t<MODE, true, NV, TWO, true>(Fr + (int64_t)k0 * ldf + i * TB + RW * h, ldf,
+                                           Fr + (int64_t)k0 * ldf + j * TB, ldf, j * TB - k0, q);
+  else if (FRB)
     wave_gemm_t<MODE, true, NV, TWO>(Z + (int64_t)k0 * ld + i * TB + RW * h, ld, Fr + (int64_t)k0 * ldf + j * TB,
                                      ldf, j * TB - k0, q);
   else
@@ -2030,8 +2038,8 @@ __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __res
         // in the split path the last column block of W^H is read only through its
         // bf16 planes, except the residual row (eta is formed from it in FP64)
         const bool keep = !(wsplit && last_w) || i * TB + RW * h + r == T.nvp + T.k + 1;
-        if (keep) tile[(int64_t)c * ld + r] = make_double2(vr, vi);
-        if (FR == FR_WRITE) Fr[(int64_t)(j * TB + c) * ldf + i * TB + RW * h + r] = vr;
+        if (keep && FR != FR_FB) tile[(int64_t)c * ld + r] = make_double2(vr, vi);
+        if (FR == FR_WRITE || FR == FR_FB) Fr[(int64_t)(j * TB + c) * ldf + i * TB + RW * h + r] = vr;
         if (wsplit) {
           // three-term bf16 splits of re and im into the wave's LDS slab
           // [RW rows][6 planes][16 columns] (row pitch WSP_PITCH bytes)
@@ -2081,10 +2089,11 @@ __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __res
 // with S0 the column-major tile S0g (FROM_TILE) or the LDS block
 // Sr/Si[r*65 + c] itself; the whole RW x 64 result is written to
 // Sr/Si[r*65 + c] (only its lower part is meaningful).  TWO: two-level
-// summation (wave_gemm_t).
-template <int MODE, bool FROM_TILE, int NV = 2, bool TWO = false>
-__device__ __forceinline__ void diag_update(const double2* __restrict__ S0g, const double2* __restrict__ P, int64_t ld,
-                                            int K, int h, double* Sr, double* Si) {
+// summation (wave_gemm_t).  PREAL: P is a real matrix (the compact copy of
+// the F block) with leading dimension ldp.
+template <int MODE, bool FROM_TILE, int NV = 2, bool TWO = false, bool PREAL = false>
+__device__ __forceinline__ void diag_update(const double2* __restrict__ S0g, const void* __restrict__ P, int64_t ld,
+                                            int K, int h, double* Sr, double* Si, int64_t ldp = 0) {
   constexpr int RW = 16 * NV;
   int lane = threadIdx.x & 63;
   __asm__ volatile("" : "+v"(lane));   // not hoisted out of a caller's loop (as in wave_tile)
@@ -2106,7 +2115,10 @@ __device__ __forceinline__ void diag_update(const double2* __restrict__ S0g, con
           q.im[u][v][t] = MODE == MM_RR ? 0.0 : Si[r * 65 + c];
         }
       }
-  wave_gemm_t<MODE, false, NV, TWO>(P + RW * h, ld, P, ld, K, q);
+  if (PREAL)
+    wave_gemm_t<MODE, true, NV, TWO, true>(reinterpret_cast<const double*>(P) + RW * h, ldp, P, ldp, K, q);
+  else
+    wave_gemm_t<MODE, false, NV, TWO>(reinterpret_cast<const double2*>(P) + RW * h, ld, P, ld, K, q);
   // item t of block (u, v): S[row RW h + 16v + (l & 15)][column 16u + 4t + (l >> 4)]
 #pragma unroll
   for (int u = 0; u < 4; ++u)
@@ -2198,8 +2210,9 @@ __global__ __launch_bounds__(NT, 3) void k_chol_fblock(DevTables T, ChunkArgs C,
   extern __shared__ double smem[];
   double* Cr = smem;
   double* Ci = Cr + 64 * 65;
-  // the factorised block is also kept as a compact real copy (L_ij below the
-  // diagonal, the diagonal tiles as stored), the real operands of the F-column launch
+  // the factorised block lives only in its compact real copy (L_ij below the
+  // diagonal, the diagonal tiles as stored): the operands of its own later
+  // tiles and of the F-column launch.  Only A (the Gram block) comes from Z.
   double* fr = C.fr + cell * fr_stride(T);
   const int64_t ldf = fr_ld(T);
   int fail = 0;
@@ -2212,14 +2225,14 @@ __global__ __launch_bounds__(NT, 3) void k_chol_fblock(DevTables T, ChunkArgs C,
         if (q <= r) Cr[r * 65 + q] = tileD[(int64_t)q * ld + r].x;
       }
     } else {
-      diag_update<MM_RR, true, 1, true>(tileD, Z + j * TB, ld, j * TB, wave, Cr, Ci);
+      diag_update<MM_RR, true, 1, true, true>(tileD, fr + j * TB, ld, j * TB, wave, Cr, Ci, ldf);
     }
     __syncthreads();
-    const int f = chol_inv_tile<true>(Cr, Ci, tileD, ld, fr + (int64_t)(j * TB) * ldf + j * TB, ldf);
+    const int f = chol_inv_tile<true>(Cr, Ci, nullptr, 0, fr + (int64_t)(j * TB) * ldf + j * TB, ldf);
     if (f && !fail) fail = j * TB + f;
     if (j + 1 == nF) break;
     __syncthreads();   // diagonal tile j stored (workgroup scope); LDS free
-    for (int i = j + 1; i < nF; ++i) wave_tile<MM_RR, FR_WRITE, 1, true>(T, C, Z, cell, i, j, wave, nullptr);
+    for (int i = j + 1; i < nF; ++i) wave_tile<MM_RR, FR_FB, 1, true>(T, C, Z, cell, i, j, wave, nullptr);
     __syncthreads();   // column block j stored
   }
 
