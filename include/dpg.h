@@ -61,7 +61,9 @@
  *     (det J <= 0 at a quadrature point or non-finite input), k > 0 = the
  *     Cholesky factorisation of the Jacobi-scaled G met a non-positive pivot
  *     at (1-based) column k of the padded test space).  Outputs of failed
- *     cells are unspecified.
+ *     cells are unspecified.  dpg_sync waits for a stream and turns both
+ *     kinds into a status: asynchronous HIP errors (DPG_ERR_HIP) and failed
+ *     cells in info[] (DPG_ERR_CELL).
  */
 #ifndef DPG_H
 #define DPG_H
@@ -77,7 +79,8 @@ typedef enum {
   DPG_ERR_ARG = -1,          /* invalid argument (null pointer, bad degree, ...) */
   DPG_ERR_ALLOC = -2,        /* device or host allocation failed */
   DPG_ERR_HIP = -3,          /* a HIP runtime call or kernel launch failed */
-  DPG_ERR_UNSUPPORTED = -4   /* valid request the library does not support */
+  DPG_ERR_UNSUPPORTED = -4,  /* valid request the library does not support */
+  DPG_ERR_CELL = -5          /* some cell failed (see info[]); returned by dpg_sync */
 } dpg_status;
 
 typedef enum {
@@ -473,6 +476,17 @@ dpg_status dpg_plan_set_profiling(dpg_plan plan, int32_t enable);
  * (launches[DPG_K_COUNT]) since the previous call; then resets.  Host only,
  * synchronises with the recorded events. */
 dpg_status dpg_plan_profile(dpg_plan plan, double* ms, int64_t* launches);
+
+/* Synchronises `stream` (a hipStream_t, NULL = the default stream) and
+ * reports what the work enqueued on it left: DPG_ERR_HIP if the stream or a
+ * kernel on it failed (an asynchronous HIP error; text in dpg_last_error),
+ * else DPG_ERR_CELL if any of info[0..n) (a device array written by a solve,
+ * range solve, condensation or reconstruction) is nonzero, else DPG_OK.
+ * *n_failed (may be NULL) receives the number of nonzero entries and
+ * *first_failed (may be NULL) the index of the first one (-1 if none).
+ * info may be NULL when n = 0.  DPG_ERR_ARG for n < 0 or a NULL info with
+ * n > 0.  Host only; reads info[] back through host memory (4 n bytes). */
+dpg_status dpg_sync(void* stream, const int32_t* info, int64_t n, int64_t* n_failed, int64_t* first_failed);
 
 const char* dpg_status_string(dpg_status s);
 

@@ -401,8 +401,39 @@ const char* dpg_status_string(dpg_status s) {
     case DPG_ERR_ALLOC: return "allocation failed";
     case DPG_ERR_HIP: return "HIP runtime error";
     case DPG_ERR_UNSUPPORTED: return "unsupported request";
+    case DPG_ERR_CELL: return "a cell failed (see info[])";
   }
   return "unknown status";
+}
+
+dpg_status dpg_sync(void* stream, const int32_t* info, int64_t n, int64_t* n_failed, int64_t* first_failed) {
+  if (n_failed) *n_failed = 0;
+  if (first_failed) *first_failed = -1;
+  if (n < 0 || (n > 0 && !info)) return DPG_ERR_ARG;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = hipStreamSynchronize(st);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error("dpg_sync: stream", e);
+    return DPG_ERR_HIP;
+  }
+  if (n == 0) return DPG_OK;
+  std::vector<int32_t> h((size_t)n);
+  e = hipMemcpyAsync(h.data(), info, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    set_error("dpg_sync: info", e);
+    return DPG_ERR_HIP;
+  }
+  int64_t cnt = 0, first = -1;
+  for (int64_t c = 0; c < n; ++c)
+    if (h[(size_t)c] != 0) {
+      if (first < 0) first = c;
+      ++cnt;
+    }
+  if (n_failed) *n_failed = cnt;
+  if (first_failed) *first_failed = first;
+  return cnt ? DPG_ERR_CELL : DPG_OK;
 }
 
 dpg_status dpg_local_dims(int32_t p, int32_t dp, int32_t* n_test, int32_t* n_interior, int32_t* n_trace) {

@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdpgmi.so")
 
-DPG_OK, DPG_ERR_ARG, DPG_ERR_ALLOC, DPG_ERR_HIP, DPG_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
+DPG_OK, DPG_ERR_ARG, DPG_ERR_ALLOC, DPG_ERR_HIP, DPG_ERR_UNSUPPORTED, DPG_ERR_CELL = 0, -1, -2, -3, -4, -5
 DPG_FP64, DPG_SPLIT_FP32 = 0, 1
 FACE_INTERIOR, FACE_PEC, FACE_PORT, FACE_ROBIN0 = 0, 1, 2, 3
 
@@ -28,7 +28,7 @@ EXPORTS = ("dpg_local_dims", "dpg_plan_create", "dpg_plan_destroy", "dpg_plan_of
            "dpg_trace_system_destroy", "dpg_trace_system_info", "dpg_trace_system_numbering", "dpg_trace_system_csr",
            "dpg_assemble", "dpg_csr_matvec", "dpg_cg_solve", "dpg_trace_system_scatter", "dpg_reconstruct",
            "dpg_dorfler_mark", "dpg_dorfler_mark_noalloc", "dpg_power_dissipation",
-           "dpg_plan_set_profiling", "dpg_plan_profile", "dpg_status_string", "dpg_last_error")
+           "dpg_plan_set_profiling", "dpg_plan_profile", "dpg_sync", "dpg_status_string", "dpg_last_error")
 KERNEL_CLASSES = ("scale", "form_SM", "form_IF", "form_pad", "form_B", "form_load", "resid", "chol_diag",
                   "chol_panel", "herk")
 
@@ -95,6 +95,7 @@ def lib():
         L.dpg_power_dissipation.argtypes = [vp, C.POINTER(dpg_problem), vp, vp, vp]
         L.dpg_plan_set_profiling.argtypes = [vp, i32]
         L.dpg_plan_profile.argtypes = [vp, vp, vp]
+        L.dpg_sync.argtypes = [vp, vp, i64, C.POINTER(i64), C.POINTER(i64)]
         L.dpg_status_string.argtypes = [i32]
         L.dpg_status_string.restype = C.c_char_p
         L.dpg_last_error.argtypes = []
@@ -371,6 +372,18 @@ def trace_numbering(cells, face_kind, degree):
     _check(lib().dpg_trace_numbering(cells.ctypes.data, fk.ctypes.data, deg.ctypes.data, int(deg.shape[0]),
                                      glob.ctypes.data, C.byref(n)), "dpg_trace_numbering")
     return glob[:total], n.value
+
+
+def sync(info=None, stream=None):
+    """dpg_sync: waits for `stream`; returns (status, failed cells, first
+    failed index) for the int32 device tensor `info` (or None).  Raises only
+    for argument and HIP errors; DPG_ERR_CELL is returned, not raised."""
+    n = 0 if info is None else int(info.numel())
+    nf, ff = C.c_int64(), C.c_int64()
+    rc = lib().dpg_sync(_stream(stream), _ptr(info) if n else None, n, C.byref(nf), C.byref(ff))
+    if rc not in (DPG_OK, DPG_ERR_CELL):
+        _check(rc, "dpg_sync")
+    return rc, nf.value, ff.value
 
 
 def cg_solve(n_rows: int, row_ptr, col, vals, b, x, tol: float, max_iter: int, stream=None):

@@ -188,17 +188,21 @@ def _mixed_2x2x2():
     return w
 
 
-@pytest.mark.parametrize("wname", ["config1", "config2_2x2x2", "mixed_p1to3_2x2x2"])
-def test_global_solve_end_to_end_matches_oracle(wname):
+@pytest.mark.parametrize("wname,split", [("config1", False), ("config2_2x2x2", False), ("mixed_p1to3_2x2x2", False),
+                                         ("config1", True), ("config2_2x2x2", True)])
+def test_global_solve_end_to_end_matches_oracle(wname, split):
+    """The FP64 pipeline, and the pipeline fed by the split-precision K_e,
+    l_e (the condensation and the global solve then carry their 1e-6
+    element-wise error, amplified by the conditioning of M1 and of A)."""
     torch = _torch()
     from paper_2609_03155_amd import dpg
     w = {"config1": W.config1, "config2_2x2x2": lambda: W.config2(nx=2, ny=2, nz=2),
          "mixed_p1to3_2x2x2": _mixed_2x2x2}[wname]()
-    _say(f"case: global solve end to end on {w.name}")
+    _say(f"case: global solve end to end on {w.name}, local solves {'split' if split else 'FP64'}")
     plan = dpg.Plan(w.degree, w.dp)
     prob = dpg.DeviceProblem.from_workload(w)
     K, l, eta, info = plan.alloc_outputs()
-    plan.local_solve(prob, None, K, l, eta, info)
+    plan.local_solve(prob, None, K, l, eta, info, dpg.DPG_SPLIT_FP32 if split else dpg.DPG_FP64)
     A, b, cinfo = plan.condense(K, l)
     sys_ = dpg.TraceSystem(plan, w.cells, w.face_kind)
     vals, rhs = sys_.assemble(A, b)
@@ -213,7 +217,7 @@ def test_global_solve_end_to_end_matches_oracle(wname):
     assert rr <= 1e-12
     assert np.all(cinfo.cpu().numpy()[:w.n_cells] == 0) and np.all(rinfo.cpu().numpy()[:w.n_cells] == 0)
     to, xo, etao, cond = _oracle_pipeline(w)
-    tol = 4.0 * cond * (1e-10 + 1e-12)
+    tol = 4.0 * cond * ((1e-6 if split else 1e-10) + 1e-12)
     tg = t.cpu().numpy()
     _say(f"  cond(A) {cond:.3e}: traces rel {rel(tg, to):.3e}, bar {tol:.3e}")
     assert rel(tg, to) <= tol

@@ -315,6 +315,27 @@ def test_degenerate_cell_reports_info_and_others_unaffected():
     check_fp64(ref, Kg, lg, eta[0], "cell 0 next to a degenerate cell")
 
 
+def test_sync_reports_failed_cells():
+    """dpg_sync: DPG_ERR_CELL with the count and first index of the failed
+    cells in info[], DPG_OK for a clean solve and for n = 0."""
+    torch = _torch()
+    from paper_2609_03155_amd import dpg
+    w = W.config1()
+    cells = w.cells.copy()
+    cells[5, [0, 1]] = cells[5, [1, 0]]          # inverted cell
+    bad = W.Workload(w.name + "_bad", w.vertices.copy(), cells, w.eps, w.mu, w.degree, w.face_kind, w.zinv, w.dp,
+                     w.freq_hz, w.port)
+    _say("case: dpg_sync after a solve with a degenerate cell")
+    for wk, want in ((w, (dpg.DPG_OK, 0, -1)), (bad, (dpg.DPG_ERR_CELL, 1, 5))):
+        plan = dpg.Plan(wk.degree, wk.dp)
+        prob = dpg.DeviceProblem.from_workload(wk)
+        K, l, eta, info = plan.alloc_outputs()
+        plan.local_solve(prob, None, K, l, eta, info)
+        assert dpg.sync(info) == want
+        plan.close()
+    assert dpg.sync(None) == (dpg.DPG_OK, 0, -1)
+
+
 def test_argument_errors_are_synchronous():
     _torch()
     from paper_2609_03155_amd import dpg
