@@ -29,11 +29,38 @@ PEAK_HBM_GBS = 8000.0
 STREAM_CELLS = 8192          # cells per range when the outputs are streamed
 
 
+def formation_flops_sf(p: int, dp: int) -> float:
+    """Flops per cell of the sum-factorised formation as the kernels compute
+    it (k_form_SM: per component pair a >= b and (i2, j2) block, the q2 pass
+    over five terms, the q1 pass and the (term, q0) GEMM; k_form_Bsf: the
+    same per (a, c) with three terms and the DG factors on the trial side;
+    G_IF from its tables, 8 flops per complex entry).  Lower triangles only,
+    no padding."""
+    Q1, P1 = p + dp + 2, p + 1
+    S = Q1 - 1
+
+    def n(comp, d):
+        return S if comp == d else Q1
+    f = 0.0
+    for a in range(3):
+        for b in range(a + 1):
+            R, ncb = n(a, 0) * n(b, 0), n(a, 1) * n(b, 1)
+            nblk = n(a, 2) * (n(a, 2) + 1) // 2 if a == b else n(a, 2) * n(b, 2)
+            f += nblk * (15 * Q1 ** 3 + 10 * ncb * Q1 * Q1 + 10 * R * ncb * Q1)
+        for c in range(3):
+            R, ncb, nblk = n(a, 0) * P1, n(a, 1) * P1, n(a, 2) * P1
+            f += nblk * (9 * Q1 ** 3 + 6 * ncb * Q1 * Q1 + 6 * R * ncb * Q1)
+    N = 3 * S * Q1 * Q1
+    return f + 8.0 * N * N
+
+
 def algorithmic_flops(p: int, dp: int) -> dict:
-    """Structure-aware algorithmic flop counts per cell: formation of the real
-    S, M, C, D, R, T contractions, complex Cholesky of the n_v x n_v Gram
-    matrix, triangular solves (half cost on the real trace columns), HERK and
-    the two GEMVs (l_e, eta)."""
+    """Algorithmic flop counts per cell: the sum-factorised formation
+    (formation_flops_sf), complex Cholesky of the n_v x n_v Gram matrix,
+    triangular solves (half cost on the real trace columns), HERK and the two
+    GEMVs (l_e, eta).  form_dense is the count of the same formation summed
+    over all quadrature points (the structure-aware count without sum
+    factorisation), kept for reference and not part of the totals."""
     s, r = p + dp + 1, p + 1
     n1 = p + dp + 2
     N = 3 * s * (s + 1) ** 2
@@ -42,9 +69,17 @@ def algorithmic_flops(p: int, dp: int) -> dict:
     nq = n1 ** 3
     nu, nt = 6 * m1, 24 * r * r
     k = nu + nt
-    return dict(form=12 * N * N * nq + 12 * N * m1 * nq + 48 * N * r * (r + 1) * n1 * n1,
+    return dict(form=formation_flops_sf(p, dp),
                 chol=4.0 / 3.0 * nv ** 3, trsm=4 * nv * nv * nu + 2 * nv * nv * nt, herk=4 * k * k * nv,
                 vec=32 * nv * k)
+
+
+def formation_flops_dense(p: int, dp: int) -> float:
+    s, r = p + dp + 1, p + 1
+    n1 = p + dp + 2
+    N = 3 * s * (s + 1) ** 2
+    m1 = (p + 1) ** 3
+    return 12 * N * N * n1 ** 3 + 12 * N * m1 * n1 ** 3 + 48 * N * r * (r + 1) * n1 * n1
 
 
 PEAK_BF16_TFLOPS = 2500.0    # MI355X dense bf16 matrix peak
@@ -597,6 +632,10 @@ def main():
                      "launches_per_step": dom_launches / args.steps,
                      "avg_launch_ms": dom_ms / max(1, dom_launches)},
         "whole_step_tflops": total_alg / (ms_step * 1e-3) / 1e12,
+        "flop_counts_per_step": {"formation_sum_factorised": fl["form"], "cholesky": fl["chol"], "trsm": fl["trsm"],
+                                 "herk": fl["herk"], "gemv": fl["vec"],
+                                 "formation_dense_reference": sum(formation_flops_dense(int(p), w.dp)
+                                                                  for p in w.degree)},
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items() if v[1]},
         "failed_cells": int(np.sum(info_h != 0)),
     }

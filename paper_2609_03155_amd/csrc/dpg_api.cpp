@@ -44,16 +44,28 @@ struct DegreeGroup {
   dpg::DevTables rt{};                // reconstruction: the same with the single right-hand-side row
 };
 
-// Algorithmic flops of one cell (structure-aware counts: formation of the
-// real S, M, C, D, R, T contractions, complex Cholesky, triangular solves,
-// HERK and the two GEMVs); only their ratios matter here (queue order and
-// workspace shares).
+// Algorithmic flops of one cell: the sum-factorised formation (per
+// component pair and (i2, j2) block: the q2 and q1 passes and the (term, q0)
+// GEMM of the S/M kernel, the same per (a, c) for D and R; G_IF from its
+// tables), complex Cholesky, triangular solves, HERK and the two GEMVs; only
+// their ratios matter here (queue order and workspace shares).
 double cell_flops(int p, int dp) {
-  const double s = p + dp + 1, r = p + 1, n1 = p + dp + 2;
+  const double s = p + dp + 1, r = p + 1;
   const double N = 3 * s * (s + 1) * (s + 1), nv = 2 * N, m1 = (p + 1.0) * (p + 1) * (p + 1);
-  const double nq = n1 * n1 * n1, nu = 6 * m1, nt = 24 * r * r, k = nu + nt;
-  return 12 * N * N * nq + 12 * N * m1 * nq + 48 * N * r * (r + 1) * n1 * n1 + 4.0 / 3.0 * nv * nv * nv +
-         4 * nv * nv * nu + 2 * nv * nv * nt + 4 * k * k * nv + 32 * nv * k;
+  const double nu = 6 * m1, nt = 24 * r * r, k = nu + nt;
+  const int Q1 = p + dp + 2, P1 = p + 1, S = Q1 - 1;
+  auto n = [&](int comp, int d) { return (double)(comp == d ? S : Q1); };
+  double form = 8.0 * N * N;
+  for (int a = 0; a < 3; ++a) {
+    for (int b = 0; b <= a; ++b) {
+      const double R = n(a, 0) * n(b, 0), ncb = n(a, 1) * n(b, 1);
+      const double nblk = a == b ? n(a, 2) * (n(a, 2) + 1) / 2 : n(a, 2) * n(b, 2);
+      form += nblk * (15.0 * Q1 * Q1 * Q1 + 10 * ncb * Q1 * Q1 + 10 * R * ncb * Q1);
+    }
+    const double R = n(a, 0) * P1, ncb = n(a, 1) * P1, nblk = n(a, 2) * P1;
+    form += 3 * nblk * (9.0 * Q1 * Q1 * Q1 + 6 * ncb * Q1 * Q1 + 6 * R * ncb * Q1);
+  }
+  return form + 4.0 / 3.0 * nv * nv * nv + 4 * nv * nv * nu + 2 * nv * nv * nt + 4 * k * k * nv + 32 * nv * k;
 }
 
 }  // namespace
