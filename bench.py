@@ -461,6 +461,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "split"])
+    ap.add_argument("--mfma-calib", type=int, default=0,
+                    help="run three n x n FP64 GEMMs (torch) before the solve, to calibrate the MFMA-busy counter")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (calibrates HBM byte counters)")
     ap.add_argument("--no-graph", action="store_true", help="time eager solves instead of HIP-graph replays")
@@ -512,6 +514,17 @@ def main():
             plan.local_solve_range(prob, a, n, xd[int(off[a]):], K, l, eta[a:], info[a:], precision=precision,
                                    stream=stream)
 
+    if args.mfma_calib > 0:
+        # a vendor FP64 GEMM of known size: its duration (kernel trace) and
+        # flops give its matrix-core utilisation, against which the MFMA-busy
+        # counter of the same run is normalised
+        n = args.mfma_calib
+        a = torch.ones((n, n), dtype=torch.float64, device="cuda")
+        b = torch.ones((n, n), dtype=torch.float64, device="cuda")
+        for _ in range(3):
+            c = a @ b
+        torch.cuda.synchronize()
+        del a, b, c
     if args.copy_calib_mib > 0:
         n = args.copy_calib_mib * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")

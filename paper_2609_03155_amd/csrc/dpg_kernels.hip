@@ -330,7 +330,8 @@ __global__ __launch_bounds__(NT) void k_form_IF(DevTables T, ProbArgs P, ChunkAr
   }
 }
 
-// Identity/zero padding of the test space (rows N..Np-1 of each field block).
+// Identity/zero padding of the test space (rows N..Np-1 of each field block),
+// consecutive threads along the rows of one column (contiguous stores).
 __global__ __launch_bounds__(NT) void k_form_pad(DevTables T, ChunkArgs C) {
   const int64_t cell = blockIdx.x;
   if (cell >= C.n) return;
@@ -340,8 +341,8 @@ __global__ __launch_bounds__(NT) void k_form_pad(DevTables T, ChunkArgs C) {
   for (int blk = 0; blk < 2; ++blk) {
     const int base = blk * T.Np;
     for (int e = threadIdx.x; e < npad * T.Np; e += NT) {
-      const int row = base + T.N + e / T.Np;
-      const int col = base + e % T.Np;
+      const int row = base + T.N + e % npad;
+      const int col = base + e / npad;
       if (col > row) continue;
       Z[(int64_t)col * ld + row] = make_double2(col == row ? 1.0 : 0.0, 0.0);
     }
