@@ -68,6 +68,7 @@
 #ifndef DPG_H
 #define DPG_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -370,14 +371,25 @@ dpg_status dpg_csr_matvec(int64_t n_rows, const int64_t* row_ptr, const int32_t*
  * stay on the device and every reduction has a fixed order (bitwise
  * reproducible); the host reads the convergence flag once per 16 iterations
  * while the next 16 are queued.  A must be Hermitian positive definite and
- * every col entry in [0, n_rows) (not checked on the device).  Allocates and
- * frees 3 n_rows complex
- * vectors and O(n_rows / 256) partial sums on the current device; returns
- * after synchronising `stream`.  DPG_ERR_ARG for null pointers, n_rows < 0,
- * max_iter < 0 or tol < 0 (or NaN). */
+ * every col entry in [0, n_rows) (not checked on the device).  For an
+ * arbitrary CSR system: allocates and frees 3 n_rows complex vectors,
+ * O(n_rows / 256) partial sums and pinned host slots on every call (the
+ * assembled trace system's CG, dpg_trace_system_cg, keeps them in the
+ * system instead); returns after synchronising `stream`.  DPG_ERR_ARG for
+ * null pointers, n_rows < 0, max_iter < 0 or tol < 0 (or NaN). */
 dpg_status dpg_cg_solve(int64_t n_rows, const int64_t* row_ptr, const int32_t* col, const double* vals,
                         const double* b, double* x, double tol, int64_t max_iter, int64_t* iters,
                         double* relres, void* stream);
+
+/* The same CG (Sec. 2.3: the condensed trace system solved without a
+ * preconditioner) on the trace system's own CSR structure: vals [nnz] and
+ * b [n_dofs] as dpg_assemble writes them, x [n_dofs] (start in, solution
+ * out), all device, complex.  Its vectors, partial sums, scalars, pinned host
+ * slots and events were allocated with the system (dpg_trace_system_create),
+ * so a call allocates nothing; calls on one system must not overlap in time.
+ * Returns after synchronising `stream`.  Errors as dpg_cg_solve. */
+dpg_status dpg_trace_system_cg(dpg_trace_system sys, const double* vals, const double* b, double* x, double tol,
+                               int64_t max_iter, int64_t* iters, double* relres, void* stream);
 
 /* The cells' local trace coefficients t_K = P_K t from the global trace
  * vector t (device, complex [n_dofs]): t_local (device, complex) is laid out
@@ -428,16 +440,22 @@ dpg_status dpg_power_dissipation(dpg_plan plan, const dpg_problem* prob, const d
  * (flags [n], device, int8): the shortest prefix of the ranking that carries
  * refine_fraction of the total is refined, the longest run of the smallest
  * values within coarsen_fraction of it is coarsened.  The sums run in a fixed
- * order, so equal inputs give equal flags.  Allocates temporaries (about
- * 40 n bytes) and returns after synchronising `stream`.  DPG_ERR_ARG for
- * n < 0 or n > 2^31 - 1, null pointers or fractions outside [0, 1]. */
+ * order, so equal inputs give equal flags.  Temporaries (about 40 n bytes
+ * and the radix sort's own): `workspace` (device, 256-byte aligned, at least
+ * dpg_dorfler_mark_workspace_size(n) bytes, owned by the caller, e.g. kept
+ * with the plan whose eta it marks), and then the call allocates nothing and
+ * is stream-ordered; or, with workspace null, an allocation per call, after
+ * which the call synchronises `stream`.  DPG_ERR_ARG for n < 0 or
+ * n > 2^31 - 1, null pointers, fractions outside [0, 1], or a workspace
+ * that is too small or misaligned (nothing is enqueued then). */
+dpg_status dpg_dorfler_mark_workspace_size(int64_t n, size_t* bytes);
 dpg_status dpg_dorfler_mark(int64_t n, const double* values, double refine_fraction, double coarsen_fraction,
-                            int8_t* flags, void* stream);
+                            int8_t* flags, void* workspace, size_t workspace_bytes, void* stream);
 
 /* Dörfler marking without any allocation, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc): the same flags as dpg_dorfler_mark
- * (bit for bit) with the same arguments, but its temporaries (sort keys and
+ * (bit for bit) from the same values and fractions, but its temporaries (sort keys and
  * cell ids, chunk sums, the sort's own temporaries) live in a static device
  * array of 64 MiB on every GPU the library runs on, held until the process
  * ends; its device address is looked up once per device on the first call.

@@ -77,7 +77,8 @@ def solve_and_mark(w, degree, refine_fraction: float = 0.30, coarsen_fraction: f
         x, rinfo = plan.reconstruct(K, l, ts.scatter(t))
         K2, l2, eta2, info2 = plan.alloc_outputs(device)
         plan.local_solve(prob, x, K2, l2, eta2, info2)
-        flags = dpg.dorfler_mark(eta2[:nc], refine_fraction, coarsen_fraction)
+        mark_ws = torch.empty(dpg.dorfler_mark_workspace_size(nc), dtype=torch.uint8, device=K.device)
+        flags = dpg.dorfler_mark(eta2[:nc], refine_fraction, coarsen_fraction, workspace=mark_ws)
         torch.cuda.synchronize(K.device)
         failed = sum(int(np.count_nonzero(a.cpu().numpy()[:nc])) for a in (info, cinfo, rinfo, info2))
         return AdaptPass(degree=degree.copy(), n_dofs=int(ts.n_dofs), cg_iterations=int(it), relres=float(rr),

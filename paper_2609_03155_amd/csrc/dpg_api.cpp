@@ -100,6 +100,14 @@ struct dpg_trace_system_s {
   int64_t* rhs_ptr = nullptr;
   int64_t* rhs_contrib = nullptr;
   int64_t* glob_dev = nullptr;        // device copy of glob (trace scatter)
+  // CG on this system (dpg_trace_system_cg), allocated with it: the vectors
+  // r, p, q, the partial sums and scalars, pinned host slots for the
+  // scalars and two events
+  double2* cg_vec = nullptr;
+  double* cg_part = nullptr;
+  double* cg_sc = nullptr;
+  double* cg_host = nullptr;
+  hipEvent_t cg_ev[2] = {nullptr, nullptr};
 };
 
 struct dpg_graph_s {
@@ -932,6 +940,14 @@ dpg_status dpg_trace_system_create(dpg_plan plan, const int64_t* cells_host, con
     S->rhs_ptr = upload(own, rptr);
     S->rhs_contrib = upload(own, rcontrib);
     S->glob_dev = upload(own, S->glob);
+    if (S->n_dofs > 0) {
+      HIP_CHECK(hipMalloc(reinterpret_cast<void**>(&S->cg_vec), sizeof(double2) * 3 * S->n_dofs));
+      HIP_CHECK(hipMalloc(reinterpret_cast<void**>(&S->cg_part), sizeof(double) * dpg::cg_part_len(S->n_dofs)));
+      HIP_CHECK(hipMalloc(reinterpret_cast<void**>(&S->cg_sc), sizeof(double) * dpg::CG_NSC));
+      HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&S->cg_host), sizeof(double) * 3 * dpg::CG_NSC,
+                              hipHostMallocDefault));
+      for (auto& e : S->cg_ev) HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
     *out = S;
     return DPG_OK;
   } catch (const std::invalid_argument&) {
@@ -950,8 +966,12 @@ dpg_status dpg_trace_system_destroy(dpg_trace_system sys) {
   if (!sys) return DPG_ERR_ARG;
   (void)hipSetDevice(sys->device);
   for (void* p : {(void*)sys->row_ptr, (void*)sys->col, (void*)sys->contrib_ptr, (void*)sys->contrib,
-                  (void*)sys->rhs_ptr, (void*)sys->rhs_contrib, (void*)sys->glob_dev})
+                  (void*)sys->rhs_ptr, (void*)sys->rhs_contrib, (void*)sys->glob_dev, (void*)sys->cg_vec,
+                  (void*)sys->cg_part, (void*)sys->cg_sc})
     if (p) (void)hipFree(p);
+  if (sys->cg_host) (void)hipHostFree(sys->cg_host);
+  for (auto e : sys->cg_ev)
+    if (e) (void)hipEventDestroy(e);
   delete sys;
   return DPG_OK;
 }
@@ -1018,6 +1038,42 @@ dpg_status dpg_trace_system_scatter(dpg_trace_system sys, const double* t, doubl
   return DPG_OK;
 }
 
+namespace {
+
+// CG iterations on g (vectors, partial sums and scalars already in g) with
+// the pinned host slots `host` [3 CG_NSC] and two events; returns after
+// synchronising st.  Throws HipError.
+void cg_run(dpg::CgArgs& g, double* host, hipEvent_t* ev, double tol, int64_t max_iter, int64_t* iters,
+            double* relres, hipStream_t st) {
+  for (int k = 0; k < 3 * dpg::CG_NSC; ++k) host[k] = 0.0;
+  host[dpg::CG_TOL2] = tol * tol;
+  HIP_CHECK(hipMemcpyAsync(g.sc, host, sizeof(double) * dpg::CG_NSC, hipMemcpyHostToDevice, st));
+  hip_check(dpg::launch_cg_start(g, st));
+  // Batches of iterations; the flag of batch k is read while batch k+1 runs
+  // (iterations past convergence return at once).
+  constexpr int64_t kBatch = 16;
+  int64_t launched = 0;
+  for (int64_t k = 0; launched < max_iter; ++k) {
+    const int64_t nb = std::min<int64_t>(kBatch, max_iter - launched);
+    hip_check(dpg::launch_cg_iterations(g, nb, st));
+    launched += nb;
+    double* slot = host + dpg::CG_NSC * (1 + (k & 1));
+    HIP_CHECK(hipMemcpyAsync(slot, g.sc, sizeof(double) * dpg::CG_NSC, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipEventRecord(ev[k & 1], st));
+    if (k > 0) {
+      HIP_CHECK(hipEventSynchronize(ev[(k - 1) & 1]));
+      if (host[dpg::CG_NSC * (1 + ((k - 1) & 1)) + dpg::CG_DONE] != 0.0) break;
+    }
+  }
+  HIP_CHECK(hipMemcpyAsync(host + dpg::CG_NSC, g.sc, sizeof(double) * dpg::CG_NSC, hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  const double* f = host + dpg::CG_NSC;
+  *iters = (int64_t)f[dpg::CG_ITERS];
+  *relres = f[dpg::CG_BN2] > 0.0 ? std::sqrt(f[dpg::CG_RR] / f[dpg::CG_BN2]) : 0.0;
+}
+
+}  // namespace
+
 dpg_status dpg_cg_solve(int64_t n_rows, const int64_t* row_ptr, const int32_t* col, const double* vals, const double* b,
                         double* x, double tol, int64_t max_iter, int64_t* iters, double* relres, void* stream) {
   if (n_rows < 0 || max_iter < 0 || !(tol >= 0.0) || !iters || !relres) return DPG_ERR_ARG;
@@ -1051,32 +1107,8 @@ dpg_status dpg_cg_solve(int64_t n_rows, const int64_t* row_ptr, const int32_t* c
     // pinned host slots: the start scalars, then two slots the scalars are
     // copied back to after each batch of iterations
     HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&host), sizeof(double) * 3 * dpg::CG_NSC, hipHostMallocDefault));
-    for (int k = 0; k < 3 * dpg::CG_NSC; ++k) host[k] = 0.0;
-    host[dpg::CG_TOL2] = tol * tol;
     for (auto& e : ev) HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    HIP_CHECK(hipMemcpyAsync(g.sc, host, sizeof(double) * dpg::CG_NSC, hipMemcpyHostToDevice, st));
-    hip_check(dpg::launch_cg_start(g, st));
-    // Batches of iterations; the flag of batch k is read while batch k+1 runs
-    // (iterations past convergence return at once).
-    constexpr int64_t kBatch = 16;
-    int64_t launched = 0;
-    for (int64_t k = 0; launched < max_iter; ++k) {
-      const int64_t nb = std::min<int64_t>(kBatch, max_iter - launched);
-      hip_check(dpg::launch_cg_iterations(g, nb, st));
-      launched += nb;
-      double* slot = host + dpg::CG_NSC * (1 + (k & 1));
-      HIP_CHECK(hipMemcpyAsync(slot, g.sc, sizeof(double) * dpg::CG_NSC, hipMemcpyDeviceToHost, st));
-      HIP_CHECK(hipEventRecord(ev[k & 1], st));
-      if (k > 0) {
-        HIP_CHECK(hipEventSynchronize(ev[(k - 1) & 1]));
-        if (host[dpg::CG_NSC * (1 + ((k - 1) & 1)) + dpg::CG_DONE] != 0.0) break;
-      }
-    }
-    HIP_CHECK(hipMemcpyAsync(host + dpg::CG_NSC, g.sc, sizeof(double) * dpg::CG_NSC, hipMemcpyDeviceToHost, st));
-    HIP_CHECK(hipStreamSynchronize(st));
-    const double* f = host + dpg::CG_NSC;
-    *iters = (int64_t)f[dpg::CG_ITERS];
-    *relres = f[dpg::CG_BN2] > 0.0 ? std::sqrt(f[dpg::CG_RR] / f[dpg::CG_BN2]) : 0.0;
+    cg_run(g, host, ev, tol, max_iter, iters, relres, st);
   } catch (const HipError&) {
     rc = DPG_ERR_HIP;
   }
@@ -1086,6 +1118,36 @@ dpg_status dpg_cg_solve(int64_t n_rows, const int64_t* row_ptr, const int32_t* c
   if (host) (void)hipHostFree(host);
   for (void* p : own) (void)hipFree(p);
   return rc;
+}
+
+dpg_status dpg_trace_system_cg(dpg_trace_system sys, const double* vals, const double* b, double* x, double tol,
+                               int64_t max_iter, int64_t* iters, double* relres, void* stream) {
+  if (!sys || max_iter < 0 || !(tol >= 0.0) || !iters || !relres) return DPG_ERR_ARG;
+  if (sys->n_dofs > 0 && (!vals || !b || !x)) return DPG_ERR_ARG;
+  *iters = 0;
+  *relres = 0.0;
+  if (sys->n_dofs == 0) return DPG_OK;
+  if (hipSetDevice(sys->device) != hipSuccess) return DPG_ERR_HIP;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  try {
+    dpg::CgArgs g{};
+    g.n = sys->n_dofs;
+    g.row_ptr = sys->row_ptr;
+    g.col = sys->col;
+    g.val = reinterpret_cast<const double2*>(vals);
+    g.b = reinterpret_cast<const double2*>(b);
+    g.x = reinterpret_cast<double2*>(x);
+    g.r = sys->cg_vec;
+    g.p = sys->cg_vec + sys->n_dofs;
+    g.q = sys->cg_vec + 2 * sys->n_dofs;
+    g.part = sys->cg_part;
+    g.sc = sys->cg_sc;
+    cg_run(g, sys->cg_host, sys->cg_ev, tol, max_iter, iters, relres, st);
+  } catch (const HipError&) {
+    (void)hipStreamSynchronize(st);
+    return DPG_ERR_HIP;
+  }
+  return DPG_OK;
 }
 
 dpg_status dpg_power_dissipation(dpg_plan plan, const dpg_problem* prob, const double* x, double* power,
@@ -1110,18 +1172,34 @@ dpg_status dpg_power_dissipation(dpg_plan plan, const dpg_problem* prob, const d
   return DPG_OK;
 }
 
+dpg_status dpg_dorfler_mark_workspace_size(int64_t n, size_t* bytes) {
+  if (n < 0 || n > INT32_MAX || !bytes) return DPG_ERR_ARG;
+  const hipError_t e = dpg::dorfler_mark_workspace(n, bytes);
+  if (e != hipSuccess) {
+    set_error("dpg_dorfler_mark_workspace_size", e);
+    return DPG_ERR_HIP;
+  }
+  return DPG_OK;
+}
+
 dpg_status dpg_dorfler_mark(int64_t n, const double* values, double refine_fraction, double coarsen_fraction,
-                            int8_t* flags, void* stream) {
+                            int8_t* flags, void* workspace, size_t workspace_bytes, void* stream) {
   if (n < 0 || n > INT32_MAX || !(refine_fraction >= 0.0 && refine_fraction <= 1.0) ||
       !(coarsen_fraction >= 0.0 && coarsen_fraction <= 1.0))
     return DPG_ERR_ARG;
   if (n == 0) return DPG_OK;
   if (!values || !flags) return DPG_ERR_ARG;
-  const hipError_t e =
-      dpg::dorfler_mark(n, values, refine_fraction, coarsen_fraction, flags, reinterpret_cast<hipStream_t>(stream));
+  bool too_small = false;
+  const hipError_t e = dpg::dorfler_mark(n, values, refine_fraction, coarsen_fraction, flags, workspace,
+                                         workspace_bytes, reinterpret_cast<hipStream_t>(stream), &too_small);
   if (e != hipSuccess) {
     set_error("dpg_dorfler_mark", e);
     return DPG_ERR_HIP;
+  }
+  if (too_small) {
+    std::snprintf(g_last_error, sizeof(g_last_error),
+                  "dpg_dorfler_mark: workspace of %zu bytes too small or not 256-byte aligned", workspace_bytes);
+    return DPG_ERR_ARG;
   }
   return DPG_OK;
 }

@@ -168,8 +168,14 @@ hipError_t launch_cg_iterations(const CgArgs& g, int64_t count, hipStream_t st);
 hipError_t launch_power(const DevTables& t, const ProbArgs& pa, const int64_t* cell_ids, int64_t n, const double2* x,
                         const int64_t* v_off, double* out, hipStream_t st);
 // Dörfler marking: flags[i] = +1 (refine), -1 (coarsen) or 0 from values[i]
-// (n cells); allocates its temporaries and synchronises the stream.
-hipError_t dorfler_mark(int64_t n, const double* values, double fr, double fc, int8_t* flags, hipStream_t st);
+// (n cells).  Its temporaries: `workspace` (256-byte aligned, at least
+// dorfler_mark_workspace(n) bytes; stream-ordered, no allocation; *too_small
+// is set and nothing runs if it is smaller or misaligned), or, when
+// workspace is null, an allocation of its own, after which the stream is
+// synchronised.
+hipError_t dorfler_mark_workspace(int64_t n, size_t* bytes);
+hipError_t dorfler_mark(int64_t n, const double* values, double fr, double fc, int8_t* flags, void* workspace,
+                        size_t workspace_bytes, hipStream_t st, bool* too_small);
 // The same marking with its temporaries in a static device array of
 // kMarkScratchBytes per GPU (no allocation, no synchronisation); n up to
 // kMarkMaxCells.  *too_large is set (and nothing runs) when n or the

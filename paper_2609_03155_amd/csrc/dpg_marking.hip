@@ -152,11 +152,27 @@ std::unordered_map<int, char*> g_scratch_ptr;   // device -> address of its copy
 
 }  // namespace
 
-hipError_t dorfler_mark(int64_t n, const double* values, double fr, double fc, int8_t* flags, hipStream_t st) {
+hipError_t dorfler_mark_workspace(int64_t n, size_t* bytes) {
+  *bytes = 0;
+  if (n <= 0) return hipSuccess;
+  size_t sort_bytes = 0;
+  return mark_scratch_bytes(n, bytes, &sort_bytes, nullptr);
+}
+
+hipError_t dorfler_mark(int64_t n, const double* values, double fr, double fc, int8_t* flags, void* workspace,
+                        size_t workspace_bytes, hipStream_t st, bool* too_small) {
+  *too_small = false;
   if (n <= 0) return hipSuccess;
   size_t total = 0, sort_bytes = 0;
   hipError_t e = mark_scratch_bytes(n, &total, &sort_bytes, st);
   if (e != hipSuccess) return e;
+  if (workspace) {
+    if (workspace_bytes < total || reinterpret_cast<uintptr_t>(workspace) % 256 != 0) {
+      *too_small = true;
+      return hipSuccess;
+    }
+    return dorfler_mark_ws(n, values, fr, fc, flags, static_cast<char*>(workspace), sort_bytes, st);
+  }
   char* ws = nullptr;
   e = hipMalloc(reinterpret_cast<void**>(&ws), total);
   if (e != hipSuccess) return e;

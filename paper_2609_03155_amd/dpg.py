@@ -26,8 +26,8 @@ EXPORTS = ("dpg_local_dims", "dpg_plan_create", "dpg_plan_destroy", "dpg_plan_of
            "dpg_form_augmented",
            "dpg_plan_trace_offsets", "dpg_condense", "dpg_trace_numbering", "dpg_trace_system_create",
            "dpg_trace_system_destroy", "dpg_trace_system_info", "dpg_trace_system_numbering", "dpg_trace_system_csr",
-           "dpg_assemble", "dpg_csr_matvec", "dpg_cg_solve", "dpg_trace_system_scatter", "dpg_reconstruct",
-           "dpg_dorfler_mark", "dpg_dorfler_mark_noalloc", "dpg_power_dissipation",
+           "dpg_assemble", "dpg_csr_matvec", "dpg_cg_solve", "dpg_trace_system_cg", "dpg_trace_system_scatter",
+           "dpg_reconstruct", "dpg_dorfler_mark_workspace_size", "dpg_dorfler_mark", "dpg_dorfler_mark_noalloc", "dpg_power_dissipation",
            "dpg_plan_set_profiling", "dpg_plan_profile", "dpg_sync", "dpg_status_string", "dpg_last_error")
 KERNEL_CLASSES = ("scale", "form_SM", "form_IF", "form_pad", "form_B", "form_load", "resid", "chol_diag",
                   "chol_panel", "herk")
@@ -88,9 +88,11 @@ def lib():
         L.dpg_assemble.argtypes = [vp, vp, vp, vp, vp, vp]
         L.dpg_csr_matvec.argtypes = [i64, vp, vp, vp, vp, vp, vp]
         L.dpg_cg_solve.argtypes = [i64, vp, vp, vp, vp, vp, dp_, i64, C.POINTER(i64), C.POINTER(dp_), vp]
+        L.dpg_trace_system_cg.argtypes = [vp, vp, vp, vp, dp_, i64, C.POINTER(i64), C.POINTER(dp_), vp]
         L.dpg_trace_system_scatter.argtypes = [vp, vp, vp, vp]
         L.dpg_reconstruct.argtypes = [vp, vp, vp, vp, vp, vp, vp]
-        L.dpg_dorfler_mark.argtypes = [i64, vp, dp_, dp_, vp, vp]
+        L.dpg_dorfler_mark_workspace_size.argtypes = [i64, C.POINTER(C.c_size_t)]
+        L.dpg_dorfler_mark.argtypes = [i64, vp, dp_, dp_, vp, vp, C.c_size_t, vp]
         L.dpg_dorfler_mark_noalloc.argtypes = [i64, vp, dp_, dp_, vp, vp]
         L.dpg_power_dissipation.argtypes = [vp, C.POINTER(dpg_problem), vp, vp, vp]
         L.dpg_plan_set_profiling.argtypes = [vp, i32]
@@ -397,15 +399,29 @@ def cg_solve(n_rows: int, row_ptr, col, vals, b, x, tol: float, max_iter: int, s
     return it.value, rr.value
 
 
-def dorfler_mark(values, refine_fraction: float = 0.30, coarsen_fraction: float = 0.05, flags=None, stream=None):
+def dorfler_mark_workspace_size(n: int) -> int:
+    """Bytes of the temporaries dorfler_mark needs for n values."""
+    b = C.c_size_t()
+    _check(lib().dpg_dorfler_mark_workspace_size(int(n), C.byref(b)), "dpg_dorfler_mark_workspace_size")
+    return b.value
+
+
+def dorfler_mark(values, refine_fraction: float = 0.30, coarsen_fraction: float = 0.05, flags=None, stream=None,
+                 workspace=None):
     """dpg_dorfler_mark: int8 device flags (+1 refine, -1 coarsen, 0 keep) from
-    the float64 device tensor `values` (one indicator per cell)."""
+    the float64 device tensor `values` (one indicator per cell).  `workspace`
+    (a device tensor of at least dorfler_mark_workspace_size(n) bytes): the
+    library then allocates nothing and does not synchronise; without it the
+    library allocates its temporaries and synchronises the stream."""
     import torch
     n = int(values.numel())
     if flags is None:
         flags = torch.empty(max(n, 1), dtype=torch.int8, device=values.device)
+    wp, wb = None, 0
+    if workspace is not None:
+        wp, wb = _ptr(workspace), int(workspace.numel() * workspace.element_size())
     _check(lib().dpg_dorfler_mark(n, _ptr(values), float(refine_fraction), float(coarsen_fraction), _ptr(flags),
-                                  _stream(stream)), "dpg_dorfler_mark")
+                                  wp, wb, _stream(stream)), "dpg_dorfler_mark")
     return flags
 
 
@@ -470,9 +486,13 @@ class TraceSystem:
         return t_local
 
     def solve(self, vals, rhs, x, tol: float, max_iter: int, stream=None):
-        """CG on the assembled system (dpg_cg_solve); x: start in, solution out.
-        Returns (iterations, relative residual)."""
-        return cg_solve(self.n_dofs, self.row_ptr_ptr, self.col_ptr, vals, rhs, x, tol, max_iter, stream)
+        """CG on the assembled system (dpg_trace_system_cg, with the system's
+        own CG vectors); x: start in, solution out.  Returns (iterations,
+        relative residual)."""
+        it, rr = C.c_int64(), C.c_double()
+        _check(lib().dpg_trace_system_cg(self._h, _ptr(vals), _ptr(rhs), _ptr(x), float(tol), int(max_iter),
+                                         C.byref(it), C.byref(rr), _stream(stream)), "dpg_trace_system_cg")
+        return it.value, rr.value
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

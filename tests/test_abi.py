@@ -63,7 +63,12 @@ def test_global_solve_entry_points_reject_bad_arguments_on_the_host():
     assert cg(0, 1e-8, -1) == dpg.DPG_ERR_ARG
     assert cg(0, 1e-8, 10, iters=False) == dpg.DPG_ERR_ARG
     assert cg(0, 1e-8, 10) == dpg.DPG_OK and it.value == 0 and rr.value == 0.0
-    mark = lambda n, fr, fc: L.dpg_dorfler_mark(n, None, fr, fc, None, None)
+    assert L.dpg_trace_system_cg(None, None, None, None, 1e-8, 10, C.byref(it), C.byref(rr), None) == dpg.DPG_ERR_ARG
+    mark = lambda n, fr, fc: L.dpg_dorfler_mark(n, None, fr, fc, None, None, 0, None)
+    ws = C.c_size_t(7)
+    assert L.dpg_dorfler_mark_workspace_size(-1, C.byref(ws)) == dpg.DPG_ERR_ARG
+    assert L.dpg_dorfler_mark_workspace_size(4, None) == dpg.DPG_ERR_ARG
+    assert L.dpg_dorfler_mark_workspace_size(0, C.byref(ws)) == dpg.DPG_OK and ws.value == 0
     assert mark(-1, 0.3, 0.05) == dpg.DPG_ERR_ARG
     assert mark(2 ** 31, 0.3, 0.05) == dpg.DPG_ERR_ARG
     assert mark(4, 0.3, 0.05) == dpg.DPG_ERR_ARG        # null device pointers

@@ -209,6 +209,11 @@ def test_global_solve_end_to_end_matches_oracle(wname, split):
     t = torch.zeros(sys_.n_dofs, dtype=torch.complex128, device="cuda")
     it, rr = sys_.solve(vals, rhs, t, 1e-12, 100000)
     _say(f"  CG: {it} iterations, relres {rr:.3e}")
+    # the trace system's CG (its own vectors) and the generic CSR CG are the
+    # same iteration: equal results bit for bit
+    t2 = torch.zeros_like(t)
+    it2, rr2 = dpg.cg_solve(sys_.n_dofs, sys_.row_ptr_ptr, sys_.col_ptr, vals, rhs, t2, 1e-12, 100000)
+    assert it2 == it and rr2 == rr and torch.equal(t2, t)
     tl = sys_.scatter(t)
     x, rinfo = plan.reconstruct(K, l, tl)
     K2, l2, eta2, info2 = plan.alloc_outputs()
@@ -221,6 +226,29 @@ def test_global_solve_end_to_end_matches_oracle(wname, split):
     tg = t.cpu().numpy()
     _say(f"  cond(A) {cond:.3e}: traces rel {rel(tg, to):.3e}, bar {tol:.3e}")
     assert rel(tg, to) <= tol
+    # The GPU's own condensed matrices through the oracle's numbering,
+    # assembly and dense solve: only the assembly's summation order and the
+    # CG stopping test (relres <= 1e-12) separate that solution from the
+    # GPU's traces, so the bar is cond(A) times 1e-12 (plus rounding).
+    from oracle import dpg_assembly as OA
+    A_off, b_off = plan.trace_offsets()
+    Ah, bh = A.cpu().numpy(), b.cpu().numpy()
+    Ac, bc = [], []
+    for c in range(w.n_cells):
+        nt = int(b_off[c + 1] - b_off[c])
+        Ac.append(Ah[A_off[c]:A_off[c + 1]].reshape(nt, nt).T)
+        bc.append(bh[b_off[c]:b_off[c + 1]])
+    glob, n = OA.trace_numbering(w.cells, w.face_kind, w.degree)
+    assert n == sys_.n_dofs
+    Ag, bg = OA.assemble(Ac, bc, glob, n)
+    Agd = Ag.toarray()
+    evg = np.linalg.eigvalsh(Agd)
+    cond_g = evg.max() / evg.min()
+    t_ref = np.linalg.solve(Agd, bg)
+    bar_g = 2.0 * cond_g * (1e-12 + 64 * U64)
+    _say(f"  against the oracle's solve of the GPU's condensed system: traces rel {rel(tg, t_ref):.3e}, "
+         f"bar {bar_g:.3e} (cond {cond_g:.3e})")
+    assert rel(tg, t_ref) <= bar_g
     xh = x.cpu().numpy()
     eg = eta2.cpu().numpy()
     worst = 0.0

@@ -73,6 +73,20 @@ def test_marking_ties_and_edge_cases():
     z = np.zeros(300)
     z[17] = -0.0
     assert np.array_equal(_gpu_mark(z, 0.3, 0.05), OM.dorfler_mark(z, 0.3, 0.05))
+    # with a caller's workspace: the same flags, no allocation by the library;
+    # a workspace that is too small is refused before anything runs
+    for n in (1, 5120, 100003):
+        v = np.exp(rng.normal(-6.0, 2.0, n))
+        vd = torch.from_numpy(v).cuda()
+        nb = dpg.dorfler_mark_workspace_size(n)
+        assert nb > 0
+        ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        fw = dpg.dorfler_mark(vd, 0.3, 0.05, workspace=ws)
+        fa = dpg.dorfler_mark(vd, 0.3, 0.05)
+        torch.cuda.synchronize()
+        assert torch.equal(fw[:n], fa[:n]), n
+        with pytest.raises(dpg.DPGError):
+            dpg.dorfler_mark(vd, 0.3, 0.05, workspace=ws[:nb - 256])
     f = dpg.dorfler_mark(torch.zeros(0, dtype=torch.float64, device="cuda"))
     torch.cuda.synchronize()
     vd = torch.ones(10, dtype=torch.float64, device="cuda")
