@@ -39,7 +39,7 @@ def test_noalloc_marking_matches_allocating_entry():
         v = torch.from_numpy(_values(n, seed)).cuda()
         ref = torch.full((n,), 9, dtype=torch.int8, device="cuda")
         got = torch.full((n,), 9, dtype=torch.int8, device="cuda")
-        assert L.dpg_dorfler_mark(n, v.data_ptr(), fr, fc, ref.data_ptr(), stream.cuda_stream) == dpg.DPG_OK
+        assert L.dpg_dorfler_mark(n, v.data_ptr(), fr, fc, ref.data_ptr(), None, 0, stream.cuda_stream) == dpg.DPG_OK
         rc = L.dpg_dorfler_mark_noalloc(n, v.data_ptr(), fr, fc, got.data_ptr(), stream.cuda_stream)
         assert rc == dpg.DPG_OK, L.dpg_last_error()
         torch.cuda.synchronize()
