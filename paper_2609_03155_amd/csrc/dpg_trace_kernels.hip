@@ -430,32 +430,66 @@ __global__ __launch_bounds__(NT) void k_recon_back(DevTables T, ChunkArgs C, Con
     // blocks m (the factorisation stores L_JJ below the block diagonal and the
     // inverses Dinv of its diagonal blocks on it):
     //   t = s[m] - sum_{m2 > m} L_JJ[m2][m]^H z[m2],  z[m] = Dinv[m]^H t.
+    // All 64 lanes of wave 0: lane (ro, cg) = (l & 15, l >> 4) takes rows
+    // ro + 16 k of columns c = 16 m + cg + 4 q (q = 0..3), so that the 16
+    // lanes of a column read consecutive rows; the sums over ro close with a
+    // butterfly in a fixed order.
     if (wave == 0) {
       const double2* tile = Z + (int64_t)(J * TB) * ld + J * TB;   // column c at tile + c ld
       double2* tb = sb + TB;                                        // [64] t of the current block
-      for (int m = 3; m >= 0; --m) {
-        if (lane < 16) {
-          const int c = 16 * m + lane;
-          double re = sb[c].x, im = sb[c].y;
-          for (int r = 16 * (m + 1); r < TB; ++r) {
-            const double2 l = tile[(int64_t)c * ld + r], z = zs[J * TB + r];
-            re -= l.x * z.x + l.y * z.y;   // conj(l) z
-            im -= l.x * z.y - l.y * z.x;
+      const int ro = lane & 15, cg = lane >> 4;
+      auto butterfly = [&](double2* acc) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int off = 8; off > 0; off >>= 1) {
+            acc[q].x += __shfl_xor(acc[q].x, off, 64);
+            acc[q].y += __shfl_xor(acc[q].y, off, 64);
           }
-          tb[c] = make_double2(re, im);
+      };
+      for (int m = 3; m >= 0; --m) {
+        double2 acc[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = make_double2(0.0, 0.0);
+        for (int r = 16 * (m + 1) + ro; r < TB; r += 16) {
+          const double2 z = zs[J * TB + r];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const double2 l = tile[(int64_t)(16 * m + cg + 4 * q) * ld + r];
+            acc[q].x += l.x * z.x + l.y * z.y;   // conj(l) z
+            acc[q].y += l.x * z.y - l.y * z.x;
+          }
+        }
+        butterfly(acc);
+        if (ro == 0) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int c = 16 * m + cg + 4 * q;
+            tb[c] = make_double2(sb[c].x - acc[q].x, sb[c].y - acc[q].y);
+          }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        if (lane < 16) {
-          const int c = 16 * m + lane;
-          double re = 0.0, im = 0.0;
-          for (int r = c; r < 16 * (m + 1); ++r) {
-            const double2 l = tile[(int64_t)c * ld + r], t = tb[r];
-            re += l.x * t.x + l.y * t.y;
-            im += l.x * t.y - l.y * t.x;
+        // z[c] = sum_{r >= c in block m} conj(Dinv[r][c]) t[r]
+        {
+          const int r = 16 * m + ro;
+          const double2 t = tb[r];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int c = 16 * m + cg + 4 * q;
+            double2 v = make_double2(0.0, 0.0);
+            if (r >= c) {
+              const double2 l = tile[(int64_t)c * ld + r];
+              v = make_double2(l.x * t.x + l.y * t.y, l.x * t.y - l.y * t.x);
+            }
+            acc[q] = v;
           }
-          zs[J * TB + c] = make_double2(re, im);
+        }
+        butterfly(acc);
+        if (ro == 0) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) zs[J * TB + 16 * m + cg + 4 * q] = acc[q];
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
