@@ -879,7 +879,6 @@ __global__ __launch_bounds__(NT) void k_form_T(DevTables T, ProbArgs P, ChunkArg
   double2* Z = C.Z + cell * T.zstride;
   const int64_t ld = T.ldz;
   const int nvp = T.nvp;
-  __shared__ double2 sTr[64][2];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int ncol = min(64, T.Np - i0);   // columns of this tile
   // interior rows of the padding test functions: zero
@@ -927,33 +926,27 @@ __global__ __launch_bounds__(NT) void k_form_T(DevTables T, ProbArgs P, ChunkArg
       aI.x += __shfl_xor(aI.x, off, 64);
       aI.y += __shfl_xor(aI.y, off, 64);
     }
-    if (lane == 0) {
-      sTr[jl][0] = aF;
-      sTr[jl][1] = aI;
-    }
-  }
-  __syncthreads();
-  // padding rows of the RHS block, zero load row, residual row
-  for (int e = threadIdx.x; e < 64 * (T.kp - T.k); e += NT) {
-    const int jl = e % 64, rr = e / 64;
-    const int ii = i0 + jl;
-    if (ii >= T.Np) continue;
-    const int row = nvp + T.k + rr;
-    double2 vF = make_double2(0.0, 0.0), vI = vF;
-    if (rr == 1 && xc) {
-      if (ii < T.N) {
-        vF = Z[(int64_t)ii * ld + row];
-        vI = Z[(int64_t)(T.Np + ii) * ld + row];
+    // the rows after the trace rows, by the same wave right after them (one
+    // contiguous run per column): zero load row, residual row (its volume
+    // part, if any, plus the trace part, conjugated), zero padding
+    for (int rr = lane; rr < T.kp - T.k; rr += 64) {
+      const int row = nvp + T.k + rr;
+      double2 vF = make_double2(0.0, 0.0), vI = vF;
+      if (rr == 1 && xc) {
+        if (ii < T.N) {
+          vF = Z[(int64_t)ii * ld + row];
+          vI = Z[(int64_t)(T.Np + ii) * ld + row];
+        }
+        vF.x += aF.x;
+        vF.y += aF.y;
+        vI.x += aI.x;
+        vI.y += aI.y;
+        vF.y = -vF.y;
+        vI.y = -vI.y;
       }
-      vF.x += sTr[jl][0].x;
-      vF.y += sTr[jl][0].y;
-      vI.x += sTr[jl][1].x;
-      vI.y += sTr[jl][1].y;
-      vF.y = -vF.y;
-      vI.y = -vI.y;
+      Z[(int64_t)ii * ld + row] = vF;
+      Z[(int64_t)(T.Np + ii) * ld + row] = vI;
     }
-    Z[(int64_t)ii * ld + row] = vF;
-    Z[(int64_t)(T.Np + ii) * ld + row] = vI;
   }
 }
 
