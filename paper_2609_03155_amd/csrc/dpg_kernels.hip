@@ -1761,9 +1761,7 @@ struct WPipe {
 // lda) or, when FRA, from a real matrix, B from the complex panel Bj or, when
 // FRB, from a real matrix (the compact copy of the factorised F block,
 // leading dimension ldb).
-// NU: the first NU 16-row blocks of the column panel only (the blocks of Q
-// on and below the diagonal of a diagonal-block update).
-template <int MODE, bool FRB, int NV, bool FRA = false, int NU = 4>
+template <int MODE, bool FRB, int NV, bool FRA = false>
 __device__ __forceinline__ void wave_load(const void* __restrict__ Ai, int64_t lda, const void* __restrict__ Bj,
                                           int64_t ldb, int ks, WOpsT<NV>& o) {
   const int lane = threadIdx.x & 63;
@@ -1777,7 +1775,7 @@ __device__ __forceinline__ void wave_load(const void* __restrict__ Ai, int64_t l
   }
   const int64_t offb = (int64_t)(4 * ks + (lane >> 4)) * ldb + (lane & 15);
 #pragma unroll
-  for (int u = 0; u < NU; ++u) {
+  for (int u = 0; u < 4; ++u) {
     if (FRB) o.b[u].x = reinterpret_cast<const double*>(Bj)[offb + 16 * u];
     else if (MODE == MM_CC) o.b[u] = reinterpret_cast<const double2*>(Bj)[offb + 16 * u];
     else o.b[u].x = reinterpret_cast<const double*>(reinterpret_cast<const double2*>(Bj) + offb + 16 * u)[0];
@@ -1785,29 +1783,29 @@ __device__ __forceinline__ void wave_load(const void* __restrict__ Ai, int64_t l
 }
 
 // re -= br ar + bi ai,  im -= br ai - bi ar   (Q -= conj(b) a)
-template <int MODE, int NV, int NU = 4>
+template <int MODE, int NV>
 __device__ __forceinline__ void wave_step(const WOpsT<NV>& o, WAccT<NV>& q) {
   double nbr[4];
 #pragma unroll
-  for (int u = 0; u < NU; ++u) nbr[u] = -o.b[u].x;
+  for (int u = 0; u < 4; ++u) nbr[u] = -o.b[u].x;
 #pragma unroll
-  for (int u = 0; u < NU; ++u)
+  for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < NV; ++v) q.re[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(nbr[u], o.a[v].x, q.re[u][v], 0, 0, 0);
   if (MODE == MM_RR) return;
 #pragma unroll
-  for (int u = 0; u < NU; ++u)
+  for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < NV; ++v) q.im[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(nbr[u], o.a[v].y, q.im[u][v], 0, 0, 0);
   if (MODE == MM_CR) return;
 #pragma unroll
-  for (int u = 0; u < NU; ++u) {
+  for (int u = 0; u < 4; ++u) {
     const double nbi = -o.b[u].y;
 #pragma unroll
     for (int v = 0; v < NV; ++v) q.re[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(nbi, o.a[v].y, q.re[u][v], 0, 0, 0);
   }
 #pragma unroll
-  for (int u = 0; u < NU; ++u)
+  for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < NV; ++v) q.im[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(o.b[u].y, o.a[v].x, q.im[u][v], 0, 0, 0);
 }
@@ -1822,7 +1820,7 @@ __device__ __forceinline__ void wave_step(const WOpsT<NV>& o, WAccT<NV>& q) {
 // thousands of terms at p = 4) then grow with the runs' partial sums instead
 // of the running total (measured in an emulation of the sweep: K_e and eta
 // three to twenty times closer to the exact solve at p = 4, dp = 2).
-template <int MODE, bool FRB = false, int NV = 2, bool TWO = false, bool FRA = false, int NU = 4>
+template <int MODE, bool FRB = false, int NV = 2, bool TWO = false, bool FRA = false>
 __device__ __forceinline__ void wave_gemm_t(const void* __restrict__ Ai, int64_t lda, const void* __restrict__ Bj,
                                             int64_t ldb, int K, WAccT<NV>& q) {
   constexpr int NB = WPipe<MODE, NV, TWO>::NB, KS = WPipe<MODE, NV, TWO>::KS;
@@ -1833,7 +1831,7 @@ __device__ __forceinline__ void wave_gemm_t(const void* __restrict__ Ai, int64_t
   WAccT<NV> qb;                   // the current run's sum (TWO)
   auto zero_run = [&]() {
 #pragma unroll
-    for (int u = 0; u < NU; ++u)
+    for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         qb.re[u][v] = d4{0, 0, 0, 0};
@@ -1842,7 +1840,7 @@ __device__ __forceinline__ void wave_gemm_t(const void* __restrict__ Ai, int64_t
   };
   auto fold_run = [&]() {
 #pragma unroll
-    for (int u = 0; u < NU; ++u)
+    for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         q.re[u][v] += qb.re[u][v];
@@ -1855,17 +1853,17 @@ __device__ __forceinline__ void wave_gemm_t(const void* __restrict__ Ai, int64_t
 #pragma unroll
   for (int s = 0; s < NB - 1; ++s)
 #pragma unroll
-    for (int u = 0; u < KS; ++u) wave_load<MODE, FRB, NV, FRA, NU>(Ai, lda, Bj, ldb, min(s, nks - 1) * KS + u, o[s][u]);
+    for (int u = 0; u < KS; ++u) wave_load<MODE, FRB, NV, FRA>(Ai, lda, Bj, ldb, min(s, nks - 1) * KS + u, o[s][u]);
   for (int k0 = 0; k0 < nfull; k0 += NB) {
 #pragma unroll
     for (int s = 0; s < NB; ++s) {
 #pragma unroll
       for (int u = 0; u < KS; ++u)
-        wave_load<MODE, FRB, NV, FRA, NU>(Ai, lda, Bj, ldb, min(k0 + s + NB - 1, nks - 1) * KS + u,
+        wave_load<MODE, FRB, NV, FRA>(Ai, lda, Bj, ldb, min(k0 + s + NB - 1, nks - 1) * KS + u,
                                       o[(s + NB - 1) % NB][u]);
       __builtin_amdgcn_sched_barrier(0);   // keep each prefetch in its slot (bounded live ranges)
 #pragma unroll
-      for (int u = 0; u < KS; ++u) wave_step<MODE, NV, NU>(o[s][u], acc);
+      for (int u = 0; u < KS; ++u) wave_step<MODE, NV>(o[s][u], acc);
       __builtin_amdgcn_sched_barrier(0);
     }
     if (TWO && ((k0 + NB) & 15) == 0) {
@@ -1877,7 +1875,7 @@ __device__ __forceinline__ void wave_gemm_t(const void* __restrict__ Ai, int64_t
   for (int s = 0; s < NB - 1; ++s)
     if (s < nks - nfull) {
 #pragma unroll
-      for (int u = 0; u < KS; ++u) wave_step<MODE, NV, NU>(o[s][u], acc);
+      for (int u = 0; u < KS; ++u) wave_step<MODE, NV>(o[s][u], acc);
     }
   if (TWO && (nks & 15) != 0) fold_run();
 }
@@ -2083,20 +2081,20 @@ __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __res
 // Rows [RW h, RW h + RW) (RW = 16 NV) of a diagonal block update, one wave:
 //   S = S0 - P_h P^H ,  P the 64-row panel (columns [0, K) at P), P_h its rows [RW h, RW h + RW),
 // with S0 the column-major tile S0g (FROM_TILE) or the LDS block
-// Sr/Si[r*65 + c] itself; columns [0, 16 NU) of the RW x 64 result are
-// formed and written to Sr/Si[r*65 + c] (only the lower part of the block is
-// meaningful).  TWO: two-level summation (wave_gemm_t).  PREAL: P is a real
-// matrix (the compact copy of the F block) with leading dimension ldp.
-template <int MODE, bool FROM_TILE, int NV = 2, bool TWO = false, bool PREAL = false, int NU = 4>
-__device__ __forceinline__ void diag_update_nu(const double2* __restrict__ S0g, const void* __restrict__ P,
-                                               int64_t ld, int K, int h, double* Sr, double* Si, int64_t ldp) {
+// Sr/Si[r*65 + c] itself; the whole RW x 64 result is written to
+// Sr/Si[r*65 + c] (only its lower part is meaningful).  TWO: two-level
+// summation (wave_gemm_t).  PREAL: P is a real matrix (the compact copy of
+// the F block) with leading dimension ldp.
+template <int MODE, bool FROM_TILE, int NV = 2, bool TWO = false, bool PREAL = false>
+__device__ __forceinline__ void diag_update(const double2* __restrict__ S0g, const void* __restrict__ P, int64_t ld,
+                                            int K, int h, double* Sr, double* Si, int64_t ldp = 0) {
   constexpr int RW = 16 * NV;
   int lane = threadIdx.x & 63;
   __asm__ volatile("" : "+v"(lane));   // not hoisted out of a caller's loop (as in wave_tile)
   __asm__ volatile("" : "+s"(ld));
   WAccT<NV> q;
 #pragma unroll
-  for (int u = 0; u < NU; ++u)
+  for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
@@ -2112,12 +2110,12 @@ __device__ __forceinline__ void diag_update_nu(const double2* __restrict__ S0g, 
         }
       }
   if (PREAL)
-    wave_gemm_t<MODE, true, NV, TWO, true, NU>(reinterpret_cast<const double*>(P) + RW * h, ldp, P, ldp, K, q);
+    wave_gemm_t<MODE, true, NV, TWO, true>(reinterpret_cast<const double*>(P) + RW * h, ldp, P, ldp, K, q);
   else
-    wave_gemm_t<MODE, false, NV, TWO, false, NU>(reinterpret_cast<const double2*>(P) + RW * h, ld, P, ld, K, q);
+    wave_gemm_t<MODE, false, NV, TWO>(reinterpret_cast<const double2*>(P) + RW * h, ld, P, ld, K, q);
   // item t of block (u, v): S[row RW h + 16v + (l & 15)][column 16u + 4t + (l >> 4)]
 #pragma unroll
-  for (int u = 0; u < NU; ++u)
+  for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
@@ -2126,25 +2124,6 @@ __device__ __forceinline__ void diag_update_nu(const double2* __restrict__ S0g, 
         Sr[r * 65 + c] = q.re[u][v][t];
         if (MODE != MM_RR) Si[r * 65 + c] = q.im[u][v][t];   // a real block has no Si
       }
-}
-
-// Rows [RW h, RW h + RW) of a diagonal block update (diag_update_nu): with
-// 16-row waves only the column blocks u <= h, on and below the diagonal, are
-// formed (the factorisation reads the lower part only); their arithmetic is
-// the same as in a full update.
-template <int MODE, bool FROM_TILE, int NV = 2, bool TWO = false, bool PREAL = false>
-__device__ __forceinline__ void diag_update(const double2* __restrict__ S0g, const void* __restrict__ P, int64_t ld,
-                                            int K, int h, double* Sr, double* Si, int64_t ldp = 0) {
-  if (NV != 1) {
-    diag_update_nu<MODE, FROM_TILE, NV, TWO, PREAL, 4>(S0g, P, ld, K, h, Sr, Si, ldp);
-    return;
-  }
-  switch (h) {
-    case 0: diag_update_nu<MODE, FROM_TILE, NV, TWO, PREAL, 1>(S0g, P, ld, K, h, Sr, Si, ldp); break;
-    case 1: diag_update_nu<MODE, FROM_TILE, NV, TWO, PREAL, 2>(S0g, P, ld, K, h, Sr, Si, ldp); break;
-    case 2: diag_update_nu<MODE, FROM_TILE, NV, TWO, PREAL, 3>(S0g, P, ld, K, h, Sr, Si, ldp); break;
-    default: diag_update_nu<MODE, FROM_TILE, NV, TWO, PREAL, 4>(S0g, P, ld, K, h, Sr, Si, ldp); break;
-  }
 }
 
 // Step j of the left-looking factorisation over the row tiles i > j:
