@@ -1761,17 +1761,24 @@ struct WPipe {
 // lda) or, when FRA, from a real matrix, B from the complex panel Bj or, when
 // FRB, from a real matrix (the compact copy of the factorised F block,
 // leading dimension ldb).
-template <int MODE, bool FRB, int NV, bool FRA = false>
+// NTA: the A operand (the wave's own rows, read once per launch) is loaded
+// non-temporally, so that it does not push the shared column panel out of L2.
+template <int MODE, bool FRB, int NV, bool FRA = false, bool NTA = false>
 __device__ __forceinline__ void wave_load(const void* __restrict__ Ai, int64_t lda, const void* __restrict__ Bj,
                                           int64_t ldb, int ks, WOpsT<NV>& o) {
   const int lane = threadIdx.x & 63;
   const int64_t offa = (int64_t)(4 * ks + (lane >> 4)) * lda + (lane & 15);
+  typedef double ntd2 __attribute__((ext_vector_type(2)));
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     if (FRA) o.a[v].x = reinterpret_cast<const double*>(Ai)[offa + 16 * v];
     else if (MODE == MM_RR)
-      o.a[v].x = reinterpret_cast<const double*>(reinterpret_cast<const double2*>(Ai) + offa + 16 * v)[0];
-    else o.a[v] = reinterpret_cast<const double2*>(Ai)[offa + 16 * v];
+      o.a[v].x = NTA ? __builtin_nontemporal_load(reinterpret_cast<const double*>(reinterpret_cast<const double2*>(Ai) + offa + 16 * v))
+                     : reinterpret_cast<const double*>(reinterpret_cast<const double2*>(Ai) + offa + 16 * v)[0];
+    else if (NTA) {
+      const ntd2 t = __builtin_nontemporal_load(reinterpret_cast<const ntd2*>(reinterpret_cast<const double2*>(Ai) + offa + 16 * v));
+      o.a[v] = make_double2(t.x, t.y);
+    } else o.a[v] = reinterpret_cast<const double2*>(Ai)[offa + 16 * v];
   }
   const int64_t offb = (int64_t)(4 * ks + (lane >> 4)) * ldb + (lane & 15);
 #pragma unroll
@@ -1820,7 +1827,7 @@ __device__ __forceinline__ void wave_step(const WOpsT<NV>& o, WAccT<NV>& q) {
 // thousands of terms at p = 4) then grow with the runs' partial sums instead
 // of the running total (measured in an emulation of the sweep: K_e and eta
 // three to twenty times closer to the exact solve at p = 4, dp = 2).
-template <int MODE, bool FRB = false, int NV = 2, bool TWO = false, bool FRA = false>
+template <int MODE, bool FRB = false, int NV = 2, bool TWO = false, bool FRA = false, bool NTA = false>
 __device__ __forceinline__ void wave_gemm_t(const void* __restrict__ Ai, int64_t lda, const void* __restrict__ Bj,
                                             int64_t ldb, int K, WAccT<NV>& q) {
   constexpr int NB = WPipe<MODE, NV, TWO>::NB, KS = WPipe<MODE, NV, TWO>::KS;
@@ -1853,13 +1860,13 @@ __device__ __forceinline__ void wave_gemm_t(const void* __restrict__ Ai, int64_t
 #pragma unroll
   for (int s = 0; s < NB - 1; ++s)
 #pragma unroll
-    for (int u = 0; u < KS; ++u) wave_load<MODE, FRB, NV, FRA>(Ai, lda, Bj, ldb, min(s, nks - 1) * KS + u, o[s][u]);
+    for (int u = 0; u < KS; ++u) wave_load<MODE, FRB, NV, FRA, NTA>(Ai, lda, Bj, ldb, min(s, nks - 1) * KS + u, o[s][u]);
   for (int k0 = 0; k0 < nfull; k0 += NB) {
 #pragma unroll
     for (int s = 0; s < NB; ++s) {
 #pragma unroll
       for (int u = 0; u < KS; ++u)
-        wave_load<MODE, FRB, NV, FRA>(Ai, lda, Bj, ldb, min(k0 + s + NB - 1, nks - 1) * KS + u,
+        wave_load<MODE, FRB, NV, FRA, NTA>(Ai, lda, Bj, ldb, min(k0 + s + NB - 1, nks - 1) * KS + u,
                                       o[(s + NB - 1) % NB][u]);
       __builtin_amdgcn_sched_barrier(0);   // keep each prefetch in its slot (bounded live ranges)
 #pragma unroll
@@ -1925,7 +1932,7 @@ constexpr int RTPW = 4 / RWPT;            // regular tiles per workgroup
 // and the output to it only.
 enum { FR_NONE = 0, FR_READ = 1, FR_WRITE = 2, FR_FB = 3 };
 
-template <int MODE, int FR = FR_NONE, int NV = 2, bool TWO = false>
+template <int MODE, int FR = FR_NONE, int NV = 2, bool TWO = false, bool NTA = false>
 __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __restrict__ Z, int64_t cell, int i, int j,
                           int h, unsigned char* slab, int k0 = 0) {
   constexpr int RW = 16 * NV;   // rows of the wave: [RW h, RW h + RW) of the tile
@@ -1962,8 +1969,8 @@ __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __res
     wave_gemm_t<MODE, true, NV, TWO>(Z + (int64_t)k0 * ld + i * TB + RW * h, ld, Fr + (int64_t)k0 * ldf + j * TB,
                                      ldf, j * TB - k0, q);
   else
-    wave_gemm_t<MODE, false, NV, TWO>(Z + (int64_t)k0 * ld + i * TB + RW * h, ld, Z + (int64_t)k0 * ld + j * TB, ld,
-                                      j * TB - k0, q);
+    wave_gemm_t<MODE, false, NV, TWO, false, NTA>(Z + (int64_t)k0 * ld + i * TB + RW * h, ld,
+                                                  Z + (int64_t)k0 * ld + j * TB, ld, j * TB - k0, q);
   __builtin_amdgcn_sched_barrier(0);
   const double2* tL = Z + (int64_t)(j * TB) * ld + j * TB;   // diagonal tile j (chol_inv_tile's storage)
   const double* tLr = FRB ? Fr + (int64_t)(j * TB) * ldf + j * TB : nullptr;
@@ -2159,7 +2166,7 @@ __global__ __launch_bounds__(NT, 2) void k_chol_step(DevTables T, ChunkArgs C, i
     // rows that are zero in the F columns stay zero there (k_chol_fpanel leaves them), so their sum starts after
     const int r0 = i * TB + 16 * RNV * h;
     const int k0 = frows_class(T, r0, 16 * RNV) == FROWS_ZERO ? (T.Np / TB) * TB : 0;
-    wave_tile<MM_CC, FR_NONE, RNV, true>(T, C, Z, cell, i, j, h, slab, k0);
+    wave_tile<MM_CC, FR_NONE, RNV, true, true>(T, C, Z, cell, i, j, h, slab, k0);
     return;
   }
   // ---- lookahead workgroup: tile (i, j), i = j + 1, on the four waves (16
