@@ -1738,6 +1738,10 @@ using WAcc = WAccT<2>;
 constexpr int WSP_PITCH = 208;
 constexpr int WSP_BYTES = 32 * WSP_PITCH;
 static_assert(4 * WSP_BYTES <= kFactorSmem, "four wave slabs fit the step kernel's LDS");
+// A wave's LDS region in the F-column kernel: the running total of its
+// two-level sums (32 doubles per lane) during the k-loop, then its split slab.
+constexpr int WLDS_BYTES = 32 * 64 * 8;
+static_assert(WSP_BYTES <= WLDS_BYTES && 4 * WLDS_BYTES <= kFactorSmem, "four wave regions fit the LDS");
 
 template <int NV = 2>
 struct WOpsT {
@@ -1747,7 +1751,7 @@ struct WOpsT {
 // Register buffers of the k-step pipeline (prefetch distance NB - 1): the
 // fewer MFMAs a k-step has, the deeper the prefetch; sized to what the
 // register file holds next to the accumulators without spilling.
-template <int MODE, int NV = 2, bool TWO = false>
+template <int MODE, int NV = 2, int TWO = 0>
 struct WPipe {
   // a wave of 16 rows (NV = 1) has half the accumulators, so room for twice the
   // buffers, unless the two-level summation takes that room for its run sums
@@ -1780,6 +1784,19 @@ __device__ __forceinline__ void wave_load(const void* __restrict__ Ai, int64_t l
       o.a[v] = make_double2(t.x, t.y);
     } else o.a[v] = reinterpret_cast<const double2*>(Ai)[offa + 16 * v];
   }
+  const int64_t offb = (int64_t)(4 * ks + (lane >> 4)) * ldb + (lane & 15);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    if (FRB) o.b[u].x = reinterpret_cast<const double*>(Bj)[offb + 16 * u];
+    else if (MODE == MM_CC) o.b[u] = reinterpret_cast<const double2*>(Bj)[offb + 16 * u];
+    else o.b[u].x = reinterpret_cast<const double*>(reinterpret_cast<const double2*>(Bj) + offb + 16 * u)[0];
+  }
+}
+
+// The column-panel (B) part of wave_load alone.
+template <int MODE, bool FRB, int NV>
+__device__ __forceinline__ void wave_load_b(const void* __restrict__ Bj, int64_t ldb, int ks, WOpsT<NV>& o) {
+  const int lane = threadIdx.x & 63;
   const int64_t offb = (int64_t)(4 * ks + (lane >> 4)) * ldb + (lane & 15);
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
@@ -1827,22 +1844,40 @@ __device__ __forceinline__ void wave_step(const WOpsT<NV>& o, WAccT<NV>& q) {
 // thousands of terms at p = 4) then grow with the runs' partial sums instead
 // of the running total (measured in an emulation of the sweep: K_e and eta
 // three to twenty times closer to the exact solve at p = 4, dp = 2).
-template <int MODE, bool FRB = false, int NV = 2, bool TWO = false, bool FRA = false, bool NTA = false>
+// TAIL: the last 64 columns of A are the wave's previous tile of the same
+// rows, still in registers (*tail, in the accumulator layout, which for
+// k-step t of that tile is exactly the A operand: item t % 4 of block t / 4);
+// only the column panel is loaded for them.  The products and their order
+// are those of the loads from memory.
+// TWO == 2: the running total of the two-level sum in the wave's LDS region
+// `tot` (32 NV doubles per lane, item e of lane l at tot[64 e + l]) and the
+// run summed in q itself, which frees one accumulator set of registers; the
+// additions and their order are those of TWO == 1.
+template <int MODE, bool FRB = false, int NV = 2, int TWO = 0, bool FRA = false, bool NTA = false,
+          bool TAIL = false>
 __device__ __forceinline__ void wave_gemm_t(const void* __restrict__ Ai, int64_t lda, const void* __restrict__ Bj,
-                                            int64_t ldb, int K, WAccT<NV>& q) {
+                                            int64_t ldb, int K, WAccT<NV>& q, const WAccT<NV>* tail = nullptr,
+                                            double* tot = nullptr) {
   constexpr int NB = WPipe<MODE, NV, TWO>::NB, KS = WPipe<MODE, NV, TWO>::KS;
   static_assert(!TWO || 16 % NB == 0, "a run of 16 k-steps spans whole pipeline rounds");
-  const int nks = K / (4 * KS);   // buffers' worth of k-steps (K is a multiple of 64)
-  if (nks <= 0) return;
+  static_assert(!TAIL || KS == 1, "the tail is taken one k-step at a time");
+  const int nks_all = K / (4 * KS);   // buffers' worth of k-steps (K is a multiple of 64)
+  if (nks_all <= 0) return;
+  const int nks = TAIL ? nks_all - 16 : nks_all;   // k-steps with A from memory
   const int nfull = nks - nks % NB;
-  WAccT<NV> qb;                   // the current run's sum (TWO)
+  const int lane = threadIdx.x & 63;
+  WAccT<NV> qb;                   // the current run's sum (TWO == 1)
+  auto tot_at = [&](int part, int u, int v, int t) -> double& {
+    return tot[64 * (((part * 4 + u) * NV + v) * 4 + t) + lane];
+  };
   auto zero_run = [&]() {
+    WAccT<NV>& z = TWO == 2 ? q : qb;
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        qb.re[u][v] = d4{0, 0, 0, 0};
-        qb.im[u][v] = d4{0, 0, 0, 0};
+        z.re[u][v] = d4{0, 0, 0, 0};
+        z.im[u][v] = d4{0, 0, 0, 0};
       }
   };
   auto fold_run = [&]() {
@@ -1850,17 +1885,38 @@ __device__ __forceinline__ void wave_gemm_t(const void* __restrict__ Ai, int64_t
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        q.re[u][v] += qb.re[u][v];
-        if (MODE != MM_RR) q.im[u][v] += qb.im[u][v];
+        if (TWO == 2) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            tot_at(0, u, v, t) += q.re[u][v][t];
+            if (MODE != MM_RR) tot_at(1, u, v, t) += q.im[u][v][t];
+          }
+        } else {
+          q.re[u][v] += qb.re[u][v];
+          if (MODE != MM_RR) q.im[u][v] += qb.im[u][v];
+        }
       }
   };
+  if (TWO == 2) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          tot_at(0, u, v, t) = q.re[u][v][t];
+          if (MODE != MM_RR) tot_at(1, u, v, t) = q.im[u][v][t];
+        }
+  }
   if (TWO) zero_run();
-  WAccT<NV>& acc = TWO ? qb : q;
+  WAccT<NV>& acc = TWO == 1 ? qb : q;
   WOpsT<NV> o[NB][KS];
+  if (nks > 0) {
 #pragma unroll
   for (int s = 0; s < NB - 1; ++s)
 #pragma unroll
     for (int u = 0; u < KS; ++u) wave_load<MODE, FRB, NV, FRA, NTA>(Ai, lda, Bj, ldb, min(s, nks - 1) * KS + u, o[s][u]);
+  }
   for (int k0 = 0; k0 < nfull; k0 += NB) {
 #pragma unroll
     for (int s = 0; s < NB; ++s) {
@@ -1885,6 +1941,34 @@ __device__ __forceinline__ void wave_gemm_t(const void* __restrict__ Ai, int64_t
       for (int u = 0; u < KS; ++u) wave_step<MODE, NV>(o[s][u], acc);
     }
   if (TWO && (nks & 15) != 0) fold_run();
+  if (TAIL) {
+    // the previous tile's 16 k-steps: one run of the two-level sum (nks is a
+    // multiple of 16, so the run boundaries are those of the full loop)
+    WOpsT<NV> ob[2];
+    wave_load_b<MODE, FRB, NV>(Bj, ldb, nks, ob[0]);
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      if (t + 1 < 16) wave_load_b<MODE, FRB, NV>(Bj, ldb, nks + t + 1, ob[(t + 1) & 1]);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        ob[t & 1].a[v] = make_double2(tail->re[t >> 2][v][t & 3], MODE == MM_RR ? 0.0 : tail->im[t >> 2][v][t & 3]);
+      wave_step<MODE, NV>(ob[t & 1], acc);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (TWO) fold_run();
+  }
+  if (TWO == 2) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          q.re[u][v][t] = tot_at(0, u, v, t);
+          q.im[u][v][t] = MODE != MM_RR ? tot_at(1, u, v, t) : 0.0;
+        }
+  }
 }
 
 // Structure of the augmented rows [r0, r0 + nr) in the F columns: the
@@ -1932,9 +2016,11 @@ constexpr int RTPW = 4 / RWPT;            // regular tiles per workgroup
 // and the output to it only.
 enum { FR_NONE = 0, FR_READ = 1, FR_WRITE = 2, FR_FB = 3 };
 
-template <int MODE, int FR = FR_NONE, int NV = 2, bool TWO = false, bool NTA = false>
+// keep (TAIL): in, the wave's tile (i, j - 1) as left by the previous call
+// (used for the last 64 columns of the sum when j > 0); out, this tile.
+template <int MODE, int FR = FR_NONE, int NV = 2, int TWO = 0, bool NTA = false, bool TAIL = false>
 __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __restrict__ Z, int64_t cell, int i, int j,
-                          int h, unsigned char* slab, int k0 = 0) {
+                          int h, unsigned char* slab, int k0 = 0, WAccT<NV>* keep = nullptr) {
   constexpr int RW = 16 * NV;   // rows of the wave: [RW h, RW h + RW) of the tile
   // ld and lane pass through empty asm so that, in a loop over tiles, the
   // compiler recomputes the lane addresses per tile instead of keeping them
@@ -1965,6 +2051,10 @@ __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __res
   if (FR == FR_FB)
     wave_gemm_t<MODE, true, NV, TWO, true>(Fr + (int64_t)k0 * ldf + i * TB + RW * h, ldf,
                                            Fr + (int64_t)k0 * ldf + j * TB, ldf, j * TB - k0, q);
+  else if (FRB && TAIL)
+    wave_gemm_t<MODE, true, NV, TWO, false, false, true>(Z + (int64_t)k0 * ld + i * TB + RW * h, ld,
+                                                         Fr + (int64_t)k0 * ldf + j * TB, ldf, j * TB - k0, q, keep,
+                                                         TWO == 2 ? reinterpret_cast<double*>(slab) : nullptr);
   else if (FRB)
     wave_gemm_t<MODE, true, NV, TWO>(Z + (int64_t)k0 * ld + i * TB + RW * h, ld, Fr + (int64_t)k0 * ldf + j * TB,
                                      ldf, j * TB - k0, q);
@@ -2083,6 +2173,7 @@ __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __res
       if (MODE != MM_RR) q.im[mb][nb] = yi[nb];
     }
   }
+  if (TAIL) *keep = q;
 }
 
 // Rows [RW h, RW h + RW) (RW = 16 NV) of a diagonal block update, one wave:
@@ -2245,30 +2336,37 @@ __global__ __launch_bounds__(NT, 3) void k_chol_fblock(DevTables T, ChunkArgs C,
 // nothing else for their F columns: each 16-row wave walks its rows through
 // j = 0 .. nF-1,
 //   L_ij = (A_ij - sum_{m<j} L_im L_jm^T) L_jj^{-T} ,
-// and reads back the row panel L_i,<j it has just written, which is still
-// in the caches, instead of every step re-reading it from HBM in a launch of
-// its own.  Row tile nF is taken by the first workgroups (one per cell): the
-// four waves walk it, then form A_ii - sum_{m<nF} L_im L_im^H in LDS and
-// factorise it for the step nF.  Every sum is two-level.
+// reading back the row panel L_i,<j it has written at the earlier j (the
+// last of its tiles, L_i,j-1, straight from its registers), instead of every
+// step re-reading it in a launch of its own.  Row tile nF has a workgroup of
+// its own per cell: its four waves walk it, then form A_ii - sum_{m<nF}
+// L_im L_im^H in LDS and factorise it for the step nF.  Per XCD the cells
+// come in order, each as that workgroup followed by those of its other row
+// tiles, so that the long row-nF workgroups run beside the others instead
+// of all at the start.  Every sum is two-level (the running totals of the
+// other row tiles in LDS, which frees the registers of the kept tile).
 __global__ __launch_bounds__(NT, 2) void k_chol_fpanel(DevTables T, ChunkArgs C, int nF) {
   const int nrb = T.nrows / TB;
   const int nreg = nrb - nF - 1;   // row tiles after nF, RTPW per workgroup
   const int64_t n8 = (C.n + 7) / 8 * 8;
   const int wave = (int)(threadIdx.x >> 6);
   extern __shared__ double smem[];
-  if ((int64_t)blockIdx.x >= n8) {
-    // per XCD x the (cell, tile) pairs of its cells c = 8 m + x in (m, tile) order, RTPW per workgroup
-    const int64_t w = (int64_t)blockIdx.x - n8;
-    const int64_t item = (w >> 3) * RTPW + wave / RWPT;
+  static_assert(RTPW == 1, "one row tile per workgroup");
+  // per XCD x its cells c = 8 m + x in order, each as its row-nF workgroup
+  // followed by its regular row tiles
+  const int64_t w = blockIdx.x;
+  const int64_t slot = w >> 3;
+  const int64_t m = slot / (1 + nreg);
+  const int tt = (int)(slot - m * (1 + nreg));
+  if (tt > 0) {
     const int h = wave % RWPT;
-    const int64_t m = item / nreg;
-    const int t = (int)(item - m * nreg);
+    const int t = tt - 1;
     const int64_t cell = m * 8 + (w & 7);
     if (cell >= C.n) return;   // whole waves: no barrier on this path
     const int i = nF + 1 + t;
     constexpr int RW = 16 * RNV;
     double2* Z = C.Z + cell * T.zstride;
-    unsigned char* slab = reinterpret_cast<unsigned char*>(smem) + wave * WSP_BYTES;
+    unsigned char* slab = reinterpret_cast<unsigned char*>(smem) + wave * WLDS_BYTES;
     const int cls = frows_class(T, i * TB + RW * h, RW);
     if (cls == FROWS_ZERO) {
       // L_i,F = 0 (A_i,F = 0, already so in the workspace); only the bf16
@@ -2287,9 +2385,10 @@ __global__ __launch_bounds__(NT, 2) void k_chol_fpanel(DevTables T, ChunkArgs C,
       }
       return;
     }
+    WAccT<RNV> prev;   // this wave's tile (i, j - 1): the last 64 columns of the next sum
     for (int j = 0; j < nF; ++j) {
-      if (cls == FROWS_REAL) wave_tile<MM_RR, FR_READ, RNV, true>(T, C, Z, cell, i, j, h, slab);
-      else wave_tile<MM_CR, FR_READ, RNV, true>(T, C, Z, cell, i, j, h, slab);
+      if (cls == FROWS_REAL) wave_tile<MM_RR, FR_READ, RNV, 2, false, true>(T, C, Z, cell, i, j, h, slab, 0, &prev);
+      else wave_tile<MM_CR, FR_READ, RNV, 2, false, true>(T, C, Z, cell, i, j, h, slab, 0, &prev);
       // L_ij (stored by all lanes) feeds the loads of step j + 1
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
       __builtin_amdgcn_wave_barrier();
@@ -2297,8 +2396,8 @@ __global__ __launch_bounds__(NT, 2) void k_chol_fpanel(DevTables T, ChunkArgs C,
     }
     return;
   }
-  const int64_t cell = blockIdx.x;
-  if (cell >= C.n) return;
+  const int64_t cell = m * 8 + (w & 7);
+  if (cell >= C.n) return;   // the whole workgroup
   const int i = nF;
   const int64_t ld = T.ldz;
   double2* Z = C.Z + cell * T.zstride;
@@ -2726,7 +2825,9 @@ hipError_t launch_factor(const DevTables& t, const ChunkArgs& ca, hipStream_t st
   if (ca.n <= 0) return hipSuccess;
   const int nvb = t.nvp / TB, nrb = t.nrows / TB;
   const int64_t n8 = (ca.n + 7) / 8 * 8;
-  // lookahead workgroups (one per cell) + two wave-pair tiles per workgroup
+  // the lookahead (or row-nF) workgroup of every cell + one row tile per
+  // workgroup (the step kernel puts all lookahead workgroups first, the
+  // F-column kernel each cell's row-nF workgroup before its row tiles)
   auto grid_of = [&](bool la, int nreg) {
     return (unsigned)((la ? n8 : 0) + 8 * ((n8 / 8 * nreg + RTPW - 1) / RTPW));
   };
