@@ -388,6 +388,7 @@ dpg_status form_cells(dpg_plan plan, const dpg_problem* prob, int64_t first, int
     ca.Z = grp->Z;
     ca.dscale = grp->dscale;
     ca.met = grp->met;
+    ca.fr = grp->fr;   // the formation writes the real F block there
     ca.K_off = plan->K_off_dev;
     ca.v_off = plan->v_off_dev;
     ca.cell_base = first;

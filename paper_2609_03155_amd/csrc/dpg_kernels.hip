@@ -338,13 +338,18 @@ __global__ __launch_bounds__(NT) void k_form_pad(DevTables T, ChunkArgs C) {
   double2* Z = C.Z + cell * T.zstride;
   const int64_t ld = T.ldz;
   const int npad = T.Np - T.N;
+  const int nfb = (T.Np / TB) * TB;     // the real F block lives in its compact copy
+  double* fr = C.fr + cell * fr_stride(T);
+  const int64_t ldf = fr_ld(T);
   for (int blk = 0; blk < 2; ++blk) {
     const int base = blk * T.Np;
     for (int e = threadIdx.x; e < npad * T.Np; e += NT) {
       const int row = base + T.N + e % npad;
       const int col = base + e / npad;
       if (col > row) continue;
-      Z[(int64_t)col * ld + row] = make_double2(col == row ? 1.0 : 0.0, 0.0);
+      const double v = col == row ? 1.0 : 0.0;
+      if (row < nfb) fr[(int64_t)col * ldf + row] = v;
+      else Z[(int64_t)col * ld + row] = make_double2(v, 0.0);
     }
   }
 }
@@ -1312,6 +1317,11 @@ __device__ __forceinline__ void sf_pair_block(const DevTables& T, const ProbArgs
   const double* dsc = C.dscale + cell * (int64_t)T.nvp;
   double2* Z = C.Z + cell * T.zstride;
   const int64_t ld = T.ldz;
+  // the leading 64 floor(Np / 64) rows and columns of G_FF (the real F block
+  // the factorisation works on) go to its compact real copy, not to Z
+  const int nfb = (T.Np / TB) * TB;
+  double* fr = C.fr + cell * fr_stride(T);
+  const int64_t ldf = fr_ld(T);
 
   for (int g0 = 0; g0 < nblk; g0 += nbc) {
     const int nb = min(nbc, nblk - g0);
@@ -1464,7 +1474,9 @@ __device__ __forceinline__ void sf_pair_block(const DevTables& T, const ProbArgs
         if (row >= R) continue;
         const int i = ic + row % na0, j = jc + row / na0;
         if (tri && j > i) continue;
-        Z[(int64_t)j * ld + i] = make_double2(dsc[i] * dsc[j] * acS[k][it], 0.0);
+        const double gff = dsc[i] * dsc[j] * acS[k][it];
+        if (i < nfb && j < nfb) fr[(int64_t)j * ldf + i] = gff;   // the real F block: its compact copy only
+        else Z[(int64_t)j * ld + i] = make_double2(gff, 0.0);
         Z[(int64_t)(T.Np + j) * ld + T.Np + i] = make_double2(dsc[T.Np + i] * dsc[T.Np + j] * acM[k][it], 0.0);
       }
     }
@@ -2030,7 +2042,12 @@ __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __res
   int lane = threadIdx.x & 63;
   __asm__ volatile("" : "+v"(lane));
   double2* tile = Z + (int64_t)(j * TB) * ld + i * TB + RW * h;   // rows of A_ij in, of L_ij out
-  // the accumulators start as A_ij^T, so that they end as X^T
+  // panel j and the diagonal tile j: from Z, or from the real copy of the F block
+  constexpr bool FRB = FR == FR_READ || FR == FR_FB;
+  const int64_t ldf = fr_ld(T);
+  double* Fr = FR != FR_NONE ? C.fr + cell * fr_stride(T) : nullptr;
+  // the accumulators start as A_ij^T, so that they end as X^T (a tile of the
+  // F block starts from the real copy, where its Gram block is)
   WAccT<NV> q;
 #pragma unroll
   for (int u = 0; u < 4; ++u)
@@ -2039,15 +2056,16 @@ __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __res
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int r = 16 * v + (lane & 15), c = 16 * u + 4 * t + (lane >> 4);
-        const double2 a = tile[(int64_t)c * ld + r];
-        q.re[u][v][t] = a.x;
-        q.im[u][v][t] = MODE == MM_RR ? 0.0 : a.y;
+        if (FR == FR_FB) {
+          q.re[u][v][t] = Fr[(int64_t)(j * TB + c) * ldf + i * TB + RW * h + r];
+          q.im[u][v][t] = 0.0;
+        } else {
+          const double2 a = tile[(int64_t)c * ld + r];
+          q.re[u][v][t] = a.x;
+          q.im[u][v][t] = MODE == MM_RR ? 0.0 : a.y;
+        }
       }
   __builtin_amdgcn_sched_barrier(0);
-  // panel j and the diagonal tile j: from Z, or from the real copy of the F block
-  constexpr bool FRB = FR == FR_READ || FR == FR_FB;
-  const int64_t ldf = fr_ld(T);
-  double* Fr = FR != FR_NONE ? C.fr + cell * fr_stride(T) : nullptr;
   if (FR == FR_FB)
     wave_gemm_t<MODE, true, NV, TWO, true>(Fr + (int64_t)k0 * ldf + i * TB + RW * h, ldf,
                                            Fr + (int64_t)k0 * ldf + j * TB, ldf, j * TB - k0, q);
@@ -2182,8 +2200,9 @@ __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __res
 // Sr/Si[r*65 + c] itself; the whole RW x 64 result is written to
 // Sr/Si[r*65 + c] (only its lower part is meaningful).  TWO: two-level
 // summation (wave_gemm_t).  PREAL: P is a real matrix (the compact copy of
-// the F block) with leading dimension ldp.
-template <int MODE, bool FROM_TILE, int NV = 2, bool TWO = false, bool PREAL = false>
+// the F block) with leading dimension ldp; S0REAL: so is S0g (the real tile
+// at S0g, leading dimension ldp).
+template <int MODE, bool FROM_TILE, int NV = 2, bool TWO = false, bool PREAL = false, bool S0REAL = false>
 __device__ __forceinline__ void diag_update(const double2* __restrict__ S0g, const void* __restrict__ P, int64_t ld,
                                             int K, int h, double* Sr, double* Si, int64_t ldp = 0) {
   constexpr int RW = 16 * NV;
@@ -2198,7 +2217,10 @@ __device__ __forceinline__ void diag_update(const double2* __restrict__ S0g, con
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int r = RW * h + 16 * v + (lane & 15), c = 16 * u + 4 * t + (lane >> 4);
-        if (FROM_TILE) {
+        if (FROM_TILE && S0REAL) {
+          q.re[u][v][t] = reinterpret_cast<const double*>(S0g)[(int64_t)c * ldp + r];
+          q.im[u][v][t] = 0.0;
+        } else if (FROM_TILE) {
           const double2 a = S0g[(int64_t)c * ld + r];
           q.re[u][v][t] = a.x;
           q.im[u][v][t] = MODE == MM_RR ? 0.0 : a.y;
@@ -2302,22 +2324,24 @@ __global__ __launch_bounds__(NT, 3) void k_chol_fblock(DevTables T, ChunkArgs C,
   extern __shared__ double smem[];
   double* Cr = smem;
   double* Ci = Cr + 64 * 65;
-  // the factorised block lives only in its compact real copy (L_ij below the
-  // diagonal, the diagonal tiles as stored): the operands of its own later
-  // tiles and of the F-column launch.  Only A (the Gram block) comes from Z.
+  // the block lives only in its compact real copy: the formation writes the
+  // Gram block there, and the factorisation overwrites it in place (L_ij below
+  // the diagonal, the diagonal tiles as stored), the operands of its own later
+  // tiles and of the F-column launch.
   double* fr = C.fr + cell * fr_stride(T);
   const int64_t ldf = fr_ld(T);
   int fail = 0;
   for (int j = 0;; ++j) {
     // diagonal block j, updated by the columns before it, into LDS
-    double2* tileD = Z + (int64_t)(j * TB) * ld + j * TB;
+    const double* tileD = fr + (int64_t)(j * TB) * ldf + j * TB;
     if (j == 0) {
       for (int e = threadIdx.x; e < 64 * 64; e += NT) {
         const int q = e >> 6, r = e & 63;
-        if (q <= r) Cr[r * 65 + q] = tileD[(int64_t)q * ld + r].x;
+        if (q <= r) Cr[r * 65 + q] = tileD[(int64_t)q * ldf + r];
       }
     } else {
-      diag_update<MM_RR, true, 1, true, true>(tileD, fr + j * TB, ld, j * TB, wave, Cr, Ci, ldf);
+      diag_update<MM_RR, true, 1, true, true, true>(reinterpret_cast<const double2*>(tileD), fr + j * TB, ld, j * TB,
+                                                    wave, Cr, Ci, ldf);
     }
     __syncthreads();
     const int f = chol_inv_tile<true>(Cr, Ci, nullptr, 0, fr + (int64_t)(j * TB) * ldf + j * TB, ldf);
@@ -2715,7 +2739,12 @@ __global__ __launch_bounds__(NT) void k_extract(DevTables T, ChunkArgs C, double
   if (e < nG) {
     const int i = (int)(e % nv), jj = (int)(e / nv);
     const int zi = zrow(i), zj = zrow(jj);
-    double2 v = (zi >= zj) ? Z[(int64_t)zj * ld + zi] : cconj(Z[(int64_t)zi * ld + zj]);
+    const int nfb = (T.Np / TB) * TB;   // the real F block is in its compact copy
+    double2 v;
+    if (zi < nfb && zj < nfb)
+      v = make_double2(C.fr[cell * fr_stride(T) + (int64_t)min(zi, zj) * fr_ld(T) + max(zi, zj)], 0.0);
+    else
+      v = (zi >= zj) ? Z[(int64_t)zj * ld + zi] : cconj(Z[(int64_t)zi * ld + zj]);
     const double s = SCALED ? 1.0 : 1.0 / (d[zi] * d[zj]);
     G[cell * nG + e] = make_double2(v.x * s, v.y * s);
   } else if (e < nG + nB) {
