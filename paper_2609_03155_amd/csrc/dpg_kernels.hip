@@ -143,6 +143,43 @@ __device__ inline double2 cmul(double2 a, double2 b) {
 }
 __device__ inline double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 
+// Structure of the augmented rows [r0, r0 + nr) in the F columns: the
+// rows of the E-hat trace unknowns pair with no F test function (zero there,
+// so are the padding rows), those of H-hat only through the real trace table
+// (real); the interior, load and residual rows and the I test rows are complex.
+enum { FROWS_COMPLEX = 0, FROWS_REAL = 1, FROWS_ZERO = 2 };
+__device__ inline int frows_class(const DevTables& T, int r0, int nr = 32) {
+  const int eh0 = T.nvp + T.nu, hh0 = eh0 + T.nt1, lr0 = T.nvp + T.k, pad0 = lr0 + 2;
+  const int r1 = r0 + nr;
+  if (r0 < eh0 || (r0 < pad0 && r1 > lr0)) return FROWS_COMPLEX;
+  if (r0 < lr0 && r1 > hh0) return FROWS_REAL;
+  return FROWS_ZERO;
+}
+
+// First column of the sum W_a^H W_b over the test columns: the F columns
+// contribute nothing when either 64-row block of W^H is zero there.
+__device__ inline int herk_k0(const DevTables& T, int a, int b) {
+  auto zero_f = [&](int blk) {
+    const int r0 = T.nvp + blk * TB;
+    return frows_class(T, r0) == FROWS_ZERO && frows_class(T, r0 + 32) == FROWS_ZERO;
+  };
+  return zero_f(a) || zero_f(b) ? (T.Np / TB) * TB : 0;
+}
+
+// Trace-row entries of the workspace that the formation leaves unwritten
+// because they are zero and no kernel reads them: the E-hat rows in the
+// columns of the real F block (c < 64 nF) inside a 64-row block of W whose F
+// columns are all zero.  Their F-column tiles are skipped, the sums of their
+// step tiles and of the HERK start after the F block, and no other tile reads
+// these rows.  None without an F block (the condensation and reconstruction
+// matrices).
+__device__ inline bool trace_unwritten(const DevTables& T, int r, int c) {
+  const int eh0 = T.nvp + T.nu, hh0 = eh0 + T.nt1;
+  if (T.Np <= 0 || r < eh0 || r >= hh0 || c >= (T.Np / TB) * TB) return false;
+  const int b0 = T.nvp + (r - T.nvp) / TB * TB;
+  return frows_class(T, b0) == FROWS_ZERO && frows_class(T, b0 + 32) == FROWS_ZERO;
+}
+
 // bf16 bits of a float, round to nearest even (finite inputs).
 __device__ inline uint16_t f32_to_bf16_bits(float f) {
   uint32_t u = __float_as_uint(f);
@@ -284,6 +321,9 @@ __global__ __launch_bounds__(NT) void k_cell_scale(DevTables T, ProbArgs P, Chun
 // ================================================================ G_IF
 // G_IF(i,j) = conj(G_FI(j,i)) = -i w mu C_ji - i w conj(eps) C_ij + sum_R conj(z) Rt_ij,
 // from the geometry-free C and Rt; also zero in the F-pad columns / I-pad rows.
+#ifndef DPG_IF_NB
+#define DPG_IF_NB 4
+#endif
 __global__ __launch_bounds__(NT) void k_form_IF(DevTables T, ProbArgs P, ChunkArgs C) {
   const int nt = (T.Np + 63) / 64;
   int64_t cell;
@@ -300,33 +340,50 @@ __global__ __launch_bounds__(NT) void k_form_IF(DevTables T, ProbArgs P, ChunkAr
     fk[f] = P.face_kind[gc * 6 + f];
     zc[f] = make_double2(P.zinv[(gc * 6 + f) * 2], -P.zinv[(gc * 6 + f) * 2 + 1]);
   }
-  const double* d = C.dscale + cell * (int64_t)T.nvp;
-  double2* Z = C.Z + cell * T.zstride;
+  const double* __restrict__ d = C.dscale + cell * (int64_t)T.nvp;
+  double2* __restrict__ Z = C.Z + cell * T.zstride;
+  const double* __restrict__ Cref = T.Cref;
+  const double* __restrict__ CrefT = T.CrefT;
   const int64_t ld = T.ldz;
   const int il = threadIdx.x & 63;
   const int i = I0 + il;
   if (i >= T.Np) return;
-  for (int jl = threadIdx.x >> 6; jl < 64; jl += NT / 64) {
-    const int j = J0 + jl;
-    if (j >= T.Np) break;
-    double2 v = make_double2(0.0, 0.0);
-    if (i < T.N && j < T.N) {
-      const double cji = T.Cref[(size_t)j * T.N + i];
-      const double cij = T.CrefT[(size_t)j * T.N + i];
-      // -i w mu cji = w (mu.y, -mu.x) cji ; -i w conj(eps) cij = w (-eps.y, -eps.x) cij
-      v.x = om * (mu.y * cji - eps.y * cij);
-      v.y = om * (-mu.x * cji - eps.x * cij);
-      for (int f = 0; f < 6; ++f) {
-        if (!is_robin(fk[f])) continue;
-        const double rt = T.RtT[((size_t)f * T.N + j) * T.N + i];
-        v.x += zc[f].x * rt;
-        v.y += zc[f].y * rt;
-      }
-      const double s = d[T.Np + i] * d[j];
-      v.x *= s;
-      v.y *= s;
+  // the wave's columns jl = wave + 4 n in batches of NB: the table loads of a
+  // batch are in flight together
+  constexpr int NB = DPG_IF_NB;
+  const int wv = threadIdx.x >> 6;
+  const double di = d[T.Np + i];
+  for (int jb = J0 + wv; jb < J0 + 64 && jb < T.Np; jb += NB * (NT / 64)) {
+    double cji[NB], cij[NB], dj[NB];
+#pragma unroll
+    for (int n = 0; n < NB; ++n) {
+      const int j = jb + n * (NT / 64);
+      const bool ok = i < T.N && j < T.N;
+      cji[n] = ok ? Cref[(size_t)j * T.N + i] : 0.0;
+      cij[n] = ok ? CrefT[(size_t)j * T.N + i] : 0.0;
+      dj[n] = j < T.Np ? d[j] : 0.0;
     }
-    Z[(int64_t)j * ld + T.Np + i] = v;
+#pragma unroll
+    for (int n = 0; n < NB; ++n) {
+      const int j = jb + n * (NT / 64);
+      if (j >= T.Np || j >= J0 + 64) break;
+      double2 v = make_double2(0.0, 0.0);
+      if (i < T.N && j < T.N) {
+        // -i w mu cji = w (mu.y, -mu.x) cji ; -i w conj(eps) cij = w (-eps.y, -eps.x) cij
+        v.x = om * (mu.y * cji[n] - eps.y * cij[n]);
+        v.y = om * (-mu.x * cji[n] - eps.x * cij[n]);
+        for (int f = 0; f < 6; ++f) {
+          if (!is_robin(fk[f])) continue;
+          const double rt = T.RtT[((size_t)f * T.N + j) * T.N + i];
+          v.x += zc[f].x * rt;
+          v.y += zc[f].y * rt;
+        }
+        const double sc = di * dj[n];
+        v.x *= sc;
+        v.y *= sc;
+      }
+      Z[(int64_t)j * ld + T.Np + i] = v;
+    }
   }
 }
 
@@ -865,10 +922,11 @@ __global__ __launch_bounds__(NT, 2) void k_form_Bt(DevTables T, ProbArgs P, Chun
 // Robin faces are taken off it for the F rows), the zero rows of the
 // padding test functions, the zero load row (k_form_load writes the load on
 // port cells) and the residual row conj(D B_f x), whose volume and Robin
-// parts k_form_resid and k_form_Bt left in the row.  One wave per column, its
-// lanes along the trace rows in chunks of 64 (coalesced stores); each lane
-// sums its rows' part of D B_f x over the chunks and the wave reduces the
-// column's sum once, in a fixed order.
+// parts k_form_resid and k_form_Bt left in the row.  A wave takes two columns
+// at a time, its lanes along the trace rows in chunks of 64 (coalesced
+// stores); each lane sums its rows' part of D B_f x over the chunks and the
+// wave reduces each column's sum once, in a fixed order.  The zero E-hat
+// entries that no kernel reads (trace_unwritten) are not stored.
 __global__ __launch_bounds__(NT) void k_form_T(DevTables T, ProbArgs P, ChunkArgs C) {
   const int nrt = (T.Np + 63) / 64;
   int64_t cell;
@@ -876,12 +934,12 @@ __global__ __launch_bounds__(NT) void k_form_T(DevTables T, ProbArgs P, ChunkArg
   if (!decode_cell_tile(C.n, nrt, cell, tile)) return;
   const int64_t gc = C.cell_ids[cell];
   const int i0 = tile * 64;
-  const double2* xc = C.x ? C.x + (C.v_off[gc] - C.v_base) : nullptr;
+  const double2* __restrict__ xc = C.x ? C.x + (C.v_off[gc] - C.v_base) : nullptr;
   int rmask = 0;
   for (int f = 0; f < 6; ++f) rmask |= is_robin(P.face_kind[gc * 6 + f]) ? 1 << f : 0;
   const int nrobin = __builtin_popcount(rmask);
-  const double* d = C.dscale + cell * (int64_t)T.nvp;
-  double2* Z = C.Z + cell * T.zstride;
+  const double* __restrict__ d = C.dscale + cell * (int64_t)T.nvp;
+  double2* __restrict__ Z = C.Z + cell * T.zstride;
   const int64_t ld = T.ldz;
   const int nvp = T.nvp;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -895,62 +953,96 @@ __global__ __launch_bounds__(NT) void k_form_T(DevTables T, ProbArgs P, ChunkArg
       Z[(int64_t)(T.Np + ii) * ld + nvp + r] = make_double2(0.0, 0.0);
     }
   }
-#pragma unroll 2
-  for (int jl = wv; jl < ncol; jl += NT / 64) {
-    const int ii = i0 + jl;
-    const double dF = d[ii], dI = d[T.Np + ii];
-    double2 aF = make_double2(0.0, 0.0), aI = aF;
+  // G columns of the wave at a time (jl = jb + 4 g): the table loads of a
+  // chunk of trace rows for all G columns, and the x values of the chunk once
+  // for them, are in flight together
+  constexpr int G = 2;
+  const double* __restrict__ Tsum = T.Tsum;
+  for (int jb = wv; jb < ncol; jb += G * (NT / 64)) {
+    double dF[G], dI[G];
+    double2 aF[G], aI[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int ii = i0 + min(jb + g * (NT / 64), ncol - 1);
+      dF[g] = d[ii];
+      dI[g] = d[T.Np + ii];
+      aF[g] = make_double2(0.0, 0.0);
+      aI[g] = aF[g];
+    }
     for (int c0 = 0; c0 < T.nt1; c0 += 64) {
       const int jt = c0 + lane;
-      const bool okt = jt < T.nt1, okc = ii < T.N && okt;
-      double tI = okc ? T.Tsum[(size_t)ii * T.nt1 + jt] : 0.0, tF = tI;
-      if (nrobin && okc) {
-        for (int f = 0; f < 6; ++f)
-          if ((rmask >> f) & 1) tF -= T.T[((size_t)f * T.N + ii) * T.nt1 + jt];
+      const bool okt = jt < T.nt1;
+      double2 xe = make_double2(0.0, 0.0), xh = xe;
+      if (xc && okt) {
+        xe = xc[T.nu + jt];
+        xh = xc[T.nu + T.nt1 + jt];
       }
-      const double tf = dF * tF, ti = dI * tI;
-      if (okt) {
-        const int rowEh = nvp + T.nu + jt, rowHh = nvp + T.nu + T.nt1 + jt;
-        Z[(int64_t)ii * ld + rowEh] = make_double2(0.0, 0.0);
-        Z[(int64_t)ii * ld + rowHh] = make_double2(tf, 0.0);
-        Z[(int64_t)(T.Np + ii) * ld + rowEh] = make_double2(ti, 0.0);
-        Z[(int64_t)(T.Np + ii) * ld + rowHh] = make_double2(0.0, 0.0);
-        if (xc) {
-          const double2 xe = xc[T.nu + jt], xh = xc[T.nu + T.nt1 + jt];
-          aF.x += tf * xh.x;
-          aF.y += tf * xh.y;
-          aI.x += ti * xe.x;
-          aI.y += ti * xe.y;
+      double tI[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int ii = i0 + jb + g * (NT / 64);
+        tI[g] = (ii < T.N && okt && jb + g * (NT / 64) < ncol) ? Tsum[(size_t)ii * T.nt1 + jt] : 0.0;
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int jl = jb + g * (NT / 64);
+        if (jl >= ncol) break;
+        const int ii = i0 + jl;
+        const bool okc = ii < T.N && okt;
+        double tF = tI[g];
+        if (nrobin && okc) {
+          for (int f = 0; f < 6; ++f)
+            if ((rmask >> f) & 1) tF -= T.T[((size_t)f * T.N + ii) * T.nt1 + jt];
+        }
+        const double tf = dF[g] * tF, ti = dI[g] * tI[g];
+        if (okt) {
+          const int rowEh = nvp + T.nu + jt, rowHh = nvp + T.nu + T.nt1 + jt;
+          if (!trace_unwritten(T, rowEh, ii)) Z[(int64_t)ii * ld + rowEh] = make_double2(0.0, 0.0);
+          Z[(int64_t)ii * ld + rowHh] = make_double2(tf, 0.0);
+          Z[(int64_t)(T.Np + ii) * ld + rowEh] = make_double2(ti, 0.0);
+          Z[(int64_t)(T.Np + ii) * ld + rowHh] = make_double2(0.0, 0.0);
+          if (xc) {
+            aF[g].x += tf * xh.x;
+            aF[g].y += tf * xh.y;
+            aI[g].x += ti * xe.x;
+            aI[g].y += ti * xe.y;
+          }
         }
       }
     }
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      aF.x += __shfl_xor(aF.x, off, 64);
-      aF.y += __shfl_xor(aF.y, off, 64);
-      aI.x += __shfl_xor(aI.x, off, 64);
-      aI.y += __shfl_xor(aI.y, off, 64);
-    }
-    // the rows after the trace rows, by the same wave right after them (one
-    // contiguous run per column): zero load row, residual row (its volume
-    // part, if any, plus the trace part, conjugated), zero padding
-    for (int rr = lane; rr < T.kp - T.k; rr += 64) {
-      const int row = nvp + T.k + rr;
-      double2 vF = make_double2(0.0, 0.0), vI = vF;
-      if (rr == 1 && xc) {
-        if (ii < T.N) {
-          vF = Z[(int64_t)ii * ld + row];
-          vI = Z[(int64_t)(T.Np + ii) * ld + row];
-        }
-        vF.x += aF.x;
-        vF.y += aF.y;
-        vI.x += aI.x;
-        vI.y += aI.y;
-        vF.y = -vF.y;
-        vI.y = -vI.y;
+    for (int g = 0; g < G; ++g) {
+      const int jl = jb + g * (NT / 64);
+      if (jl >= ncol) break;
+      const int ii = i0 + jl;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        aF[g].x += __shfl_xor(aF[g].x, off, 64);
+        aF[g].y += __shfl_xor(aF[g].y, off, 64);
+        aI[g].x += __shfl_xor(aI[g].x, off, 64);
+        aI[g].y += __shfl_xor(aI[g].y, off, 64);
       }
-      Z[(int64_t)ii * ld + row] = vF;
-      Z[(int64_t)(T.Np + ii) * ld + row] = vI;
+      // the rows after the trace rows, by the same wave right after them (one
+      // contiguous run per column): zero load row, residual row (its volume
+      // part, if any, plus the trace part, conjugated), zero padding
+      for (int rr = lane; rr < T.kp - T.k; rr += 64) {
+        const int row = nvp + T.k + rr;
+        double2 vF = make_double2(0.0, 0.0), vI = vF;
+        if (rr == 1 && xc) {
+          if (ii < T.N) {
+            vF = Z[(int64_t)ii * ld + row];
+            vI = Z[(int64_t)(T.Np + ii) * ld + row];
+          }
+          vF.x += aF[g].x;
+          vF.y += aF[g].y;
+          vI.x += aI[g].x;
+          vI.y += aI[g].y;
+          vF.y = -vF.y;
+          vI.y = -vI.y;
+        }
+        Z[(int64_t)ii * ld + row] = vF;
+        Z[(int64_t)(T.Np + ii) * ld + row] = vI;
+      }
     }
   }
 }
@@ -1983,29 +2075,6 @@ __device__ __forceinline__ void wave_gemm_t(const void* __restrict__ Ai, int64_t
   }
 }
 
-// Structure of the augmented rows [r0, r0 + nr) in the F columns: the
-// rows of the E-hat trace unknowns pair with no F test function (zero there,
-// so are the padding rows), those of H-hat only through the real trace table
-// (real); the interior, load and residual rows and the I test rows are complex.
-enum { FROWS_COMPLEX = 0, FROWS_REAL = 1, FROWS_ZERO = 2 };
-__device__ inline int frows_class(const DevTables& T, int r0, int nr = 32) {
-  const int eh0 = T.nvp + T.nu, hh0 = eh0 + T.nt1, lr0 = T.nvp + T.k, pad0 = lr0 + 2;
-  const int r1 = r0 + nr;
-  if (r0 < eh0 || (r0 < pad0 && r1 > lr0)) return FROWS_COMPLEX;
-  if (r0 < lr0 && r1 > hh0) return FROWS_REAL;
-  return FROWS_ZERO;
-}
-
-// First column of the sum W_a^H W_b over the test columns: the F columns
-// contribute nothing when either 64-row block of W^H is zero there.
-__device__ inline int herk_k0(const DevTables& T, int a, int b) {
-  auto zero_f = [&](int blk) {
-    const int r0 = T.nvp + blk * TB;
-    return frows_class(T, r0) == FROWS_ZERO && frows_class(T, r0 + 32) == FROWS_ZERO;
-  };
-  return zero_f(a) || zero_f(b) ? (T.Np / TB) * TB : 0;
-}
-
 // Rows [16 NV h, 16 NV (h + 1)) of the tile (i, j) of step j, one wave:
 // X = A_ij - L_i,<j L_j,<j^H (the sum over columns from k0, the caller's bound
 // below which the rows are zero), then L_ij = X L_jj^{-H} by block
@@ -2751,7 +2820,8 @@ __global__ __launch_bounds__(NT) void k_extract(DevTables T, ChunkArgs C, double
     const int64_t f = e - nG;
     const int i = (int)(f % nv), a = (int)(f / nv);
     const int zi = zrow(i);
-    const double2 v = cconj(Z[(int64_t)zi * ld + T.nvp + a]);
+    const double2 v =
+        trace_unwritten(T, T.nvp + a, zi) ? make_double2(0.0, 0.0) : cconj(Z[(int64_t)zi * ld + T.nvp + a]);
     Bf[cell * nB + f] = SCALED ? v : make_double2(v.x / d[zi], v.y / d[zi]);
   } else if (e < nG + nB + nv) {
     const int i = (int)(e - nG - nB);
