@@ -180,21 +180,21 @@ __device__ inline bool trace_unwritten(const DevTables& T, int r, int c) {
   return frows_class(T, b0) == FROWS_ZERO && frows_class(T, b0 + 32) == FROWS_ZERO;
 }
 
-// bf16 bits of a float, round to nearest even (finite inputs).
-__device__ inline uint16_t f32_to_bf16_bits(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-__device__ inline double bf16_bits_to_f64(uint16_t h) { return (double)__uint_as_float((uint32_t)h << 16); }
-
-// v ~ h0 + h1 + h2 with bf16 terms: each term captures the remainder of the
-// previous ones (about 24 significant bits in total).
-__device__ inline void split3_bf16(double v, uint16_t h[3]) {
-  double rem = v;
+// Three-term bf16 splits of a complex value: v ~ h0 + h1 + h2 for its real and
+// imaginary parts, each term the remainder of the previous ones rounded to
+// bf16 (through float, round to nearest even; about 24 significant bits in
+// total).  p[t] holds the t-th terms, the real part's bits in the low half and
+// the imaginary part's in the high half: one packed conversion makes both.
+__device__ inline void split3_bf16_pair(double vr, double vi, uint32_t p[3]) {
+  double rr = vr, ri = vi;
+#pragma unroll
   for (int t = 0; t < 3; ++t) {
-    h[t] = f32_to_bf16_bits((float)rem);
-    rem -= bf16_bits_to_f64(h[t]);
+    // both halves in one packed conversion (rounding to nearest even); the
+    // float values are rounded from the doubles first, as written
+    const float fr = (float)rr, fi = (float)ri;
+    __asm__("v_cvt_pk_bf16_f32 %0, %1, %2" : "=v"(p[t]) : "v"(fr), "v"(fi));
+    rr -= (double)__uint_as_float(p[t] << 16);
+    ri -= (double)__uint_as_float(p[t] & 0xffff0000u);
   }
 }
 
@@ -2222,15 +2222,14 @@ __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __res
           // three-term bf16 splits of re and im into the wave's LDS slab
           // [RW rows][6 planes][16 columns] (row pitch WSP_PITCH bytes)
           uint16_t* sl = reinterpret_cast<uint16_t*>(slab + r * WSP_PITCH) + 4 * t + (lane >> 4);
-          uint16_t hb[3];
-          split3_bf16(vr, hb);
-          sl[0] = hb[0];
-          sl[16] = hb[1];
-          sl[32] = hb[2];
-          split3_bf16(vi, hb);
-          sl[48] = hb[0];
-          sl[64] = hb[1];
-          sl[80] = hb[2];
+          uint32_t hp[3];
+          split3_bf16_pair(vr, vi, hp);
+          sl[0] = (uint16_t)hp[0];
+          sl[16] = (uint16_t)hp[1];
+          sl[32] = (uint16_t)hp[2];
+          sl[48] = (uint16_t)(hp[0] >> 16);
+          sl[64] = (uint16_t)(hp[1] >> 16);
+          sl[80] = (uint16_t)(hp[2] >> 16);
         }
       }
     if (wsplit) {
