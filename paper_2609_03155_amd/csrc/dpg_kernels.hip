@@ -2206,17 +2206,31 @@ __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __res
         }
       }
     }
+    // Y[mb] replaces Q[mb]: the B operand of the later blocks' updates
+#pragma unroll
+    for (int nb = 0; nb < NV; ++nb) {
+      q.re[mb][nb] = yr[nb];
+      if (MODE != MM_RR) q.im[mb][nb] = yi[nb];
+    }
+  }
+  // The stores of L_ij (and of its bf16 planes) follow the substitution: on
+  // this hardware a wait for a load also waits for the stores issued before
+  // it, so stores between the blocks would hold up the loads of the next
+  // block's diagonal-tile operands.
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb) {
+    __builtin_amdgcn_sched_barrier(0);
     // item t of block (mb, nb): L_ij[row RW h + 16 nb + (l & 15)][column 16 mb + 4 t + (l >> 4)]
 #pragma unroll
     for (int nb = 0; nb < NV; ++nb)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int r = 16 * nb + (lane & 15), c = 16 * mb + 4 * t + (lane >> 4);
-        const double vr = yr[nb][t], vi = MODE == MM_RR ? 0.0 : yi[nb][t];
+        const double vr = q.re[mb][nb][t], vi = MODE == MM_RR ? 0.0 : q.im[mb][nb][t];
         // in the split path the last column block of W^H is read only through its
         // bf16 planes, except the residual row (eta is formed from it in FP64)
-        const bool keep = !(wsplit && last_w) || i * TB + RW * h + r == T.nvp + T.k + 1;
-        if (keep && FR != FR_FB) tile[(int64_t)c * ld + r] = make_double2(vr, vi);
+        const bool store_l = !(wsplit && last_w) || i * TB + RW * h + r == T.nvp + T.k + 1;
+        if (store_l && FR != FR_FB) tile[(int64_t)c * ld + r] = make_double2(vr, vi);
         if (FR == FR_WRITE || FR == FR_FB) Fr[(int64_t)(j * TB + c) * ldf + i * TB + RW * h + r] = vr;
         if (wsplit) {
           // three-term bf16 splits of re and im into the wave's LDS slab
@@ -2251,12 +2265,6 @@ __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __res
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-    // Y[mb] replaces Q[mb]: the B operand of the later blocks' updates
-#pragma unroll
-    for (int nb = 0; nb < NV; ++nb) {
-      q.re[mb][nb] = yr[nb];
-      if (MODE != MM_RR) q.im[mb][nb] = yi[nb];
     }
   }
   if (TAIL) *keep = q;
