@@ -927,6 +927,7 @@ __global__ __launch_bounds__(NT, 2) void k_form_Bt(DevTables T, ProbArgs P, Chun
 // stores); each lane sums its rows' part of D B_f x over the chunks and the
 // wave reduces each column's sum once, in a fixed order.  The zero E-hat
 // entries that no kernel reads (trace_unwritten) are not stored.
+template <int MCH>   // chunks of 64 trace rows: ceil(nt1 / 64)
 __global__ __launch_bounds__(NT) void k_form_T(DevTables T, ProbArgs P, ChunkArgs C) {
   const int nrt = (T.Np + 63) / 64;
   int64_t cell;
@@ -953,48 +954,59 @@ __global__ __launch_bounds__(NT) void k_form_T(DevTables T, ProbArgs P, ChunkArg
       Z[(int64_t)(T.Np + ii) * ld + nvp + r] = make_double2(0.0, 0.0);
     }
   }
-  // G columns of the wave at a time (jl = jb + 4 g): the table loads of a
-  // chunk of trace rows for all G columns, and the x values of the chunk once
-  // for them, are in flight together
+  // G columns of the wave at a time (jl = jb + 4 g).  Every load of a batch
+  // (table values of all its chunks of trace rows, the residual row's volume
+  // part) is issued before its stores, and the x values of the trace rows
+  // once per wave: a wait for a load also waits for the stores issued before
+  // it.
   constexpr int G = 2;
   const double* __restrict__ Tsum = T.Tsum;
+  double2 xe[MCH], xh[MCH];
+#pragma unroll
+  for (int c = 0; c < MCH; ++c) {
+    const int jt = 64 * c + lane;
+    const bool ok = xc && jt < T.nt1;
+    xe[c] = ok ? xc[T.nu + jt] : make_double2(0.0, 0.0);
+    xh[c] = ok ? xc[T.nu + T.nt1 + jt] : make_double2(0.0, 0.0);
+  }
   for (int jb = wv; jb < ncol; jb += G * (NT / 64)) {
-    double dF[G], dI[G];
-    double2 aF[G], aI[G];
+    double dF[G], dI[G], tI[MCH][G];
+    double2 aF[G], aI[G], rF[G], rI[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      const int ii = i0 + min(jb + g * (NT / 64), ncol - 1);
+      const int jl = min(jb + g * (NT / 64), ncol - 1), ii = i0 + jl;
       dF[g] = d[ii];
       dI[g] = d[T.Np + ii];
       aF[g] = make_double2(0.0, 0.0);
       aI[g] = aF[g];
-    }
-    for (int c0 = 0; c0 < T.nt1; c0 += 64) {
-      const int jt = c0 + lane;
-      const bool okt = jt < T.nt1;
-      double2 xe = make_double2(0.0, 0.0), xh = xe;
-      if (xc && okt) {
-        xe = xc[T.nu + jt];
-        xh = xc[T.nu + T.nt1 + jt];
-      }
-      double tI[G];
+      // the residual row's volume part (lane 1 carries the row in the tail below)
+      const bool rv = xc && lane == 1 && ii < T.N && jb + g * (NT / 64) < ncol;
+      const int row = nvp + T.k + 1;
+      rF[g] = rv ? Z[(int64_t)ii * ld + row] : make_double2(0.0, 0.0);
+      rI[g] = rv ? Z[(int64_t)(T.Np + ii) * ld + row] : make_double2(0.0, 0.0);
 #pragma unroll
-      for (int g = 0; g < G; ++g) {
-        const int ii = i0 + jb + g * (NT / 64);
-        tI[g] = (ii < T.N && okt && jb + g * (NT / 64) < ncol) ? Tsum[(size_t)ii * T.nt1 + jt] : 0.0;
+      for (int c = 0; c < MCH; ++c) {
+        const int jt = 64 * c + lane;
+        tI[c][g] = (ii < T.N && jt < T.nt1 && jb + g * (NT / 64) < ncol) ? Tsum[(size_t)ii * T.nt1 + jt] : 0.0;
       }
+    }
+#pragma unroll
+    for (int c = 0; c < MCH; ++c) {
+      const int jt = 64 * c + lane;
+      if (64 * c >= T.nt1) break;
+      const bool okt = jt < T.nt1;
 #pragma unroll
       for (int g = 0; g < G; ++g) {
         const int jl = jb + g * (NT / 64);
         if (jl >= ncol) break;
         const int ii = i0 + jl;
         const bool okc = ii < T.N && okt;
-        double tF = tI[g];
+        double tF = tI[c][g];
         if (nrobin && okc) {
           for (int f = 0; f < 6; ++f)
             if ((rmask >> f) & 1) tF -= T.T[((size_t)f * T.N + ii) * T.nt1 + jt];
         }
-        const double tf = dF[g] * tF, ti = dI[g] * tI[g];
+        const double tf = dF[g] * tF, ti = dI[g] * tI[c][g];
         if (okt) {
           const int rowEh = nvp + T.nu + jt, rowHh = nvp + T.nu + T.nt1 + jt;
           if (!trace_unwritten(T, rowEh, ii)) Z[(int64_t)ii * ld + rowEh] = make_double2(0.0, 0.0);
@@ -1002,10 +1014,10 @@ __global__ __launch_bounds__(NT) void k_form_T(DevTables T, ProbArgs P, ChunkArg
           Z[(int64_t)(T.Np + ii) * ld + rowEh] = make_double2(ti, 0.0);
           Z[(int64_t)(T.Np + ii) * ld + rowHh] = make_double2(0.0, 0.0);
           if (xc) {
-            aF[g].x += tf * xh.x;
-            aF[g].y += tf * xh.y;
-            aI[g].x += ti * xe.x;
-            aI[g].y += ti * xe.y;
+            aF[g].x += tf * xh[c].x;
+            aF[g].y += tf * xh[c].y;
+            aI[g].x += ti * xe[c].x;
+            aI[g].y += ti * xe[c].y;
           }
         }
       }
@@ -1029,10 +1041,8 @@ __global__ __launch_bounds__(NT) void k_form_T(DevTables T, ProbArgs P, ChunkArg
         const int row = nvp + T.k + rr;
         double2 vF = make_double2(0.0, 0.0), vI = vF;
         if (rr == 1 && xc) {
-          if (ii < T.N) {
-            vF = Z[(int64_t)ii * ld + row];
-            vI = Z[(int64_t)(T.Np + ii) * ld + row];
-          }
+          vF = rF[g];
+          vI = rI[g];
           vF.x += aF[g].x;
           vF.y += aF[g].y;
           vI.x += aI[g].x;
@@ -2921,7 +2931,18 @@ hipError_t launch_formation(const DevTables& t, const ProbArgs& pa, const ChunkA
   }
   DPG_LAUNCH(KC_FORM_B, prof, st, k_form_Bt, dim3(grid_cells_tiles(ca.n, nt)), dim3(NT), sizeof(double) * BQC * t.m1,
              st, t, pa, ca);
-  DPG_LAUNCH(KC_FORM_B, prof, st, k_form_T, dim3(grid_cells_tiles(ca.n, nt)), dim3(NT), 0, st, t, pa, ca);
+  switch ((t.nt1 + 63) / 64) {   // nt1 = 12 (p + 1)^2: 48, 108, 192, 300
+#define DPG_T_CASE(M) \
+  case M:             \
+    DPG_LAUNCH(KC_FORM_B, prof, st, k_form_T<M>, dim3(grid_cells_tiles(ca.n, nt)), dim3(NT), 0, st, t, pa, ca); break;
+    DPG_T_CASE(1)
+    DPG_T_CASE(2)
+    DPG_T_CASE(3)
+    DPG_T_CASE(5)
+#undef DPG_T_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
   DPG_LAUNCH(KC_FORM_LOAD, prof, st, k_form_load, dim3(grid_cells_tiles(ca.n, nt)), dim3(NT),
              sizeof(double2) * 3 * t.nfq, st, t, pa, ca);
   return hipGetLastError();
