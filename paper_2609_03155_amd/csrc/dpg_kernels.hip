@@ -587,31 +587,41 @@ __device__ __forceinline__ void sfb_block(const DevTables& T, const ProbArgs& P,
     for (int ks = 0; ks < KD; ++ks) kstep(ks, acD);
 #pragma unroll 2
     for (int ks = KD; ks < KS; ++ks) kstep(ks, acR);
-    // ---- the four entries of every (i, m)
+    // ---- the four entries of every (i, m) (the scale factors are all
+    // loaded before the first store: a wait for a load also waits for the
+    // stores issued before it)
+    double sF[4][4], sI[4][4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int tau = w + 4 * k;
-      if (tau >= Tn) continue;
-      const int col = (tau / Rt) * 16 + (lane & 15);
-      const int blk = col / ncb, cc = col - blk * ncb;
-      if (blk >= nb) continue;
-      const int g = g0 + blk, m2 = g % P1, i2 = g / P1;
-      const int ib = a * T.nc + na0 * ((cc / P1) + na1 * i2), mb = P1 * ((cc % P1) + P1 * m2);
+    for (int pass = 0; pass < 2; ++pass)
 #pragma unroll
-      for (int it = 0; it < 4; ++it) {
-        const int row = (tau % Rt) * 16 + (lane >> 4) + 4 * it;
-        if (row >= R) continue;
-        const int i = ib + row / P1, m = mb + row % P1;
-        const double D = acD[k][it], Rv = acR[k][it];
-        const double dF = dsc[i], dI = dsc[T.Np + i];
-        double2* zf = Z + (int64_t)i * ld;
-        double2* zi = Z + (int64_t)(T.Np + i) * ld;
-        zf[rowE + m] = make_double2(-dF * om * eps.y * D, -dF * om * eps.x * D);
-        zf[rowH + m] = make_double2(dF * Rv, 0.0);
-        zi[rowE + m] = make_double2(dI * Rv, 0.0);
-        zi[rowH + m] = make_double2(dI * om * mu.y * D, dI * om * mu.x * D);
+      for (int k = 0; k < 4; ++k) {
+        const int tau = w + 4 * k;
+        if (tau >= Tn) continue;
+        const int col = (tau / Rt) * 16 + (lane & 15);
+        const int blk = col / ncb, cc = col - blk * ncb;
+        if (blk >= nb) continue;
+        const int g = g0 + blk, m2 = g % P1, i2 = g / P1;
+        const int ib = a * T.nc + na0 * ((cc / P1) + na1 * i2), mb = P1 * ((cc % P1) + P1 * m2);
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+          const int row = (tau % Rt) * 16 + (lane >> 4) + 4 * it;
+          if (row >= R) continue;
+          const int i = ib + row / P1, m = mb + row % P1;
+          if (pass == 0) {
+            sF[k][it] = dsc[i];
+            sI[k][it] = dsc[T.Np + i];
+            continue;
+          }
+          const double D = acD[k][it], Rv = acR[k][it];
+          const double dF = sF[k][it], dI = sI[k][it];
+          double2* zf = Z + (int64_t)i * ld;
+          double2* zi = Z + (int64_t)(T.Np + i) * ld;
+          zf[rowE + m] = make_double2(-dF * om * eps.y * D, -dF * om * eps.x * D);
+          zf[rowH + m] = make_double2(dF * Rv, 0.0);
+          zi[rowE + m] = make_double2(dI * Rv, 0.0);
+          zi[rowH + m] = make_double2(dI * om * mu.y * D, dI * om * mu.x * D);
+        }
       }
-    }
   }
 }
 
@@ -1560,28 +1570,38 @@ __device__ __forceinline__ void sf_pair_block(const DevTables& T, const ProbArgs
       }
     }
     // ---- scaled lower triangles of the (a, b) blocks of D G_FF D and D G_II D
+    // (the scale factors are all loaded before the first store: a wait for a
+    // load also waits for the stores issued before it)
+    double sF[4][4], sI[4][4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int tau = w + 4 * k;
-      if (tau >= Tn) continue;
-      const int col = (tau / Rt) * 16 + (lane & 15);
-      const int blk = col / ncb, cc = col - blk * ncb;
-      if (blk >= nb) continue;
-      int i2, j2;
-      sf_block(g0 + blk, tri, na2, i2, j2);
-      const int ic = a * T.nc + na0 * ((cc % na1) + na1 * i2), jc = b * T.nc + nb0 * ((cc / na1) + nb1 * j2);
+    for (int pass = 0; pass < 2; ++pass)
 #pragma unroll
-      for (int it = 0; it < 4; ++it) {
-        const int row = (tau % Rt) * 16 + (lane >> 4) + 4 * it;
-        if (row >= R) continue;
-        const int i = ic + row % na0, j = jc + row / na0;
-        if (tri && j > i) continue;
-        const double gff = dsc[i] * dsc[j] * acS[k][it];
-        if (i < nfb && j < nfb) fr[(int64_t)j * ldf + i] = gff;   // the real F block: its compact copy only
-        else Z[(int64_t)j * ld + i] = make_double2(gff, 0.0);
-        Z[(int64_t)(T.Np + j) * ld + T.Np + i] = make_double2(dsc[T.Np + i] * dsc[T.Np + j] * acM[k][it], 0.0);
+      for (int k = 0; k < 4; ++k) {
+        const int tau = w + 4 * k;
+        if (tau >= Tn) continue;
+        const int col = (tau / Rt) * 16 + (lane & 15);
+        const int blk = col / ncb, cc = col - blk * ncb;
+        if (blk >= nb) continue;
+        int i2, j2;
+        sf_block(g0 + blk, tri, na2, i2, j2);
+        const int ic = a * T.nc + na0 * ((cc % na1) + na1 * i2), jc = b * T.nc + nb0 * ((cc / na1) + nb1 * j2);
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+          const int row = (tau % Rt) * 16 + (lane >> 4) + 4 * it;
+          if (row >= R) continue;
+          const int i = ic + row % na0, j = jc + row / na0;
+          if (tri && j > i) continue;
+          if (pass == 0) {
+            sF[k][it] = dsc[i] * dsc[j];
+            sI[k][it] = dsc[T.Np + i] * dsc[T.Np + j];
+            continue;
+          }
+          const double gff = sF[k][it] * acS[k][it];
+          if (i < nfb && j < nfb) fr[(int64_t)j * ldf + i] = gff;   // the real F block: its compact copy only
+          else Z[(int64_t)j * ld + i] = make_double2(gff, 0.0);
+          Z[(int64_t)(T.Np + j) * ld + T.Np + i] = make_double2(sI[k][it] * acM[k][it], 0.0);
+        }
       }
-    }
   }
 }
 
