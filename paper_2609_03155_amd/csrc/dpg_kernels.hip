@@ -2179,6 +2179,14 @@ __device__ void wave_tile(const DevTables& T, const ChunkArgs& C, double2* __res
     wave_gemm_t<MODE, false, NV, TWO, false, NTA>(Z + (int64_t)k0 * ld + i * TB + RW * h, ld,
                                                   Z + (int64_t)k0 * ld + j * TB, ld, j * TB - k0, q);
   __builtin_amdgcn_sched_barrier(0);
+  if (TAIL) {
+    // the previous tile of these rows came from registers (keep); its stores,
+    // read from memory by the tile after this one, are made visible here,
+    // long after they were issued, instead of right after them
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  }
   const double2* tL = Z + (int64_t)(j * TB) * ld + j * TB;   // diagonal tile j (chol_inv_tile's storage)
   const double* tLr = FRB ? Fr + (int64_t)(j * TB) * ldf + j * TB : nullptr;
   const int nvb = T.nvp / TB;
@@ -2517,12 +2525,11 @@ __global__ __launch_bounds__(NT, 2) void k_chol_fpanel(DevTables T, ChunkArgs C,
     }
     WAccT<RNV> prev;   // this wave's tile (i, j - 1): the last 64 columns of the next sum
     for (int j = 0; j < nF; ++j) {
+      // L_ij (stored by all lanes) feeds the loads of step j + 2 (step j + 1
+      // takes it from registers): wave_tile makes it visible after the k-loop
+      // of step j + 1
       if (cls == FROWS_REAL) wave_tile<MM_RR, FR_READ, RNV, 2, false, true>(T, C, Z, cell, i, j, h, slab, 0, &prev);
       else wave_tile<MM_CR, FR_READ, RNV, 2, false, true>(T, C, Z, cell, i, j, h, slab, 0, &prev);
-      // L_ij (stored by all lanes) feeds the loads of step j + 1
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
     return;
   }
