@@ -321,9 +321,6 @@ __global__ __launch_bounds__(NT) void k_cell_scale(DevTables T, ProbArgs P, Chun
 // ================================================================ G_IF
 // G_IF(i,j) = conj(G_FI(j,i)) = -i w mu C_ji - i w conj(eps) C_ij + sum_R conj(z) Rt_ij,
 // from the geometry-free C and Rt; also zero in the F-pad columns / I-pad rows.
-#ifndef DPG_IF_NB
-#define DPG_IF_NB 4
-#endif
 __global__ __launch_bounds__(NT) void k_form_IF(DevTables T, ProbArgs P, ChunkArgs C) {
   const int nt = (T.Np + 63) / 64;
   int64_t cell;
@@ -348,9 +345,10 @@ __global__ __launch_bounds__(NT) void k_form_IF(DevTables T, ProbArgs P, ChunkAr
   const int il = threadIdx.x & 63;
   const int i = I0 + il;
   if (i >= T.Np) return;
-  // the wave's columns jl = wave + 4 n in batches of NB: the table loads of a
-  // batch are in flight together
-  constexpr int NB = DPG_IF_NB;
+  // the wave's columns jl = wave + 4 n in batches of NB = 4: the table loads
+  // of a batch are in flight together (all sixteen at once take too many
+  // registers: 3 waves per SIMD, slower)
+  constexpr int NB = 4;
   const int wv = threadIdx.x >> 6;
   const double di = d[T.Np + i];
   for (int jb = J0 + wv; jb < J0 + 64 && jb < T.Np; jb += NB * (NT / 64)) {
