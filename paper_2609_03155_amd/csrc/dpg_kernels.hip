@@ -1889,8 +1889,9 @@ struct WPipe {
   // buffers, unless the two-level summation takes that room for its run sums
   static constexpr int NB = (NV == 2 || TWO) ? (MODE == MM_RR ? 4 : 2) : (MODE == MM_RR ? 8 : 4);
   // k-steps per buffer (more than one lets a mode with few MFMAs per k-step
-  // keep more work in flight; two for the complex x real mode spilled, so one)
-  static constexpr int KS = 1;
+  // keep more work in flight): two for complex x real once the running totals
+  // are in LDS (TWO == 2; with them in registers two spilled), else one
+  static constexpr int KS = (MODE == MM_CR && TWO == 2) ? 2 : 1;
 };
 
 // Operands of one k-step: A from the complex panel Ai (leading dimension
@@ -1991,11 +1992,10 @@ __device__ __forceinline__ void wave_gemm_t(const void* __restrict__ Ai, int64_t
                                             int64_t ldb, int K, WAccT<NV>& q, const WAccT<NV>* tail = nullptr,
                                             double* tot = nullptr) {
   constexpr int NB = WPipe<MODE, NV, TWO>::NB, KS = WPipe<MODE, NV, TWO>::KS;
-  static_assert(!TWO || 16 % NB == 0, "a run of 16 k-steps spans whole pipeline rounds");
-  static_assert(!TAIL || KS == 1, "the tail is taken one k-step at a time");
+  static_assert(!TWO || 16 % (NB * KS) == 0, "a run of 16 k-steps spans whole pipeline rounds");
   const int nks_all = K / (4 * KS);   // buffers' worth of k-steps (K is a multiple of 64)
   if (nks_all <= 0) return;
-  const int nks = TAIL ? nks_all - 16 : nks_all;   // k-steps with A from memory
+  const int nks = TAIL ? nks_all - 16 / KS : nks_all;   // buffers with A from memory
   const int nfull = nks - nks % NB;
   const int lane = threadIdx.x & 63;
   WAccT<NV> qb;                   // the current run's sum (TWO == 1)
@@ -2061,7 +2061,7 @@ __device__ __forceinline__ void wave_gemm_t(const void* __restrict__ Ai, int64_t
       for (int u = 0; u < KS; ++u) wave_step<MODE, NV>(o[s][u], acc);
       __builtin_amdgcn_sched_barrier(0);
     }
-    if (TWO && ((k0 + NB) & 15) == 0) {
+    if (TWO && (((k0 + NB) * KS) & 15) == 0) {
       fold_run();
       zero_run();
     }
@@ -2072,15 +2072,15 @@ __device__ __forceinline__ void wave_gemm_t(const void* __restrict__ Ai, int64_t
 #pragma unroll
       for (int u = 0; u < KS; ++u) wave_step<MODE, NV>(o[s][u], acc);
     }
-  if (TWO && (nks & 15) != 0) fold_run();
+  if (TWO && ((nks * KS) & 15) != 0) fold_run();
   if (TAIL) {
-    // the previous tile's 16 k-steps: one run of the two-level sum (nks is a
-    // multiple of 16, so the run boundaries are those of the full loop)
+    // the previous tile's 16 k-steps: one run of the two-level sum (nks KS is
+    // a multiple of 16, so the run boundaries are those of the full loop)
     WOpsT<NV> ob[2];
-    wave_load_b<MODE, FRB, NV>(Bj, ldb, nks, ob[0]);
+    wave_load_b<MODE, FRB, NV>(Bj, ldb, nks * KS, ob[0]);
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
-      if (t + 1 < 16) wave_load_b<MODE, FRB, NV>(Bj, ldb, nks + t + 1, ob[(t + 1) & 1]);
+      if (t + 1 < 16) wave_load_b<MODE, FRB, NV>(Bj, ldb, nks * KS + t + 1, ob[(t + 1) & 1]);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int v = 0; v < NV; ++v)
